@@ -1,0 +1,169 @@
+"""One IPCS_ABCN time step in FP64, following the paper step by step.
+
+Passages: the generic fractional-step loop (Alg. 1, one inner iteration),
+the high-performance assembly of the coefficient matrix (Alg. 2 and its
+implementation figure: assemble C into A, scale by -1/2, add M/dt and
+-nu K/2, form the partial right-hand side with A U^{n-1}, reset A to
+-A + 2M/dt, apply Dirichlet rows), the pressure-gradient matrices
+(eq:dp_matrix), the algebraic pressure-correction equation with
+dU^k = dP^k for equal spaces, and the lumped-mass velocity update
+(Sec. 5, last paragraphs; the channel runs of Sec. 6.2 use lumping).
+
+Readings (where the paper is silent or inconsistent):
+* Pressure sign: K phi = -(1/dt) sum_k dP^k U^{k,I}.  This is the algebraic
+  form of Sec. 5 and the only sign consistent with the correction
+  u^n = u^I - dt grad(phi) (eq:correction) making u^n divergence free;
+  eq:pressure and eq:pressureVF print the opposite sign.
+* The velocity update subtracts dt * M_L^{-1} dP^k phi (the correction phi,
+  as in eq:correction), not the full pressure.
+* One inner iteration (plain IPCS), lumped-mass update.
+* Dirichlet rows of A become identity rows (columns kept); b_i = g_i there.
+  All velocity components share the Dirichlet dof set, so one A serves all.
+* No pressure boundary condition: b_phi is projected onto 1-perp before the
+  solve, phi and p are shifted to zero arithmetic mean of their dof values.
+* Initial guesses: U^{k,n-1} for the tentative velocity, phi_prev for the
+  pressure correction.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import krylov, p1
+
+
+@dataclasses.dataclass
+class Setup:
+    mesh: object
+    nu: float
+    dt: float
+    f: np.ndarray
+    M: sp.csr_matrix
+    K: sp.csr_matrix
+    dP: list
+    ML: np.ndarray
+    b0: np.ndarray          # [d, N]
+    geo: tuple
+
+
+@dataclasses.dataclass
+class State:
+    U1: np.ndarray          # [d, N]  U^{n-1}
+    U2: np.ndarray          # [d, N]  U^{n-2}
+    p: np.ndarray           # [N]     p* (pressure from the last step)
+    phi_prev: np.ndarray    # [N]
+    t: float
+
+
+@dataclasses.dataclass
+class StepOut:
+    state: State
+    A: sp.csr_matrix        # tentative-velocity matrix after Dirichlet rows
+    b: np.ndarray           # [d, N] tentative right-hand sides after Dirichlet values
+    UI: np.ndarray          # [d, N] tentative velocity
+    b_phi: np.ndarray       # [N] projected pressure right-hand side
+    phi: np.ndarray         # [N] pressure correction (zero mean)
+    iters_u: list
+    iters_p: int
+    res_u: list
+    res_p: float
+    status: int
+
+
+def setup(mesh, nu, dt, f):
+    """Preassemble the constant matrices (Sec. 5: M, K once; dP^k once)."""
+    geo = p1.element_geometry(mesh)
+    M = p1.mass_matrix(mesh, geo)
+    K = p1.stiffness_matrix(mesh, geo)
+    dP = [p1.gradient_matrix(mesh, k, geo) for k in range(mesh.dim)]
+    ML = np.asarray(M.sum(axis=1)).ravel()
+    b0 = np.stack([f[k] * ML for k in range(mesh.dim)])
+    return Setup(mesh, float(nu), float(dt), np.asarray(f, float), M, K, dP, ML, b0, geo)
+
+
+def apply_dirichlet_rows(A, rows):
+    """Replace the given rows of a CSR matrix by identity rows (in a copy)."""
+    A = A.tocsr(copy=True)
+    is_bc = np.zeros(A.shape[0], bool)
+    is_bc[rows] = True
+    row_of = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    m = is_bc[row_of]
+    A.data[m] = 0.0
+    A.data[m & (A.indices == row_of)] = 1.0
+    return A
+
+
+def tentative_system(S: Setup, st: State, t_new: float, bc_vals):
+    """Alg. 2 literal: returns (A after BC rows, b [d, N] after BC values)."""
+    mesh = S.mesh
+    d = mesh.dim
+    ubar = 1.5 * st.U1 - 0.5 * st.U2
+    A = p1.convection_matrix(mesh, ubar, S.geo)          # A <- C
+    A = -0.5 * A                                         # A._scale(-0.5)
+    A = A + (1.0 / S.dt) * S.M                           # A.axpy(1/dt, M)
+    A = A + (-0.5 * S.nu) * S.K                          # A.axpy(-nu/2, K)
+    b_tmp = np.stack([S.b0[k] + A @ st.U1[k] for k in range(d)])
+    A = -1.0 * A                                         # A._scale(-1)
+    A = A + (2.0 / S.dt) * S.M                           # A.axpy(2/dt, M)
+    A = apply_dirichlet_rows(A, mesh.bc_dofs)
+    b = np.stack([b_tmp[k] - S.dP[k] @ st.p for k in range(d)])
+    if mesh.bc_dofs.size:
+        b[:, mesh.bc_dofs] = bc_vals
+    return A.tocsr(), b
+
+
+def pressure_rhs(S: Setup, UI):
+    b_phi = -(1.0 / S.dt) * sum(S.dP[k] @ UI[k] for k in range(S.mesh.dim))
+    return b_phi - b_phi.mean()
+
+
+def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
+         phi_guess=None) -> StepOut:
+    """Advance one time step.  bc_values: callable t -> [d, n_bc]."""
+    mesh = S.mesh
+    d = mesh.dim
+    t_new = st.t + S.dt
+    g = bc_values(t_new) if mesh.bc_dofs.size else np.zeros((d, 0))
+    A, b = tentative_system(S, st, t_new, g)
+    UI = np.empty_like(st.U1)
+    iters_u, res_u = [], []
+    status = 0
+    for k in range(d):
+        r = krylov.bicgstab(A, b[k], st.U1[k], rtol=rtol_u, maxit=maxit)
+        UI[k] = r.x
+        iters_u.append(r.iters)
+        res_u.append(r.rel_res)
+        status = max(status, r.status)
+    b_phi = pressure_rhs(S, UI)
+    x0 = st.phi_prev if phi_guess is None else phi_guess
+    rp = krylov.pcg(S.K, b_phi, x0, rtol=rtol_p, maxit=maxit)
+    status = max(status, rp.status)
+    phi = rp.x - rp.x.mean()
+    p_new = st.p + phi
+    p_new = p_new - p_new.mean()
+    Un = np.stack([UI[k] - S.dt * (S.dP[k] @ phi) / S.ML for k in range(d)])
+    if mesh.bc_dofs.size:
+        Un[:, mesh.bc_dofs] = g
+    new = State(Un, st.U1.copy(), p_new, phi, t_new)
+    return StepOut(new, A, b, UI, b_phi, phi, iters_u, rp.iters, res_u, rp.rel_res, status)
+
+
+def initial_state(problem) -> State:
+    return State(problem.U1.copy(), problem.U2.copy(), problem.p.copy(),
+                 problem.phi_prev.copy(), problem.t0)
+
+
+def run(problem, steps, rtol_u=None, rtol_p=None, callback=None):
+    S = setup(problem.mesh, problem.nu, problem.dt, problem.f)
+    st = initial_state(problem)
+    out = None
+    for n in range(steps):
+        out = step(S, st, problem.bc_values,
+                   rtol_u=problem.rtol_u if rtol_u is None else rtol_u,
+                   rtol_p=problem.rtol_p if rtol_p is None else rtol_p)
+        st = out.state
+        if callback is not None:
+            callback(n, out)
+    return S, st, out

@@ -1,0 +1,110 @@
+"""Mixed-precision Krylov with iterative refinement (not in the paper).
+
+Outer loop in FP64: r = b - A x; stop when ||r||_2 <= rtol ||b||_2.
+Inner solve of A e = r with the Krylov method of ``oracle.krylov`` carried
+out in FP32 storage: matrix values and vectors rounded to float32, sparse
+products accumulated in float32, inner products and norms accumulated in
+float64.  The inner loop stops when its recursive residual drops below
+inner_rtol * ||r||; then x += e in FP64.
+
+Reading: inner tolerance 1e-4 by default, Jacobi preconditioner from the
+FP32 diagonal, at most ``max_outer`` refinement steps (not converged after
+that is reported as status 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .krylov import KrylovResult, NOTCONV, OK
+
+
+def _pcg32(A32, d32, r, rtol, maxit):
+    b = r.astype(np.float32)
+    x = np.zeros_like(b)
+    rr = b.copy()
+    bn = float(np.sqrt(np.dot(b.astype(np.float64), b.astype(np.float64))))
+    tol = rtol * bn
+    z = (rr / d32).astype(np.float32)
+    p = z.copy()
+    rz = float(np.dot(rr.astype(np.float64), z.astype(np.float64)))
+    it = 0
+    while it < maxit:
+        q = (A32 @ p).astype(np.float32)
+        pq = float(np.dot(p.astype(np.float64), q.astype(np.float64)))
+        if pq <= 0.0:
+            break
+        alpha = rz / pq
+        x = (x + np.float32(alpha) * p).astype(np.float32)
+        rr = (rr - np.float32(alpha) * q).astype(np.float32)
+        it += 1
+        if np.sqrt(np.dot(rr.astype(np.float64), rr.astype(np.float64))) <= tol:
+            break
+        z = (rr / d32).astype(np.float32)
+        rz_new = float(np.dot(rr.astype(np.float64), z.astype(np.float64)))
+        p = (z + np.float32(rz_new / rz) * p).astype(np.float32)
+        rz = rz_new
+    return x.astype(np.float64), it
+
+
+def _bicgstab32(A32, d32, r0, rtol, maxit):
+    b = (r0.astype(np.float32) / d32).astype(np.float32)     # left Jacobi
+    dd = d32.astype(np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    tol = rtol * float(np.linalg.norm(r0))
+    rhat = r.copy()
+    rho_old = alpha = omega = 1.0
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    it = 0
+    f64 = lambda a: a.astype(np.float64)  # noqa: E731
+    while it < maxit:
+        rho = float(np.dot(f64(rhat), f64(r)))
+        if rho == 0.0:
+            break
+        beta = (rho / rho_old) * (alpha / omega)
+        p = (r + np.float32(beta) * (p - np.float32(omega) * v)).astype(np.float32)
+        v = ((A32 @ p) / d32).astype(np.float32)
+        rv = float(np.dot(f64(rhat), f64(v)))
+        if rv == 0.0:
+            break
+        alpha = rho / rv
+        s = (r - np.float32(alpha) * v).astype(np.float32)
+        it += 1
+        if np.linalg.norm(dd * f64(s)) <= tol:
+            x = (x + np.float32(alpha) * p).astype(np.float32)
+            break
+        t = ((A32 @ s) / d32).astype(np.float32)
+        tt = float(np.dot(f64(t), f64(t)))
+        omega = float(np.dot(f64(t), f64(s))) / tt if tt > 0 else 0.0
+        x = (x + np.float32(alpha) * p + np.float32(omega) * s).astype(np.float32)
+        r = (s - np.float32(omega) * t).astype(np.float32)
+        if np.linalg.norm(dd * f64(r)) <= tol or omega == 0.0:
+            break
+        rho_old = rho
+    return x.astype(np.float64), it
+
+
+def refine(method, A, b, x0, rtol=1e-8, inner_rtol=1e-4, maxit=10000, max_outer=50):
+    """method: 'cg' or 'bicgstab'.  Returns KrylovResult with iters = total inner
+    iterations and history = inner iterations per outer step."""
+    A32 = A.astype(np.float32)
+    d32 = A.diagonal().astype(np.float32)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    bn = float(np.linalg.norm(b))
+    total = 0
+    hist = []
+    inner = _pcg32 if method == "cg" else _bicgstab32
+    for _ in range(max_outer):
+        r = b - A @ x
+        rn = float(np.linalg.norm(r))
+        if rn <= rtol * bn:
+            return KrylovResult(x, total, rn / bn, OK, hist)
+        e, it = inner(A32, d32, r, inner_rtol, maxit - total)
+        x += e
+        total += it
+        hist.append(it)
+        if total >= maxit:
+            break
+    rn = float(np.linalg.norm(b - A @ x))
+    return KrylovResult(x, total, rn / bn, OK if rn <= rtol * bn else NOTCONV, hist)

@@ -1,0 +1,101 @@
+"""Pins for the oracle's Krylov loops: direct solves, pseudo-inverse on the
+singular pressure matrix, CG energy-norm monotonicity, finite termination,
+and the failure paths (not converged, breakdown, NaN)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import ipcs, krylov, mixed
+
+
+def _tent(problem):
+    S = ipcs.setup(problem.mesh, problem.nu, problem.dt, problem.f)
+    st = ipcs.initial_state(problem)
+    A, b = ipcs.tentative_system(S, st, problem.t0 + problem.dt, problem.bc_values(problem.dt))
+    return S, st, A, b
+
+
+@pytest.mark.parametrize("prob", [synth.taylor_green(16), synth.channel_flow("tiny", displace_seed=1)],
+                         ids=lambda p: p.name)
+def test_bicgstab_matches_direct_solve(prob):
+    S, st, A, b = _tent(prob)
+    A = A.tocsc()
+    for k in range(prob.mesh.dim):
+        x_ref = spla.spsolve(A, b[k])
+        r = krylov.bicgstab(A.tocsr(), b[k], st.U1[k], rtol=1e-12)
+        assert r.status == krylov.OK
+        assert r.rel_res <= 1e-12
+        kappa = np.linalg.cond(A.toarray())
+        assert np.linalg.norm(r.x - x_ref) <= 10 * kappa * 1e-12 * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("prob", [synth.taylor_green(12), synth.channel_flow("tiny")], ids=lambda p: p.name)
+def test_pcg_singular_pressure_matches_pseudoinverse(prob):
+    S, st, A, b = _tent(prob)
+    K = S.K
+    rng = np.random.default_rng(3)
+    bphi = rng.normal(size=K.shape[0])
+    bphi -= bphi.mean()
+    r = krylov.pcg(K, bphi, np.zeros_like(bphi), rtol=1e-13)
+    assert r.status == krylov.OK
+    x = r.x - r.x.mean()
+    x_ref = np.linalg.lstsq(K.toarray(), bphi, rcond=None)[0]
+    x_ref -= x_ref.mean()
+    assert np.linalg.norm(x - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+def test_pcg_energy_error_monotone_and_finite_termination():
+    rng = np.random.default_rng(5)
+    n = 24
+    Q = rng.normal(size=(n, n))
+    A = sp.csr_matrix(Q @ Q.T + n * np.eye(n))
+    xs = rng.normal(size=n)
+    b = A @ xs
+    errs = []
+    x = np.zeros(n)
+    for it in range(1, n + 1):
+        r = krylov.pcg(A, b, x * 0, rtol=1e-30, maxit=it)
+        e = r.x - xs
+        errs.append(float(e @ (A @ e)))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-12) for i in range(len(errs) - 1))
+    r = krylov.pcg(A, b, np.zeros(n), rtol=1e-12, maxit=3 * n)
+    assert r.status == krylov.OK and r.iters <= n + 5
+
+
+def test_failure_paths():
+    A = sp.csr_matrix(np.array([[4.0, 1.0], [1.0, 3.0]]))
+    b = np.array([1.0, 2.0])
+    r = krylov.pcg(A, b, np.zeros(2), rtol=1e-14, maxit=1)
+    assert r.status == krylov.NOTCONV and r.iters == 1
+    r = krylov.bicgstab(A, b, np.zeros(2), rtol=1e-14, maxit=1)
+    assert r.status == krylov.NOTCONV
+    # indefinite matrix with positive diagonal: p^T A p < 0 stops CG
+    Ai = sp.csr_matrix(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    r = krylov.pcg(Ai, np.array([1.0, -1.0]), np.zeros(2), rtol=1e-12)
+    assert r.status == krylov.BREAKDOWN
+    # (r_hat, D^{-1} A r_hat) = 0 twice: BiCGStab breakdown after one restart
+    Ab = sp.csr_matrix(np.array([[1.0, -2.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]))
+    r = krylov.bicgstab(Ab, np.array([1.0, 1.0, 0.0]), np.zeros(3), rtol=1e-12)
+    assert r.status == krylov.BREAKDOWN
+    bn = b.copy()
+    bn[0] = np.nan
+    assert krylov.pcg(A, bn, np.zeros(2)).status == krylov.NAN
+    assert krylov.bicgstab(A, bn, np.zeros(2)).status == krylov.NAN
+
+
+def test_mixed_refinement_reaches_fp64_tolerance():
+    prob = synth.channel_flow("small")
+    S, st, A, b = _tent(prob)
+    rng = np.random.default_rng(9)
+    bphi = rng.normal(size=S.K.shape[0])
+    bphi -= bphi.mean()
+    ref = krylov.pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-12)
+    r = mixed.refine("cg", S.K, bphi, np.zeros_like(bphi), rtol=1e-8, inner_rtol=1e-4)
+    assert r.status == krylov.OK and r.rel_res <= 1e-8
+    assert len(r.history) >= 2          # more than one refinement step was needed
+    rel = np.linalg.norm((r.x - r.x.mean()) - (ref.x - ref.x.mean())) / np.linalg.norm(ref.x - ref.x.mean())
+    assert rel < 1e-5
+    rb = mixed.refine("bicgstab", A, b[0], st.U1[0], rtol=1e-10, inner_rtol=1e-4)
+    assert rb.status == krylov.OK and rb.rel_res <= 1e-10
