@@ -1,0 +1,335 @@
+/*
+ * oasis.h — C ABI of the MI355X (gfx950) P1-P1 IPCS hot-path library.
+ *
+ * Method (Mortensen & Valen-Sendstad, "Oasis: a high-level/high-performance
+ * open source Navier-Stokes solver"): the incremental pressure-correction
+ * scheme with Adams-Bashforth projected convecting velocity and
+ * Crank-Nicolson convected velocity (Sec. 2, eq:NStentative, eq:pressure,
+ * eq:correction, eq:convection_ABCN), discretised with P1 elements for
+ * velocity and pressure, and implemented on the algebraic level of Sec. 5
+ * (preassembled M, K, dP^k; Alg. 2 for the coefficient matrix; lumped-mass
+ * velocity update).
+ *
+ * Conventions for every entry point
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    All device work is enqueued on it and is asynchronous unless stated.
+ *  - Pointers documented "device" must be device-accessible memory owned
+ *    by the caller; "host" pointers are ordinary host memory.  The library
+ *    never allocates or frees device memory: every scratch buffer is a
+ *    caller-provided workspace whose size is returned by a *_workspace_size
+ *    query.  Workspaces must be 256-byte aligned.
+ *  - Indices are int32; dense vectors are contiguous; multi-component
+ *    fields are stored component-major ([dim][n]).
+ *  - Every function returns an int status: 0 = OASIS_OK or a negative
+ *    error code; no C++ exception crosses the ABI.  oasis_strerror() gives
+ *    text, oasis_last_hip_error() the last HIP runtime error of the calling
+ *    thread.
+ *  - Results are deterministic: all reductions are fixed-order; no
+ *    floating-point atomics are used.
+ */
+#ifndef OASIS_H
+#define OASIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define OASIS_OK            0
+#define OASIS_EINVAL       -1   /* bad argument: null/misaligned pointer, dim, dtype, size */
+#define OASIS_EHIP         -2   /* a HIP runtime call failed (see oasis_last_hip_error) */
+#define OASIS_ENOTCONV     -3   /* Krylov: maxit reached; x holds the last iterate, stats filled */
+#define OASIS_EBREAKDOWN   -4   /* Krylov: breakdown (after one restart for BiCGStab) */
+#define OASIS_ENAN         -5   /* non-finite value met in a reduction */
+#define OASIS_EWORKSPACE   -6   /* workspace smaller than the queried size */
+#define OASIS_EUNSUPPORTED -7   /* mesh/graph outside a documented limit */
+
+#define OASIS_F64 0
+#define OASIS_F32 1
+
+/* forms for oasis_assemble_p1 (row = test function i, column = trial j) */
+#define OASIS_FORM_MASS   0   /* M_ij  = int phi_j phi_i                    */
+#define OASIS_FORM_STIFF  1   /* K_ij  = int grad phi_j . grad phi_i        */
+#define OASIS_FORM_GRAD_X 2   /* dP^0_ij = int d_x phi_j phi_i  (eq:dp_matrix) */
+#define OASIS_FORM_GRAD_Y 3   /* dP^1 */
+#define OASIS_FORM_GRAD_Z 4   /* dP^2 (3D only) */
+#define OASIS_FORM_CONV   5   /* C_ij  = int (u_bar . grad phi_j) phi_i      */
+
+/* ---- data types -------------------------------------------------------- */
+
+/* CSR matrix; row_ptr [n+1], col_idx [nnz] (sorted within rows), val [nnz]
+ * of dtype OASIS_F64 (double) or OASIS_F32 (float).  All device pointers. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    void *val;
+    int32_t dtype;
+} oasis_csr;
+
+/* Simplex mesh with P1 dofs.  dim is 2 (triangles) or 3 (tetrahedra).
+ *  coords   device double [n_vert][dim]   vertex coordinates
+ *  cells    device int32  [n_cell][dim+1] vertex indices
+ *  vert2dof device int32  [n_vert]        dof of every vertex; several
+ *                                         vertices may share a dof
+ *                                         (periodic identification)
+ *  n_colors, color_ptr (HOST int32 [n_colors+1]), color_cells (device
+ *  int32 [n_cell]): cells grouped so that no two cells of one colour share
+ *  a dof (from oasis_color_cells / oasis_color_classes).  Needed by the
+ *  assembly and IPCS entry points; ignored by the pattern and colouring
+ *  entry points. */
+typedef struct {
+    int32_t dim;
+    int32_t n_vert;
+    int32_t n_cell;
+    int32_t n_dof;
+    const double *coords;
+    const int32_t *cells;
+    const int32_t *vert2dof;
+    int32_t n_colors;
+    const int32_t *color_ptr;
+    const int32_t *color_cells;
+} oasis_mesh;
+
+/* ---- graph set-up (shared sparsity pattern, Sec. 5 after Alg. 2) -------- */
+
+/* Workspace for oasis_p1_pattern / oasis_color_cells on this mesh. */
+int oasis_graph_workspace_size(const oasis_mesh *mesh, size_t *bytes);
+
+/* P1 sparsity pattern over dofs: (i, j) is stored iff some cell holds
+ * both dofs.  Pass col_idx = NULL to get row_ptr (device int32 [n_dof+1])
+ * and *nnz_out (host) only; call again with col_idx (device int32
+ * [col_capacity]) to fill sorted column indices.  Synchronises `stream`.
+ * EWORKSPACE if ws is too small, EINVAL if col_capacity < nnz. */
+int oasis_p1_pattern(void *stream, const oasis_mesh *mesh, int32_t *row_ptr,
+                     int32_t *col_idx, int64_t col_capacity, int32_t *nnz_out,
+                     void *ws, size_t ws_bytes);
+
+/* Greedy first-fit colouring of the cells, visiting cells in decreasing
+ * `priority` (device int32 [n_cell], pairwise distinct): every cell takes
+ * the least colour not used by an already coloured cell sharing a dof.
+ * Writes color (device int32 [n_cell]) and *n_colors_out (host).  At most
+ * 128 colours (else EUNSUPPORTED).  Synchronises `stream`. */
+int oasis_color_cells(void *stream, const oasis_mesh *mesh, const int32_t *priority,
+                      int32_t *color, int32_t *n_colors_out, void *ws, size_t ws_bytes);
+
+/* Group cells by colour: color_ptr (HOST int32 [n_colors+1]) and
+ * color_cells (device int32 [n_cell]) listing each colour's cells in
+ * increasing cell index.  ws: at least oasis_graph_workspace_size bytes.
+ * Synchronises `stream`. */
+int oasis_color_classes(void *stream, int32_t n_cell, const int32_t *color, int32_t n_colors,
+                        int32_t *color_ptr, int32_t *color_cells, void *ws, size_t ws_bytes);
+
+/* Workspace for oasis_rcm on an n-vertex graph. */
+int oasis_rcm_workspace_size(int32_t n, size_t *bytes);
+
+/* Reverse Cuthill-McKee ordering of the symmetric pattern (row_ptr,
+ * col_idx; diagonal stored).  Component roots: least (degree, index)
+ * unvisited vertex refined by George-Liu pseudo-peripheral search; at each
+ * vertex, unvisited neighbours are appended in (degree, index) order; the
+ * sequence is reversed.  Writes perm (device int32 [n], perm[old] = new)
+ * and order (device int32 [n], order[new] = old).  Synchronises `stream`. */
+int oasis_rcm(void *stream, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+              int32_t *perm, int32_t *order, void *ws, size_t ws_bytes);
+
+/* out[i] = perm[in[i]] for i < count (relabel vert2dof or a dof list). */
+int oasis_relabel(void *stream, int32_t count, const int32_t *in, const int32_t *perm,
+                  int32_t *out);
+
+/* ---- assembly (Sec. 5, Alg. 2) ----------------------------------------- */
+
+/* out.val = (base ? base.val : 0) + alpha * (assembled `form`) on the
+ * pattern of `out` (which must contain the P1 pattern of the mesh; base, if
+ * given, must share it).  FORM_CONV needs uab[0..dim-1], device double
+ * [n_dof] each: the nodal convecting velocity u_bar.  out.dtype must be
+ * F64.  Element matrices are evaluated in closed form in FP64; cells are
+ * scattered colour by colour, so no two threads touch one row.  The mesh
+ * colouring is required. */
+int oasis_assemble_p1(void *stream, const oasis_mesh *mesh, int32_t form,
+                      const double *const *uab, double alpha, const oasis_csr *base,
+                      oasis_csr *out);
+
+/* ---- sparse matrix-vector product (Sec. 5, eq:tent_algebraic terms) ----- */
+
+/* y = alpha * A x + beta * y.  x and y have A's dtype; F32 products are
+ * accumulated in FP32, F64 in FP64.  With beta == 0, y is not read. */
+int oasis_spmv(void *stream, const oasis_csr *A, const void *x, void *y, double alpha,
+               double beta);
+
+/* ---- Krylov solvers (Sec. 6.2: BiCGStab + Jacobi; CG for pressure) ------ */
+
+typedef struct {
+    double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) */
+    int32_t maxit;        /* total (inner) iteration cap */
+    int32_t precision;    /* OASIS_F64, or OASIS_F32 = FP32 inner / FP64 outer refinement */
+    double inner_rtol;    /* F32 mode: inner stop, relative to the outer residual */
+    int32_t max_outer;    /* F32 mode: cap on refinement steps (0 = 50) */
+    int32_t check_every;  /* iterations launched between host convergence polls (0 = auto) */
+    int32_t flags;        /* OASIS_KRYLOV_TIME: time the dominant kernel with HIP events */
+} oasis_krylov_opts;
+
+#define OASIS_KRYLOV_TIME 1
+
+typedef struct {
+    int32_t iters;        /* total (inner) iterations */
+    int32_t outer_iters;  /* refinement steps (F32 mode) */
+    int32_t status;       /* OASIS_OK / ENOTCONV / EBREAKDOWN / ENAN */
+    int32_t restarts;     /* BiCGStab breakdown restarts, residual replacements */
+    double rel_res;       /* final true ||b - A x|| / ||b|| */
+    double kernel_ms;     /* OASIS_KRYLOV_TIME: summed time of the SpMV kernel */
+    int32_t kernel_count; /* number of timed launches */
+    int32_t pad;
+} oasis_krylov_stats;
+
+/* Workspace for oasis_pcg / oasis_bicgstab with nrhs right-hand sides. */
+int oasis_krylov_workspace_size(int32_t n, int32_t nnz, int32_t nrhs,
+                                const oasis_krylov_opts *opt, size_t *bytes);
+
+/* Jacobi-preconditioned CG on an SPD (or SPSD with consistent b) F64 CSR
+ * matrix.  b: device double [n]; x: device double [n], in: x0, out:
+ * solution (last iterate on ENOTCONV).  stats: host.  Synchronises
+ * `stream`.  The iteration is CG on D^{-1/2} A D^{-1/2} (same iterates as
+ * z = D^{-1} r preconditioning in exact arithmetic). */
+int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x,
+              const oasis_krylov_opts *opt, void *ws, size_t ws_bytes,
+              oasis_krylov_stats *stats);
+
+/* BiCGStab (van der Vorst) with left Jacobi preconditioning on an F64 CSR
+ * matrix, for nrhs in {1,2,3} right-hand sides sharing A (one pass over A
+ * per product for all of them).  b, x: device double [nrhs][n]; stats:
+ * host [nrhs].  On a breakdown the solve restarts once with r_hat = r.
+ * Returns the worst status over the right-hand sides.  Synchronises. */
+int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, const double *b,
+                   double *x, const oasis_krylov_opts *opt, void *ws, size_t ws_bytes,
+                   oasis_krylov_stats *stats);
+
+/* ---- the IPCS time step (Alg. 1 with one inner iteration + Alg. 2) ------ */
+
+typedef struct {
+    double dt, nu;
+    double f[3];              /* constant body force */
+    int32_t n_bc;             /* velocity Dirichlet dofs (same set for all components) */
+    const int32_t *bc_dofs;   /* device int32 [n_bc] */
+    double rtol_u, rtol_p;    /* Krylov relative tolerances (true residual) */
+    int32_t maxit;
+    int32_t precision;        /* OASIS_F64 or OASIS_F32 (FP32 inner Krylov + FP64 refinement) */
+    double inner_rtol;        /* F32 mode inner tolerance */
+} oasis_ipcs_params;
+
+typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
+
+/* Fields of one step; all device double arrays of length n_dof.
+ *  U1[k]  U^{k,n-1}   (read)       U2[k]  U^{k,n-2} (read)
+ *  Un[k]  U^{k,n}     (written; may not alias U1/U2)
+ *  p      p* on entry, p^{n-1/2} (zero mean) on return
+ *  phi    phi_prev on entry (initial guess), the new correction on return
+ *  UI[k], b_phi: optional (NULL) outputs of the tentative velocity and the
+ *  projected pressure right-hand side. */
+typedef struct {
+    const double *U1[3];
+    const double *U2[3];
+    double *Un[3];
+    double *p;
+    double *phi;
+    double *UI[3];
+    double *b_phi;
+} oasis_state;
+
+typedef struct {
+    int32_t iters_u[3], iters_p;
+    int32_t outer_u, outer_p;
+    int32_t status;           /* worst Krylov status of the step */
+    int32_t guess_used;       /* 1 if phi_guess gave the smaller initial residual */
+    double res_u[3], res_p;   /* final true relative residuals */
+    double ms_assemble, ms_velocity, ms_pressure, ms_update, ms_total;  /* HIP-event phase times */
+} oasis_step_stats;
+
+/* Workspace for a handle on this mesh/pattern/params. */
+int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz,
+                              const oasis_ipcs_params *par, size_t *bytes);
+
+/* Preassemble M, K, dP^k, M_L and the constant part B = M/dt + nu K/2
+ * (Sec. 5: matrices that do not change in time are assembled once).
+ * row_ptr/col_idx: the P1 pattern of the mesh (device, kept by reference,
+ * like the mesh arrays and bc_dofs, for the handle's lifetime).  The
+ * handle is host memory; the workspace holds every matrix and vector.
+ * Synchronises `stream`. */
+int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_ptr,
+                      const int32_t *col_idx, int32_t nnz, const oasis_ipcs_params *par,
+                      void *ws, size_t ws_bytes, oasis_ipcs **out);
+
+/* One time step t^{n-1} -> t^n: u_bar, convection assembly with
+ * A = M/dt + C/2 + nu K/2 and the right-hand side of eq:tent_intermediate1
+ * (Alg. 2), pressure gradient (eq:dp_matrix), Dirichlet rows, BiCGStab for
+ * all velocity components, pressure right-hand side -(1/dt) sum_k dP^k U^I
+ * projected on 1-perp, Jacobi-PCG for phi, p update and normalisation,
+ * lumped velocity update.  bc_values: device double [dim][n_bc] at t^n.
+ * phi_guess (device, nullable): a candidate initial guess for the
+ * pressure solve; it is used only if its initial residual is below that of
+ * phi_prev.  stats: host (nullable).  Synchronises `stream`. */
+int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
+                    const double *bc_values, const double *phi_guess,
+                    oasis_step_stats *stats);
+
+/* Device pointers to the handle's preassembled matrices (values on the
+ * shared pattern) for inspection: which = OASIS_FORM_MASS, _STIFF (the
+ * unscaled K is returned as scaled values plus sqrt of its diagonal, see
+ * below) or _GRAD_X.. ; lumped mass via which = -1.  *scaled_diag_sqrt
+ * (may be NULL) receives sqrt(diag K) for _STIFF, with K_ij = Ks_ij *
+ * s_i * s_j. */
+int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const double **val,
+                      const double **scaled_diag_sqrt);
+
+int oasis_ipcs_destroy(oasis_ipcs *h);
+
+/* ---- learned warm start (message-passing network; not in the paper) ----- */
+
+#define OASIS_MPNN_IN 6
+#define OASIS_MPNN_HID 32
+#define OASIS_MPNN_LAYERS 3
+/* Parameter block (host or device float32, packed in this order):
+ * We[32][6], ce[32], Ws[3][32][32], Wn[3][32][32], c[3][32], wd[32], cd[1] */
+#define OASIS_MPNN_NPARAM (32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1)
+
+/* Workspace for the network on an n-node graph (activations kept for the
+ * backward pass). */
+int oasis_mpnn_workspace_size(int32_t n, size_t *bytes);
+
+/* Features and forward pass.  K: the pressure matrix as held by an IPCS
+ * handle (scaled values Ks with Ks_ii = 1 and s = sqrt(diag K)); the edge
+ * weights are w_ij = -K_ij / K_ii on off-diagonal entries.  b_phi, phi_prev:
+ * device double [n]; coords: device double [n][dim] (dof coordinates);
+ * params: device float [OASIS_MPNN_NPARAM].  Writes guess = phi_prev +
+ * sigma * delta (device double [n], nullable) and delta (device float [n],
+ * nullable); activations stay in ws for oasis_mpnn_backward. */
+int oasis_mpnn_forward(void *stream, const oasis_csr *Ks, const double *s, int32_t dim,
+                       const double *coords, const double *b_phi, const double *phi_prev,
+                       const float *params, double *guess, float *delta,
+                       void *ws, size_t ws_bytes);
+
+/* Loss mean((delta - target)^2) with target = (phi - phi_prev)/sigma, and the
+ * parameter gradient (device float [OASIS_MPNN_NPARAM], overwritten) of the
+ * forward pass whose activations ws holds.  *loss_out: host, nullable
+ * (synchronises when given). */
+int oasis_mpnn_backward(void *stream, const oasis_csr *Ks, const double *s,
+                        const double *phi, const double *phi_prev, const float *params,
+                        float *grad, double *loss_out, void *ws, size_t ws_bytes);
+
+/* Adam step on device float32 params with moments m, v (device float
+ * [OASIS_MPNN_NPARAM], zero-initialised by the caller); t = 1, 2, ... */
+int oasis_mpnn_adam(void *stream, float *params, const float *grad, float *m, float *v,
+                    int32_t t, float lr, float beta1, float beta2, float eps);
+
+/* ---- diagnostics ------------------------------------------------------- */
+const char *oasis_strerror(int code);
+int oasis_last_hip_error(void);
+const char *oasis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OASIS_H */

@@ -1,0 +1,20 @@
+"""MI355X (gfx950) hot path of the P1-P1 IPCS_ABCN Navier-Stokes scheme.
+
+The compute lives in liboasis.so (hand-written HIP kernels behind the C ABI
+of include/oasis.h); this package is its ctypes binding plus a small
+time-stepping driver.  Importing it loads the library and fails loudly if
+it has not been built.
+"""
+from . import _lib
+from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUNSUPPORTED, F32, F64,
+                   FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, OasisError)
+
+_lib.load()
+
+from .api import (IPCS, DeviceCSR, DeviceMesh, assemble_p1, bicgstab, color_cells, color_classes,  # noqa: E402
+                  colorize, p1_pattern, pcg, rcm, relabel, spmv)
+
+__all__ = ["IPCS", "DeviceCSR", "DeviceMesh", "assemble_p1", "bicgstab", "color_cells", "color_classes",
+           "colorize", "p1_pattern", "pcg", "rcm", "relabel", "spmv", "OasisError",
+           "OK", "EINVAL", "EHIP", "ENOTCONV", "EBREAKDOWN", "ENAN", "EWORKSPACE", "EUNSUPPORTED", "F32", "F64",
+           "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV"]

@@ -1,0 +1,127 @@
+"""ctypes declarations of the C ABI in include/oasis.h.
+
+Loading fails loudly when liboasis.so has not been built: there is no CPU
+fallback for anything the library computes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboasis.so")
+
+OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+F64, F32 = 0, 1
+FORM_MASS, FORM_STIFF, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_CONV = range(6)
+KRYLOV_TIME = 1
+MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
+MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
+
+i32 = C.c_int32
+i64 = C.c_int64
+f64 = C.c_double
+f32 = C.c_float
+vp = C.c_void_p
+sz = C.c_size_t
+P = C.POINTER
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", i32), ("nnz", i32), ("row_ptr", vp), ("col_idx", vp), ("val", vp), ("dtype", i32)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", i32), ("n_vert", i32), ("n_cell", i32), ("n_dof", i32), ("coords", vp),
+                ("cells", vp), ("vert2dof", vp), ("n_colors", i32), ("color_ptr", P(i32)),
+                ("color_cells", vp)]
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("rtol", f64), ("maxit", i32), ("precision", i32), ("inner_rtol", f64),
+                ("max_outer", i32), ("check_every", i32), ("flags", i32)]
+
+
+class KrylovStats(C.Structure):
+    _fields_ = [("iters", i32), ("outer_iters", i32), ("status", i32), ("restarts", i32),
+                ("rel_res", f64), ("kernel_ms", f64), ("kernel_count", i32), ("pad", i32)]
+
+
+class IpcsParams(C.Structure):
+    _fields_ = [("dt", f64), ("nu", f64), ("f", f64 * 3), ("n_bc", i32), ("bc_dofs", vp),
+                ("rtol_u", f64), ("rtol_p", f64), ("maxit", i32), ("precision", i32),
+                ("inner_rtol", f64)]
+
+
+class State(C.Structure):
+    _fields_ = [("U1", vp * 3), ("U2", vp * 3), ("Un", vp * 3), ("p", vp), ("phi", vp),
+                ("UI", vp * 3), ("b_phi", vp)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters_u", i32 * 3), ("iters_p", i32), ("outer_u", i32), ("outer_p", i32),
+                ("status", i32), ("guess_used", i32), ("res_u", f64 * 3), ("res_p", f64),
+                ("ms_assemble", f64), ("ms_velocity", f64), ("ms_pressure", f64),
+                ("ms_update", f64), ("ms_total", f64)]
+
+
+_SIGS = {
+    "oasis_graph_workspace_size": (i32, [P(Mesh), P(sz)]),
+    "oasis_p1_pattern": (i32, [vp, P(Mesh), vp, vp, i64, P(i32), vp, sz]),
+    "oasis_color_cells": (i32, [vp, P(Mesh), vp, vp, P(i32), vp, sz]),
+    "oasis_color_classes": (i32, [vp, i32, vp, i32, P(i32), vp, vp, sz]),
+    "oasis_rcm_workspace_size": (i32, [i32, P(sz)]),
+    "oasis_rcm": (i32, [vp, i32, vp, vp, vp, vp, vp, sz]),
+    "oasis_relabel": (i32, [vp, i32, vp, vp, vp]),
+    "oasis_assemble_p1": (i32, [vp, P(Mesh), i32, P(vp), f64, P(Csr), P(Csr)]),
+    "oasis_spmv": (i32, [vp, P(Csr), vp, vp, f64, f64]),
+    "oasis_krylov_workspace_size": (i32, [i32, i32, i32, P(KrylovOpts), P(sz)]),
+    "oasis_pcg": (i32, [vp, P(Csr), vp, vp, P(KrylovOpts), vp, sz, P(KrylovStats)]),
+    "oasis_bicgstab": (i32, [vp, P(Csr), i32, vp, vp, P(KrylovOpts), vp, sz, P(KrylovStats)]),
+    "oasis_ipcs_workspace_size": (i32, [P(Mesh), i32, P(IpcsParams), P(sz)]),
+    "oasis_ipcs_create": (i32, [vp, P(Mesh), vp, vp, i32, P(IpcsParams), vp, sz, P(vp)]),
+    "oasis_ipcs_step": (i32, [vp, vp, P(State), vp, vp, P(StepStats)]),
+    "oasis_ipcs_matrix": (i32, [vp, i32, P(vp), P(vp)]),
+    "oasis_ipcs_destroy": (i32, [vp]),
+    "oasis_mpnn_workspace_size": (i32, [i32, P(sz)]),
+    "oasis_mpnn_forward": (i32, [vp, P(Csr), vp, i32, vp, vp, vp, vp, vp, vp, vp, sz]),
+    "oasis_mpnn_backward": (i32, [vp, P(Csr), vp, vp, vp, vp, vp, P(f64), vp, sz]),
+    "oasis_mpnn_adam": (i32, [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32]),
+    "oasis_strerror": (C.c_char_p, [i32]),
+    "oasis_last_hip_error": (i32, []),
+    "oasis_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load liboasis.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liboasis.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class OasisError(RuntimeError):
+    def __init__(self, code, where):
+        lib = load()
+        msg = lib.oasis_strerror(code).decode()
+        if code == EHIP:
+            msg += " (hipError %d)" % lib.oasis_last_hip_error()
+        super().__init__("%s: %s [%d]" % (where, msg, code))
+        self.code = code
+
+
+def check(code, where, allow=()):
+    if code != OK and code not in allow:
+        raise OasisError(code, where)
+    return code

@@ -1,0 +1,132 @@
+// Internal helpers shared by the library's translation units: error
+// plumbing, workspace carving, deterministic wave/block reductions and the
+// "consumer reduces" pattern used to hand a global sum from one kernel to
+// the next without atomics or cross-block fences.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "oasis.h"
+
+namespace oasis {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 2048;   // producer kernels launch at most this many blocks
+
+void set_hip_error(hipError_t e);
+
+#define OASIS_TRY_HIP(call)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) {                              \
+            ::oasis::set_hip_error(e_);                      \
+            return OASIS_EHIP;                               \
+        }                                                    \
+    } while (0)
+
+#define OASIS_TRY_LAUNCH() OASIS_TRY_HIP(hipGetLastError())
+
+#define OASIS_TRY(expr)                  \
+    do {                                 \
+        int rc_ = (expr);                \
+        if (rc_ != OASIS_OK) return rc_; \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Sequential sub-allocation of a caller workspace.  With base == nullptr it
+// only measures; the same sequence of take() calls is used for both.
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t off = 0;
+    bool ok = true;
+    Carver(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t a = (off + 255) & ~size_t(255);
+        size_t need = a + count * sizeof(T);
+        off = need;
+        if (base == nullptr) return nullptr;
+        if (need > cap) {
+            ok = false;
+            return nullptr;
+        }
+        return reinterpret_cast<T *>(base + a);
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+inline int grid_for(long long work, int per_block, int cap = kMaxPartials) {
+    long long g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+// ---------------------------------------------------------------------------
+// device reductions (fixed order => bitwise deterministic)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum NV values over the block; every thread receives the totals.
+// lds must hold NV * (blockDim/64) doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * nw + wid] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[k * nw + w];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Producer side: the block's NV partial sums go to part[blockIdx.x][NV].
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *part, double *lds) {
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) part[blockIdx.x * NV + k] = v[k];
+    }
+}
+
+// Consumer side: every block sums the nparts partials of the previous kernel
+// in the same order, so all blocks hold identical totals.
+template <int NV>
+__device__ __forceinline__ void read_partials(const double *part, int nparts, double (&out)[NV],
+                                              double *lds) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] += part[i * NV + k];
+    }
+    block_sum<NV>(out, lds);
+}
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+}  // namespace oasis

@@ -1,0 +1,1057 @@
+// The IPCS_ABCN time step on the device, and the stand-alone Krylov entry
+// points.
+//
+// Per step (Alg. 1 with one inner iteration, Alg. 2, Sec. 5):
+//   1  A = B + C(u_bar)/2 with B = M/dt + nu K/2 preassembled and
+//      u_bar = 1.5 U^{n-1} - 0.5 U^{n-2} formed inside the assembly.
+//      This is the coefficient matrix Alg. 2 leaves in A; its intermediate
+//      M/dt - C/2 - nu K/2 = 2M/dt - A is never stored: the explicit part of
+//      the right-hand side is evaluated row by row as (2M/dt - A) U^{n-1}.
+//   2  one pass per row: b^k = f_k M_L + (2M/dt - A) U^{k,n-1} - dP^k p*,
+//      Dirichlet rows (identity row, b = g), then the row is divided by its
+//      diagonal (left Jacobi) for the BiCGStab solve.
+//   3  BiCGStab for all velocity components at once (x0 = U^{k,n-1}).
+//   4  b_phi = -(1/dt) sum_k dP^k U^{k,I}, projected on 1-perp, symmetric
+//      Jacobi scaling, CG from phi_prev (or the better of phi_prev and a
+//      supplied guess).
+//   5  phi and p^{n-1/2} = p* + phi shifted to zero mean.
+//   6  U^{k,n} = U^{k,I} - dt (dP^k phi) / M_L, Dirichlet values restored.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "assemble.hpp"
+#include "krylov.hpp"
+#include "spmv.hpp"
+
+namespace oasis {
+
+// ---------------------------------------------------------------------------
+// matrix preparation kernels
+
+// diag[i] = A_ii (0 when absent)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const T *__restrict__ val, double *__restrict__ d) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int j = rp[i]; j < rp[i + 1]; ++j)
+            if (ci[j] == i) v = val[j];
+        d[i] = v;
+    }
+}
+
+// sym: out_ij = a_ij / (s_i s_j);  row: out_ij = a_ij / d_i.  Optional FP32 copy.
+__global__ __launch_bounds__(kBlock) void k_scale_matrix(int n, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ s, int sym,
+                                                         double *__restrict__ out,
+                                                         float *__restrict__ out32) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double si = s[i];
+        for (int j = rp[i]; j < rp[i + 1]; ++j) {
+            const double v = sym ? a[j] / (si * s[ci[j]]) : a[j] / si;
+            out[j] = v;
+            if (out32) out32[j] = static_cast<float>(v);
+        }
+    }
+}
+
+// per-row vector set-up from a diagonal: mode 0 (CG): s = sqrt(d), w = d;
+// mode 1 (BiCGStab): s = d, w = d^2.  flag set if a diagonal is unusable.
+__global__ __launch_bounds__(kBlock) void k_diag_vectors(int n, const double *d, int mode, double *s,
+                                                         double *w, float *w32, int *flag) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double v = d[i];
+        if (mode == 0 ? !(v > 0.0) : !(v != 0.0) || !__builtin_isfinite(v)) atomicOr(flag, 1);
+        s[i] = mode == 0 ? sqrt(v) : v;
+        w[i] = mode == 0 ? v : v * v;
+        if (w32) w32[i] = static_cast<float>(w[i]);
+    }
+}
+
+// y = x * a / s (op 0) or y = x * s (op 1) or y = x / s (op 2)
+__global__ __launch_bounds__(kBlock) void k_vscale(int n, const double *__restrict__ x,
+                                                   const double *__restrict__ s, int op,
+                                                   double *__restrict__ y) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = op == 1 ? x[i] * s[i] : x[i] / s[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_sums(int n, const int *__restrict__ rp,
+                                                     const double *__restrict__ a, double *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int j = rp[i]; j < rp[i + 1]; ++j) v += a[j];
+        out[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_lincomb(long long n, double *__restrict__ y, const double *__restrict__ a,
+                                                    double ca, const double *__restrict__ b, double cb) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = ca * a[i] + cb * b[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bc_index(int nbc, int n, const int *bc, int *idx, int *flag) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nbc;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int d = bc[q];
+        if (d >= 0 && d < n)
+            idx[d] = (int)q;
+        else
+            atomicOr(flag, 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(long long n, const double *__restrict__ x, float *__restrict__ y) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = static_cast<float>(x[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_f32(long long n, double *__restrict__ x, const float *__restrict__ e) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] += static_cast<double>(e[i]);
+}
+
+// ---------------------------------------------------------------------------
+// step kernels
+
+// Right-hand side, Dirichlet rows and left Jacobi scaling of A, one row per
+// lane group.  x0 of the velocity solve (U^{n-1}) is copied on the way.
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void k_tent_rows(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ M,
+    double *__restrict__ A, float *__restrict__ A32, P3 dP, P3 U1, const double *__restrict__ p,
+    const double *__restrict__ ML, const int *__restrict__ bc_index, const double *__restrict__ g,
+    int nbc, double f0, double f1, double f2, double two_over_dt, double *__restrict__ b0,
+    double *__restrict__ b1, double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1,
+    double *__restrict__ x2, double *__restrict__ dA, double *__restrict__ wA,
+    float *__restrict__ wA32) {
+    const int lane = threadIdx.x & (L - 1);
+    const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
+    const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
+    double *bo[3] = {b0, b1, b2};
+    double *xo[3] = {x0, x1, x2};
+    const double f[3] = {f0, f1, f2};
+    for (long long row = gid; row < n; row += ngroups) {
+        const int i = static_cast<int>(row);
+        const int s = rp[i], e = rp[i + 1];
+        double acc[D], accp[D], diag = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = accp[k] = 0.0;
+        for (int j = s + lane; j < e; j += L) {
+            const int c = ci[j];
+            const double a = A[j];
+            const double rhs_coef = two_over_dt * M[j] - a;
+            const double pc = p[c];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                acc[k] += rhs_coef * U1.p[k][c];
+                accp[k] += dP.p[k][j] * pc;
+            }
+            if (c == i) diag = a;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            acc[k] = group_sum<L>(acc[k]);
+            accp[k] = group_sum<L>(accp[k]);
+        }
+        diag = group_sum<L>(diag);
+        const int q = bc_index[i];
+        const double dd = q >= 0 ? 1.0 : diag;
+        const double inv = 1.0 / dd;
+        for (int j = s + lane; j < e; j += L) {
+            double a = A[j];
+            if (q >= 0) a = (ci[j] == i) ? 1.0 : 0.0;
+            a *= inv;
+            A[j] = a;
+            if (A32) A32[j] = static_cast<float>(a);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double bk = q >= 0 ? g[k * nbc + q] : f[k] * ML[i] + acc[k] - accp[k];
+                bo[k][i] = bk * inv;
+                xo[k][i] = U1.p[k][i];
+            }
+            dA[i] = dd;
+            wA[i] = dd * dd;
+            if (wA32) wA32[i] = static_cast<float>(dd * dd);
+        }
+    }
+}
+
+// b_phi = -(1/dt) sum_k dP^k U^{k,I}; partial sum of b_phi
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void k_div_rows(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci, P3 dP, P3 UI,
+                                                     double minv_dt, double *__restrict__ bphi,
+                                                     double *part) {
+    __shared__ double lds[kBlock / kWave];
+    double tot[1] = {0.0};
+    const int lane = threadIdx.x & (L - 1);
+    const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
+    const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
+    for (long long row = gid; row < n; row += ngroups) {
+        const int s = rp[row], e = rp[row + 1];
+        double acc = 0.0;
+        for (int j = s + lane; j < e; j += L) {
+            const int c = ci[j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc += dP.p[k][j] * UI.p[k][c];
+        }
+        acc = group_sum<L>(acc);
+        if (lane == 0) {
+            const double v = minv_dt * acc;
+            bphi[row] = v;
+            tot[0] += v;
+        }
+    }
+    write_partials<1>(tot, part, lds);
+}
+
+// projection on 1-perp and scaling: b_s = (b_phi - mean)/s, x_s = s * phi_prev
+__global__ __launch_bounds__(kBlock) void k_bphi_finish(int n, const double *part, int np,
+                                                        double *__restrict__ bphi,
+                                                        const double *__restrict__ s,
+                                                        const double *__restrict__ phi_prev,
+                                                        double *__restrict__ bs, double *__restrict__ xs) {
+    __shared__ double lds[kBlock / kWave];
+    double v[1];
+    read_partials<1>(part, np, v, lds);
+    const double mean = v[0] / n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double b = bphi[i] - mean;
+        bphi[i] = b;
+        bs[i] = b / s[i];
+        xs[i] = phi_prev[i] * s[i];
+    }
+}
+
+// phi = x_s / s; partial sum
+__global__ __launch_bounds__(kBlock) void k_phi_a(int n, const double *__restrict__ xs,
+                                                  const double *__restrict__ s, double *__restrict__ phi,
+                                                  double *part) {
+    __shared__ double lds[kBlock / kWave];
+    double tot[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double v = xs[i] / s[i];
+        phi[i] = v;
+        tot[0] += v;
+    }
+    write_partials<1>(tot, part, lds);
+}
+
+// phi -= mean(phi); p += phi; partial sum of p
+__global__ __launch_bounds__(kBlock) void k_phi_b(int n, const double *partIn, int np,
+                                                  double *__restrict__ phi, double *__restrict__ p,
+                                                  double *partOut) {
+    __shared__ double lds[kBlock / kWave];
+    double v[1];
+    read_partials<1>(partIn, np, v, lds);
+    const double mean = v[0] / n;
+    double tot[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double f = phi[i] - mean;
+        phi[i] = f;
+        const double q = p[i] + f;
+        p[i] = q;
+        tot[0] += q;
+    }
+    write_partials<1>(tot, partOut, lds);
+}
+
+// p -= mean(p)
+__global__ __launch_bounds__(kBlock) void k_phi_c(int n, const double *partIn, int np, double *__restrict__ p) {
+    __shared__ double lds[kBlock / kWave];
+    double v[1];
+    read_partials<1>(partIn, np, v, lds);
+    const double mean = v[0] / n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] -= mean;
+}
+
+// U^{k,n} = U^{k,I} - dt (dP^k phi) / M_L; Dirichlet values
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__restrict__ rp,
+                                                        const int *__restrict__ ci, P3 dP, P3 UI,
+                                                        const double *__restrict__ phi,
+                                                        const double *__restrict__ ML,
+                                                        const int *__restrict__ bc_index,
+                                                        const double *__restrict__ g, int nbc,
+                                                        double dt, double *__restrict__ u0,
+                                                        double *__restrict__ u1, double *__restrict__ u2) {
+    double *uo[3] = {u0, u1, u2};
+    const int lane = threadIdx.x & (L - 1);
+    const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
+    const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
+    for (long long row = gid; row < n; row += ngroups) {
+        const int s = rp[row], e = rp[row + 1];
+        double acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = 0.0;
+        for (int j = s + lane; j < e; j += L) {
+            const double f = phi[ci[j]];
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] += dP.p[k][j] * f;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = group_sum<L>(acc[k]);
+        if (lane == 0) {
+            const int q = bc_index[row];
+            const double inv = dt / ML[row];
+#pragma unroll
+            for (int k = 0; k < D; ++k) uo[k][row] = q >= 0 ? g[k * nbc + q] : UI.p[k][row] - inv * acc[k];
+        }
+    }
+}
+
+// outer residual of the refinement loop: r = b - A x (FP64), r32 = (float) r,
+// partials (sum w r^2, sum w b^2) per component
+template <int NR, int L>
+__global__ __launch_bounds__(kBlock) void k_ir_resid(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci,
+                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ w, P3 b, P3 x,
+                                                     float *r0, float *r1, float *r2, double *part) {
+    __shared__ double lds[6 * kBlock / kWave];
+    float *ro[3] = {r0, r1, r2};
+    double acc2[2 * NR];
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) acc2[k] = 0.0;
+    csr_rows<double, NR, L>(
+        n, rp, ci, val,
+        [&](int, int c, double v, double(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) a[k] += v * x.p[k][c];
+        },
+        [&](int row, int lane, double(&a)[NR]) {
+            if (lane != 0) return;
+            const double wd = w[row];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const double bk = b.p[k][row];
+                const double r = bk - a[k];
+                ro[k][row] = static_cast<float>(r);
+                acc2[2 * k] += wd * r * r;
+                acc2[2 * k + 1] += wd * bk * bk;
+            }
+        });
+    write_partials<2 * NR>(acc2, part, lds);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_sum_to(const double *part, int np, double *out) {
+    __shared__ double lds[NV * kBlock / kWave];
+    double v[NV];
+    read_partials<NV>(part, np, v, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) out[k] = v[k];
+}
+
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int n, int *x, int v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_d(long long n, double *__restrict__ y, const double *__restrict__ x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_f(long long n, float *x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// refinement drivers (FP32 inner Krylov, FP64 outer residual)
+
+struct IRBufs {
+    float *r32[3] = {nullptr, nullptr, nullptr};
+    float *e32[3] = {nullptr, nullptr, nullptr};
+    double *part = nullptr;
+    double *sums = nullptr;   // device [8]
+};
+
+static void carve_ir(Carver &c, int n, int nr, IRBufs &ir) {
+    for (int k = 0; k < nr; ++k) {
+        ir.r32[k] = c.take<float>(n);
+        ir.e32[k] = c.take<float>(n);
+    }
+    ir.part = c.take<double>(6 * kMaxPartials);
+    ir.sums = c.take<double>(8);
+}
+
+static int ir_outer_resid(hipStream_t s, int n, int nr, const int *rp, const int *ci,
+                          const double *val, const double *w, P3 b, P3 x, IRBufs &ir,
+                          double *host_sums) {
+    constexpr int L = 8;
+    const int g = grid_for(n, kBlock / L);
+    if (nr == 1) {
+        hipLaunchKernelGGL((k_ir_resid<1, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
+                           ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL((k_sum_to<2>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
+    } else if (nr == 2) {
+        hipLaunchKernelGGL((k_ir_resid<2, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
+                           ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL((k_sum_to<4>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
+    } else {
+        hipLaunchKernelGGL((k_ir_resid<3, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
+                           ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL((k_sum_to<6>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
+    }
+    OASIS_TRY_LAUNCH();
+    OASIS_TRY_HIP(hipMemcpyAsync(host_sums, ir.sums, 2 * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    return OASIS_OK;
+}
+
+struct KOpts {
+    double rtol;
+    int maxit;
+    double inner_rtol;
+    int max_outer;
+    int check_every;
+    bool time;
+};
+
+// CG with FP32 inner solves on the scaled system; x (FP64) refined until the
+// FP64 weighted residual meets rtol.
+static int ir_cg(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
+                 const float *val32, const double *w, const float *w32, const double *b, double *x,
+                 const KOpts &o, CGWork<float> &cw, IRBufs &ir, SolveOut &out) {
+    out = SolveOut();
+    const int gv = grid_for(n, kBlock, 8192);
+    P3 pb{}, px{};
+    pb.p[0] = b;
+    px.p[0] = x;
+    double hs[2];
+    int total = 0;
+    for (int outer = 0;; ++outer) {
+        OASIS_TRY(ir_outer_resid(s, n, 1, rp, ci, val, w, pb, px, ir, hs));
+        out.rel_res = hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : std::sqrt(hs[0]);
+        if (!std::isfinite(hs[0])) {
+            out.status = OASIS_ENAN;
+            break;
+        }
+        if (hs[0] <= o.rtol * o.rtol * hs[1]) {
+            out.status = OASIS_OK;
+            break;
+        }
+        if (outer >= o.max_outer || total >= o.maxit) {
+            out.status = OASIS_ENOTCONV;
+            break;
+        }
+        hipLaunchKernelGGL(k_zero_f, dim3(gv), dim3(kBlock), 0, s, (long long)n, ir.e32[0]);
+        OASIS_TRY_LAUNCH();
+        SolveOut in;
+        const int rc = cg_solve<float>(s, n, rp, ci, val32, w32, ir.r32[0], ir.e32[0], o.inner_rtol,
+                                       o.maxit - total, o.check_every, o.time, cw, in);
+        if (rc == OASIS_EHIP) return rc;
+        total += in.iters;
+        out.kernel_ms += in.kernel_ms;
+        out.kernel_count += in.kernel_count;
+        out.outer += 1;
+        hipLaunchKernelGGL(k_add_f32, dim3(gv), dim3(kBlock), 0, s, (long long)n, x, ir.e32[0]);
+        OASIS_TRY_LAUNCH();
+        if (rc == OASIS_ENAN) {
+            out.status = OASIS_ENAN;
+            break;
+        }
+    }
+    out.iters = total;
+    return out.status;
+}
+
+// BiCGStab for nr right-hand sides with FP32 inner solves (row-scaled system).
+static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *ci,
+                       const double *val, const float *val32, const double *w, const float *w32,
+                       double *const *b, double *const *x, const KOpts &o, BiWork<float> &bw,
+                       IRBufs &ir, SolveOut *out) {
+    const int gv = grid_for(n, kBlock, 8192);
+    P3 pb{}, px{};
+    for (int k = 0; k < nr; ++k) {
+        pb.p[k] = b[k];
+        px.p[k] = x[k];
+        out[k] = SolveOut();
+        out[k].status = OASIS_ENOTCONV;
+    }
+    bool done[3] = {false, false, false};
+    double hs[6];
+    for (int outer = 0;; ++outer) {
+        OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, w, pb, px, ir, hs));
+        int active[3], na = 0;
+        for (int k = 0; k < nr; ++k) {
+            if (done[k]) continue;
+            out[k].rel_res = hs[2 * k + 1] > 0 ? std::sqrt(hs[2 * k] / hs[2 * k + 1]) : std::sqrt(hs[2 * k]);
+            if (!std::isfinite(hs[2 * k])) {
+                out[k].status = OASIS_ENAN;
+                done[k] = true;
+            } else if (hs[2 * k] <= o.rtol * o.rtol * hs[2 * k + 1]) {
+                out[k].status = OASIS_OK;
+                done[k] = true;
+            } else if (outer >= o.max_outer || out[k].iters >= o.maxit) {
+                out[k].status = OASIS_ENOTCONV;
+                done[k] = true;
+            } else {
+                active[na++] = k;
+            }
+        }
+        if (na == 0) break;
+        const float *bb[3];
+        float *xx[3];
+        for (int q = 0; q < na; ++q) {
+            const int k = active[q];
+            bb[q] = ir.r32[k];
+            xx[q] = ir.e32[k];
+            hipLaunchKernelGGL(k_zero_f, dim3(gv), dim3(kBlock), 0, s, (long long)n, ir.e32[k]);
+            OASIS_TRY_LAUNCH();
+        }
+        SolveOut in[3];
+        const int rc = bicgstab_solve<float>(s, n, na, rp, ci, val32, w32, bb, xx, o.inner_rtol,
+                                             o.maxit, o.check_every, o.time, bw, in);
+        if (rc == OASIS_EHIP) return rc;
+        for (int q = 0; q < na; ++q) {
+            const int k = active[q];
+            out[k].iters += in[q].iters;
+            out[k].outer += 1;
+            out[k].kernel_ms += in[q].kernel_ms;
+            out[k].kernel_count += in[q].kernel_count;
+            hipLaunchKernelGGL(k_add_f32, dim3(gv), dim3(kBlock), 0, s, (long long)n, x[k], ir.e32[k]);
+            OASIS_TRY_LAUNCH();
+        }
+    }
+    int worst = OASIS_OK;
+    for (int k = 0; k < nr; ++k)
+        if (out[k].status != OASIS_OK && (worst == OASIS_OK || out[k].status < worst)) worst = out[k].status;
+    return worst;
+}
+
+static KOpts kopts(const oasis_krylov_opts *o) {
+    KOpts k;
+    k.rtol = o->rtol;
+    k.maxit = o->maxit > 0 ? o->maxit : 10000;
+    k.inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-4;
+    k.max_outer = o->max_outer > 0 ? o->max_outer : 50;
+    k.check_every = o->check_every;
+    k.time = (o->flags & OASIS_KRYLOV_TIME) != 0;
+    return k;
+}
+
+}  // namespace oasis
+
+using namespace oasis;
+
+// ---------------------------------------------------------------------------
+// the IPCS handle
+
+struct oasis_ipcs {
+    oasis_mesh mesh;
+    std::vector<int> color_ptr;
+    int dim = 0, n = 0, nnz = 0;
+    const int *rp = nullptr, *ci = nullptr;
+    oasis_ipcs_params par;
+    bool mixed = false;
+    double *M = nullptr, *Ks = nullptr, *dP[3] = {nullptr, nullptr, nullptr}, *B = nullptr, *A = nullptr;
+    float *A32 = nullptr, *Ks32 = nullptr;
+    double *ML = nullptr, *sK = nullptr, *wK = nullptr, *dA = nullptr, *wA = nullptr, *dtmp = nullptr;
+    float *wK32 = nullptr, *wA32 = nullptr;
+    int *bc_index = nullptr, *flag = nullptr;
+    double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
+    double *bphi = nullptr, *bs = nullptr, *xs = nullptr, *xg = nullptr, *red = nullptr;
+    CGWork<double> cg;
+    CGWork<float> cg32;
+    BiWork<double> bi;
+    BiWork<float> bi32;
+    IRBufs ir;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+static void carve_ipcs(Carver &c, int dim, int n, int nnz, bool mixed, oasis_ipcs &h) {
+    h.M = c.take<double>(nnz);
+    h.Ks = c.take<double>(nnz);
+    for (int k = 0; k < dim; ++k) h.dP[k] = c.take<double>(nnz);
+    h.B = c.take<double>(nnz);
+    h.A = c.take<double>(nnz);
+    if (mixed) {
+        h.A32 = c.take<float>(nnz);
+        h.Ks32 = c.take<float>(nnz);
+        h.wK32 = c.take<float>(n);
+        h.wA32 = c.take<float>(n);
+    }
+    h.ML = c.take<double>(n);
+    h.sK = c.take<double>(n);
+    h.wK = c.take<double>(n);
+    h.dA = c.take<double>(n);
+    h.wA = c.take<double>(n);
+    h.dtmp = c.take<double>(n);
+    h.bc_index = c.take<int>(n);
+    h.flag = c.take<int>(16);
+    for (int k = 0; k < dim; ++k) {
+        h.bt[k] = c.take<double>(n);
+        h.ui[k] = c.take<double>(n);
+    }
+    h.bphi = c.take<double>(n);
+    h.bs = c.take<double>(n);
+    h.xs = c.take<double>(n);
+    h.xg = c.take<double>(n);
+    h.red = c.take<double>(2 * kMaxPartials);
+    carve_cg<double>(c, n, h.cg);
+    carve_bi<double>(c, n, dim, h.bi);
+    if (mixed) {
+        carve_cg<float>(c, n, h.cg32);
+        carve_bi<float>(c, n, dim, h.bi32);
+        carve_ir(c, n, dim, h.ir);
+    }
+}
+
+static int check_params(const oasis_ipcs_params *p) {
+    if (!p || !(p->dt > 0) || !(p->nu >= 0) || p->n_bc < 0 || (p->n_bc > 0 && !p->bc_dofs)) return OASIS_EINVAL;
+    if (!(p->rtol_u > 0) || !(p->rtol_p > 0)) return OASIS_EINVAL;
+    if (p->precision != OASIS_F64 && p->precision != OASIS_F32) return OASIS_EINVAL;
+    return OASIS_OK;
+}
+
+extern "C" int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz, const oasis_ipcs_params *par,
+                                         size_t *bytes) {
+    if (!mesh || !bytes || nnz <= 0 || (mesh->dim != 2 && mesh->dim != 3) || mesh->n_dof <= 0) return OASIS_EINVAL;
+    OASIS_TRY(check_params(par));
+    Carver c(nullptr, 0);
+    oasis_ipcs h;
+    carve_ipcs(c, mesh->dim, mesh->n_dof, nnz, par->precision == OASIS_F32, h);
+    *bytes = c.bytes();
+    return OASIS_OK;
+}
+
+static inline int gvec(int n) { return grid_for(n, kBlock, 8192); }
+
+extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_ptr,
+                                 const int32_t *col_idx, int32_t nnz, const oasis_ipcs_params *par,
+                                 void *ws, size_t ws_bytes, oasis_ipcs **out) {
+    if (!out) return OASIS_EINVAL;
+    *out = nullptr;
+    OASIS_TRY(check_mesh_colored(mesh));
+    OASIS_TRY(check_params(par));
+    if (!row_ptr || !col_idx || nnz <= 0 || !ws || !aligned(ws, 256)) return OASIS_EINVAL;
+    hipStream_t s = as_stream(stream);
+    oasis_ipcs *h = new (std::nothrow) oasis_ipcs();
+    if (!h) return OASIS_EINVAL;
+    h->mesh = *mesh;
+    h->color_ptr.assign(mesh->color_ptr, mesh->color_ptr + mesh->n_colors + 1);
+    h->mesh.color_ptr = h->color_ptr.data();
+    h->dim = mesh->dim;
+    h->n = mesh->n_dof;
+    h->nnz = nnz;
+    h->rp = row_ptr;
+    h->ci = col_idx;
+    h->par = *par;
+    h->mixed = par->precision == OASIS_F32;
+    Carver c(ws, ws_bytes);
+    carve_ipcs(c, h->dim, h->n, nnz, h->mixed, *h);
+    auto fail = [&](int rc) {
+        delete h;
+        return rc;
+    };
+    if (!c.ok) return fail(OASIS_EWORKSPACE);
+    for (int k = 0; k < 5; ++k)
+        if (hipEventCreate(&h->ev[k]) != hipSuccess) return fail(OASIS_EHIP);
+    const int n = h->n, D = h->dim;
+    int rc = OASIS_OK;
+    auto step = [&](int r) {
+        if (rc == OASIS_OK && r != OASIS_OK) rc = r;
+    };
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, h->flag, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->bc_index, -1);
+    if (par->n_bc > 0)
+        hipLaunchKernelGGL(k_bc_index, dim3(gvec(par->n_bc)), dim3(kBlock), 0, s, par->n_bc, n, par->bc_dofs,
+                           h->bc_index, h->flag + 2);
+    P3 none{};
+    // preassembled matrices (Sec. 5: assembled once)
+    step(scale_copy(s, nnz, h->M, nullptr, 0.0));
+    step(assemble_colored(s, &h->mesh, row_ptr, col_idx, h->M, OASIS_FORM_MASS, 1.0, none, none, 0, 0, h->flag));
+    step(scale_copy(s, nnz, h->B, nullptr, 0.0));
+    step(assemble_colored(s, &h->mesh, row_ptr, col_idx, h->B, OASIS_FORM_STIFF, 1.0, none, none, 0, 0, h->flag));
+    for (int k = 0; k < D; ++k) {
+        step(scale_copy(s, nnz, h->dP[k], nullptr, 0.0));
+        step(assemble_colored(s, &h->mesh, row_ptr, col_idx, h->dP[k], OASIS_FORM_GRAD_X + k, 1.0, none, none,
+                              0, 0, h->flag));
+    }
+    if (rc != OASIS_OK) return fail(rc);
+    // K currently in B: diagonal, scaled copy, then B = M/dt + nu K / 2
+    hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->B, h->dtmp);
+    hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dtmp, 0, h->sK, h->wK, h->wK32,
+                       h->flag + 1);
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->B, h->sK, 1,
+                       h->Ks, h->Ks32);
+    hipLaunchKernelGGL(k_lincomb, dim3(gvec(nnz)), dim3(kBlock), 0, s, (long long)nnz, h->B, h->M,
+                       1.0 / par->dt, h->B, 0.5 * par->nu);
+    hipLaunchKernelGGL(k_row_sums, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->M, h->ML);
+    if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
+    int fl[3] = {0, 0, 0};
+    if (hipMemcpyAsync(fl, h->flag, sizeof(fl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(OASIS_EHIP);
+    if (fl[0] || fl[1] || fl[2]) return fail(OASIS_EINVAL);
+    *out = h;
+    return OASIS_OK;
+}
+
+extern "C" int oasis_ipcs_destroy(oasis_ipcs *h) {
+    if (!h) return OASIS_EINVAL;
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete h;
+    return OASIS_OK;
+}
+
+extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const double **val,
+                                 const double **scaled_diag_sqrt) {
+    if (!h || !val) return OASIS_EINVAL;
+    if (scaled_diag_sqrt) *scaled_diag_sqrt = nullptr;
+    switch (which) {
+        case -1: *val = h->ML; return OASIS_OK;
+        case OASIS_FORM_MASS: *val = h->M; return OASIS_OK;
+        case OASIS_FORM_STIFF:
+            *val = h->Ks;
+            if (scaled_diag_sqrt) *scaled_diag_sqrt = h->sK;
+            return OASIS_OK;
+        case OASIS_FORM_GRAD_X: case OASIS_FORM_GRAD_Y: case OASIS_FORM_GRAD_Z:
+            if (which - OASIS_FORM_GRAD_X >= h->dim) return OASIS_EINVAL;
+            *val = h->dP[which - OASIS_FORM_GRAD_X];
+            return OASIS_OK;
+        case 100: *val = h->A; return OASIS_OK;      // last tentative matrix, row-scaled
+        case 101: *val = h->dA; return OASIS_OK;     // its diagonal before scaling
+        default: return OASIS_EINVAL;
+    }
+}
+
+template <int D, int L>
+static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g,
+                                     double *const *x) {
+    const int n = h->n;
+    P3 dP{}, U1{};
+    for (int k = 0; k < D; ++k) {
+        dP.p[k] = h->dP[k];
+        U1.p[k] = st->U1[k];
+    }
+    const int grid = grid_for(n, kBlock / L, 1 << 20);
+    hipLaunchKernelGGL((k_tent_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A, h->A32,
+                       dP, U1, st->p, h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1],
+                       h->par.f[2], 2.0 / h->par.dt, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0],
+                       x[1], D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
+}
+
+template <int D, int L>
+static void launch_div(hipStream_t s, oasis_ipcs *h, double *const *x, int *gout) {
+    P3 dP{}, UI{};
+    for (int k = 0; k < D; ++k) {
+        dP.p[k] = h->dP[k];
+        UI.p[k] = x[k];
+    }
+    const int grid = grid_for(h->n, kBlock / L);
+    *gout = grid;
+    hipLaunchKernelGGL((k_div_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, h->n, h->rp, h->ci, dP, UI,
+                       -1.0 / h->par.dt, h->bphi, h->red);
+}
+
+template <int D, int L>
+static void launch_update(hipStream_t s, oasis_ipcs *h, double *const *x, const double *phi, const double *g,
+                          double *const *un) {
+    P3 dP{}, UI{};
+    for (int k = 0; k < D; ++k) {
+        dP.p[k] = h->dP[k];
+        UI.p[k] = x[k];
+    }
+    const int grid = grid_for(h->n, kBlock / L, 1 << 20);
+    hipLaunchKernelGGL((k_update_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, h->n, h->rp, h->ci, dP, UI, phi,
+                       h->ML, h->bc_index, g, h->par.n_bc, h->par.dt, un[0], un[1], D > 2 ? un[2] : nullptr);
+}
+
+extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, const double *bc_values,
+                               const double *phi_guess, oasis_step_stats *stats) {
+    if (!h || !st || !st->p || !st->phi) return OASIS_EINVAL;
+    const int D = h->dim, n = h->n;
+    for (int k = 0; k < D; ++k)
+        if (!st->U1[k] || !st->U2[k] || !st->Un[k] || st->Un[k] == st->U1[k] || st->Un[k] == st->U2[k])
+            return OASIS_EINVAL;
+    if (h->par.n_bc > 0 && !bc_values) return OASIS_EINVAL;
+    hipStream_t s = as_stream(stream);
+    oasis_step_stats loc{};
+    oasis_step_stats &S = stats ? *stats : loc;
+    S = oasis_step_stats{};
+    OASIS_TRY_HIP(hipEventRecord(h->ev[0], s));
+    // 1. A = B + C(u_bar)/2
+    OASIS_TRY(scale_copy(s, h->nnz, h->A, h->B, 1.0));
+    P3 U1{}, U2{};
+    for (int k = 0; k < D; ++k) {
+        U1.p[k] = st->U1[k];
+        U2.p[k] = st->U2[k];
+    }
+    OASIS_TRY(assemble_colored(s, &h->mesh, h->rp, h->ci, h->A, OASIS_FORM_CONV, 0.5, U1, U2, 1.5, -0.5, nullptr));
+    // 2. right-hand sides, Dirichlet rows, scaling; x0 = U^{n-1}
+    double *x[3];
+    for (int k = 0; k < D; ++k) x[k] = st->UI[k] ? st->UI[k] : h->ui[k];
+    if (D == 3)
+        launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
+    else
+        launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
+    OASIS_TRY_LAUNCH();
+    OASIS_TRY_HIP(hipEventRecord(h->ev[1], s));
+    // 3. tentative velocity
+    oasis_krylov_opts o{};
+    o.rtol = h->par.rtol_u;
+    o.maxit = h->par.maxit > 0 ? h->par.maxit : 10000;
+    o.inner_rtol = h->par.inner_rtol;
+    KOpts ko = kopts(&o);
+    SolveOut su[3];
+    int rc_u;
+    if (h->mixed)
+        rc_u = ir_bicgstab(s, n, D, h->rp, h->ci, h->A, h->A32, h->wA, h->wA32, h->bt, x, ko, h->bi32, h->ir, su);
+    else
+        rc_u = bicgstab_solve<double>(s, n, D, h->rp, h->ci, h->A, h->wA, h->bt, x, ko.rtol, ko.maxit, 0, false,
+                                      h->bi, su);
+    if (rc_u == OASIS_EHIP) return rc_u;
+    OASIS_TRY_HIP(hipEventRecord(h->ev[2], s));
+    // 4. pressure correction
+    int gd = 0;
+    if (D == 3)
+        launch_div<3, 8>(s, h, x, &gd);
+    else
+        launch_div<2, 8>(s, h, x, &gd);
+    OASIS_TRY_LAUNCH();
+    hipLaunchKernelGGL(k_bphi_finish, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->red, gd, h->bphi, h->sK,
+                       st->phi, h->bs, h->xs);
+    OASIS_TRY_LAUNCH();
+    if (st->b_phi) {
+        hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, st->b_phi, h->bphi);
+        OASIS_TRY_LAUNCH();
+    }
+    S.guess_used = 0;
+    if (phi_guess) {
+        double wr_prev = 0, wr_guess = 0, wbb = 0;
+        hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, phi_guess, h->sK, 1, h->xg);
+        OASIS_TRY_LAUNCH();
+        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->dtmp, h->cg, &wr_prev, &wbb));
+        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->dtmp, h->cg, &wr_guess, &wbb));
+        if (std::isfinite(wr_guess) && wr_guess < wr_prev) {
+            hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, h->xs, h->xg);
+            OASIS_TRY_LAUNCH();
+            S.guess_used = 1;
+        }
+    }
+    o.rtol = h->par.rtol_p;
+    ko = kopts(&o);
+    SolveOut sp;
+    int rc_p;
+    if (h->mixed)
+        rc_p = ir_cg(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->bs, h->xs, ko, h->cg32, h->ir, sp);
+    else
+        rc_p = cg_solve<double>(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, 0, false,
+                                h->cg, sp);
+    if (rc_p == OASIS_EHIP) return rc_p;
+    OASIS_TRY_HIP(hipEventRecord(h->ev[3], s));
+    // 5. phi, p normalisation
+    const int gp = grid_for(n, kBlock);
+    hipLaunchKernelGGL(k_phi_a, dim3(gp), dim3(kBlock), 0, s, n, h->xs, h->sK, st->phi, h->red);
+    hipLaunchKernelGGL(k_phi_b, dim3(gp), dim3(kBlock), 0, s, n, h->red, gp, st->phi, st->p, h->red + kMaxPartials);
+    hipLaunchKernelGGL(k_phi_c, dim3(gp), dim3(kBlock), 0, s, n, h->red + kMaxPartials, gp, st->p);
+    OASIS_TRY_LAUNCH();
+    // 6. velocity correction
+    if (D == 3)
+        launch_update<3, 8>(s, h, x, st->phi, bc_values, st->Un);
+    else
+        launch_update<2, 8>(s, h, x, st->phi, bc_values, st->Un);
+    OASIS_TRY_LAUNCH();
+    OASIS_TRY_HIP(hipEventRecord(h->ev[4], s));
+    OASIS_TRY_HIP(hipEventSynchronize(h->ev[4]));
+    float t[4];
+    for (int k = 0; k < 4; ++k) OASIS_TRY_HIP(hipEventElapsedTime(&t[k], h->ev[k], h->ev[k + 1]));
+    S.ms_assemble = t[0];
+    S.ms_velocity = t[1];
+    S.ms_pressure = t[2];
+    S.ms_update = t[3];
+    S.ms_total = t[0] + t[1] + t[2] + t[3];
+    int worst = OASIS_OK;
+    for (int k = 0; k < D; ++k) {
+        S.iters_u[k] = su[k].iters;
+        S.res_u[k] = su[k].rel_res;
+        S.outer_u = std::max(S.outer_u, su[k].outer);
+        if (su[k].status != OASIS_OK && (worst == OASIS_OK || su[k].status < worst)) worst = su[k].status;
+    }
+    S.iters_p = sp.iters;
+    S.res_p = sp.rel_res;
+    S.outer_p = sp.outer;
+    if (sp.status != OASIS_OK && (worst == OASIS_OK || sp.status < worst)) worst = sp.status;
+    S.status = worst;
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone Krylov entry points
+
+struct KrylovWs {
+    double *val, *s, *w, *b, *x;
+    float *val32, *w32;
+    int *flag;
+    CGWork<double> cg;
+    CGWork<float> cg32;
+    BiWork<double> bi;
+    BiWork<float> bi32;
+    IRBufs ir;
+    double *bt[3];
+};
+
+static void carve_krylov(Carver &c, int n, int nnz, int nrhs, bool mixed, KrylovWs &k) {
+    std::memset(&k, 0, sizeof(k));
+    k.val = c.take<double>(nnz);
+    k.s = c.take<double>(n);
+    k.w = c.take<double>(n);
+    k.b = c.take<double>(n);
+    k.x = c.take<double>(n);
+    k.flag = c.take<int>(16);
+    for (int q = 0; q < nrhs; ++q) k.bt[q] = c.take<double>(n);
+    carve_cg<double>(c, n, k.cg);
+    carve_bi<double>(c, n, nrhs, k.bi);
+    if (mixed) {
+        k.val32 = c.take<float>(nnz);
+        k.w32 = c.take<float>(n);
+        carve_cg<float>(c, n, k.cg32);
+        carve_bi<float>(c, n, nrhs, k.bi32);
+        carve_ir(c, n, nrhs, k.ir);
+    }
+}
+
+extern "C" int oasis_krylov_workspace_size(int32_t n, int32_t nnz, int32_t nrhs, const oasis_krylov_opts *opt,
+                                           size_t *bytes) {
+    if (n <= 0 || nnz <= 0 || nrhs < 1 || nrhs > 3 || !opt || !bytes) return OASIS_EINVAL;
+    Carver c(nullptr, 0);
+    KrylovWs k;
+    carve_krylov(c, n, nnz, nrhs, opt->precision == OASIS_F32, k);
+    *bytes = c.bytes();
+    return OASIS_OK;
+}
+
+static void fill_stats(const SolveOut &o, oasis_krylov_stats *st) {
+    st->iters = o.iters;
+    st->outer_iters = o.outer;
+    st->status = o.status;
+    st->restarts = o.replacements;
+    st->rel_res = o.rel_res;
+    st->kernel_ms = o.kernel_ms;
+    st->kernel_count = o.kernel_count;
+    st->pad = 0;
+}
+
+static int check_opts(const oasis_krylov_opts *o) {
+    if (!o || !(o->rtol > 0) || o->maxit < 0) return OASIS_EINVAL;
+    if (o->precision != OASIS_F64 && o->precision != OASIS_F32) return OASIS_EINVAL;
+    return OASIS_OK;
+}
+
+extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x, const oasis_krylov_opts *opt,
+                         void *ws, size_t ws_bytes, oasis_krylov_stats *stats) {
+    OASIS_TRY(check_csr(A));
+    OASIS_TRY(check_opts(opt));
+    if (A->dtype != OASIS_F64 || !b || !x || !ws || !stats || !aligned(ws, 256)) return OASIS_EINVAL;
+    const bool mixed = opt->precision == OASIS_F32;
+    const int n = A->n, nnz = A->nnz;
+    Carver c(ws, ws_bytes);
+    KrylovWs k;
+    carve_krylov(c, n, nnz, 1, mixed, k);
+    if (!c.ok) return OASIS_EWORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const double *val = static_cast<const double *>(A->val);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
+    hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.b);
+    hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.b, 0, k.s, k.w, k.w32, k.flag);
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s, 1,
+                       k.val, k.val32);
+    hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, b, k.s, 2, k.b);
+    hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, x, k.s, 1, k.x);
+    OASIS_TRY_LAUNCH();
+    int fl = 0;
+    OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    if (fl) return OASIS_EINVAL;
+    const KOpts ko = kopts(opt);
+    SolveOut so;
+    int rc;
+    if (mixed)
+        rc = ir_cg(s, n, A->row_ptr, A->col_idx, k.val, k.val32, k.w, k.w32, k.b, k.x, ko, k.cg32, k.ir, so);
+    else
+        rc = cg_solve<double>(s, n, A->row_ptr, A->col_idx, k.val, k.w, k.b, k.x, ko.rtol, ko.maxit, ko.check_every,
+                              ko.time, k.cg, so);
+    if (rc == OASIS_EHIP) return rc;
+    hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.x, k.s, 2, x);
+    OASIS_TRY_LAUNCH();
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    fill_stats(so, stats);
+    return rc;
+}
+
+extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, const double *b, double *x,
+                              const oasis_krylov_opts *opt, void *ws, size_t ws_bytes, oasis_krylov_stats *stats) {
+    OASIS_TRY(check_csr(A));
+    OASIS_TRY(check_opts(opt));
+    if (A->dtype != OASIS_F64 || nrhs < 1 || nrhs > 3 || !b || !x || !ws || !stats || !aligned(ws, 256))
+        return OASIS_EINVAL;
+    const bool mixed = opt->precision == OASIS_F32;
+    const int n = A->n, nnz = A->nnz;
+    Carver c(ws, ws_bytes);
+    KrylovWs k;
+    carve_krylov(c, n, nnz, nrhs, mixed, k);
+    if (!c.ok) return OASIS_EWORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const double *val = static_cast<const double *>(A->val);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
+    hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.b);
+    hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.b, 1, k.s, k.w, k.w32, k.flag);
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s, 0,
+                       k.val, k.val32);
+    double *xs[3];
+    for (int q = 0; q < nrhs; ++q) {
+        hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, b + (size_t)q * n, k.s, 2, k.bt[q]);
+        xs[q] = x + (size_t)q * n;
+    }
+    OASIS_TRY_LAUNCH();
+    int fl = 0;
+    OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    if (fl) return OASIS_EINVAL;
+    const KOpts ko = kopts(opt);
+    SolveOut so[3];
+    int rc;
+    if (mixed)
+        rc = ir_bicgstab(s, n, nrhs, A->row_ptr, A->col_idx, k.val, k.val32, k.w, k.w32, k.bt, xs, ko, k.bi32, k.ir,
+                         so);
+    else
+        rc = bicgstab_solve<double>(s, n, nrhs, A->row_ptr, A->col_idx, k.val, k.w, k.bt, xs, ko.rtol, ko.maxit,
+                                    ko.check_every, ko.time, k.bi, so);
+    if (rc == OASIS_EHIP) return rc;
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < nrhs; ++q) fill_stats(so[q], stats + q);
+    return rc;
+}

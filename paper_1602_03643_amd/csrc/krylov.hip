@@ -1,0 +1,949 @@
+// Krylov solvers for the tentative velocity (BiCGStab + Jacobi) and the
+// pressure correction (Jacobi-preconditioned CG), Sec. 6.2 of the paper.
+//
+// Both run on pre-scaled matrices so that the Jacobi preconditioner costs
+// nothing inside the loop:
+//   CG       : Ms = D^{-1/2} K D^{-1/2} (unit diagonal); same iterates as
+//              CG with z = D^{-1} r in exact arithmetic.
+//   BiCGStab : As = D^{-1} A (left Jacobi); residual norms are weighted so
+//              that the stopping test is on the unscaled ||b - A x||.
+//
+// Convergence is decided on the device.  Every kernel of an iteration
+// first sums the partials of the previous kernel (fixed order, identical in
+// all blocks), so scalars such as alpha and beta never leave the GPU; a
+// kernel that detects convergence, breakdown or a non-finite value raises a
+// flag that makes the remaining launched kernels return at once.  The host
+// enqueues iterations in chunks and polls the small state block between
+// chunks; on a convergence candidate it confirms with an explicit residual.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "krylov.hpp"
+#include "spmv.hpp"
+
+namespace oasis {
+
+int spmv_lanes() {
+    static int lanes = [] {
+        const char *e = std::getenv("OASIS_SPMV_LANES");
+        int v = e ? std::atoi(e) : 8;
+        return (v == 4 || v == 8 || v == 16) ? v : 8;
+    }();
+    return lanes;
+}
+
+// A flag written by an earlier kernel (or by block 0 of this one when it
+// decides to stop, a decision every block reaches identically), read once
+// per block so that the early return is uniform.
+__device__ __forceinline__ int block_read_flag(const int *p) {
+    __shared__ int v;
+    if (threadIdx.x == 0) v = __atomic_load_n(p, __ATOMIC_RELAXED);
+    __syncthreads();
+    int r = v;
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// vector helpers
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int n, T *x, T v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(int n, T *__restrict__ y, const T *__restrict__ x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels
+
+// r = b - Ms x; partials (r.r, sum wgt r^2, sum wgt b^2)
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ ci,
+                                                    const T *__restrict__ val,
+                                                    const T *__restrict__ wgt,
+                                                    const T *__restrict__ b,
+                                                    const T *__restrict__ x, T *__restrict__ r,
+                                                    double *part) {
+    __shared__ double lds[3 * kBlock / kWave];
+    double acc[3] = {0.0, 0.0, 0.0};
+    csr_rows<T, 1, L>(
+        n, rp, ci, val, [&](int, int c, T v, T(&a)[1]) { a[0] += v * x[c]; },
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) {
+                const T ri = b[row] - a[0];
+                r[row] = ri;
+                const double rd = ri, bd = b[row], wd = wgt[row];
+                acc[0] += rd * rd;
+                acc[1] += wd * rd * rd;
+                acc[2] += wd * bd * bd;
+            }
+        });
+    write_partials<3>(acc, part, lds);
+}
+
+// mode 0: start of a solve (sets tol2); mode 1: explicit-residual check
+__global__ __launch_bounds__(kBlock) void k_cg_finalize(const double *part, int nparts, CGState *st,
+                                                        double rtol2, int mode) {
+    __shared__ double lds[3 * kBlock / kWave];
+    double v[3];
+    read_partials<3>(part, nparts, v, lds);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            st->tol2 = rtol2 * v[2];
+            st->wbb = v[2];
+        }
+        st->wrr = v[1];
+        st->flag = 0;
+        st->it_done = -1;
+    }
+}
+
+// Iteration part 1: convergence test on the incoming residual, direction
+// p_new = r + beta p_old (formed on the fly for the gathered operand),
+// q = Ms p_new, partial p_new.q.
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__ rp,
+                                                  const int *__restrict__ ci,
+                                                  const T *__restrict__ val,
+                                                  const T *__restrict__ r,
+                                                  const T *__restrict__ pold,
+                                                  T *__restrict__ pnew, T *__restrict__ q,
+                                                  const double *partIn, int nIn, CGState *st,
+                                                  int it, int beta_zero, double *partOut) {
+    __shared__ double lds[3 * kBlock / kWave];
+    if (block_read_flag(&st->flag)) return;
+    double v[3];
+    read_partials<3>(partIn, nIn, v, lds);
+    const double rr = v[0], wrr = v[1];
+    int flag = 0;
+    if (!finite(wrr) || !finite(rr))
+        flag = 3;
+    else if (wrr <= st->tol2)
+        flag = 1;
+    if (flag) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->flag = flag;
+            st->it_done = it;
+            st->wrr = wrr;
+        }
+        return;
+    }
+    const double beta = beta_zero ? 0.0 : rr / st->rr[(it + 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
+    const T bt = static_cast<T>(beta);
+    double acc[1] = {0.0};
+    csr_rows<T, 1, L>(
+        n, rp, ci, val, [&](int, int c, T vv, T(&a)[1]) { a[0] += vv * (r[c] + bt * pold[c]); },
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) {
+                const T pn = r[row] + bt * pold[row];
+                pnew[row] = pn;
+                q[row] = a[0];
+                acc[0] += static_cast<double>(pn) * static_cast<double>(a[0]);
+            }
+        });
+    write_partials<1>(acc, partOut, lds);
+}
+
+// Iteration part 2: alpha = r.r / p.q, x += alpha p, r -= alpha q,
+// partials (r.r, sum wgt r^2, 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_p2(int n, T *__restrict__ r, const T *__restrict__ p,
+                                                  const T *__restrict__ q, T *__restrict__ x,
+                                                  const T *__restrict__ wgt, const double *partIn,
+                                                  int nIn, CGState *st, int it, double *partOut) {
+    __shared__ double lds[3 * kBlock / kWave];
+    if (block_read_flag(&st->flag)) return;
+    double v[1];
+    read_partials<1>(partIn, nIn, v, lds);
+    const double pq = v[0];
+    if (!(pq > 0.0) || !finite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->flag = finite(pq) ? 2 : 3;
+            st->it_done = it;
+        }
+        return;
+    }
+    const T a = static_cast<T>(st->rr[it & 1] / pq);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const T xi = x[i] + a * p[i];
+        const T ri = r[i] - a * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        const double rd = ri;
+        acc[0] += rd * rd;
+        acc[1] += static_cast<double>(wgt[i]) * rd * rd;
+    }
+    write_partials<3>(acc, partOut, lds);
+}
+
+template <typename T>
+void carve_cg(Carver &c, int n, CGWork<T> &w) {
+    w.r = c.take<T>(n);
+    w.p[0] = c.take<T>(n);
+    w.p[1] = c.take<T>(n);
+    w.q = c.take<T>(n);
+    w.partA = c.take<double>(3 * kMaxPartials);
+    w.partB = c.take<double>(3 * kMaxPartials);
+    w.st = c.take<CGState>(1);
+}
+
+template <typename T, int L>
+static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
+                  const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
+                  CGWork<T> &w, SolveOut &out) {
+    const int g1 = grid_for(n, kBlock / L);
+    const int g2 = grid_for(n, kBlock);
+    out = SolveOut();
+    auto residual = [&](int mode) -> int {
+        hipLaunchKernelGGL((k_cg_init<T, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+                           b, x, w.r, w.partB);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
+                           rtol * rtol, mode);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    OASIS_TRY(residual(0));
+    CGState h;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (time_kernel) {
+        OASIS_TRY_HIP(hipEventCreate(&e0));
+        OASIS_TRY_HIP(hipEventCreate(&e1));
+    }
+    const int chunk = check_every > 0 ? check_every : 32;
+    int it = 0, restart_at = 0;
+    int rc = OASIS_OK;
+    auto finish = [&](double wrr, double wbb) {
+        out.rel_res = wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr);
+    };
+    while (true) {
+        const int m = std::min(chunk, maxit - it);
+        for (int j = 0; j < m; ++j) {
+            const int itj = it + j;
+            if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
+            hipLaunchKernelGGL((k_cg_p1<T, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, w.r,
+                               w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
+                               itj == restart_at ? g1 : g2, w.st, itj, itj == restart_at ? 1 : 0,
+                               w.partA);
+            OASIS_TRY_LAUNCH();
+            if (time_kernel) {
+                OASIS_TRY_HIP(hipEventRecord(e1, s));
+                OASIS_TRY_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                OASIS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+                out.kernel_ms += ms;
+                out.kernel_count += 1;
+            }
+            hipLaunchKernelGGL((k_cg_p2<T>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
+                               w.q, x, wgt, w.partA, g1, w.st, itj, w.partB);
+            OASIS_TRY_LAUNCH();
+        }
+        it += m;
+        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        if (h.flag == 0) {
+            if (it < maxit) continue;
+            const double wbb = h.wbb, tol2 = h.tol2;
+            OASIS_TRY(residual(1));
+            OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+            OASIS_TRY_HIP(hipStreamSynchronize(s));
+            out.iters = it;
+            finish(h.wrr, wbb);
+            out.status = rc = (h.wrr <= tol2) ? OASIS_OK : OASIS_ENOTCONV;
+            break;
+        }
+        if (h.flag == 1) {
+            const int itd = h.it_done;
+            const double wbb = h.wbb, tol2 = h.tol2;
+            OASIS_TRY(residual(1));
+            OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+            OASIS_TRY_HIP(hipStreamSynchronize(s));
+            if (h.wrr <= tol2) {
+                out.iters = itd;
+                finish(h.wrr, wbb);
+                out.status = rc = OASIS_OK;
+                break;
+            }
+            // continue from the explicit residual with a fresh direction
+            out.replacements += 1;
+            it = itd;
+            restart_at = itd;
+            if (it >= maxit) {
+                out.iters = it;
+                finish(h.wrr, wbb);
+                out.status = rc = OASIS_ENOTCONV;
+                break;
+            }
+            continue;
+        }
+        out.iters = h.it_done;
+        out.status = rc = (h.flag == 2) ? OASIS_EBREAKDOWN : OASIS_ENAN;
+        out.rel_res = NAN;
+        break;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+template <typename T>
+int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
+             const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
+             CGWork<T> &w, SolveOut &out) {
+    switch (spmv_lanes()) {
+        case 4:
+            return cg_run<T, 4>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
+                                time_kernel, w, out);
+        case 16:
+            return cg_run<T, 16>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
+                                 time_kernel, w, out);
+        default:
+            return cg_run<T, 8>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
+                                time_kernel, w, out);
+    }
+}
+
+int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
+                const double *wgt, const double *b, const double *x, double *r,
+                CGWork<double> &w, double *wrr, double *wbb) {
+    const int g1 = grid_for(n, kBlock / 8);
+    hipLaunchKernelGGL((k_cg_init<double, 8>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+                       b, x, r, w.partB);
+    OASIS_TRY_LAUNCH();
+    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0);
+    OASIS_TRY_LAUNCH();
+    CGState h;
+    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    *wrr = h.wrr;
+    *wbb = h.wbb;
+    return OASIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab kernels (nr right-hand sides share every pass over the matrix)
+//
+// Events raised per right-hand side (any event pauses all of them):
+//   1 converged candidate (||r|| test)      2 rho = 0 or omega = 0
+//   3 non-finite value                      4 (r_hat, v) = 0
+//   5 converged candidate at the s stage
+
+template <typename T>
+struct V3 {
+    T *p[3];
+};
+template <typename T>
+struct C3 {
+    const T *p[3];
+};
+
+// r_k = b_k - As xsrc_k for k in mask_res; r_hat_k = r_k for k in mask_rhat;
+// partials (r_hat.r, sum wgt r^2, sum wgt b^2) for every k.
+template <typename T, int NR, int L>
+__global__ __launch_bounds__(kBlock) void k_bi_resid(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci,
+                                                     const T *__restrict__ val,
+                                                     const T *__restrict__ wgt, C3<T> b,
+                                                     C3<T> xsrc, V3<T> r, V3<T> rhat, int mask_res,
+                                                     int mask_rhat, double *part) {
+    __shared__ double lds[9 * kBlock / kWave];
+    double acc[3 * NR];
+#pragma unroll
+    for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
+    csr_rows<T, NR, L>(
+        n, rp, ci, val,
+        [&](int, int c, T v, T(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+                if ((mask_res >> k) & 1) a[k] += v * xsrc.p[k][c];
+        },
+        [&](int row, int lane, T(&a)[NR]) {
+            if (lane != 0) return;
+            const double wd = wgt[row];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                T rk;
+                if ((mask_res >> k) & 1) {
+                    rk = b.p[k][row] - a[k];
+                    r.p[k][row] = rk;
+                } else {
+                    rk = r.p[k][row];
+                }
+                T hk;
+                if ((mask_rhat >> k) & 1) {
+                    rhat.p[k][row] = rk;
+                    hk = rk;
+                } else {
+                    hk = rhat.p[k][row];
+                }
+                const double rd = rk, bd = b.p[k][row];
+                acc[3 * k + 0] += static_cast<double>(hk) * rd;
+                acc[3 * k + 1] += wd * rd * rd;
+                acc[3 * k + 2] += wd * bd * bd;
+            }
+        });
+    write_partials<3 * NR>(acc, part, lds);
+}
+
+template <int NR>
+__global__ __launch_bounds__(kBlock) void k_bi_finalize(const double *part, int nparts, BiState *st,
+                                                        double rtol2, int mode) {
+    __shared__ double lds[9 * kBlock / kWave];
+    double v[3 * NR];
+    read_partials<3 * NR>(part, nparts, v, lds);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NR; ++k) {
+            if (mode == 0) {
+                st[k].tol2 = rtol2 * v[3 * k + 2];
+                st[k].wbb = v[3 * k + 2];
+            }
+            st[k].wrr = v[3 * k + 1];
+        }
+    }
+}
+
+__device__ __forceinline__ void bi_pause(BiGlobal *g, int phase, int it) {
+    g->phase = phase;
+    g->pause_it = it;
+    g->pause = 1;
+}
+
+// part 1: tests on the incoming residual, p = r + beta (p - omega v),
+// v = As p, partial r_hat.v
+template <typename T, int NR, int L>
+__global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ rp,
+                                                 const int *__restrict__ ci,
+                                                 const T *__restrict__ val, C3<T> r, C3<T> rhat,
+                                                 C3<T> pold, C3<T> vold, V3<T> pnew, V3<T> vnew,
+                                                 const double *partIn, int nIn, BiState *st,
+                                                 BiGlobal *glob, int it, double *partOut) {
+    __shared__ double lds[9 * kBlock / kWave];
+    if (block_read_flag(&glob->pause)) return;
+    double v[3 * NR];
+    read_partials<3 * NR>(partIn, nIn, v, lds);
+    const int prev = (it + 1) & 1;
+    int ev[NR];
+    int any = 0;
+    int active = 0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        ev[k] = 0;
+        if (!st[k].active) continue;
+        active |= 1 << k;
+        const double rr = v[3 * k], wrr = v[3 * k + 1];
+        if (!finite(rr) || !finite(wrr))
+            ev[k] = 3;
+        else if (wrr <= st[k].tol2)
+            ev[k] = 1;
+        else if (rr == 0.0 || st[k].omega[prev] == 0.0)
+            ev[k] = 2;
+        any |= ev[k];
+    }
+    if (any) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            for (int k = 0; k < NR; ++k)
+                if (ev[k]) st[k].event = ev[k];
+            bi_pause(glob, 1, it);
+        }
+        return;
+    }
+    T beta[NR], om[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const double rr = v[3 * k];
+        beta[k] = static_cast<T>((rr / st[k].rho[prev]) * (st[k].alpha[prev] / st[k].omega[prev]));
+        om[k] = static_cast<T>(st[k].omega[prev]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < NR; ++k)
+            if ((active >> k) & 1) st[k].rho[it & 1] = v[3 * k];
+    }
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    csr_rows<T, NR, L>(
+        n, rp, ci, val,
+        [&](int, int c, T vv, T(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+                if ((active >> k) & 1)
+                    a[k] += vv * (r.p[k][c] + beta[k] * (pold.p[k][c] - om[k] * vold.p[k][c]));
+        },
+        [&](int row, int lane, T(&a)[NR]) {
+            if (lane != 0) return;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (!((active >> k) & 1)) continue;
+                const T pn = r.p[k][row] + beta[k] * (pold.p[k][row] - om[k] * vold.p[k][row]);
+                pnew.p[k][row] = pn;
+                vnew.p[k][row] = a[k];
+                acc[k] += static_cast<double>(rhat.p[k][row]) * static_cast<double>(a[k]);
+            }
+        });
+    write_partials<NR>(acc, partOut, lds);
+}
+
+// part 2: alpha = rho / (r_hat.v), s = r - alpha v, t = As s,
+// partials (t.s, t.t, sum wgt s^2)
+template <typename T, int NR, int L>
+__global__ __launch_bounds__(kBlock) void k_bi_2(int n, const int *__restrict__ rp,
+                                                 const int *__restrict__ ci,
+                                                 const T *__restrict__ val,
+                                                 const T *__restrict__ wgt, C3<T> r, C3<T> vv,
+                                                 V3<T> s, V3<T> t, const double *partIn, int nIn,
+                                                 BiState *st, BiGlobal *glob, int it,
+                                                 double *partOut) {
+    __shared__ double lds[9 * kBlock / kWave];
+    if (block_read_flag(&glob->pause)) return;
+    double v[NR];
+    read_partials<NR>(partIn, nIn, v, lds);
+    const int cur = it & 1;
+    int ev[NR];
+    int any = 0, active = 0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        ev[k] = 0;
+        if (!st[k].active) continue;
+        active |= 1 << k;
+        if (!finite(v[k]))
+            ev[k] = 3;
+        else if (v[k] == 0.0)
+            ev[k] = 4;
+        any |= ev[k];
+    }
+    if (any) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            for (int k = 0; k < NR; ++k)
+                if (ev[k]) st[k].event = ev[k];
+            bi_pause(glob, 2, it);
+        }
+        return;
+    }
+    T al[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) al[k] = static_cast<T>(st[k].rho[cur] / v[k]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < NR; ++k)
+            if ((active >> k) & 1) st[k].alpha[cur] = st[k].rho[cur] / v[k];
+    }
+    double acc[3 * NR];
+#pragma unroll
+    for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
+    csr_rows<T, NR, L>(
+        n, rp, ci, val,
+        [&](int, int c, T w, T(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+                if ((active >> k) & 1) a[k] += w * (r.p[k][c] - al[k] * vv.p[k][c]);
+        },
+        [&](int row, int lane, T(&a)[NR]) {
+            if (lane != 0) return;
+            const double wd = wgt[row];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (!((active >> k) & 1)) continue;
+                const T sn = r.p[k][row] - al[k] * vv.p[k][row];
+                s.p[k][row] = sn;
+                t.p[k][row] = a[k];
+                const double sd = sn, td = a[k];
+                acc[3 * k + 0] += td * sd;
+                acc[3 * k + 1] += td * td;
+                acc[3 * k + 2] += wd * sd * sd;
+            }
+        });
+    write_partials<3 * NR>(acc, partOut, lds);
+}
+
+// part 3: s-stage test, omega = (t.s)/(t.t), x += alpha p + omega s,
+// r = s - omega t, partials (r_hat.r, sum wgt r^2, 0)
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void k_bi_3(int n, const T *__restrict__ wgt, V3<T> x,
+                                                 V3<T> r, C3<T> rhat, C3<T> p, C3<T> s, C3<T> t,
+                                                 const double *partIn, int nIn, BiState *st,
+                                                 BiGlobal *glob, int it, double *partOut) {
+    __shared__ double lds[9 * kBlock / kWave];
+    if (block_read_flag(&glob->pause)) return;
+    double v[3 * NR];
+    read_partials<3 * NR>(partIn, nIn, v, lds);
+    const int cur = it & 1;
+    int ev[NR];
+    int any = 0, active = 0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        ev[k] = 0;
+        if (!st[k].active) continue;
+        active |= 1 << k;
+        if (v[3 * k + 2] <= st[k].tol2 && st[k].no_sexit_it != it) ev[k] = 5;
+        any |= ev[k];
+    }
+    if (any) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            for (int k = 0; k < NR; ++k)
+                if (ev[k]) st[k].event = ev[k];
+            bi_pause(glob, 3, it);
+        }
+        return;
+    }
+    T al[NR], om[NR];
+    double omd[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const double ts = v[3 * k], tt = v[3 * k + 1];
+        omd[k] = tt > 0.0 ? ts / tt : 0.0;
+        om[k] = static_cast<T>(omd[k]);
+        al[k] = static_cast<T>(st[k].alpha[cur]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < NR; ++k)
+            if ((active >> k) & 1) st[k].omega[cur] = omd[k];
+    }
+    double acc[3 * NR];
+#pragma unroll
+    for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double wd = wgt[i];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!((active >> k) & 1)) continue;
+            const T sk = s.p[k][i];
+            x.p[k][i] = x.p[k][i] + al[k] * p.p[k][i] + om[k] * sk;
+            const T rk = sk - om[k] * t.p[k][i];
+            r.p[k][i] = rk;
+            const double rd = rk;
+            acc[3 * k + 0] += static_cast<double>(rhat.p[k][i]) * rd;
+            acc[3 * k + 1] += wd * rd * rd;
+        }
+    }
+    write_partials<3 * NR>(acc, partOut, lds);
+}
+
+// xs_k = x_k + alpha_k p_k for k in mask (s-stage candidates)
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void k_bi_xs(int n, C3<T> x, C3<T> p, V3<T> xs,
+                                                  const BiState *st, int it, int mask) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            if ((mask >> k) & 1)
+                xs.p[k][i] = x.p[k][i] + static_cast<T>(st[k].alpha[it & 1]) * p.p[k][i];
+    }
+}
+
+template <typename T>
+void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
+    std::memset(&w, 0, sizeof(w));
+    for (int k = 0; k < nrhs; ++k) {
+        w.r[k] = c.take<T>(n);
+        w.rhat[k] = c.take<T>(n);
+        w.p[0][k] = c.take<T>(n);
+        w.p[1][k] = c.take<T>(n);
+        w.v[0][k] = c.take<T>(n);
+        w.v[1][k] = c.take<T>(n);
+        w.s[k] = c.take<T>(n);
+        w.t[k] = c.take<T>(n);
+        w.xs[k] = c.take<T>(n);
+    }
+    w.part1 = c.take<double>(9 * kMaxPartials);
+    w.part2 = c.take<double>(9 * kMaxPartials);
+    w.part3 = c.take<double>(9 * kMaxPartials);
+    w.st = c.take<BiState>(3);
+    w.glob = c.take<BiGlobal>(1);
+}
+
+template <typename T, int NR, int L>
+static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
+                  const T *const *b, T *const *x, double rtol, int maxit, int check_every,
+                  bool time_kernel, BiWork<T> &w, SolveOut *out) {
+    const int g1 = grid_for(n, kBlock / L);
+    const int g2 = grid_for(n, kBlock);
+    const int gv = grid_for(n, kBlock, 4096);
+    C3<T> cb{}, cx{}, cr{}, crh{}, cs{}, ct{}, cp[2]{}, cvv[2]{};
+    V3<T> vx{}, vr{}, vrh{}, vs{}, vt{}, vp[2]{}, vvv[2]{}, vxs{};
+    for (int k = 0; k < NR; ++k) {
+        cb.p[k] = b[k];
+        cx.p[k] = x[k];
+        vx.p[k] = x[k];
+        cr.p[k] = vr.p[k] = w.r[k];
+        crh.p[k] = vrh.p[k] = w.rhat[k];
+        cs.p[k] = vs.p[k] = w.s[k];
+        ct.p[k] = vt.p[k] = w.t[k];
+        vxs.p[k] = w.xs[k];
+        for (int q = 0; q < 2; ++q) {
+            cp[q].p[k] = vp[q].p[k] = w.p[q][k];
+            cvv[q].p[k] = vvv[q].p[k] = w.v[q][k];
+        }
+    }
+    BiState hs[3];
+    BiGlobal hg{};
+    for (int k = 0; k < 3; ++k) {
+        hs[k] = BiState{};
+        for (int q = 0; q < 2; ++q) hs[k].rho[q] = hs[k].alpha[q] = hs[k].omega[q] = 1.0;
+        hs[k].active = k < NR ? 1 : 0;
+        hs[k].no_sexit_it = -1;
+        out[k < NR ? k : 0] = SolveOut();
+    }
+    auto push_state = [&]() -> int {
+        OASIS_TRY_HIP(hipMemcpyAsync(w.st, hs, sizeof(hs), hipMemcpyHostToDevice, s));
+        OASIS_TRY_HIP(hipMemcpyAsync(w.glob, &hg, sizeof(hg), hipMemcpyHostToDevice, s));
+        return OASIS_OK;
+    };
+    auto pull_state = [&]() -> int {
+        OASIS_TRY_HIP(hipMemcpyAsync(hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipMemcpyAsync(&hg, w.glob, sizeof(hg), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        return OASIS_OK;
+    };
+    auto zero_dirs = [&](int k) -> int {
+        for (int q = 0; q < 2; ++q) {
+            hipLaunchKernelGGL((k_fill<T>), dim3(gv), dim3(kBlock), 0, s, n, w.p[q][k], T(0));
+            OASIS_TRY_LAUNCH();
+            hipLaunchKernelGGL((k_fill<T>), dim3(gv), dim3(kBlock), 0, s, n, w.v[q][k], T(0));
+            OASIS_TRY_LAUNCH();
+        }
+        return OASIS_OK;
+    };
+    auto resid = [&](int mask_res, int mask_rhat, C3<T> src) -> int {
+        hipLaunchKernelGGL((k_bi_resid<T, NR, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+                           cb, src, vr, vrh, mask_res, mask_rhat, w.part3);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    auto finalize = [&](int mode) -> int {
+        hipLaunchKernelGGL((k_bi_finalize<NR>), dim3(1), dim3(kBlock), 0, s, w.part3, g1, w.st,
+                           rtol * rtol, mode);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    const int all = (1 << NR) - 1;
+    OASIS_TRY(push_state());
+    for (int k = 0; k < NR; ++k) OASIS_TRY(zero_dirs(k));
+    OASIS_TRY(resid(all, all, cx));
+    OASIS_TRY(finalize(0));
+    OASIS_TRY(pull_state());
+    double wbb[3], tol2[3];
+    for (int k = 0; k < NR; ++k) {
+        wbb[k] = hs[k].wbb;
+        tol2[k] = hs[k].tol2;
+    }
+    auto rel = [&](int k, double wrr) { return wbb[k] > 0 ? std::sqrt(wrr / wbb[k]) : std::sqrt(wrr); };
+    int restarted[3] = {0, 0, 0};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (time_kernel) {
+        OASIS_TRY_HIP(hipEventCreate(&e0));
+        OASIS_TRY_HIP(hipEventCreate(&e1));
+    }
+    const int chunk = check_every > 0 ? check_every : 8;
+    int it = 0, phase = 1;
+    int part3_count = g1;
+    auto n_active = [&]() {
+        int a = 0;
+        for (int k = 0; k < NR; ++k) a += hs[k].active;
+        return a;
+    };
+    auto restart = [&](int k, int pit, int &mask_rhat) -> int {
+        if (restarted[k]) {
+            hs[k].active = 0;
+            out[k].status = OASIS_EBREAKDOWN;
+            out[k].iters = pit;
+            return OASIS_OK;
+        }
+        restarted[k] = 1;
+        out[k].replacements += 1;
+        OASIS_TRY(zero_dirs(k));
+        const int prev = (pit + 1) & 1;
+        hs[k].rho[prev] = hs[k].alpha[prev] = hs[k].omega[prev] = 1.0;
+        mask_rhat |= 1 << k;
+        return OASIS_OK;
+    };
+    while (n_active() > 0) {
+        // enqueue up to `chunk` iterations
+        int launched = 0;
+        while (launched < chunk && it < maxit) {
+            if (phase == 1) {
+                if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
+                hipLaunchKernelGGL((k_bi_1<T, NR, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                                   cr, crh, cp[(it + 1) & 1], cvv[(it + 1) & 1], vp[it & 1],
+                                   vvv[it & 1], w.part3, part3_count, w.st, w.glob, it, w.part1);
+                OASIS_TRY_LAUNCH();
+                if (time_kernel) {
+                    OASIS_TRY_HIP(hipEventRecord(e1, s));
+                    OASIS_TRY_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    OASIS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    out[0].kernel_ms += ms;
+                    out[0].kernel_count += 1;
+                }
+                hipLaunchKernelGGL((k_bi_2<T, NR, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                                   wgt, cr, cvv[it & 1], vs, vt, w.part1, g1, w.st, w.glob, it,
+                                   w.part2);
+                OASIS_TRY_LAUNCH();
+            }
+            hipLaunchKernelGGL((k_bi_3<T, NR>), dim3(g2), dim3(kBlock), 0, s, n, wgt, vx, vr, crh,
+                               cp[it & 1], cs, ct, w.part2, g1, w.st, w.glob, it, w.part3);
+            OASIS_TRY_LAUNCH();
+            part3_count = g2;
+            phase = 1;
+            ++it;
+            ++launched;
+        }
+        OASIS_TRY(pull_state());
+        if (!hg.pause) {
+            if (it < maxit) continue;
+            // iteration cap: confirm with the explicit residual
+            int mask = 0;
+            for (int k = 0; k < NR; ++k)
+                if (hs[k].active) mask |= 1 << k;
+            OASIS_TRY(resid(mask, 0, cx));
+            OASIS_TRY(finalize(1));
+            OASIS_TRY(pull_state());
+            for (int k = 0; k < NR; ++k) {
+                if (!((mask >> k) & 1)) continue;
+                out[k].iters = it;
+                out[k].rel_res = rel(k, hs[k].wrr);
+                out[k].status = hs[k].wrr <= tol2[k] ? OASIS_OK : OASIS_ENOTCONV;
+                hs[k].active = 0;
+            }
+            break;
+        }
+        const int pit = hg.pause_it, ph = hg.phase;
+        int mask_rhat = 0;
+        if (ph == 1 || ph == 2) {
+            int cands = 0;
+            for (int k = 0; k < NR; ++k)
+                if (hs[k].active && hs[k].event == 1) cands |= 1 << k;
+            if (cands) {
+                OASIS_TRY(resid(cands, 0, cx));
+                OASIS_TRY(finalize(1));
+                OASIS_TRY(pull_state());
+                for (int k = 0; k < NR; ++k) {
+                    if (!((cands >> k) & 1)) continue;
+                    if (hs[k].wrr <= tol2[k]) {
+                        hs[k].active = 0;
+                        out[k].status = OASIS_OK;
+                        out[k].iters = pit;
+                        out[k].rel_res = rel(k, hs[k].wrr);
+                    } else {
+                        out[k].replacements += 1;
+                    }
+                }
+            }
+            for (int k = 0; k < NR; ++k) {
+                if (!hs[k].active) continue;
+                if (hs[k].event == 3) {
+                    hs[k].active = 0;
+                    out[k].status = OASIS_ENAN;
+                    out[k].iters = pit;
+                    out[k].rel_res = NAN;
+                } else if (hs[k].event == 2 || hs[k].event == 4) {
+                    OASIS_TRY(restart(k, pit, mask_rhat));
+                }
+            }
+            for (int k = 0; k < NR; ++k) hs[k].event = 0;
+            hg = BiGlobal{};
+            OASIS_TRY(push_state());
+            OASIS_TRY(resid(0, mask_rhat, cx));
+            part3_count = g1;
+            it = pit;
+            phase = 1;
+        } else {
+            int cands = 0;
+            for (int k = 0; k < NR; ++k)
+                if (hs[k].active && hs[k].event == 5) cands |= 1 << k;
+            hipLaunchKernelGGL((k_bi_xs<T, NR>), dim3(gv), dim3(kBlock), 0, s, n, cx, cp[pit & 1], vxs,
+                               w.st, pit, cands);
+            OASIS_TRY_LAUNCH();
+            C3<T> src = cx;
+            for (int k = 0; k < NR; ++k)
+                if ((cands >> k) & 1) src.p[k] = w.xs[k];
+            OASIS_TRY(resid(cands, 0, src));
+            OASIS_TRY(finalize(1));
+            OASIS_TRY(pull_state());
+            for (int k = 0; k < NR; ++k) {
+                if (!((cands >> k) & 1)) continue;
+                if (hs[k].wrr <= tol2[k]) {
+                    hipLaunchKernelGGL((k_copy<T>), dim3(gv), dim3(kBlock), 0, s, n, x[k], w.xs[k]);
+                    OASIS_TRY_LAUNCH();
+                    hs[k].active = 0;
+                    out[k].status = OASIS_OK;
+                    out[k].iters = pit + 1;
+                    out[k].rel_res = rel(k, hs[k].wrr);
+                } else {
+                    hs[k].no_sexit_it = pit;
+                    out[k].replacements += 1;
+                }
+            }
+            for (int k = 0; k < NR; ++k) hs[k].event = 0;
+            hg = BiGlobal{};
+            OASIS_TRY(push_state());
+            it = pit;
+            phase = 3;
+        }
+    }
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    int worst = OASIS_OK;
+    for (int k = 0; k < NR; ++k)
+        if (out[k].status != OASIS_OK && (worst == OASIS_OK || out[k].status < worst)) worst = out[k].status;
+    return worst;
+}
+
+template <typename T>
+int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
+                   const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
+                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out) {
+#define OASIS_BI(NR, L)                                                                       \
+    return bi_run<T, NR, L>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, \
+                            w, out)
+    const int L = spmv_lanes();
+    if (nrhs == 1) {
+        if (L == 4) OASIS_BI(1, 4);
+        if (L == 16) OASIS_BI(1, 16);
+        OASIS_BI(1, 8);
+    } else if (nrhs == 2) {
+        if (L == 4) OASIS_BI(2, 4);
+        if (L == 16) OASIS_BI(2, 16);
+        OASIS_BI(2, 8);
+    } else {
+        if (L == 4) OASIS_BI(3, 4);
+        if (L == 16) OASIS_BI(3, 16);
+        OASIS_BI(3, 8);
+    }
+#undef OASIS_BI
+}
+
+template void carve_cg<double>(Carver &, int, CGWork<double> &);
+template void carve_cg<float>(Carver &, int, CGWork<float> &);
+template void carve_bi<double>(Carver &, int, int, BiWork<double> &);
+template void carve_bi<float>(Carver &, int, int, BiWork<float> &);
+template int cg_solve<double>(hipStream_t, int, const int *, const int *, const double *,
+                              const double *, const double *, double *, double, int, int, bool,
+                              CGWork<double> &, SolveOut &);
+template int cg_solve<float>(hipStream_t, int, const int *, const int *, const float *,
+                             const float *, const float *, float *, double, int, int, bool,
+                             CGWork<float> &, SolveOut &);
+template int bicgstab_solve<double>(hipStream_t, int, int, const int *, const int *,
+                                    const double *, const double *, const double *const *,
+                                    double *const *, double, int, int, bool, BiWork<double> &,
+                                    SolveOut *);
+template int bicgstab_solve<float>(hipStream_t, int, int, const int *, const int *, const float *,
+                                   const float *, const float *const *, float *const *, double,
+                                   int, int, bool, BiWork<float> &, SolveOut *);
+
+}  // namespace oasis

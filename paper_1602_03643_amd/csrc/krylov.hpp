@@ -1,0 +1,87 @@
+// Internal Krylov solver interfaces (CG on a symmetrically scaled SPD
+// matrix, BiCGStab on a row-scaled matrix) shared by the standalone entry
+// points and the IPCS step.
+#pragma once
+
+#include "internal.hpp"
+
+namespace oasis {
+
+struct CGState {
+    double rr[2];      // r.r of the residual entering iteration it, slot it & 1
+    double tol2;       // (rtol ||b||)^2 in the weighted norm
+    double wbb;        // weighted ||b||^2
+    double wrr;        // weighted ||r||^2 seen by the last finalize
+    int flag;          // 0 running, 1 converged candidate, 2 breakdown, 3 non-finite
+    int it_done;       // iteration index at which flag was raised
+};
+
+template <typename T>
+struct CGWork {
+    T *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    double *partA = nullptr, *partB = nullptr;
+    CGState *st = nullptr;
+};
+
+struct BiState {
+    double rho[2], alpha[2], omega[2];
+    double tol2, wbb, wrr;
+    int active;        // 1 while iterating
+    int event;         // see krylov.hip
+    int no_sexit_it;   // iteration whose s-exit test is disabled
+    int pad;
+};
+
+struct BiGlobal {
+    int pause;
+    int phase;         // 1, 2, 3: kernel of iteration pause_it that paused
+    int pause_it;
+    int pad;
+};
+
+template <typename T>
+struct BiWork {
+    T *r[3], *rhat[3], *p[2][3], *v[2][3], *s[3], *t[3], *xs[3];
+    double *part1, *part2, *part3;
+    BiState *st;       // [3]
+    BiGlobal *glob;
+};
+
+struct SolveOut {
+    int iters = 0;
+    int status = OASIS_OK;
+    int replacements = 0;
+    int outer = 0;            // refinement steps (mixed precision)
+    double rel_res = 0.0;
+    double kernel_ms = 0.0;
+    int kernel_count = 0;
+};
+
+// Lanes per CSR row used by the sparse kernels (4, 8 or 16).
+int spmv_lanes();
+
+template <typename T>
+void carve_cg(Carver &c, int n, CGWork<T> &w);
+template <typename T>
+void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w);
+
+// CG on Ms x = b with Ms the scaled matrix (unit diagonal).  The stopping
+// test uses sum_i wgt_i r_i^2 <= rtol^2 sum_i wgt_i b_i^2.
+template <typename T>
+int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
+             const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
+             CGWork<T> &w, SolveOut &out);
+
+// BiCGStab for nrhs systems with the row-scaled matrix As (left Jacobi).
+template <typename T>
+int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
+                   const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
+                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out);
+
+// Weighted residual of x for the scaled system: r = b - Ms x, returns
+// (sum wgt r^2, sum wgt b^2) on the host.  Uses w's buffers.
+int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
+                const double *wgt, const double *b, const double *x, double *r,
+                CGWork<double> &w, double *wrr, double *wbb);
+
+}  // namespace oasis
