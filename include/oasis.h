@@ -165,14 +165,23 @@ int oasis_spmv(void *stream, const oasis_csr *A, const void *x, void *y, double 
 typedef struct {
     double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) */
     int32_t maxit;        /* total (inner) iteration cap */
-    int32_t precision;    /* OASIS_F64, or OASIS_F32 = FP32 inner / FP64 outer refinement */
-    double inner_rtol;    /* F32 mode: inner stop, relative to the outer residual */
-    int32_t max_outer;    /* F32 mode: cap on refinement steps (0 = 50) */
+    int32_t precision;    /* OASIS_F64, or OASIS_F32: FP32 matrix/vectors inside the
+                             iteration, FP64 dot products and FP64 refinement */
+    double inner_rtol;    /* F32 mode.  CG: the FP64 residual replaces the FP32 one each
+                             time the latter fell by this factor (reliable updates; 0 =
+                             0.1).  BiCGStab: inner tolerance of each refinement step
+                             (0 = 1e-4; tightened automatically for the last step) */
+    int32_t max_outer;    /* F32 mode BiCGStab: cap on refinement steps (0 = 50) */
     int32_t check_every;  /* iterations launched between host convergence polls (0 = auto) */
     int32_t flags;        /* OASIS_KRYLOV_TIME: time the dominant kernel with HIP events */
 } oasis_krylov_opts;
 
 #define OASIS_KRYLOV_TIME 1
+/* The matrix is singular with the constant vector as null space (pure
+ * Neumann pressure matrix) and b is consistent.  In F32 mode the FP32
+ * iterations then keep their residual orthogonal to the (scaled) null
+ * vector, which FP32 rounding of the matrix would otherwise perturb. */
+#define OASIS_KRYLOV_NULLSPACE_CONST 2
 
 typedef struct {
     int32_t iters;        /* total (inner) iterations */

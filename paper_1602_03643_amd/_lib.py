@@ -9,12 +9,13 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboasis.so")
+LIB_PATH = os.environ.get("OASIS_LIB") or os.path.join(HERE, "liboasis.so")
 
 OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32 = 0, 1
 FORM_MASS, FORM_STIFF, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_CONV = range(6)
 KRYLOV_TIME = 1
+KRYLOV_NULLSPACE_CONST = 2
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
 

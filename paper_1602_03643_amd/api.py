@@ -208,10 +208,14 @@ def _stats(st):
                 rel_res=st.rel_res, kernel_ms=st.kernel_ms, kernel_count=st.kernel_count)
 
 
-def pcg(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4, max_outer=50,
-        check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True):
+def pcg(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=0.1, max_outer=50,
+        check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True, nullspace_const=False):
+    """F32 mode: FP32 iterations with reliable updates every `inner_rtol`
+    reduction of the residual."""
     lib = _lib()
     o = _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel)
+    if nullspace_const:
+        o.flags |= L.KRYLOV_NULLSPACE_CONST
     nb = C.c_size_t()
     L.check(lib.oasis_krylov_workspace_size(A.n, A.nnz, 1, C.byref(o), C.byref(nb)), "oasis_krylov_workspace_size")
     if ws is None or ws.numel() < nb.value:

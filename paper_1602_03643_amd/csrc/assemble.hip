@@ -8,6 +8,8 @@
 // of its 256 cells in LDS (one thread per cell computes geometry and the
 // (D+1)^2 entries), then all threads cooperate on the scatter so that the
 // lanes writing one row sit next to each other.
+#include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "assemble.hpp"
@@ -119,14 +121,18 @@ int scale_copy(hipStream_t s, long long n, double *y, const double *x, double a)
     return OASIS_OK;
 }
 
-template <typename T, int L>
+template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int *__restrict__ rp,
                                                  const int *__restrict__ ci,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ x, T *__restrict__ y, T alpha,
                                                  T beta) {
-    csr_rows<T, 1, L>(
-        n, rp, ci, val, [&](int, int c, T v, T(&a)[1]) { a[0] += v * x[c]; },
+    csr_rows<T, 1, C>(
+        n, rp, ci, val,
+        [&](int, int c, T v, bool ok, T(&a)[1]) {
+            const T t = v * x[c];
+            a[0] += ok ? t : T(0);
+        },
         [&](int row, int lane, T(&a)[1]) {
             if (lane == 0) y[row] = beta == T(0) ? alpha * a[0] : alpha * a[0] + beta * y[row];
         });
@@ -134,20 +140,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int *__restrict__ 
 
 template <typename T>
 static int spmv_launch(hipStream_t s, const oasis_csr *A, const T *x, T *y, T alpha, T beta) {
-    const int L = spmv_lanes();
-    const int g = grid_for(A->n, kBlock / L, 1 << 20);
     const T *val = static_cast<const T *>(A->val);
-    if (L == 4)
-        hipLaunchKernelGGL((k_spmv<T, 4>), dim3(g), dim3(kBlock), 0, s, A->n, A->row_ptr, A->col_idx,
-                           val, x, y, alpha, beta);
-    else if (L == 16)
-        hipLaunchKernelGGL((k_spmv<T, 16>), dim3(g), dim3(kBlock), 0, s, A->n, A->row_ptr,
-                           A->col_idx, val, x, y, alpha, beta);
-    else
-        hipLaunchKernelGGL((k_spmv<T, 8>), dim3(g), dim3(kBlock), 0, s, A->n, A->row_ptr, A->col_idx,
-                           val, x, y, alpha, beta);
-    OASIS_TRY_LAUNCH();
-    return OASIS_OK;
+    return with_cfg([&](auto c) -> int {
+        using C = decltype(c);
+        static const int cap = [] {
+            const char *e = std::getenv("OASIS_SPMV_GRIDCAP");
+            return e ? std::max(8, std::atoi(e)) : (1 << 20);
+        }();
+        const int g = grid_for(A->n, rows_per_block<C>(), cap);
+        hipLaunchKernelGGL((k_spmv<T, C>), dim3(g), dim3(kBlock), 0, s, A->n, A->row_ptr, A->col_idx, val, x,
+                           y, alpha, beta);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    });
 }
 
 int check_csr(const oasis_csr *A) {

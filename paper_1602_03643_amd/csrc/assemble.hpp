@@ -20,6 +20,5 @@ int assemble_colored(hipStream_t s, const oasis_mesh *m, const int *rp, const in
 // y = a * x (x == nullptr: y = 0)
 int scale_copy(hipStream_t s, long long n, double *y, const double *x, double a);
 
-int spmv_lanes();
 
 }  // namespace oasis

@@ -63,10 +63,13 @@ struct Carver {
     size_t bytes() const { return (off + 255) & ~size_t(255); }
 };
 
+// Blocks for `work` items at `per_block` each, at most `cap`; rounded up to
+// a multiple of 8 (one share per XCD) once there are at least 8.
 inline int grid_for(long long work, int per_block, int cap = kMaxPartials) {
     long long g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;
-    if (g > cap) g = cap;
+    if (g >= 8) g = (g + 7) / 8 * 8;
+    if (g > cap) g = cap / 8 * 8;
     return static_cast<int>(g);
 }
 
@@ -115,14 +118,27 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *part, do
 
 // Consumer side: every block sums the nparts partials of the previous kernel
 // in the same order, so all blocks hold identical totals.
+// The loads are unrolled so that a thread issues all of its (at most
+// kMaxPartials / kBlock) loads at once: one cache round trip, not eight.
 template <int NV>
 __device__ __forceinline__ void read_partials(const double *part, int nparts, double (&out)[NV],
                                               double *lds) {
+    constexpr int PER = kMaxPartials / kBlock;
+    constexpr int U = NV <= 3 ? PER : 2;     // bound the registers held in flight
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    for (int q0 = 0; q0 < PER; q0 += U) {
+        double t[U][NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) out[k] += part[i * NV + k];
+        for (int q = 0; q < U; ++q) {
+            const int i = threadIdx.x + (q0 + q) * kBlock;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) t[q][k] = i < nparts ? part[i * NV + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) out[k] += t[q][k];
     }
     block_sum<NV>(out, lds);
 }

@@ -124,6 +124,37 @@ __global__ __launch_bounds__(kBlock) void k_add_f32(long long n, double *__restr
         x[i] += static_cast<double>(e[i]);
 }
 
+// partial sums of x^2
+__global__ __launch_bounds__(kBlock) void k_sumsq(int n, const double *__restrict__ x, double *part) {
+    __shared__ double lds[kBlock / kWave];
+    double acc[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        acc[0] += x[i] * x[i];
+    write_partials<1>(acc, part, lds);
+}
+
+// out32 = x / ||x||
+__global__ __launch_bounds__(kBlock) void k_unit_f32(int n, const double *__restrict__ x, const double *part,
+                                                     int np, float *__restrict__ out32) {
+    __shared__ double lds[kBlock / kWave];
+    double v[1];
+    read_partials<1>(part, np, v, lds);
+    const double inv = 1.0 / sqrt(v[0]);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out32[i] = static_cast<float>(x[i] * inv);
+}
+
+static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, float *out) {
+    const int g = grid_for(n, kBlock);
+    hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(kBlock), 0, s, n, x, part);
+    OASIS_TRY_LAUNCH();
+    hipLaunchKernelGGL(k_unit_f32, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, x, part, g, out);
+    OASIS_TRY_LAUNCH();
+    return OASIS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // step kernels
 
@@ -323,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__rest
 
 // outer residual of the refinement loop: r = b - A x (FP64), r32 = (float) r,
 // partials (sum w r^2, sum w b^2) per component
-template <int NR, int L>
+template <int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_ir_resid(int n, const int *__restrict__ rp,
                                                      const int *__restrict__ ci,
                                                      const double *__restrict__ val,
@@ -334,11 +365,14 @@ __global__ __launch_bounds__(kBlock) void k_ir_resid(int n, const int *__restric
     double acc2[2 * NR];
 #pragma unroll
     for (int k = 0; k < 2 * NR; ++k) acc2[k] = 0.0;
-    csr_rows<double, NR, L>(
+    csr_rows<double, NR, C>(
         n, rp, ci, val,
-        [&](int, int c, double v, double(&a)[NR]) {
+        [&](int, int c, double v, bool ok, double(&a)[NR]) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) a[k] += v * x.p[k][c];
+            for (int k = 0; k < NR; ++k) {
+                const double t = v * x.p[k][c];
+                a[k] += ok ? t : 0.0;
+            }
         },
         [&](int row, int lane, double(&a)[NR]) {
             if (lane != 0) return;
@@ -405,8 +439,8 @@ static void carve_ir(Carver &c, int n, int nr, IRBufs &ir) {
 static int ir_outer_resid(hipStream_t s, int n, int nr, const int *rp, const int *ci,
                           const double *val, const double *w, P3 b, P3 x, IRBufs &ir,
                           double *host_sums) {
-    constexpr int L = 8;
-    const int g = grid_for(n, kBlock / L);
+    using L = Cfg8x2x1;
+    const int g = grid_for(n, rows_per_block<L>(), partial_cap());
     if (nr == 1) {
         hipLaunchKernelGGL((k_ir_resid<1, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
                            ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
@@ -521,6 +555,14 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
             }
         }
         if (na == 0) break;
+        // inner tolerance: the configured one, loosened when less suffices to reach rtol
+        double inner = o.inner_rtol;
+        double need = 1.0;
+        for (int q = 0; q < na; ++q) {
+            const int k = active[q];
+            if (hs[2 * k] > 0) need = std::min(need, 0.5 * o.rtol * std::sqrt(hs[2 * k + 1] / hs[2 * k]));
+        }
+        inner = std::max(inner, need);
         const float *bb[3];
         float *xx[3];
         for (int q = 0; q < na; ++q) {
@@ -531,7 +573,7 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
             OASIS_TRY_LAUNCH();
         }
         SolveOut in[3];
-        const int rc = bicgstab_solve<float>(s, n, na, rp, ci, val32, w32, bb, xx, o.inner_rtol,
+        const int rc = bicgstab_solve<float>(s, n, na, rp, ci, val32, w32, bb, xx, inner,
                                              o.maxit, o.check_every, o.time, bw, in);
         if (rc == OASIS_EHIP) return rc;
         for (int q = 0; q < na; ++q) {
@@ -549,6 +591,8 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
         if (out[k].status != OASIS_OK && (worst == OASIS_OK || out[k].status < worst)) worst = out[k].status;
     return worst;
 }
+
+static double reliable_delta(double inner) { return (inner > 0.0 && inner < 1.0) ? inner : 0.1; }
 
 static KOpts kopts(const oasis_krylov_opts *o) {
     KOpts k;
@@ -578,7 +622,8 @@ struct oasis_ipcs {
     double *M = nullptr, *Ks = nullptr, *dP[3] = {nullptr, nullptr, nullptr}, *B = nullptr, *A = nullptr;
     float *A32 = nullptr, *Ks32 = nullptr;
     double *ML = nullptr, *sK = nullptr, *wK = nullptr, *dA = nullptr, *wA = nullptr, *dtmp = nullptr;
-    float *wK32 = nullptr, *wA32 = nullptr;
+    float *wK32 = nullptr, *wA32 = nullptr, *vnull32 = nullptr, *xlo = nullptr;
+    double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
     double *bphi = nullptr, *bs = nullptr, *xs = nullptr, *xg = nullptr, *red = nullptr;
@@ -601,6 +646,9 @@ static void carve_ipcs(Carver &c, int dim, int n, int nnz, bool mixed, oasis_ipc
         h.Ks32 = c.take<float>(nnz);
         h.wK32 = c.take<float>(n);
         h.wA32 = c.take<float>(n);
+        h.vnull32 = c.take<float>(n);
+        h.xlo = c.take<float>(n);
+        h.rhi = c.take<double>(n);
     }
     h.ML = c.take<double>(n);
     h.sK = c.take<double>(n);
@@ -710,6 +758,8 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
                        1.0 / par->dt, h->B, 0.5 * par->nu);
     hipLaunchKernelGGL(k_row_sums, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->M, h->ML);
     if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
+    // the scaled pressure matrix has null vector s = sqrt(diag K) (K 1 = 0)
+    if (h->mixed && unit_vector_f32(s, n, h->sK, h->red, h->vnull32) != OASIS_OK) return fail(OASIS_EHIP);
     int fl[3] = {0, 0, 0};
     if (hipMemcpyAsync(fl, h->flag, sizeof(fl), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -867,7 +917,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     SolveOut sp;
     int rc_p;
     if (h->mixed)
-        rc_p = ir_cg(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->bs, h->xs, ko, h->cg32, h->ir, sp);
+        rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->bs, h->xs,
+                              ko.rtol, reliable_delta(0.0), ko.maxit, 0, false, h->cg32, h->xlo,
+                              h->rhi, sp);
     else
         rc_p = cg_solve<double>(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, 0, false,
                                 h->cg, sp);
@@ -913,8 +965,8 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
 // stand-alone Krylov entry points
 
 struct KrylovWs {
-    double *val, *s, *w, *b, *x;
-    float *val32, *w32;
+    double *val, *s, *w, *b, *x, *rhi;
+    float *val32, *w32, *vnull32, *xlo;
     int *flag;
     CGWork<double> cg;
     CGWork<float> cg32;
@@ -938,6 +990,9 @@ static void carve_krylov(Carver &c, int n, int nnz, int nrhs, bool mixed, Krylov
     if (mixed) {
         k.val32 = c.take<float>(nnz);
         k.w32 = c.take<float>(n);
+        k.vnull32 = c.take<float>(n);
+        k.xlo = c.take<float>(n);
+        k.rhi = c.take<double>(n);
         carve_cg<float>(c, n, k.cg32);
         carve_bi<float>(c, n, nrhs, k.bi32);
         carve_ir(c, n, nrhs, k.ir);
@@ -999,8 +1054,16 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     const KOpts ko = kopts(opt);
     SolveOut so;
     int rc;
-    if (mixed)
-        rc = ir_cg(s, n, A->row_ptr, A->col_idx, k.val, k.val32, k.w, k.w32, k.b, k.x, ko, k.cg32, k.ir, so);
+    if (mixed) {
+        const float *vn = nullptr;
+        if (opt->flags & OASIS_KRYLOV_NULLSPACE_CONST) {
+            OASIS_TRY(unit_vector_f32(s, n, k.s, k.ir.part, k.vnull32));
+            vn = k.vnull32;
+        }
+        rc = cg_mixed_solve(s, n, A->row_ptr, A->col_idx, k.val, k.val32, k.w, k.w32, vn, k.b, k.x, ko.rtol,
+                            reliable_delta(opt->inner_rtol), ko.maxit, ko.check_every, ko.time, k.cg32, k.xlo,
+                            k.rhi, so);
+    }
     else
         rc = cg_solve<double>(s, n, A->row_ptr, A->col_idx, k.val, k.w, k.b, k.x, ko.rtol, ko.maxit, ko.check_every,
                               ko.time, k.cg, so);

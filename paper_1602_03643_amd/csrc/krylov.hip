@@ -25,13 +25,22 @@
 
 namespace oasis {
 
-int spmv_lanes() {
-    static int lanes = [] {
-        const char *e = std::getenv("OASIS_SPMV_LANES");
-        int v = e ? std::atoi(e) : 8;
-        return (v == 4 || v == 8 || v == 16) ? v : 8;
+int spmv_cfg() {
+    static int cfg = [] {
+        const char *e = std::getenv("OASIS_SPMV_CFG");
+        const int v = e ? std::atoi(e) : 1;
+        return (v >= 0 && v <= 4) ? v : 1;
     }();
-    return lanes;
+    return cfg;
+}
+
+int partial_cap() {
+    static int cap = [] {
+        const char *e = std::getenv("OASIS_PARTIALS");
+        const int v = e ? std::atoi(e) : kMaxPartials;
+        return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials;
+    }();
+    return cap;
 }
 
 // A flag written by an earlier kernel (or by block 0 of this one when it
@@ -67,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(int n, T *__restrict__ y, const
 // CG kernels
 
 // r = b - Ms x; partials (r.r, sum wgt r^2, sum wgt b^2)
-template <typename T, int L>
+template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ ci,
                                                     const T *__restrict__ val,
@@ -77,8 +86,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict
                                                     double *part) {
     __shared__ double lds[3 * kBlock / kWave];
     double acc[3] = {0.0, 0.0, 0.0};
-    csr_rows<T, 1, L>(
-        n, rp, ci, val, [&](int, int c, T v, T(&a)[1]) { a[0] += v * x[c]; },
+    csr_rows<T, 1, C>(
+        n, rp, ci, val, [&](int, int c, T v, bool ok, T(&a)[1]) {
+            const T t = v * x[c];
+            a[0] += ok ? t : T(0);
+        },
         [&](int row, int lane, T(&a)[1]) {
             if (lane == 0) {
                 const T ri = b[row] - a[0];
@@ -92,9 +104,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict
     write_partials<3>(acc, part, lds);
 }
 
-// mode 0: start of a solve (sets tol2); mode 1: explicit-residual check
+// mode 0: start of a solve (sets tol2); mode 1: explicit-residual check.
+// upd_factor > 0 arms the next residual replacement at upd_factor * wrr.
 __global__ __launch_bounds__(kBlock) void k_cg_finalize(const double *part, int nparts, CGState *st,
-                                                        double rtol2, int mode) {
+                                                        double rtol2, int mode, double upd_factor) {
     __shared__ double lds[3 * kBlock / kWave];
     double v[3];
     read_partials<3>(part, nparts, v, lds);
@@ -104,15 +117,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_finalize(const double *part, int 
             st->wbb = v[2];
         }
         st->wrr = v[1];
+        st->upd2 = upd_factor * v[1];
         st->flag = 0;
         st->it_done = -1;
     }
 }
 
+// r_lo = (float) r_hi, x_lo = 0; partials of r_lo in the k_cg_init layout
+__global__ __launch_bounds__(kBlock) void k_cg_cast(int n, const double *__restrict__ rhi,
+                                                    const float *__restrict__ wgt,
+                                                    float *__restrict__ rlo, float *__restrict__ xlo,
+                                                    double *part) {
+    __shared__ double lds[3 * kBlock / kWave];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float r = static_cast<float>(rhi[i]);
+        rlo[i] = r;
+        xlo[i] = 0.f;
+        const double rd = r;
+        acc[0] += rd * rd;
+        acc[1] += static_cast<double>(wgt[i]) * rd * rd;
+    }
+    write_partials<3>(acc, part, lds);
+}
+
 // Iteration part 1: convergence test on the incoming residual, direction
 // p_new = r + beta p_old (formed on the fly for the gathered operand),
 // q = Ms p_new, partial p_new.q.
-template <typename T, int L>
+template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__ rp,
                                                   const int *__restrict__ ci,
                                                   const T *__restrict__ val,
@@ -120,7 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
                                                   const T *__restrict__ pold,
                                                   T *__restrict__ pnew, T *__restrict__ q,
                                                   const double *partIn, int nIn, CGState *st,
-                                                  int it, int beta_zero, double *partOut) {
+                                                  int it, int beta_zero, const T *__restrict__ vnull,
+                                                  double *partOut) {
     __shared__ double lds[3 * kBlock / kWave];
     if (block_read_flag(&st->flag)) return;
     double v[3];
@@ -131,6 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
         flag = 3;
     else if (wrr <= st->tol2)
         flag = 1;
+    else if (wrr <= st->upd2)
+        flag = 4;
     if (flag) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->flag = flag;
@@ -142,18 +178,34 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
     const double beta = beta_zero ? 0.0 : rr / st->rr[(it + 1) & 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
     const T bt = static_cast<T>(beta);
-    double acc[1] = {0.0};
-    csr_rows<T, 1, L>(
-        n, rp, ci, val, [&](int, int c, T vv, T(&a)[1]) { a[0] += vv * (r[c] + bt * pold[c]); },
-        [&](int row, int lane, T(&a)[1]) {
-            if (lane == 0) {
-                const T pn = r[row] + bt * pold[row];
-                pnew[row] = pn;
-                q[row] = a[0];
-                acc[0] += static_cast<double>(pn) * static_cast<double>(a[0]);
-            }
-        });
-    write_partials<1>(acc, partOut, lds);
+    double acc[2] = {0.0, 0.0};
+    auto finish = [&](int row, int lane, T(&a)[1]) {
+        if (lane == 0) {
+            const T pn = beta_zero ? r[row] : r[row] + bt * pold[row];
+            pnew[row] = pn;
+            q[row] = a[0];
+            acc[0] += static_cast<double>(pn) * static_cast<double>(a[0]);
+            if (vnull) acc[1] += static_cast<double>(vnull[row]) * static_cast<double>(a[0]);
+        }
+    };
+    // a fresh direction never reads p_old (its buffer may hold stale values)
+    if (beta_zero)
+        csr_rows<T, 1, C>(
+            n, rp, ci, val,
+            [&](int, int c, T vv, bool ok, T(&a)[1]) {
+                const T t = vv * r[c];
+                a[0] += ok ? t : T(0);
+            },
+            finish);
+    else
+        csr_rows<T, 1, C>(
+            n, rp, ci, val,
+            [&](int, int c, T vv, bool ok, T(&a)[1]) {
+                const T t = vv * (r[c] + bt * pold[c]);
+                a[0] += ok ? t : T(0);
+            },
+            finish);
+    write_partials<2>(acc, partOut, lds);
 }
 
 // Iteration part 2: alpha = r.r / p.q, x += alpha p, r -= alpha q,
@@ -162,11 +214,12 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_p2(int n, T *__restrict__ r, const T *__restrict__ p,
                                                   const T *__restrict__ q, T *__restrict__ x,
                                                   const T *__restrict__ wgt, const double *partIn,
-                                                  int nIn, CGState *st, int it, double *partOut) {
+                                                  int nIn, CGState *st, int it,
+                                                  const T *__restrict__ vnull, double *partOut) {
     __shared__ double lds[3 * kBlock / kWave];
     if (block_read_flag(&st->flag)) return;
-    double v[1];
-    read_partials<1>(partIn, nIn, v, lds);
+    double v[2];
+    read_partials<2>(partIn, nIn, v, lds);
     const double pq = v[0];
     if (!(pq > 0.0) || !finite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -176,11 +229,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_p2(int n, T *__restrict__ r, cons
         return;
     }
     const T a = static_cast<T>(st->rr[it & 1] / pq);
+    const T cv = static_cast<T>(v[1]);    // (v.q) for a unit null vector v
     double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const T xi = x[i] + a * p[i];
-        const T ri = r[i] - a * q[i];
+        const T qi = vnull ? q[i] - cv * vnull[i] : q[i];
+        const T ri = r[i] - a * qi;
         x[i] = xi;
         r[i] = ri;
         const double rd = ri;
@@ -201,19 +256,19 @@ void carve_cg(Carver &c, int n, CGWork<T> &w) {
     w.st = c.take<CGState>(1);
 }
 
-template <typename T, int L>
+template <typename T, class C>
 static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
                   CGWork<T> &w, SolveOut &out) {
-    const int g1 = grid_for(n, kBlock / L);
-    const int g2 = grid_for(n, kBlock);
+    const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
+    const int g2 = grid_for(n, kBlock, partial_cap());
     out = SolveOut();
     auto residual = [&](int mode) -> int {
-        hipLaunchKernelGGL((k_cg_init<T, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+        hipLaunchKernelGGL((k_cg_init<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
                            b, x, w.r, w.partB);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
-                           rtol * rtol, mode);
+                           rtol * rtol, mode, 0.0);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
@@ -235,10 +290,10 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
             if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
-            hipLaunchKernelGGL((k_cg_p1<T, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, w.r,
+            hipLaunchKernelGGL((k_cg_p1<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, w.r,
                                w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
                                itj == restart_at ? g1 : g2, w.st, itj, itj == restart_at ? 1 : 0,
-                               w.partA);
+                               static_cast<const T *>(nullptr), w.partA);
             OASIS_TRY_LAUNCH();
             if (time_kernel) {
                 OASIS_TRY_HIP(hipEventRecord(e1, s));
@@ -249,7 +304,8 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                 out.kernel_count += 1;
             }
             hipLaunchKernelGGL((k_cg_p2<T>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
-                               w.q, x, wgt, w.partA, g1, w.st, itj, w.partB);
+                               w.q, x, wgt, w.partA, g1, w.st, itj, static_cast<const T *>(nullptr),
+                               w.partB);
             OASIS_TRY_LAUNCH();
         }
         it += m;
@@ -304,27 +360,157 @@ template <typename T>
 int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
              const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
              CGWork<T> &w, SolveOut &out) {
-    switch (spmv_lanes()) {
-        case 4:
-            return cg_run<T, 4>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
-                                time_kernel, w, out);
-        case 16:
-            return cg_run<T, 16>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
-                                 time_kernel, w, out);
-        default:
-            return cg_run<T, 8>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
-                                time_kernel, w, out);
+    return with_cfg([&](auto c) {
+        return cg_run<T, decltype(c)>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
+                                      time_kernel, w, out);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_lo(int n, double *__restrict__ x, const float *__restrict__ e) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] += static_cast<double>(e[i]);
+}
+
+template <class C>
+static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
+                        const float *val32, const double *wgt, const float *wgt32,
+                        const float *vnull, const double *b, double *x, double rtol, double delta,
+                        int maxit, int check_every, bool time_kernel, CGWork<float> &w,
+                        float *xlo, double *rhi, SolveOut &out) {
+    const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
+    const int g2 = grid_for(n, kBlock, partial_cap());
+    const double upd = delta * delta;
+    out = SolveOut();
+    // FP64 residual of the FP64 accumulator, then its FP32 copy (x_lo = 0)
+    auto replace = [&](int mode) -> int {
+        hipLaunchKernelGGL((k_cg_init<double, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+                           b, x, rhi, w.partB);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
+                           rtol * rtol, mode, upd);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    auto cast = [&]() -> int {
+        hipLaunchKernelGGL(k_cg_cast, dim3(g2), dim3(kBlock), 0, s, n, rhi, wgt32, w.r, xlo, w.partB);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    auto fold = [&]() -> int {
+        hipLaunchKernelGGL(k_add_lo, dim3(g2), dim3(kBlock), 0, s, n, x, xlo);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    OASIS_TRY(replace(0));
+    CGState h;
+    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    const double wbb = h.wbb, tol2 = h.tol2;
+    auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
+    if (!std::isfinite(h.wrr)) {
+        out.status = OASIS_ENAN;
+        out.rel_res = NAN;
+        return out.status;
     }
+    if (h.wrr <= tol2) {
+        out.rel_res = rel(h.wrr);
+        return OASIS_OK;
+    }
+    OASIS_TRY(cast());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (time_kernel) {
+        OASIS_TRY_HIP(hipEventCreate(&e0));
+        OASIS_TRY_HIP(hipEventCreate(&e1));
+    }
+    const int chunk = check_every > 0 ? check_every : 32;
+    int it = 0, restart_at = 0, nin = g2;
+    int rc = OASIS_OK;
+    while (true) {
+        const int m = std::min(chunk, maxit - it);
+        for (int j = 0; j < m; ++j) {
+            const int itj = it + j;
+            if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
+            hipLaunchKernelGGL((k_cg_p1<float, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val32,
+                               w.r, w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
+                               j == 0 ? nin : g2, w.st, itj, itj == restart_at ? 1 : 0, vnull,
+                               w.partA);
+            OASIS_TRY_LAUNCH();
+            if (time_kernel) {
+                OASIS_TRY_HIP(hipEventRecord(e1, s));
+                OASIS_TRY_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                OASIS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+                out.kernel_ms += ms;
+                out.kernel_count += 1;
+            }
+            hipLaunchKernelGGL((k_cg_p2<float>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
+                               w.q, xlo, wgt32, w.partA, g1, w.st, itj, vnull, w.partB);
+            OASIS_TRY_LAUNCH();
+        }
+        it += m;
+        nin = g2;
+        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        if (h.flag == 2 || h.flag == 3) {
+            OASIS_TRY(fold());
+            out.iters = h.it_done;
+            out.status = rc = (h.flag == 2) ? OASIS_EBREAKDOWN : OASIS_ENAN;
+            out.rel_res = NAN;
+            break;
+        }
+        if (h.flag == 0 && it < maxit) continue;
+        // replacement: fold x_lo into x, FP64 residual, test, FP32 copy
+        const int at = h.flag == 0 ? it : h.it_done;
+        OASIS_TRY(fold());
+        OASIS_TRY(replace(1));
+        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        out.outer += 1;
+        out.rel_res = rel(h.wrr);
+        if (!std::isfinite(h.wrr)) {
+            out.iters = at;
+            out.status = rc = OASIS_ENAN;
+            break;
+        }
+        if (h.wrr <= tol2) {
+            out.iters = at;
+            out.status = rc = OASIS_OK;
+            break;
+        }
+        if (at >= maxit) {
+            out.iters = at;
+            out.status = rc = OASIS_ENOTCONV;
+            break;
+        }
+        OASIS_TRY(cast());
+        it = at;
+        nin = g2;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
+                   const float *val32, const double *wgt, const float *wgt32, const float *vnull,
+                   const double *b, double *x, double rtol, double delta, int maxit,
+                   int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
+                   SolveOut &out) {
+    return with_cfg([&](auto c) {
+        return cg_mixed_run<decltype(c)>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, b, x, rtol, delta,
+                                         maxit, check_every, time_kernel, w, xlo, rhi, out);
+    });
 }
 
 int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
                 const double *wgt, const double *b, const double *x, double *r,
                 CGWork<double> &w, double *wrr, double *wbb) {
-    const int g1 = grid_for(n, kBlock / 8);
-    hipLaunchKernelGGL((k_cg_init<double, 8>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+    const int g1 = grid_for(n, rows_per_block<Cfg8x2x1>(), partial_cap());
+    hipLaunchKernelGGL((k_cg_init<double, Cfg8x2x1>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
                        b, x, r, w.partB);
     OASIS_TRY_LAUNCH();
-    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0);
+    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0, 0.0);
     OASIS_TRY_LAUNCH();
     CGState h;
     OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -353,7 +539,7 @@ struct C3 {
 
 // r_k = b_k - As xsrc_k for k in mask_res; r_hat_k = r_k for k in mask_rhat;
 // partials (r_hat.r, sum wgt r^2, sum wgt b^2) for every k.
-template <typename T, int NR, int L>
+template <typename T, int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, const int *__restrict__ rp,
                                                      const int *__restrict__ ci,
                                                      const T *__restrict__ val,
@@ -364,12 +550,15 @@ __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, const int *__restric
     double acc[3 * NR];
 #pragma unroll
     for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
-    csr_rows<T, NR, L>(
+    csr_rows<T, NR, C>(
         n, rp, ci, val,
-        [&](int, int c, T v, T(&a)[NR]) {
+        [&](int, int c, T v, bool ok, T(&a)[NR]) {
 #pragma unroll
             for (int k = 0; k < NR; ++k)
-                if ((mask_res >> k) & 1) a[k] += v * xsrc.p[k][c];
+                if ((mask_res >> k) & 1) {
+                    const T t = v * xsrc.p[k][c];
+                    a[k] += ok ? t : T(0);
+                }
         },
         [&](int row, int lane, T(&a)[NR]) {
             if (lane != 0) return;
@@ -424,7 +613,7 @@ __device__ __forceinline__ void bi_pause(BiGlobal *g, int phase, int it) {
 
 // part 1: tests on the incoming residual, p = r + beta (p - omega v),
 // v = As p, partial r_hat.v
-template <typename T, int NR, int L>
+template <typename T, int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ rp,
                                                  const int *__restrict__ ci,
                                                  const T *__restrict__ val, C3<T> r, C3<T> rhat,
@@ -475,13 +664,15 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ 
     double acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    csr_rows<T, NR, L>(
+    csr_rows<T, NR, C>(
         n, rp, ci, val,
-        [&](int, int c, T vv, T(&a)[NR]) {
+        [&](int, int c, T vv, bool ok, T(&a)[NR]) {
 #pragma unroll
             for (int k = 0; k < NR; ++k)
-                if ((active >> k) & 1)
-                    a[k] += vv * (r.p[k][c] + beta[k] * (pold.p[k][c] - om[k] * vold.p[k][c]));
+                if ((active >> k) & 1) {
+                    const T t = vv * (r.p[k][c] + beta[k] * (pold.p[k][c] - om[k] * vold.p[k][c]));
+                    a[k] += ok ? t : T(0);
+                }
         },
         [&](int row, int lane, T(&a)[NR]) {
             if (lane != 0) return;
@@ -499,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ 
 
 // part 2: alpha = rho / (r_hat.v), s = r - alpha v, t = As s,
 // partials (t.s, t.t, sum wgt s^2)
-template <typename T, int NR, int L>
+template <typename T, int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_bi_2(int n, const int *__restrict__ rp,
                                                  const int *__restrict__ ci,
                                                  const T *__restrict__ val,
@@ -543,12 +734,15 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, const int *__restrict__ 
     double acc[3 * NR];
 #pragma unroll
     for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
-    csr_rows<T, NR, L>(
+    csr_rows<T, NR, C>(
         n, rp, ci, val,
-        [&](int, int c, T w, T(&a)[NR]) {
+        [&](int, int c, T w, bool ok, T(&a)[NR]) {
 #pragma unroll
             for (int k = 0; k < NR; ++k)
-                if ((active >> k) & 1) a[k] += w * (r.p[k][c] - al[k] * vv.p[k][c]);
+                if ((active >> k) & 1) {
+                    const T t = w * (r.p[k][c] - al[k] * vv.p[k][c]);
+                    a[k] += ok ? t : T(0);
+                }
         },
         [&](int row, int lane, T(&a)[NR]) {
             if (lane != 0) return;
@@ -666,12 +860,12 @@ void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
     w.glob = c.take<BiGlobal>(1);
 }
 
-template <typename T, int NR, int L>
+template <typename T, int NR, class C>
 static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *const *b, T *const *x, double rtol, int maxit, int check_every,
                   bool time_kernel, BiWork<T> &w, SolveOut *out) {
-    const int g1 = grid_for(n, kBlock / L);
-    const int g2 = grid_for(n, kBlock);
+    const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
+    const int g2 = grid_for(n, kBlock, partial_cap());
     const int gv = grid_for(n, kBlock, 4096);
     C3<T> cb{}, cx{}, cr{}, crh{}, cs{}, ct{}, cp[2]{}, cvv[2]{};
     V3<T> vx{}, vr{}, vrh{}, vs{}, vt{}, vp[2]{}, vvv[2]{}, vxs{};
@@ -719,7 +913,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         return OASIS_OK;
     };
     auto resid = [&](int mask_res, int mask_rhat, C3<T> src) -> int {
-        hipLaunchKernelGGL((k_bi_resid<T, NR, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+        hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
                            cb, src, vr, vrh, mask_res, mask_rhat, w.part3);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
@@ -777,7 +971,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         while (launched < chunk && it < maxit) {
             if (phase == 1) {
                 if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
-                hipLaunchKernelGGL((k_bi_1<T, NR, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                hipLaunchKernelGGL((k_bi_1<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
                                    cr, crh, cp[(it + 1) & 1], cvv[(it + 1) & 1], vp[it & 1],
                                    vvv[it & 1], w.part3, part3_count, w.st, w.glob, it, w.part1);
                 OASIS_TRY_LAUNCH();
@@ -789,7 +983,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                     out[0].kernel_ms += ms;
                     out[0].kernel_count += 1;
                 }
-                hipLaunchKernelGGL((k_bi_2<T, NR, L>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                hipLaunchKernelGGL((k_bi_2<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
                                    wgt, cr, cvv[it & 1], vs, vt, w.part1, g1, w.st, w.glob, it,
                                    w.part2);
                 OASIS_TRY_LAUNCH();
@@ -908,24 +1102,14 @@ template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
                    int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out) {
-#define OASIS_BI(NR, L)                                                                       \
-    return bi_run<T, NR, L>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, \
-                            w, out)
-    const int L = spmv_lanes();
-    if (nrhs == 1) {
-        if (L == 4) OASIS_BI(1, 4);
-        if (L == 16) OASIS_BI(1, 16);
-        OASIS_BI(1, 8);
-    } else if (nrhs == 2) {
-        if (L == 4) OASIS_BI(2, 4);
-        if (L == 16) OASIS_BI(2, 16);
-        OASIS_BI(2, 8);
-    } else {
-        if (L == 4) OASIS_BI(3, 4);
-        if (L == 16) OASIS_BI(3, 16);
-        OASIS_BI(3, 8);
-    }
-#undef OASIS_BI
+    return with_cfg([&](auto c) {
+        using C = decltype(c);
+        if (nrhs == 1)
+            return bi_run<T, 1, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out);
+        if (nrhs == 2)
+            return bi_run<T, 2, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out);
+        return bi_run<T, 3, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out);
+    });
 }
 
 template void carve_cg<double>(Carver &, int, CGWork<double> &);

@@ -12,7 +12,9 @@ struct CGState {
     double tol2;       // (rtol ||b||)^2 in the weighted norm
     double wbb;        // weighted ||b||^2
     double wrr;        // weighted ||r||^2 seen by the last finalize
-    int flag;          // 0 running, 1 converged candidate, 2 breakdown, 3 non-finite
+    double upd2;       // mixed precision: replace the residual once wrr <= upd2
+    int flag;          // 0 running, 1 converged candidate, 2 breakdown, 3 non-finite,
+                       // 4 residual replacement due (mixed precision)
     int it_done;       // iteration index at which flag was raised
 };
 
@@ -57,8 +59,6 @@ struct SolveOut {
     int kernel_count = 0;
 };
 
-// Lanes per CSR row used by the sparse kernels (4, 8 or 16).
-int spmv_lanes();
 
 template <typename T>
 void carve_cg(Carver &c, int n, CGWork<T> &w);
@@ -77,6 +77,18 @@ template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
                    int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out);
+
+// Mixed-precision CG with reliable updates on the scaled system: FP32
+// matrix/vectors inside the iteration, FP64 solution accumulator, and an
+// FP64 residual b - Ms x that replaces the FP32 one whenever the latter has
+// dropped by `delta` since the last replacement (the search direction is
+// kept).  vnull (nullable): unit-norm null vector of Ms, projected out of
+// the FP32 residual updates.
+int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
+                   const float *val32, const double *wgt, const float *wgt32, const float *vnull,
+                   const double *b, double *x, double rtol, double delta, int maxit,
+                   int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
+                   SolveOut &out);
 
 // Weighted residual of x for the scaled system: r = b - Ms x, returns
 // (sum wgt r^2, sum wgt b^2) on the host.  Uses w's buffers.

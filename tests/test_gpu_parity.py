@@ -232,3 +232,61 @@ def test_ipcs_ten_steps_channel(oa):
         st = ipcs.step(S, st, prob.bc_values, rtol_u=1e-13, rtol_p=1e-13).state
     assert rel(Un.cpu().numpy(), st.U1) <= 1e-10
     assert rel(p.cpu().numpy(), st.p) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 iterations, FP64 refinement.  The answer is any x
+# whose FP64 true residual meets rtol; the oracle recomputes that residual
+# from the GPU output and compares with its own FP64 solve.
+
+@pytest.mark.parametrize("prob", [synth.channel_flow("small", seed=3), synth.channel_flow((33, 33, 25), seed=1)],
+                         ids=lambda p: p.name)
+def test_pcg_mixed_meets_fp64_tolerance(oa, prob):
+    say("pcg mixed", prob.name)
+    S, st, A, b = _tent_problem(prob)
+    dm, pat, _ = device_mesh(prob.mesh)
+    Kp = p1.on_pattern(S.K, csr_host(pat))
+    rng = np.random.default_rng(8)
+    bphi = rng.normal(size=prob.mesh.n_dof)
+    bphi -= bphi.mean()
+    ref = krylov.pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8)
+    x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+    out = oa.pcg(pat.with_values(T(Kp)), T(bphi), x, rtol=1e-8, precision=oa.F32, nullspace_const=True)
+    xg = x.cpu().numpy()
+    true = np.linalg.norm(bphi - S.K @ xg) / np.linalg.norm(bphi)
+    assert out["rc"] == 0 and true <= 1.0001e-8, (out, true)
+    assert out["outer_iters"] >= 1
+    assert out["iters"] <= 1.5 * ref.iters + 20, (out["iters"], ref.iters)
+    xr = ref.x - ref.x.mean()
+    assert rel(xg - xg.mean(), xr) < 1e-5
+
+
+def test_bicgstab_mixed_meets_fp64_tolerance(oa):
+    prob = synth.channel_flow("small", seed=5)
+    say("bicgstab mixed", prob.name)
+    S, st, A, b = _tent_problem(prob)
+    dm, pat, _ = device_mesh(prob.mesh)
+    Ap = p1.on_pattern(A, csr_host(pat))
+    x = T(st.U1)
+    out = oa.bicgstab(pat.with_values(T(Ap)), T(b), x, rtol=1e-10, precision=oa.F32)
+    for k in range(3):
+        xg = x[k].cpu().numpy()
+        true = np.linalg.norm(b[k] - A @ xg) / np.linalg.norm(b[k])
+        assert out[k]["status"] == 0 and true <= 1.0001e-10, (k, out[k], true)
+
+
+def test_ipcs_mixed_steps_close_to_fp64(oa):
+    prob = synth.channel_flow((33, 33, 25), seed=2)
+    say("ipcs mixed", prob.name)
+    h, Un, p, phi, UI, bphi, stats = _run_gpu_steps(oa, prob, 3, 1e-8, precision=1)
+    assert all(s["status"] == 0 for s in stats)
+    S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
+    st = ipcs.initial_state(prob)
+    for _ in range(3):
+        st = ipcs.step(S, st, prob.bc_values, rtol_u=1e-12, rtol_p=1e-12).state
+    assert rel(Un.cpu().numpy(), st.U1) < 1e-6
+    assert rel(p.cpu().numpy(), st.p) < 1e-5
+    # the last pressure solve met the FP64 tolerance on the oracle's matrix
+    ph = phi.cpu().numpy()
+    bp = bphi.cpu().numpy()
+    assert np.linalg.norm(bp - S.K @ ph) <= 1.0001e-8 * np.linalg.norm(bp)
