@@ -55,13 +55,13 @@ def step_bytes_model(n, nnz, iters_u, iters_p, dim=3):
     return asm + rhs + bicg + pcg + div_upd
 
 
-def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag):
+def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=0):
     import numpy as np
     dev = dm.coords.device
     m = pr.mesh
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, torch.as_tensor(m.bc_dofs, device=dev), rtol_u=pr.rtol_u,
-                rtol_p=pr.rtol_p, precision=precision, inner_rtol=1e-4)
+                rtol_p=pr.rtol_p, precision=precision, inner_rtol=1e-4, assembly=assembly)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--variants", default="fp64,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--assembly", type=int, default=0, help="0 rows (default), 1 colours")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path here is single-GPU (no collectives); "
@@ -180,7 +181,7 @@ def main():
     handles = {}
     for v in args.variants.split(","):
         prec = oa.F64 if v == "fp64" else oa.F32
-        h, res, _ = run_variant(oa, torch, pr, dm, pat, prec, args.steps, args.warmup, v)
+        h, res, _ = run_variant(oa, torch, pr, dm, pat, prec, args.steps, args.warmup, v, args.assembly)
         results[v] = res
         handles[v] = h
     head = max(results, key=lambda k: results[k]["steps_per_s"])

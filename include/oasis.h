@@ -226,8 +226,16 @@ typedef struct {
     double rtol_u, rtol_p;    /* Krylov relative tolerances (true residual) */
     int32_t maxit;
     int32_t precision;        /* OASIS_F64 or OASIS_F32 (FP32 inner Krylov + FP64 refinement) */
-    double inner_rtol;        /* F32 mode inner tolerance */
+    double inner_rtol;        /* F32 mode inner tolerance of the BiCGStab refinement (0 = 1e-4) */
+    int32_t assembly;         /* per-step convection assembly: OASIS_ASSEMBLE_ROWS (each row
+                                 gathers its cells' contributions; fused with the right-hand
+                                 side and scaling) or OASIS_ASSEMBLE_COLORS (colour-by-colour
+                                 element scatter as in oasis_assemble_p1); ROWS needs rows of
+                                 at most 32 entries and falls back to COLORS otherwise */
 } oasis_ipcs_params;
+
+#define OASIS_ASSEMBLE_ROWS 0
+#define OASIS_ASSEMBLE_COLORS 1
 
 typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
 

@@ -110,7 +110,8 @@ static int fill_i(hipStream_t s, long long n, int *x, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// dof -> incident cells
+// dof -> incident cells, stored as codes cell * (dim+1) + local vertex,
+// each list ascending
 
 __global__ __launch_bounds__(kBlock) void k_inc_count(int ncell, int nv, int nvert, int ndof,
                                                       const int *__restrict__ cells,
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_fill(int ncell, int nv, const in
         for (int a = 0; a < nv; ++a) {
             const int d = v2d[cells[c * nv + a]];
             const int slot = atomicAdd(&fillc[d], 1);
-            inc[ptr[d] + slot] = (int)c;
+            inc[ptr[d] + slot] = (int)(c * nv + a);   // cell and local vertex
         }
     }
 }
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_row_pattern(int ndof, int nv, const 
         while (true) {
             int best = 0x7fffffff;
             for (int i = s; i < e; ++i) {
-                const int c = inc[i];
+                const int c = inc[i] / nv;
                 for (int a = 0; a < nv; ++a) {
                     const int q = v2d[cells[(long long)c * nv + a]];
                     if (q > prev && q < best) best = q;
@@ -254,6 +255,20 @@ static int build_incidence(hipStream_t s, const oasis_mesh *m, GraphWs &g) {
     return err ? OASIS_EUNSUPPORTED : OASIS_OK;
 }
 
+// Incidence lists for an external user (the IPCS handle): iptr [n_dof+1],
+// inc [n_cell*(dim+1)], scratch cnt [max(n_dof, n_cell)+1], tmp (scan).
+int incidence_codes(hipStream_t s, const oasis_mesh *m, int *iptr, int *inc, int *cnt, int *tmp, int *flag) {
+    GraphWs g{};
+    g.iptr = iptr;
+    g.inc = inc;
+    g.cnt = cnt;
+    g.tmp = tmp;
+    g.flag = flag;
+    return build_incidence(s, m, g);
+}
+
+size_t incidence_tmp_ints(int n) { return scan_ws_ints(n) + 16; }
+
 // ---------------------------------------------------------------------------
 // greedy first-fit colouring in decreasing priority (Jones-Plassmann rounds)
 
@@ -274,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_color_round(int ncell, int nv, const
         for (int a = 0; a < nv && ready; ++a) {
             const int d = v2d[cells[c * nv + a]];
             for (int i = iptr[d]; i < iptr[d + 1]; ++i) {
-                const int o = inc[i];
+                const int o = inc[i] / nv;
                 if (o == c || pri[o] < my) continue;
                 // a higher-priority neighbour counts only once coloured in an earlier round
                 const int r = __atomic_load_n(&round_of[o], __ATOMIC_RELAXED);

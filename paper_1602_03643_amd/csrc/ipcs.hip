@@ -16,6 +16,7 @@
 //      supplied guess).
 //   5  phi and p^{n-1/2} = p* + phi shifted to zero mean.
 //   6  U^{k,n} = U^{k,I} - dt (dP^k phi) / M_L, Dirichlet values restored.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -23,9 +24,13 @@
 
 #include "assemble.hpp"
 #include "krylov.hpp"
+#include "p1.hpp"
 #include "spmv.hpp"
 
 namespace oasis {
+
+int incidence_codes(hipStream_t s, const oasis_mesh *m, int *iptr, int *inc, int *cnt, int *tmp, int *flag);
+size_t incidence_tmp_ints(int n);
 
 // ---------------------------------------------------------------------------
 // matrix preparation kernels
@@ -220,6 +225,124 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
             wA[i] = dd * dd;
             if (wA32) wA32[i] = static_cast<float>(dd * dd);
         }
+    }
+}
+
+// Row-gather form of step 1+2: every row assembles its own entries of
+// A = B + C(u_bar)/2 from the cells around its dof (the convection part of
+// Alg. 2's coefficient matrix), then forms the right-hand side, the
+// Dirichlet row and the left Jacobi scaling in the same pass.  One thread
+// owns one row; the row's columns and values live in MAXC registers and an
+// element contribution (column dof c, value v) is added to the slot whose
+// column equals c (a compile-time unrolled match).  The incident cells are
+// visited in ascending order, so the sums are deterministic; no other
+// thread writes the row, so no atomics and no colouring are needed.
+template <int D, int MAXC>
+__global__ __launch_bounds__(kBlock) void k_asm_rows(
+    int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ B,
+    const double *__restrict__ M, P3 dP, const int *__restrict__ iptr, const int *__restrict__ inc,
+    const int *__restrict__ cells, const int *__restrict__ v2d, const double *__restrict__ X, P3 U1, P3 U2,
+    const double *__restrict__ p, const double *__restrict__ ML, const int *__restrict__ bc_index,
+    const double *__restrict__ g, int nbc, double f0, double f1, double f2, double two_over_dt,
+    double *__restrict__ A, float *__restrict__ A32, double *__restrict__ b0, double *__restrict__ b1,
+    double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1, double *__restrict__ x2,
+    double *__restrict__ dA, double *__restrict__ wA, float *__restrict__ wA32) {
+    constexpr int NV = D + 1;
+    constexpr double mfac = 0.5 / ((D + 1) * (D + 2));   // C/2 and the mass-moment factor
+    double *bo[3] = {b0, b1, b2};
+    double *xo[3] = {x0, x1, x2};
+    const double f[3] = {f0, f1, f2};
+    for (long long row = blockIdx.x * (long long)blockDim.x + threadIdx.x; row < n;
+         row += (long long)gridDim.x * blockDim.x) {
+        const int i = static_cast<int>(row);
+        const int s = rp[i], len = rp[i + 1] - s;
+        int col[MAXC];
+        double a[MAXC];
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            col[q] = q < len ? ci[s + q] : -1;
+            a[q] = q < len ? B[s + q] : 0.0;
+        }
+        for (int t = iptr[i]; t < iptr[i + 1]; ++t) {
+            const int code = inc[t];
+            const int cell = code / NV, la = code - cell * NV;
+            double x[NV][D], ub[NV][D];
+            int dd[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const int v = cells[(long long)cell * NV + k];
+                dd[k] = v2d[v];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    x[k][c] = X[(long long)v * D + c];
+                    ub[k][c] = 1.5 * U1.p[c][dd[k]] - 0.5 * U2.p[c][dd[k]];
+                }
+            }
+            Elem<D> e;
+            p1_element<D>(x, e);
+            double w[D];   // S + u_bar at the row's local vertex
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double S = 0.0;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) S += ub[k][c];
+                double ua = ub[0][c];
+#pragma unroll
+                for (int k = 1; k < NV; ++k) ua = (la == k) ? ub[k][c] : ua;
+                w[c] = S + ua;
+            }
+            const double fac = e.vol * mfac;
+#pragma unroll
+            for (int jl = 0; jl < NV; ++jl) {
+                double gw = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) gw += e.g[jl][c] * w[c];
+                const double v = fac * gw;
+                const int target = dd[jl];
+#pragma unroll
+                for (int q = 0; q < MAXC; ++q) a[q] += (col[q] == target) ? v : 0.0;
+            }
+        }
+        // right-hand side (2M/dt - A) U^{n-1} - dP^k p*, Dirichlet row, scaling
+        double acc[D], accp[D], diag = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = accp[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            if (q < len) {
+                const int c = col[q];
+                const double coef = two_over_dt * M[s + q] - a[q];
+                const double pc = p[c];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    acc[k] += coef * U1.p[k][c];
+                    accp[k] += dP.p[k][s + q] * pc;
+                }
+                if (c == i) diag = a[q];
+            }
+        }
+        const int qb = bc_index[i];
+        const double dd0 = qb >= 0 ? 1.0 : diag;
+        const double inv = 1.0 / dd0;
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+            if (q < len) {
+                double v = a[q];
+                if (qb >= 0) v = (col[q] == i) ? 1.0 : 0.0;
+                v *= inv;
+                A[s + q] = v;
+                if (A32) A32[s + q] = static_cast<float>(v);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double bk = qb >= 0 ? g[k * nbc + qb] : f[k] * ML[i] + acc[k] - accp[k];
+            bo[k][i] = bk * inv;
+            xo[k][i] = U1.p[k][i];
+        }
+        dA[i] = dd0;
+        wA[i] = dd0 * dd0;
+        if (wA32) wA32[i] = static_cast<float>(dd0 * dd0);
     }
 }
 
@@ -625,6 +748,8 @@ struct oasis_ipcs {
     float *wK32 = nullptr, *wA32 = nullptr, *vnull32 = nullptr, *xlo = nullptr;
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
+    int *iptr = nullptr, *inc = nullptr, *icnt = nullptr, *itmp = nullptr;
+    int assembly = OASIS_ASSEMBLE_ROWS, maxc = 16;
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
     double *bphi = nullptr, *bs = nullptr, *xs = nullptr, *xg = nullptr, *red = nullptr;
     CGWork<double> cg;
@@ -635,7 +760,7 @@ struct oasis_ipcs {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
-static void carve_ipcs(Carver &c, int dim, int n, int nnz, bool mixed, oasis_ipcs &h) {
+static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, oasis_ipcs &h) {
     h.M = c.take<double>(nnz);
     h.Ks = c.take<double>(nnz);
     for (int k = 0; k < dim; ++k) h.dP[k] = c.take<double>(nnz);
@@ -657,7 +782,7 @@ static void carve_ipcs(Carver &c, int dim, int n, int nnz, bool mixed, oasis_ipc
     h.wA = c.take<double>(n);
     h.dtmp = c.take<double>(n);
     h.bc_index = c.take<int>(n);
-    h.flag = c.take<int>(16);
+    h.flag = c.take<int>(32);
     for (int k = 0; k < dim; ++k) {
         h.bt[k] = c.take<double>(n);
         h.ui[k] = c.take<double>(n);
@@ -667,6 +792,11 @@ static void carve_ipcs(Carver &c, int dim, int n, int nnz, bool mixed, oasis_ipc
     h.xs = c.take<double>(n);
     h.xg = c.take<double>(n);
     h.red = c.take<double>(2 * kMaxPartials);
+    const int nmax = std::max(n, ncell);
+    h.iptr = c.take<int>((size_t)n + 1);
+    h.inc = c.take<int>((size_t)ncell * (dim + 1));
+    h.icnt = c.take<int>((size_t)nmax + 1);
+    h.itmp = c.take<int>(incidence_tmp_ints(nmax));
     carve_cg<double>(c, n, h.cg);
     carve_bi<double>(c, n, dim, h.bi);
     if (mixed) {
@@ -689,7 +819,7 @@ extern "C" int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz, co
     OASIS_TRY(check_params(par));
     Carver c(nullptr, 0);
     oasis_ipcs h;
-    carve_ipcs(c, mesh->dim, mesh->n_dof, nnz, par->precision == OASIS_F32, h);
+    carve_ipcs(c, mesh->dim, mesh->n_dof, mesh->n_cell, nnz, par->precision == OASIS_F32, h);
     *bytes = c.bytes();
     return OASIS_OK;
 }
@@ -718,7 +848,7 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     h->par = *par;
     h->mixed = par->precision == OASIS_F32;
     Carver c(ws, ws_bytes);
-    carve_ipcs(c, h->dim, h->n, nnz, h->mixed, *h);
+    carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, *h);
     auto fail = [&](int rc) {
         delete h;
         return rc;
@@ -758,6 +888,26 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
                        1.0 / par->dt, h->B, 0.5 * par->nu);
     hipLaunchKernelGGL(k_row_sums, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->M, h->ML);
     if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
+    // row-gather assembly: dof -> cell lists and the longest row
+    h->assembly = par->assembly == OASIS_ASSEMBLE_COLORS ? OASIS_ASSEMBLE_COLORS : OASIS_ASSEMBLE_ROWS;
+    if (h->assembly == OASIS_ASSEMBLE_ROWS) {
+        std::vector<int> rph(n + 1);
+        if (hipMemcpyAsync(rph.data(), row_ptr, (n + 1) * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(OASIS_EHIP);
+        int maxrow = 0;
+        for (int i = 0; i < n; ++i) maxrow = std::max(maxrow, rph[i + 1] - rph[i]);
+        if (maxrow <= 16)
+            h->maxc = 16;
+        else if (maxrow <= 32)
+            h->maxc = 32;
+        else
+            h->assembly = OASIS_ASSEMBLE_COLORS;
+        if (h->assembly == OASIS_ASSEMBLE_ROWS) {
+            const int rc2 = incidence_codes(s, &h->mesh, h->iptr, h->inc, h->icnt, h->itmp, h->flag + 3);
+            if (rc2 != OASIS_OK) return fail(rc2);
+        }
+    }
     // the scaled pressure matrix has null vector s = sqrt(diag K) (K 1 = 0)
     if (h->mixed && unit_vector_f32(s, n, h->sK, h->red, h->vnull32) != OASIS_OK) return fail(OASIS_EHIP);
     int fl[3] = {0, 0, 0};
@@ -814,6 +964,23 @@ static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_s
                        x[1], D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
 }
 
+template <int D, int MAXC>
+static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g, double *const *x) {
+    const int n = h->n;
+    P3 dP{}, U1{}, U2{};
+    for (int k = 0; k < D; ++k) {
+        dP.p[k] = h->dP[k];
+        U1.p[k] = st->U1[k];
+        U2.p[k] = st->U2[k];
+    }
+    const int grid = grid_for(n, kBlock, 1 << 20);
+    hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->B, h->M, dP,
+                       h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, U1, U2, st->p, h->ML,
+                       h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1], h->par.f[2], 2.0 / h->par.dt,
+                       h->A, h->A32, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0], x[1],
+                       D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
+}
+
 template <int D, int L>
 static void launch_div(hipStream_t s, oasis_ipcs *h, double *const *x, int *gout) {
     P3 dP{}, UI{};
@@ -853,22 +1020,36 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     oasis_step_stats &S = stats ? *stats : loc;
     S = oasis_step_stats{};
     OASIS_TRY_HIP(hipEventRecord(h->ev[0], s));
-    // 1. A = B + C(u_bar)/2
-    OASIS_TRY(scale_copy(s, h->nnz, h->A, h->B, 1.0));
     P3 U1{}, U2{};
     for (int k = 0; k < D; ++k) {
         U1.p[k] = st->U1[k];
         U2.p[k] = st->U2[k];
     }
-    OASIS_TRY(assemble_colored(s, &h->mesh, h->rp, h->ci, h->A, OASIS_FORM_CONV, 0.5, U1, U2, 1.5, -0.5, nullptr));
-    // 2. right-hand sides, Dirichlet rows, scaling; x0 = U^{n-1}
     double *x[3];
     for (int k = 0; k < D; ++k) x[k] = st->UI[k] ? st->UI[k] : h->ui[k];
-    if (D == 3)
-        launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
-    else
-        launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
-    OASIS_TRY_LAUNCH();
+    if (h->assembly == OASIS_ASSEMBLE_ROWS) {
+        // 1+2. rows gather A = B + C(u_bar)/2, right-hand sides, Dirichlet rows, scaling
+        if (D == 3 && h->maxc == 16)
+            launch_asm_rows<3, 16>(s, h, st, bc_values, x);
+        else if (D == 3)
+            launch_asm_rows<3, 32>(s, h, st, bc_values, x);
+        else if (h->maxc == 16)
+            launch_asm_rows<2, 16>(s, h, st, bc_values, x);
+        else
+            launch_asm_rows<2, 32>(s, h, st, bc_values, x);
+        OASIS_TRY_LAUNCH();
+    } else {
+        // 1. A = B + C(u_bar)/2, colour by colour
+        OASIS_TRY(scale_copy(s, h->nnz, h->A, h->B, 1.0));
+        OASIS_TRY(assemble_colored(s, &h->mesh, h->rp, h->ci, h->A, OASIS_FORM_CONV, 0.5, U1, U2, 1.5, -0.5,
+                                   nullptr));
+        // 2. right-hand sides, Dirichlet rows, scaling; x0 = U^{n-1}
+        if (D == 3)
+            launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
+        else
+            launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
+        OASIS_TRY_LAUNCH();
+    }
     OASIS_TRY_HIP(hipEventRecord(h->ev[1], s));
     // 3. tentative velocity
     oasis_krylov_opts o{};

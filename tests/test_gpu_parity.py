@@ -186,11 +186,11 @@ def test_krylov_failure_paths(oa):
         oa.pcg(pat.with_values(torch.zeros_like(Kp)), T(bphi), torch.zeros_like(Kp[: prob.mesh.n_dof]))
 
 
-def _run_gpu_steps(oa, prob, steps, rtol, precision=0, guess=None):
+def _run_gpu_steps(oa, prob, steps, rtol, precision=0, guess=None, assembly=0):
     m = prob.mesh
     dm, pat, _ = device_mesh(m)
     h = oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32), rtol_u=rtol, rtol_p=rtol,
-                precision=precision)
+                precision=precision, assembly=assembly)
     U = [T(prob.U2), T(prob.U1)]
     p, phi = T(prob.p), T(prob.phi_prev)
     UI = torch.empty_like(U[0])
@@ -207,11 +207,12 @@ def _run_gpu_steps(oa, prob, steps, rtol, precision=0, guess=None):
     return h, U[1], p, phi, UI, bphi, stats
 
 
+@pytest.mark.parametrize("assembly", [0, 1], ids=["rows", "colours"])
 @pytest.mark.parametrize("prob", [synth.taylor_green(16), synth.channel_flow("tiny", seed=2),
                                   synth.channel_flow("small", seed=4, displace_seed=9)], ids=lambda p: p.name)
-def test_ipcs_step_matches_oracle(oa, prob):
-    say("ipcs step", prob.name)
-    h, Un, p, phi, UI, bphi, stats = _run_gpu_steps(oa, prob, 1, 1e-13)
+def test_ipcs_step_matches_oracle(oa, prob, assembly):
+    say("ipcs step", prob.name, "assembly", assembly)
+    h, Un, p, phi, UI, bphi, stats = _run_gpu_steps(oa, prob, 1, 1e-13, assembly=assembly)
     S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
     ref = ipcs.step(S, ipcs.initial_state(prob), prob.bc_values, rtol_u=1e-13, rtol_p=1e-13)
     assert rel(UI.cpu().numpy(), ref.UI) <= 1e-10
