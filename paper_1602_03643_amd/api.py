@@ -332,3 +332,42 @@ def _from_ptr(ptr, count, ws):
     if off < 0 or off % 8 or off + 8 * count > ws.numel():
         raise ValueError("pointer outside the workspace")
     return ws[off: off + 8 * count].view(torch.float64).clone()
+
+
+# ---------------------------------------------------------------------------
+# learned warm start
+
+class MPNN:
+    """Workspace holder for oasis_mpnn_forward / backward / adam on one graph.
+
+    Ks, s: the scaled pressure matrix (unit diagonal) and sqrt(diag K), as an
+    IPCS handle holds them (IPCS.matrix(FORM_STIFF))."""
+
+    NPARAM = L.MPNN_NPARAM
+
+    def __init__(self, Ks: DeviceCSR, s: torch.Tensor, coords: torch.Tensor | None = None):
+        lib = _lib()
+        self.Ks, self.s = Ks, s
+        self.coords = coords
+        self.dim = 0 if coords is None else int(coords.shape[1])
+        nb = C.c_size_t()
+        L.check(lib.oasis_mpnn_workspace_size(Ks.n, C.byref(nb)), "oasis_mpnn_workspace_size")
+        self.ws = _workspace(nb.value, s.device)
+
+    def forward(self, params, b_phi, phi_prev, guess=None, delta=None, stream=None):
+        L.check(_lib().oasis_mpnn_forward(_stream(stream), C.byref(self.Ks.c()), _p(self.s), self.dim,
+                                          _p(self.coords), _p(b_phi), _p(phi_prev), _p(params), _p(guess),
+                                          _p(delta), _p(self.ws), self.ws.numel()), "oasis_mpnn_forward")
+        return guess, delta
+
+    def backward(self, params, phi, phi_prev, grad, stream=None):
+        loss = C.c_double()
+        L.check(_lib().oasis_mpnn_backward(_stream(stream), C.byref(self.Ks.c()), _p(self.s), _p(phi),
+                                           _p(phi_prev), _p(params), _p(grad), C.byref(loss), _p(self.ws),
+                                           self.ws.numel()), "oasis_mpnn_backward")
+        return loss.value
+
+    @staticmethod
+    def adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        L.check(_lib().oasis_mpnn_adam(_stream(stream), _p(params), _p(grad), _p(m), _p(v), int(t), float(lr),
+                                       float(beta1), float(beta2), float(eps)), "oasis_mpnn_adam")
