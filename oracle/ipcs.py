@@ -21,8 +21,11 @@ Readings (where the paper is silent or inconsistent):
   All velocity components share the Dirichlet dof set, so one A serves all.
 * No pressure boundary condition: b_phi is projected onto 1-perp before the
   solve, phi and p are shifted to zero arithmetic mean of their dof values.
-* Initial guesses: U^{k,n-1} for the tentative velocity, phi_prev for the
-  pressure correction.
+* Initial guesses: U^{k,n-1} for the tentative velocity; for the pressure,
+  the previous pressure p* (phi_0 = 0), as in the pressure-solve routine of
+  the naive solver (Sec. 4, figure of the solver routines: the old pressure
+  is saved, the system is solved for p starting from its current value, and
+  phi is the difference).  A caller-supplied guess replaces it.
 """
 from __future__ import annotations
 
@@ -137,7 +140,7 @@ def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
         res_u.append(r.rel_res)
         status = max(status, r.status)
     b_phi = pressure_rhs(S, UI)
-    x0 = st.phi_prev if phi_guess is None else phi_guess
+    x0 = np.zeros_like(b_phi) if phi_guess is None else phi_guess
     rp = krylov.pcg(S.K, b_phi, x0, rtol=rtol_p, maxit=maxit)
     status = max(status, rp.status)
     phi = rp.x - rp.x.mean()
