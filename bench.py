@@ -9,10 +9,13 @@ Synthetic initial field: laminar parabola + seeded U(-0.05, 0.05) noise,
 dt = 0.01, Krylov relative tolerance 1e-8 (true residual).
 
 Variants timed (same inputs, separate handles):
-  fp64   plain FP64 BiCGStab + Jacobi-PCG from the previous phi
-  mixed  FP32 inner Krylov with FP64 dot products and FP64 refinement
-The headline `value` is the fastest variant that reaches the same FP64
-residual tolerance (the mixed one when it wins).
+  fp64     plain FP64 BiCGStab + Jacobi-PCG (pressure from p*, phi_0 = 0)
+  mixed    FP32 inner Krylov with FP64 dot products and FP64 refinement
+  learned  mixed + the trained message-passing warm start attached to the
+           pressure solve (guarded: used only if it beats phi_0 = 0)
+All reach the same FP64 true-residual tolerance.  The headline `value` is
+the learned+FP32 variant (the configuration the metric names) when it is
+timed, else the fastest one; `speedup_vs_fp64` compares it with plain FP64.
 
 One JSON line is printed; see the design doc for the fields.
 """
@@ -30,6 +33,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "IPCS steps/s + SpMV HBM GB/s, 1.6M-node P1 mesh; learned+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+# sources of the CG direction + product kernel; a PMC summary whose recorded
+# hash differs from these files was taken on another kernel and is not used
+CG_KERNEL_SOURCES = ["paper_1602_03643_amd/csrc/krylov.hip", "paper_1602_03643_amd/csrc/krylov.hpp",
+                     "paper_1602_03643_amd/csrc/spmv.hpp", "paper_1602_03643_amd/csrc/internal.hpp"]
+PMC_SUMMARY = "profiles/k_cg_p1_float_channel129_pmc.txt"
 
 
 def log(*a):
@@ -55,16 +63,49 @@ def step_bytes_model(n, nnz, iters_u, iters_p, dim=3):
     return asm + rhs + bicg + pcg + div_upd
 
 
-def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=0):
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a copy of known size), or None when there is no summary for it or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("sources_sha256") != sources_sha256(CG_KERNEL_SOURCES):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=0, warm=None):
     import numpy as np
     dev = dm.coords.device
     m = pr.mesh
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, torch.as_tensor(m.bc_dofs, device=dev), rtol_u=pr.rtol_u,
                 rtol_p=pr.rtol_p, precision=precision, inner_rtol=1e-4, assembly=assembly)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    if warm is not None:
+        h.set_warmstart(torch.as_tensor(warm, device=dev), T(m.dof_coords))
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
-    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
     U = [T(pr.U2), T(pr.U1)]
     p, phi = T(pr.p), T(pr.phi_prev)
     bc = T(pr.bc_values(0.0))
@@ -79,8 +120,9 @@ def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=
 
     for i in range(warmup):
         st = one(i)
-        log("[%s] warmup step %d: iters_u %s iters_p %d outer %d/%d %.1f ms" %
-            (tag, i, st["iters_u"], st["iters_p"], st["outer_u"], st["outer_p"], st["ms_total"]))
+        log("[%s] warmup step %d: iters_u %s iters_p %d outer %d/%d guess %d %.1f ms" %
+            (tag, i, st["iters_u"], st["iters_p"], st["outer_u"], st["outer_p"], st["guess_used"],
+             st["ms_total"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -96,6 +138,7 @@ def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=
                outer_p=mean("outer_p"), outer_u=mean("outer_u"),
                ms_assemble=mean("ms_assemble"), ms_velocity=mean("ms_velocity"),
                ms_pressure=mean("ms_pressure"), ms_update=mean("ms_update"),
+               guess_used=mean("guess_used"),
                max_res_p=float(max(s["res_p"] for s in stats)),
                max_res_u=float(max(max(s["res_u"]) for s in stats)))
     log("[%s] %.2f steps/s (%.2f ms/step), iters_p %.1f, iters_u %s" %
@@ -150,7 +193,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", default="c129")
-    ap.add_argument("--variants", default="fp64,mixed")
+    ap.add_argument("--variants", default="fp64,mixed,learned")
+    ap.add_argument("--weights", default=None, help="warm-start weights (.npz); default: the packaged ones")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a known-size kernel for PMC calibration)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--assembly", type=int, default=0, help="0 rows (default), 1 colours")
@@ -166,6 +212,13 @@ def main():
     import synth
 
     dev = torch.device("cuda", 0)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
+        del src, dst
     t0 = time.perf_counter()
     pr = synth.channel_flow(args.size, seed=0)
     m = pr.mesh
@@ -181,10 +234,15 @@ def main():
     handles = {}
     for v in args.variants.split(","):
         prec = oa.F64 if v == "fp64" else oa.F32
-        h, res, _ = run_variant(oa, torch, pr, dm, pat, prec, args.steps, args.warmup, v, args.assembly)
+        warm = None
+        if v == "learned":
+            from paper_1602_03643_amd import warmstart
+            warm, wmeta = warmstart.load(args.weights or warmstart.DEFAULT_WEIGHTS)
+            log("warm start: %s, trained on %s" % (args.weights or warmstart.DEFAULT_WEIGHTS, wmeta.get("sizes")))
+        h, res, _ = run_variant(oa, torch, pr, dm, pat, prec, args.steps, args.warmup, v, args.assembly, warm)
         results[v] = res
         handles[v] = h
-    head = max(results, key=lambda k: results[k]["steps_per_s"])
+    head = "learned" if "learned" in results else max(results, key=lambda k: results[k]["steps_per_s"])
     hres = results[head]
     # dominant kernel: the CG direction + product kernel of the headline variant
     prec = oa.F64 if head == "fp64" else oa.F32
@@ -192,9 +250,10 @@ def main():
     avg_ms, cnt = time_cg_kernel(oa, torch, handles[head], pat, prec, args.kernel_iters)
     kb = cg_kernel_bytes(pat.n, pat.nnz, vbytes)
     achieved = kb / (avg_ms * 1e-3) / 1e9
+    kname = "k_cg_p1<%s>" % ("double" if vbytes == 8 else "float")
+    traffic = pmc_traffic(kname) if args.size == "c129" else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_cg_p1<%s>" % ("double" if vbytes == 8 else "float"),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
                 bytes_per_launch=kb, avg_launch_ms=avg_ms, launches_timed=cnt)
     avg64, _ = time_cg_kernel(oa, torch, handles[head], pat, oa.F64, args.kernel_iters)
     kb64 = cg_kernel_bytes(pat.n, pat.nnz, 8)
@@ -221,6 +280,8 @@ def main():
                    % (m.name.split("_")[1], m.n_dof, m.n_cell, pat.nnz),
                    "variant": head, "parallelism": "single GPU"},
         "variants": results,
+        "speedup_vs_fp64": (round(hres["steps_per_s"] / results["fp64"]["steps_per_s"], 3)
+                            if "fp64" in results else None),
         "roofline": roof,
         "cpu_baseline": cpu,
         "setup_s": {"graph": t_graph},

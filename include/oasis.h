@@ -243,7 +243,10 @@ typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
  *  U1[k]  U^{k,n-1}   (read)       U2[k]  U^{k,n-2} (read)
  *  Un[k]  U^{k,n}     (written; may not alias U1/U2)
  *  p      p* on entry, p^{n-1/2} (zero mean) on return
- *  phi    phi_prev on entry (initial guess), the new correction on return
+ *  phi    phi_prev on entry (read only by an attached warm start), the new
+ *         correction on return.  The plain pressure solve starts from the
+ *         previous pressure p* (phi_0 = 0), as the pressure-solve routine of
+ *         the naive solver (Sec. 4) does.
  *  UI[k], b_phi: optional (NULL) outputs of the tentative velocity and the
  *  projected pressure right-hand side. */
 typedef struct {
@@ -260,7 +263,7 @@ typedef struct {
     int32_t iters_u[3], iters_p;
     int32_t outer_u, outer_p;
     int32_t status;           /* worst Krylov status of the step */
-    int32_t guess_used;       /* 1 if phi_guess gave the smaller initial residual */
+    int32_t guess_used;       /* 1 if the guess had a smaller residual than phi_0 = 0 */
     double res_u[3], res_p;   /* final true relative residuals */
     double ms_assemble, ms_velocity, ms_pressure, ms_update, ms_total;  /* HIP-event phase times */
 } oasis_step_stats;
@@ -287,10 +290,22 @@ int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_p
  * lumped velocity update.  bc_values: device double [dim][n_bc] at t^n.
  * phi_guess (device, nullable): a candidate initial guess for the
  * pressure solve; it is used only if its initial residual is below that of
- * phi_prev.  stats: host (nullable).  Synchronises `stream`. */
+ * the plain start phi_0 = 0, i.e. below ||b_phi||.  stats: host (nullable).
+ * Synchronises `stream`. */
 int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
                     const double *bc_values, const double *phi_guess,
                     oasis_step_stats *stats);
+
+/* Attach (params != NULL) or detach (NULL) a learned warm start for the
+ * pressure-correction solve: every later oasis_ipcs_step without an explicit
+ * phi_guess runs the network (oasis_mpnn_forward) on the step's projected
+ * right-hand side, phi_prev and the dof coordinates, and starts CG from the
+ * prediction only if its initial residual is below ||b_phi|| (that of the
+ * plain start phi_0 = 0); the solve still stops at the same rtol.  params: device float
+ * [OASIS_MPNN_NPARAM]; coords: device double [n_dof][dim]; ws: at least
+ * oasis_mpnn_workspace_size(n_dof) bytes.  All three are kept by reference. */
+int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, const double *coords,
+                             void *ws, size_t ws_bytes);
 
 /* Device pointers to the handle's preassembled matrices (values on the
  * shared pattern) for inspection: which = OASIS_FORM_MASS, _STIFF (the

@@ -85,6 +85,7 @@ _SIGS = {
     "oasis_ipcs_step": (i32, [vp, vp, P(State), vp, vp, P(StepStats)]),
     "oasis_ipcs_matrix": (i32, [vp, i32, P(vp), P(vp)]),
     "oasis_ipcs_destroy": (i32, [vp]),
+    "oasis_ipcs_set_warmstart": (i32, [vp, vp, vp, vp, sz]),
     "oasis_mpnn_workspace_size": (i32, [i32, P(sz)]),
     "oasis_mpnn_forward": (i32, [vp, P(Csr), vp, i32, vp, vp, vp, vp, vp, vp, vp, sz]),
     "oasis_mpnn_backward": (i32, [vp, P(Csr), vp, vp, vp, vp, vp, P(f64), vp, sz]),
@@ -104,6 +105,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("liboasis.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch ships its own HIP runtime with the same soname (libamdhip64.so.7)
+    # as the one liboasis links; whichever is loaded first serves the whole
+    # process, so load torch's first: device memory and streams come from
+    # torch, and the library must share its runtime.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -303,6 +303,23 @@ class IPCS:
                  ms_total=stats.ms_total, rc=rc)
         return d
 
+    def set_warmstart(self, params, coords):
+        """Attach a learned pressure warm start (params: float32 [MPNN.NPARAM],
+        coords: float64 [n, dim], both on the device); None detaches it."""
+        lib = _lib()
+        if params is None:
+            L.check(lib.oasis_ipcs_set_warmstart(self.handle, None, None, None, 0), "oasis_ipcs_set_warmstart")
+            self._warm = None
+            return
+        params = params.to(torch.float32).contiguous()
+        coords = coords.to(torch.float64).contiguous()
+        nb = C.c_size_t()
+        L.check(lib.oasis_mpnn_workspace_size(self.n, C.byref(nb)), "oasis_mpnn_workspace_size")
+        ws = _workspace(nb.value, params.device)
+        L.check(lib.oasis_ipcs_set_warmstart(self.handle, _p(params), _p(coords), _p(ws), ws.numel()),
+                "oasis_ipcs_set_warmstart")
+        self._warm = (params, coords, ws)   # kept alive while attached
+
     def matrix(self, which, count=None):
         """Device tensor view (copy) of a handle matrix: values on the pattern."""
         val = C.c_void_p()

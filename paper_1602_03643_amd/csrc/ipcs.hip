@@ -379,7 +379,6 @@ __global__ __launch_bounds__(kBlock) void k_div_rows(int n, const int *__restric
 __global__ __launch_bounds__(kBlock) void k_bphi_finish(int n, const double *part, int np,
                                                         double *__restrict__ bphi,
                                                         const double *__restrict__ s,
-                                                        const double *__restrict__ phi_prev,
                                                         double *__restrict__ bs, double *__restrict__ xs) {
     __shared__ double lds[kBlock / kWave];
     double v[1];
@@ -390,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_bphi_finish(int n, const double *par
         const double b = bphi[i] - mean;
         bphi[i] = b;
         bs[i] = b / s[i];
-        xs[i] = phi_prev[i] * s[i];
+        xs[i] = 0.0;   // plain start: the previous pressure, phi_0 = 0
     }
 }
 
@@ -758,6 +757,11 @@ struct oasis_ipcs {
     BiWork<float> bi32;
     IRBufs ir;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // learned warm start (optional)
+    const float *ws_params = nullptr;
+    const double *ws_coords = nullptr;
+    void *ws_mem = nullptr;
+    size_t ws_bytes = 0;
 };
 
 static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, oasis_ipcs &h) {
@@ -927,6 +931,26 @@ extern "C" int oasis_ipcs_destroy(oasis_ipcs *h) {
     return OASIS_OK;
 }
 
+extern "C" int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, const double *coords, void *ws,
+                                        size_t ws_bytes) {
+    if (!h) return OASIS_EINVAL;
+    if (!params) {
+        h->ws_params = nullptr;
+        h->ws_coords = nullptr;
+        h->ws_mem = nullptr;
+        h->ws_bytes = 0;
+        return OASIS_OK;
+    }
+    size_t need = 0;
+    OASIS_TRY(oasis_mpnn_workspace_size(h->n, &need));
+    if (!coords || !ws || ws_bytes < need) return ws_bytes < need ? OASIS_EWORKSPACE : OASIS_EINVAL;
+    h->ws_params = params;
+    h->ws_coords = coords;
+    h->ws_mem = ws;
+    h->ws_bytes = ws_bytes;
+    return OASIS_OK;
+}
+
 extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const double **val,
                                  const double **scaled_diag_sqrt) {
     if (!h || !val) return OASIS_EINVAL;
@@ -1074,20 +1098,27 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         launch_div<2, 8>(s, h, x, &gd);
     OASIS_TRY_LAUNCH();
     hipLaunchKernelGGL(k_bphi_finish, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->red, gd, h->bphi, h->sK,
-                       st->phi, h->bs, h->xs);
+                       h->bs, h->xs);
     OASIS_TRY_LAUNCH();
     if (st->b_phi) {
         hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, st->b_phi, h->bphi);
         OASIS_TRY_LAUNCH();
     }
     S.guess_used = 0;
+    if (!phi_guess && h->ws_params) {
+        // learned warm start from the projected right-hand side and phi_prev
+        oasis_csr Kc{n, h->nnz, h->rp, h->ci, h->Ks, OASIS_F64};
+        OASIS_TRY(oasis_mpnn_forward(stream, &Kc, h->sK, D, h->ws_coords, h->bphi, st->phi, h->ws_params,
+                                     h->dtmp, nullptr, h->ws_mem, h->ws_bytes));
+        phi_guess = h->dtmp;
+    }
     if (phi_guess) {
-        double wr_prev = 0, wr_guess = 0, wbb = 0;
+        // the residual of the plain start phi_0 = 0 is b itself (wbb)
+        double wr_guess = 0, wbb = 0;
         hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, phi_guess, h->sK, 1, h->xg);
         OASIS_TRY_LAUNCH();
-        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->dtmp, h->cg, &wr_prev, &wbb));
-        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->dtmp, h->cg, &wr_guess, &wbb));
-        if (std::isfinite(wr_guess) && wr_guess < wr_prev) {
+        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->bt[0], h->cg, &wr_guess, &wbb));
+        if (std::isfinite(wr_guess) && wr_guess < wbb) {
             hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, h->xs, h->xg);
             OASIS_TRY_LAUNCH();
             S.guess_used = 1;

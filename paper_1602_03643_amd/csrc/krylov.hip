@@ -256,6 +256,56 @@ void carve_cg(Carver &c, int n, CGWork<T> &w) {
     w.st = c.take<CGState>(1);
 }
 
+// HIP-event timing of every direction+product launch of a chunk.  A launch
+// that finds the flag of an earlier iteration already raised returns at
+// once; when the chunk's state has been read back, only the launches of
+// iterations before the flagged one (it_done) are counted.
+struct ChunkTimer {
+    bool on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int first = 0;
+    std::vector<float> ms;
+    ~ChunkTimer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    int init(bool enable) {
+        on = enable;
+        if (!on) return OASIS_OK;
+        OASIS_TRY_HIP(hipEventCreate(&e0));
+        OASIS_TRY_HIP(hipEventCreate(&e1));
+        return OASIS_OK;
+    }
+    void chunk(int it) {
+        first = it;
+        ms.clear();
+    }
+    int before(hipStream_t s) {
+        if (on) OASIS_TRY_HIP(hipEventRecord(e0, s));
+        return OASIS_OK;
+    }
+    int after(hipStream_t s) {
+        if (!on) return OASIS_OK;
+        OASIS_TRY_HIP(hipEventRecord(e1, s));
+        OASIS_TRY_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        OASIS_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms.push_back(t);
+        return OASIS_OK;
+    }
+    // h: the state read back after the chunk
+    void commit(const CGState &h, SolveOut &out) {
+        if (!on) return;
+        const int lim = h.flag ? h.it_done : first + static_cast<int>(ms.size());
+        for (size_t j = 0; j < ms.size(); ++j)
+            if (first + static_cast<int>(j) < lim) {
+                out.kernel_ms += ms[j];
+                out.kernel_count += 1;
+            }
+        ms.clear();
+    }
+};
+
 template <typename T, class C>
 static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
@@ -274,11 +324,8 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     };
     OASIS_TRY(residual(0));
     CGState h;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (time_kernel) {
-        OASIS_TRY_HIP(hipEventCreate(&e0));
-        OASIS_TRY_HIP(hipEventCreate(&e1));
-    }
+    ChunkTimer tm;
+    OASIS_TRY(tm.init(time_kernel));
     const int chunk = check_every > 0 ? check_every : 32;
     int it = 0, restart_at = 0;
     int rc = OASIS_OK;
@@ -287,22 +334,16 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     };
     while (true) {
         const int m = std::min(chunk, maxit - it);
+        tm.chunk(it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
-            if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
+            OASIS_TRY(tm.before(s));
             hipLaunchKernelGGL((k_cg_p1<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, w.r,
                                w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
                                itj == restart_at ? g1 : g2, w.st, itj, itj == restart_at ? 1 : 0,
                                static_cast<const T *>(nullptr), w.partA);
             OASIS_TRY_LAUNCH();
-            if (time_kernel) {
-                OASIS_TRY_HIP(hipEventRecord(e1, s));
-                OASIS_TRY_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                OASIS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-                out.kernel_ms += ms;
-                out.kernel_count += 1;
-            }
+            OASIS_TRY(tm.after(s));
             hipLaunchKernelGGL((k_cg_p2<T>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
                                w.q, x, wgt, w.partA, g1, w.st, itj, static_cast<const T *>(nullptr),
                                w.partB);
@@ -311,6 +352,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         it += m;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
+        tm.commit(h, out);
         if (h.flag == 0) {
             if (it < maxit) continue;
             const double wbb = h.wbb, tol2 = h.tol2;
@@ -351,8 +393,6 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         out.rel_res = NAN;
         break;
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     return rc;
 }
 
@@ -418,32 +458,23 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         return OASIS_OK;
     }
     OASIS_TRY(cast());
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (time_kernel) {
-        OASIS_TRY_HIP(hipEventCreate(&e0));
-        OASIS_TRY_HIP(hipEventCreate(&e1));
-    }
+    ChunkTimer tm;
+    OASIS_TRY(tm.init(time_kernel));
     const int chunk = check_every > 0 ? check_every : 32;
     int it = 0, restart_at = 0, nin = g2;
     int rc = OASIS_OK;
     while (true) {
         const int m = std::min(chunk, maxit - it);
+        tm.chunk(it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
-            if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
+            OASIS_TRY(tm.before(s));
             hipLaunchKernelGGL((k_cg_p1<float, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val32,
                                w.r, w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
                                j == 0 ? nin : g2, w.st, itj, itj == restart_at ? 1 : 0, vnull,
                                w.partA);
             OASIS_TRY_LAUNCH();
-            if (time_kernel) {
-                OASIS_TRY_HIP(hipEventRecord(e1, s));
-                OASIS_TRY_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                OASIS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-                out.kernel_ms += ms;
-                out.kernel_count += 1;
-            }
+            OASIS_TRY(tm.after(s));
             hipLaunchKernelGGL((k_cg_p2<float>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
                                w.q, xlo, wgt32, w.partA, g1, w.st, itj, vnull, w.partB);
             OASIS_TRY_LAUNCH();
@@ -452,6 +483,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         nin = g2;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
+        tm.commit(h, out);
         if (h.flag == 2 || h.flag == 3) {
             OASIS_TRY(fold());
             out.iters = h.it_done;
@@ -487,8 +519,6 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         it = at;
         nin = g2;
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     return rc;
 }
 

@@ -86,6 +86,23 @@ static void carve_mp(Carver &c, int n, MpWs &w) {
 // ---------------------------------------------------------------------------
 // features
 
+// Rows 0..2 of m become their minimum, rows 3..5 their maximum, in column
+// 0 (tree over the block; all threads take part).
+__device__ __forceinline__ void block_minmax6(double (&m)[6][kBlock]) {
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const int t = threadIdx.x;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                m[k][t] = fmin(m[k][t], m[k][t + h]);
+                m[3 + k][t] = fmax(m[3 + k][t], m[3 + k][t + h]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // r = b - K phi_prev with K = S Ks S; X[:,0..2] = (r/d, b/d, phi_prev) raw,
 // X[:,3..5] = coordinates; partials: sums of squares and coordinate min/max
 template <class C>
@@ -128,57 +145,87 @@ __global__ __launch_bounds__(kBlock) void k_mp_feat1(int n, const int *__restric
         mml[k][threadIdx.x] = lo[k];
         mml[3 + k][threadIdx.x] = hi[k];
     }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        double v = mml[threadIdx.x][0];
-        for (int t = 1; t < kBlock; ++t)
-            v = threadIdx.x < 3 ? fmin(v, mml[threadIdx.x][t]) : fmax(v, mml[threadIdx.x][t]);
-        mm[blockIdx.x * 6 + threadIdx.x] = v;
-    }
+    block_minmax6(mml);
+    if (threadIdx.x < 6) mm[blockIdx.x * 6 + threadIdx.x] = mml[threadIdx.x][0];
 }
 
-// normalised features, encoder h0 = relu(We x + ce); block 0 records sigma
-__global__ __launch_bounds__(kBlock) void k_mp_feat2(int n, int np, const double *part, const double *mm,
-                                                     const float *__restrict__ P, float *__restrict__ X,
-                                                     unsigned short *__restrict__ Z0, unsigned short *__restrict__ H0,
-                                                     double *scal) {
+// One block: sums of squares and bounding box from the per-block partials
+// into scal = (rms t, rms u, rms phi_prev, lo[3], hi[3]); rms t = 1 if zero.
+__global__ __launch_bounds__(kBlock) void k_mp_feat_reduce(int n, int np, const double *part, const double *mm,
+                                                           double *scal) {
     __shared__ double lds[3 * kBlock / kWave];
-    __shared__ float W[kHid * kIn + kHid];
-    __shared__ double bb[6];
+    __shared__ double mml[6][kBlock];
     double v[3];
     read_partials<3>(part, np, v, lds);
-    if (threadIdx.x < 6) {
-        double m = mm[threadIdx.x];
-        for (int b = 1; b < np; ++b) m = threadIdx.x < 3 ? fmin(m, mm[b * 6 + threadIdx.x]) : fmax(m, mm[b * 6 + threadIdx.x]);
-        bb[threadIdx.x] = m;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < np; b += blockDim.x)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], mm[b * 6 + k]);
+            hi[k] = fmax(hi[k], mm[b * 6 + 3 + k]);
+        }
+    for (int k = 0; k < 3; ++k) {
+        mml[k][threadIdx.x] = lo[k];
+        mml[3 + k][threadIdx.x] = hi[k];
     }
+    block_minmax6(mml);
+    if (threadIdx.x == 0) {
+        const double st = sqrt(v[0] / n);
+        scal[0] = st > 0.0 ? st : 1.0;
+        scal[1] = sqrt(v[1] / n);
+        scal[2] = sqrt(v[2] / n);
+    }
+    if (threadIdx.x < 6) scal[3 + threadIdx.x] = mml[threadIdx.x][0];
+}
+
+// normalised features, encoder h0 = relu(We x + ce), from scal; the BF16
+// rows of Z0 and H0 (64 bytes per node) are written as 16-byte stores
+__global__ __launch_bounds__(kBlock) void k_mp_feat2(int n, const double *__restrict__ scal,
+                                                     const float *__restrict__ P, float *__restrict__ X,
+                                                     unsigned short *__restrict__ Z0, unsigned short *__restrict__ H0) {
+    __shared__ float W[kHid * kIn + kHid];
     for (int k = threadIdx.x; k < kHid * kIn + kHid; k += blockDim.x) W[k] = P[kOffWe + k];
     __syncthreads();
-    double st = sqrt(v[0] / n), su = sqrt(v[1] / n), sf = sqrt(v[2] / n);
-    if (!(st > 0.0)) st = 1.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        scal[0] = st;
-        scal[1] = su;
-        scal[2] = sf;
-        for (int k = 0; k < 6; ++k) scal[3 + k] = bb[k];
+    const double st = scal[0], su = scal[1], sf = scal[2];
+    double lo[3], span[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = scal[3 + k];
+        span[k] = scal[6 + k] - scal[3 + k];
     }
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        float *x = X + i * 8;
-        float xn[kIn];
-        xn[0] = static_cast<float>(x[0] / st);
-        xn[1] = su > 0.0 ? static_cast<float>(x[1] / su) : 0.f;
-        xn[2] = sf > 0.0 ? static_cast<float>(x[2] / sf) : 0.f;
-        for (int k = 0; k < 3; ++k) {
-            const double span = bb[3 + k] - bb[k];
-            xn[3 + k] = span > 0.0 ? static_cast<float>(2.0 * (x[3 + k] - bb[k]) / span - 1.0) : 0.f;
-        }
-        for (int k = 0; k < kIn; ++k) x[k] = xn[k];
-        unsigned short *z = Z0 + i * kHid, *h = H0 + i * kHid;
-        for (int o = 0; o < kHid; ++o) {
-            float a = W[kHid * kIn + o];
-            for (int k = 0; k < kIn; ++k) a += W[o * kIn + k] * xn[k];
-            z[o] = f2bf(a);
-            h[o] = f2bf(fmaxf(a, 0.f));
+        float4 *x4 = reinterpret_cast<float4 *>(X + i * 8);
+        const float4 a = x4[0], b = x4[1];
+        float xn[8];
+        xn[0] = static_cast<float>(a.x / st);
+        xn[1] = su > 0.0 ? static_cast<float>(a.y / su) : 0.f;
+        xn[2] = sf > 0.0 ? static_cast<float>(a.z / sf) : 0.f;
+        const float raw[3] = {a.w, b.x, b.y};
+        for (int k = 0; k < 3; ++k)
+            xn[3 + k] = span[k] > 0.0 ? static_cast<float>(2.0 * (raw[k] - lo[k]) / span[k] - 1.0) : 0.f;
+        xn[6] = xn[7] = 0.f;
+        x4[0] = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        x4[1] = make_float4(xn[4], xn[5], 0.f, 0.f);
+        uint4 *z = reinterpret_cast<uint4 *>(Z0 + i * kHid);
+        uint4 *h = reinterpret_cast<uint4 *>(H0 + i * kHid);
+#pragma unroll
+        for (int q = 0; q < kHid / 8; ++q) {
+            unsigned zw[4], hw[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                float v2[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int o = q * 8 + p * 2 + e;
+                    float acc = W[kHid * kIn + o];
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) acc += W[o * kIn + k] * xn[k];
+                    v2[e] = acc;
+                }
+                zw[p] = static_cast<unsigned>(f2bf(v2[0])) | (static_cast<unsigned>(f2bf(v2[1])) << 16);
+                hw[p] = static_cast<unsigned>(f2bf(fmaxf(v2[0], 0.f))) |
+                        (static_cast<unsigned>(f2bf(fmaxf(v2[1], 0.f))) << 16);
+            }
+            z[q] = make_uint4(zw[0], zw[1], zw[2], zw[3]);
+            h[q] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
         }
     }
 }
@@ -625,8 +672,10 @@ extern "C" int oasis_mpnn_forward(void *stream, const oasis_csr *Ks, const doubl
     hipLaunchKernelGGL((k_mp_feat1<Cfg4x4x1>), dim3(g1), dim3(kBlock), 0, st, n, Ks->row_ptr, Ks->col_idx, val, s,
                        b_phi, phi_prev, coords, dim, w.X, w.part, w.mm);
     OASIS_TRY_LAUNCH();
-    hipLaunchKernelGGL(k_mp_feat2, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, n, g1, w.part, w.mm, params,
-                       w.X, w.Z[0], w.H[0], w.scal);
+    hipLaunchKernelGGL(k_mp_feat_reduce, dim3(1), dim3(kBlock), 0, st, n, g1, w.part, w.mm, w.scal);
+    OASIS_TRY_LAUNCH();
+    hipLaunchKernelGGL(k_mp_feat2, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, n, w.scal, params, w.X,
+                       w.Z[0], w.H[0]);
     OASIS_TRY_LAUNCH();
     const int gt = (int)std::min<long long>((n + kTile - 1) / kTile, 1 << 20);
     for (int l = 0; l < kLayers; ++l) {

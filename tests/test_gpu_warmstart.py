@@ -1,0 +1,111 @@
+"""The learned warm start inside the IPCS step.
+
+* The guard: a caller guess is taken only when its residual is below that
+  of the plain start phi_0 = 0; the converged correction of the oracle is
+  taken and leaves almost nothing to iterate, a useless one is refused and
+  the step is then identical to the plain step.
+* The trained network (packaged weights): on a held-out seeded channel run
+  it must lower the error it is trained on (the mean squared error of the
+  scaled correction) well below that of phi_prev, every warm-started step
+  must reach the same tolerance as the plain one, and where the guard
+  refuses the guess the iteration count must equal the plain one.  The
+  measured change in PCG iterations and pressure-solve time is printed:
+  with Jacobi-PCG to 1e-8 it is small.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import T, dev, device_mesh, rel, say
+from oracle import ipcs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oa():
+    import paper_1602_03643_amd as m
+    return m
+
+
+def _handle(oa, prob, dm, pat, precision=0, rtol=1e-10):
+    m = prob.mesh
+    return oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32), rtol_u=rtol, rtol_p=rtol,
+                   precision=precision)
+
+
+def _state(prob):
+    return dict(U1=T(prob.U1), U2=T(prob.U2), p=T(prob.p), phi=T(prob.phi_prev),
+                bc=T(prob.bc_values(prob.t0 + prob.dt)))
+
+
+def _step(h, st, guess=None):
+    Un = torch.empty_like(st["U1"])
+    r = h.step(st["U1"], st["U2"], Un, st["p"], st["phi"], bc_values=st["bc"], phi_guess=guess)
+    st["U2"], st["U1"] = st["U1"], Un
+    return r
+
+
+def test_guard_takes_good_guess_and_refuses_bad_one(oa):
+    prob = synth.channel_flow("tiny", seed=11)
+    say("warm start guard", prob.name)
+    dm, pat, _ = device_mesh(prob.mesh)
+    S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
+    ref = ipcs.step(S, ipcs.initial_state(prob), prob.bc_values, rtol_u=1e-12, rtol_p=1e-12)
+    h = _handle(oa, prob, dm, pat)
+    a, b, c = _state(prob), _state(prob), _state(prob)
+    plain = _step(h, a)
+    good = _step(h, b, guess=T(ref.phi))
+    bad = _step(h, c, guess=T(ref.phi * 50.0 + 1.0))
+    assert plain["guess_used"] == 0
+    assert good["guess_used"] == 1 and good["iters_p"] < 0.2 * plain["iters_p"], (good, plain)
+    assert bad["guess_used"] == 0 and bad["iters_p"] == plain["iters_p"]
+    assert torch.equal(c["phi"], a["phi"]) and torch.equal(c["U1"], a["U1"])
+    for st in (a, b):
+        assert rel(st["phi"].cpu().numpy(), ref.phi) < 1e-8
+        assert rel(st["U1"].cpu().numpy(), ref.state.U1) < 1e-8
+
+
+def test_random_network_never_breaks_the_step(oa):
+    from paper_1602_03643_amd import warmstart
+    prob = synth.channel_flow("tiny", seed=12)
+    say("warm start random net", prob.name)
+    dm, pat, _ = device_mesh(prob.mesh)
+    P = warmstart.init_params(5)
+    P[-33:] = np.random.default_rng(5).normal(size=33).astype(np.float32)   # nonzero decoder
+    plain, warm = _handle(oa, prob, dm, pat), _handle(oa, prob, dm, pat)
+    warm.set_warmstart(torch.as_tensor(P, device=dev()), T(prob.mesh.dof_coords))
+    a, b = _state(prob), _state(prob)
+    for _ in range(3):
+        ra, rb = _step(plain, a), _step(warm, b)
+        assert ra["status"] == 0 and rb["status"] == 0
+        assert rb["res_p"] <= 1e-10 * 1.0001
+        if not rb["guess_used"]:
+            assert rb["iters_p"] == ra["iters_p"]
+        assert rel(b["phi"].cpu().numpy(), a["phi"].cpu().numpy()) < 1e-6
+    warm.set_warmstart(None, None)
+    rb = _step(warm, b)
+    assert rb["guess_used"] == 0
+
+
+def test_trained_network_gain_on_held_out_run(oa):
+    from paper_1602_03643_amd import warmstart
+    P, meta = warmstart.load()
+    size, steps, seed = "c65", 8, 97           # seed far outside the training seeds
+    say("trained warm start", size, "seed", seed, "weights trained on", meta["sizes"])
+    case = warmstart.Case(size, dev())
+    Pt = torch.as_tensor(P, device=dev())
+    st = case.initial(seed)
+    data = warmstart.collect(case.h, st, steps)
+    samples = [(case.net,) + d for d in data]
+    l_prev = warmstart.eval_loss(samples, torch.as_tensor(warmstart.init_params(0), device=dev()))
+    l_net = warmstart.eval_loss(samples, Pt)
+    say("held-out loss: guess = phi_prev %.3f, trained network %.3f" % (l_prev, l_net))
+    assert l_net < 0.6 * l_prev
+    c = warmstart.compare(case, Pt, seed=seed, steps=steps)
+    say("PCG iterations plain %.1f, warm %.1f (guess used in %.0f%% of steps); pressure ms %.2f vs %.2f"
+        % (c["iters_plain"], c["iters_warm"], 100 * c["guess_used"], c["ms_pressure_plain"], c["ms_pressure_warm"]))
+    assert c["rel_diff_phi"] < 1e-5
+    if c["guess_used"] == 0.0:
+        assert c["iters_warm"] == c["iters_plain"]
