@@ -9,13 +9,16 @@ Synthetic initial field: laminar parabola + seeded U(-0.05, 0.05) noise,
 dt = 0.01, Krylov relative tolerance 1e-8 (true residual).
 
 Variants timed (same inputs, separate handles):
-  fp64     plain FP64 BiCGStab + Jacobi-PCG (pressure from p*, phi_0 = 0)
+  fp64     plain FP64 BiCGStab + Jacobi-PCG, pressure solve from phi_prev
   mixed    FP32 inner Krylov with FP64 dot products and FP64 refinement
   learned  mixed + the trained message-passing warm start attached to the
-           pressure solve (guarded: used only if it beats phi_0 = 0)
+           pressure solve (guarded: used only if it beats phi_prev)
+  *_zero   the same with the pressure solve started from phi_0 = 0 (solving
+           for p from p*) instead of phi_prev
 All reach the same FP64 true-residual tolerance.  The headline `value` is
-the learned+FP32 variant (the configuration the metric names) when it is
-timed, else the fastest one; `speedup_vs_fp64` compares it with plain FP64.
+the faster learned+FP32 variant (the configuration the metric names; its
+plain start is a solver option) when one is timed, else the fastest one;
+`speedup_vs_fp64` compares it with plain FP64 from phi_prev.
 
 One JSON line is printed; see the design doc for the fields.
 """
@@ -94,13 +97,13 @@ def pmc_traffic(kernel):
         return None
 
 
-def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=0, warm=None):
+def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=0, warm=None, pstart=0):
     import numpy as np
     dev = dm.coords.device
     m = pr.mesh
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, torch.as_tensor(m.bc_dofs, device=dev), rtol_u=pr.rtol_u,
-                rtol_p=pr.rtol_p, precision=precision, inner_rtol=1e-4, assembly=assembly)
+                rtol_p=pr.rtol_p, precision=precision, inner_rtol=1e-4, assembly=assembly, pressure_start=pstart)
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
     if warm is not None:
         h.set_warmstart(torch.as_tensor(warm, device=dev), T(m.dof_coords))
@@ -193,7 +196,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", default="c129")
-    ap.add_argument("--variants", default="fp64,mixed,learned")
+    ap.add_argument("--variants", default="fp64,mixed,learned,fp64_zero,mixed_zero,learned_zero")
     ap.add_argument("--weights", default=None, help="warm-start weights (.npz); default: the packaged ones")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a known-size kernel for PMC calibration)")
@@ -233,19 +236,25 @@ def main():
     results = {}
     handles = {}
     for v in args.variants.split(","):
-        prec = oa.F64 if v == "fp64" else oa.F32
+        base = v[:-5] if v.endswith("_zero") else v
+        if base not in ("fp64", "mixed", "learned"):
+            raise SystemExit("unknown variant %s" % v)
+        prec = oa.F64 if base == "fp64" else oa.F32
+        pstart = oa.PSTART_ZERO if v.endswith("_zero") else oa.PSTART_PREV
         warm = None
-        if v == "learned":
+        if base == "learned":
             from paper_1602_03643_amd import warmstart
             warm, wmeta = warmstart.load(args.weights or warmstart.DEFAULT_WEIGHTS)
             log("warm start: %s, trained on %s" % (args.weights or warmstart.DEFAULT_WEIGHTS, wmeta.get("sizes")))
-        h, res, _ = run_variant(oa, torch, pr, dm, pat, prec, args.steps, args.warmup, v, args.assembly, warm)
+        h, res, _ = run_variant(oa, torch, pr, dm, pat, prec, args.steps, args.warmup, v, args.assembly, warm,
+                                pstart)
         results[v] = res
         handles[v] = h
-    head = "learned" if "learned" in results else max(results, key=lambda k: results[k]["steps_per_s"])
+    learned = [k for k in results if k.startswith("learned")]
+    head = max(learned or list(results), key=lambda k: results[k]["steps_per_s"])
     hres = results[head]
     # dominant kernel: the CG direction + product kernel of the headline variant
-    prec = oa.F64 if head == "fp64" else oa.F32
+    prec = oa.F64 if head.startswith("fp64") else oa.F32
     vbytes = 8 if prec == oa.F64 else 4
     avg_ms, cnt = time_cg_kernel(oa, torch, handles[head], pat, prec, args.kernel_iters)
     kb = cg_kernel_bytes(pat.n, pat.nnz, vbytes)
@@ -274,7 +283,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": "f64" if head.startswith("fp64") else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "channel %s: %d dofs/field, %d tets, nnz %d, Re_tau 180, dt 0.01, rtol 1e-8"
                    % (m.name.split("_")[1], m.n_dof, m.n_cell, pat.nnz),

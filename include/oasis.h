@@ -232,10 +232,15 @@ typedef struct {
                                  side and scaling) or OASIS_ASSEMBLE_COLORS (colour-by-colour
                                  element scatter as in oasis_assemble_p1); ROWS needs rows of
                                  at most 32 entries and falls back to COLORS otherwise */
+    int32_t pressure_start;   /* plain start of the pressure-correction solve (the paper does
+                                 not fix it): OASIS_PSTART_PREV (phi_prev, default) or
+                                 OASIS_PSTART_ZERO (phi_0 = 0: solving for p from p*) */
 } oasis_ipcs_params;
 
 #define OASIS_ASSEMBLE_ROWS 0
 #define OASIS_ASSEMBLE_COLORS 1
+#define OASIS_PSTART_PREV 0
+#define OASIS_PSTART_ZERO 1
 
 typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
 
@@ -243,10 +248,9 @@ typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
  *  U1[k]  U^{k,n-1}   (read)       U2[k]  U^{k,n-2} (read)
  *  Un[k]  U^{k,n}     (written; may not alias U1/U2)
  *  p      p* on entry, p^{n-1/2} (zero mean) on return
- *  phi    phi_prev on entry (read only by an attached warm start), the new
- *         correction on return.  The plain pressure solve starts from the
- *         previous pressure p* (phi_0 = 0), as the pressure-solve routine of
- *         the naive solver (Sec. 4) does.
+ *  phi    phi_prev on entry (the plain start of the pressure solve under
+ *         OASIS_PSTART_PREV, and an input of an attached warm start), the
+ *         new correction on return
  *  UI[k], b_phi: optional (NULL) outputs of the tentative velocity and the
  *  projected pressure right-hand side. */
 typedef struct {
@@ -263,7 +267,7 @@ typedef struct {
     int32_t iters_u[3], iters_p;
     int32_t outer_u, outer_p;
     int32_t status;           /* worst Krylov status of the step */
-    int32_t guess_used;       /* 1 if the guess had a smaller residual than phi_0 = 0 */
+    int32_t guess_used;       /* 1 if the guess had a smaller residual than the plain start */
     double res_u[3], res_p;   /* final true relative residuals */
     double ms_assemble, ms_velocity, ms_pressure, ms_update, ms_total;  /* HIP-event phase times */
 } oasis_step_stats;
@@ -290,7 +294,7 @@ int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_p
  * lumped velocity update.  bc_values: device double [dim][n_bc] at t^n.
  * phi_guess (device, nullable): a candidate initial guess for the
  * pressure solve; it is used only if its initial residual is below that of
- * the plain start phi_0 = 0, i.e. below ||b_phi||.  stats: host (nullable).
+ * the plain start (par->pressure_start).  stats: host (nullable).
  * Synchronises `stream`. */
 int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
                     const double *bc_values, const double *phi_guess,
@@ -300,8 +304,8 @@ int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
  * pressure-correction solve: every later oasis_ipcs_step without an explicit
  * phi_guess runs the network (oasis_mpnn_forward) on the step's projected
  * right-hand side, phi_prev and the dof coordinates, and starts CG from the
- * prediction only if its initial residual is below ||b_phi|| (that of the
- * plain start phi_0 = 0); the solve still stops at the same rtol.  params: device float
+ * prediction only if its initial residual is below that of the plain start
+ * (par->pressure_start); the solve still stops at the same rtol.  params: device float
  * [OASIS_MPNN_NPARAM]; coords: device double [n_dof][dim]; ws: at least
  * oasis_mpnn_workspace_size(n_dof) bytes.  All three are kept by reference. */
 int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, const double *coords,

@@ -21,11 +21,12 @@ Readings (where the paper is silent or inconsistent):
   All velocity components share the Dirichlet dof set, so one A serves all.
 * No pressure boundary condition: b_phi is projected onto 1-perp before the
   solve, phi and p are shifted to zero arithmetic mean of their dof values.
-* Initial guesses: U^{k,n-1} for the tentative velocity; for the pressure,
-  the previous pressure p* (phi_0 = 0), as in the pressure-solve routine of
-  the naive solver (Sec. 4, figure of the solver routines: the old pressure
-  is saved, the system is solved for p starting from its current value, and
-  phi is the difference).  A caller-supplied guess replaces it.
+* Initial guesses (the paper does not fix them): U^{k,n-1} for the
+  tentative velocity; for the pressure correction the previous correction
+  phi_prev (pressure_start="prev").  pressure_start="zero" starts from
+  phi_0 = 0, i.e. solving for p from p*, as the pressure-solve routine of
+  the naive solver (Sec. 4) would with an iterative solver.  A caller
+  guess (phi_guess) replaces either.
 """
 from __future__ import annotations
 
@@ -123,7 +124,7 @@ def pressure_rhs(S: Setup, UI):
 
 
 def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
-         phi_guess=None) -> StepOut:
+         phi_guess=None, pressure_start="prev") -> StepOut:
     """Advance one time step.  bc_values: callable t -> [d, n_bc]."""
     mesh = S.mesh
     d = mesh.dim
@@ -140,7 +141,7 @@ def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
         res_u.append(r.rel_res)
         status = max(status, r.status)
     b_phi = pressure_rhs(S, UI)
-    x0 = np.zeros_like(b_phi) if phi_guess is None else phi_guess
+    x0 = plain_pressure_start(st, b_phi, pressure_start) if phi_guess is None else phi_guess
     rp = krylov.pcg(S.K, b_phi, x0, rtol=rtol_p, maxit=maxit)
     status = max(status, rp.status)
     phi = rp.x - rp.x.mean()
@@ -151,6 +152,14 @@ def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
         Un[:, mesh.bc_dofs] = g
     new = State(Un, st.U1.copy(), p_new, phi, t_new)
     return StepOut(new, A, b, UI, b_phi, phi, iters_u, rp.iters, res_u, rp.rel_res, status)
+
+
+def plain_pressure_start(st: State, b_phi, pressure_start="prev"):
+    if pressure_start == "prev":
+        return st.phi_prev
+    if pressure_start == "zero":
+        return np.zeros_like(b_phi)
+    raise ValueError(pressure_start)
 
 
 def initial_state(problem) -> State:

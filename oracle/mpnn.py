@@ -20,7 +20,8 @@ Network (hidden width 32, 3 message-passing layers):
 Guess: phi_prev + sigma * delta.  Training target: (phi - phi_prev) / sigma,
 loss = mean over nodes of (delta - target)^2, averaged over samples.
 The solve starts from the guess only if its residual is below that of the
-plain start phi_0 = 0 (guarded_start); PCG then runs to the same tolerance.
+plain start (phi_prev, or 0; guarded_start); PCG then runs to the same
+tolerance.
 Adam (beta1 0.9, beta2 0.999, eps 1e-8), bias-corrected.
 """
 from __future__ import annotations
@@ -156,11 +157,12 @@ def predict_guess(P, K, b_phi, phi_prev, coords):
     return phi_prev + sigma * delta
 
 
-def guarded_start(K, b_phi, guess):
+def guarded_start(K, b_phi, plain, guess):
     """The guess is used only if its initial residual is smaller than that of
-    the plain start phi_0 = 0 (i.e. ||b_phi||); otherwise PCG starts from 0."""
+    the plain start `plain` (phi_prev, or zeros); otherwise PCG starts from
+    `plain`."""
     r_g = np.linalg.norm(b_phi - K @ guess)
-    r_0 = np.linalg.norm(b_phi)
-    if np.isfinite(r_g) and r_g < r_0:
+    r_p = np.linalg.norm(b_phi - K @ plain)
+    if np.isfinite(r_g) and r_g < r_p:
         return guess, True
-    return np.zeros_like(b_phi), False
+    return plain, False

@@ -7,7 +7,8 @@ it has not been built.
 """
 from . import _lib
 from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUNSUPPORTED, F32, F64,
-                   FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, OasisError)
+                   FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, PSTART_PREV,
+                   PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, OasisError)
 
 _lib.load()
 
@@ -17,4 +18,5 @@ from .api import (IPCS, MPNN, DeviceCSR, DeviceMesh, assemble_p1, bicgstab, colo
 __all__ = ["IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bicgstab", "color_cells", "color_classes",
            "colorize", "p1_pattern", "pcg", "rcm", "relabel", "spmv", "OasisError",
            "OK", "EINVAL", "EHIP", "ENOTCONV", "EBREAKDOWN", "ENAN", "EWORKSPACE", "EUNSUPPORTED", "F32", "F64",
-           "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV"]
+           "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV", "PSTART_PREV",
+           "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS"]

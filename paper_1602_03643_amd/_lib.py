@@ -17,6 +17,7 @@ FORM_MASS, FORM_STIFF, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_CONV = range(
 KRYLOV_TIME = 1
 KRYLOV_NULLSPACE_CONST = 2
 ASSEMBLE_ROWS, ASSEMBLE_COLORS = 0, 1
+PSTART_PREV, PSTART_ZERO = 0, 1
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
 
@@ -52,7 +53,7 @@ class KrylovStats(C.Structure):
 class IpcsParams(C.Structure):
     _fields_ = [("dt", f64), ("nu", f64), ("f", f64 * 3), ("n_bc", i32), ("bc_dofs", vp),
                 ("rtol_u", f64), ("rtol_p", f64), ("maxit", i32), ("precision", i32),
-                ("inner_rtol", f64), ("assembly", i32)]
+                ("inner_rtol", f64), ("assembly", i32), ("pressure_start", i32)]
 
 
 class State(C.Structure):

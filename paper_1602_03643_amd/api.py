@@ -256,7 +256,7 @@ class IPCS:
 
     def __init__(self, mesh: DeviceMesh, pattern: DeviceCSR, dt, nu, f, bc_dofs: torch.Tensor,
                  rtol_u=1e-8, rtol_p=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4,
-                 assembly=L.ASSEMBLE_ROWS, stream=None):
+                 assembly=L.ASSEMBLE_ROWS, pressure_start=L.PSTART_PREV, stream=None):
         lib = _lib()
         self.mesh, self.pattern = mesh, pattern
         self.dim, self.n = mesh.dim, mesh.n_dof
@@ -265,7 +265,7 @@ class IPCS:
         self.params = L.IpcsParams(float(dt), float(nu), fv, int(self.bc_dofs.numel()),
                                    self.bc_dofs.data_ptr() if self.bc_dofs.numel() else None,
                                    float(rtol_u), float(rtol_p), int(maxit), int(precision), float(inner_rtol),
-                                   int(assembly))
+                                   int(assembly), int(pressure_start))
         cm = mesh.c()
         nb = C.c_size_t()
         L.check(lib.oasis_ipcs_workspace_size(C.byref(cm), pattern.nnz, C.byref(self.params), C.byref(nb)),

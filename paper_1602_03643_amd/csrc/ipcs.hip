@@ -379,6 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_div_rows(int n, const int *__restric
 __global__ __launch_bounds__(kBlock) void k_bphi_finish(int n, const double *part, int np,
                                                         double *__restrict__ bphi,
                                                         const double *__restrict__ s,
+                                                        const double *__restrict__ phi_prev, int zero_start,
                                                         double *__restrict__ bs, double *__restrict__ xs) {
     __shared__ double lds[kBlock / kWave];
     double v[1];
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_bphi_finish(int n, const double *par
         const double b = bphi[i] - mean;
         bphi[i] = b;
         bs[i] = b / s[i];
-        xs[i] = 0.0;   // plain start: the previous pressure, phi_0 = 0
+        xs[i] = zero_start ? 0.0 : phi_prev[i] * s[i];
     }
 }
 
@@ -814,6 +815,7 @@ static int check_params(const oasis_ipcs_params *p) {
     if (!p || !(p->dt > 0) || !(p->nu >= 0) || p->n_bc < 0 || (p->n_bc > 0 && !p->bc_dofs)) return OASIS_EINVAL;
     if (!(p->rtol_u > 0) || !(p->rtol_p > 0)) return OASIS_EINVAL;
     if (p->precision != OASIS_F64 && p->precision != OASIS_F32) return OASIS_EINVAL;
+    if (p->pressure_start != OASIS_PSTART_PREV && p->pressure_start != OASIS_PSTART_ZERO) return OASIS_EINVAL;
     return OASIS_OK;
 }
 
@@ -1097,8 +1099,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     else
         launch_div<2, 8>(s, h, x, &gd);
     OASIS_TRY_LAUNCH();
+    const int zero_start = h->par.pressure_start == OASIS_PSTART_ZERO ? 1 : 0;
     hipLaunchKernelGGL(k_bphi_finish, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->red, gd, h->bphi, h->sK,
-                       h->bs, h->xs);
+                       st->phi, zero_start, h->bs, h->xs);
     OASIS_TRY_LAUNCH();
     if (st->b_phi) {
         hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, st->b_phi, h->bphi);
@@ -1113,12 +1116,17 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         phi_guess = h->dtmp;
     }
     if (phi_guess) {
-        // the residual of the plain start phi_0 = 0 is b itself (wbb)
-        double wr_guess = 0, wbb = 0;
+        // compare with the plain start (its residual is b itself for phi_0 = 0)
+        double wr_plain = 0, wr_guess = 0, wbb = 0;
         hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, phi_guess, h->sK, 1, h->xg);
         OASIS_TRY_LAUNCH();
         OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->bt[0], h->cg, &wr_guess, &wbb));
-        if (std::isfinite(wr_guess) && wr_guess < wbb) {
+        if (zero_start)
+            wr_plain = wbb;
+        else
+            OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->bt[0], h->cg, &wr_plain,
+                                  &wbb));
+        if (std::isfinite(wr_guess) && wr_guess < wr_plain) {
             hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, h->xs, h->xg);
             OASIS_TRY_LAUNCH();
             S.guess_used = 1;

@@ -1,9 +1,10 @@
 """The learned warm start inside the IPCS step.
 
 * The guard: a caller guess is taken only when its residual is below that
-  of the plain start phi_0 = 0; the converged correction of the oracle is
-  taken and leaves almost nothing to iterate, a useless one is refused and
-  the step is then identical to the plain step.
+  of the plain start (phi_prev, or phi_0 = 0); the converged correction of
+  the oracle is taken and leaves almost nothing to iterate, a useless one
+  is refused and the step is then identical to the plain step.
+* The phi_0 = 0 start matches the oracle's zero start.
 * The trained network (packaged weights): on a held-out seeded channel run
   it must lower the error it is trained on (the mean squared error of the
   scaled correction) well below that of phi_prev, every warm-started step
@@ -29,10 +30,10 @@ def oa():
     return m
 
 
-def _handle(oa, prob, dm, pat, precision=0, rtol=1e-10):
+def _handle(oa, prob, dm, pat, precision=0, rtol=1e-10, pstart=0):
     m = prob.mesh
     return oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32), rtol_u=rtol, rtol_p=rtol,
-                   precision=precision)
+                   precision=precision, pressure_start=pstart)
 
 
 def _state(prob):
@@ -47,13 +48,14 @@ def _step(h, st, guess=None):
     return r
 
 
-def test_guard_takes_good_guess_and_refuses_bad_one(oa):
+@pytest.mark.parametrize("pstart", [0, 1], ids=["prev", "zero"])
+def test_guard_takes_good_guess_and_refuses_bad_one(oa, pstart):
     prob = synth.channel_flow("tiny", seed=11)
-    say("warm start guard", prob.name)
+    say("warm start guard", prob.name, "pressure start", pstart)
     dm, pat, _ = device_mesh(prob.mesh)
     S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
     ref = ipcs.step(S, ipcs.initial_state(prob), prob.bc_values, rtol_u=1e-12, rtol_p=1e-12)
-    h = _handle(oa, prob, dm, pat)
+    h = _handle(oa, prob, dm, pat, pstart=pstart)
     a, b, c = _state(prob), _state(prob), _state(prob)
     plain = _step(h, a)
     good = _step(h, b, guess=T(ref.phi))
@@ -65,6 +67,24 @@ def test_guard_takes_good_guess_and_refuses_bad_one(oa):
     for st in (a, b):
         assert rel(st["phi"].cpu().numpy(), ref.phi) < 1e-8
         assert rel(st["U1"].cpu().numpy(), ref.state.U1) < 1e-8
+
+
+def test_zero_pressure_start_matches_oracle(oa):
+    prob = synth.channel_flow("tiny", seed=13)
+    say("zero pressure start", prob.name)
+    dm, pat, _ = device_mesh(prob.mesh)
+    S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
+    st = ipcs.initial_state(prob)
+    h = _handle(oa, prob, dm, pat, rtol=1e-13, pstart=1)
+    g = _state(prob)
+    for _ in range(3):          # phi_prev is nonzero from the second step on
+        ref = ipcs.step(S, st, prob.bc_values, rtol_u=1e-13, rtol_p=1e-13, pressure_start="zero")
+        r = _step(h, g)
+        assert r["status"] == 0
+        assert rel(g["phi"].cpu().numpy(), ref.phi) <= 1e-10
+        assert rel(g["p"].cpu().numpy(), ref.state.p) <= 1e-10
+        assert rel(g["U1"].cpu().numpy(), ref.state.U1) <= 1e-10
+        st = ref.state
 
 
 def test_random_network_never_breaks_the_step(oa):

@@ -142,10 +142,13 @@ def test_mpnn_zero_decoder_is_fallback_and_guard():
     np.testing.assert_array_equal(g, phi_prev)
     bad = phi_prev + 1e6
     bad[0] = np.nan
-    x0, used = mpnn.guarded_start(S.K, out.b_phi, bad)
-    assert not used and not np.any(x0)                  # falls back to the plain start phi_0 = 0
+    x0, used = mpnn.guarded_start(S.K, out.b_phi, phi_prev, bad)
+    assert not used and x0 is phi_prev                  # falls back to the plain start
+    zero = np.zeros_like(phi_prev)
+    x0, used = mpnn.guarded_start(S.K, out.b_phi, zero, bad)
+    assert not used and x0 is zero
     # the converged correction itself has a tiny residual: it is taken
-    x0, used = mpnn.guarded_start(S.K, out.b_phi, out.phi)
+    x0, used = mpnn.guarded_start(S.K, out.b_phi, phi_prev, out.phi)
     assert used and x0 is out.phi
 
 

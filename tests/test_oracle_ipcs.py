@@ -144,3 +144,21 @@ def test_step_outputs_have_zero_mean_pressure():
         assert abs(out.phi.mean()) < 1e-12 * (1 + np.abs(out.phi).max())
         assert out.status == 0
         assert np.all(st.U1[:, pr.mesh.bc_dofs] == 0.0)
+
+
+def test_pressure_start_changes_only_the_iterate():
+    """phi_prev and phi_0 = 0 starts reach the same correction within the
+    solver tolerance (the stopping test is relative to ||b_phi||, not to
+    the initial residual), and a guess equal to phi_prev is the prev start."""
+    prob = synth.channel_flow((9, 9, 7), seed=3)
+    S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
+    st = ipcs.step(S, ipcs.initial_state(prob), prob.bc_values, rtol_u=1e-12, rtol_p=1e-12).state
+    assert np.linalg.norm(st.phi_prev) > 0
+    a = ipcs.step(S, st, prob.bc_values, rtol_u=1e-12, rtol_p=1e-12, pressure_start="prev")
+    b = ipcs.step(S, st, prob.bc_values, rtol_u=1e-12, rtol_p=1e-12, pressure_start="zero")
+    c = ipcs.step(S, st, prob.bc_values, rtol_u=1e-12, rtol_p=1e-12, phi_guess=st.phi_prev)
+    assert np.linalg.norm(a.phi - b.phi) <= 1e-8 * np.linalg.norm(a.phi)
+    np.testing.assert_array_equal(a.phi, c.phi)
+    assert a.iters_p == c.iters_p
+    with pytest.raises(ValueError):
+        ipcs.step(S, st, prob.bc_values, pressure_start="other")
