@@ -10,6 +10,16 @@ inner_rtol * ||r||; then x += e in FP64.
 Reading: inner tolerance 1e-4 by default, Jacobi preconditioner from the
 FP32 diagonal, at most ``max_outer`` refinement steps (not converged after
 that is reported as status 1).
+
+``reliable_pcg`` is the variant used for the pressure solve: one Jacobi-PCG
+whose recurrences run in FP32 while an FP64 accumulator holds the iterate;
+whenever the FP32 recursive residual has dropped by a factor delta since
+the last true residual (or below the tolerance), the FP32 correction is
+added to the FP64 iterate, the true residual b - A x is recomputed in FP64
+and replaces the recursive one, and the iteration continues with the same
+search direction (residual replacement in the sense of van der Vorst and
+Ye's reliable updates).  It stops when the FP64 true residual meets
+rtol ||b||.  With FP64 recurrences it is plain Jacobi-PCG.
 """
 from __future__ import annotations
 
@@ -108,3 +118,55 @@ def refine(method, A, b, x0, rtol=1e-8, inner_rtol=1e-4, maxit=10000, max_outer=
             break
     rn = float(np.linalg.norm(b - A @ x))
     return KrylovResult(x, total, rn / bn, OK if rn <= rtol * bn else NOTCONV, hist)
+
+
+def reliable_pcg(A, b, x0, rtol=1e-8, delta=0.1, maxit=10000, inner_dtype=np.float32):
+    """Reliable-update Jacobi-PCG (see the module docstring).  Returns
+    KrylovResult with iters = CG iterations and history = the iteration
+    numbers at which the residual was replaced."""
+    lo = np.dtype(inner_dtype)
+    f64 = lambda a: a.astype(np.float64)  # noqa: E731
+    A_lo = A.astype(lo)
+    d_lo = A.diagonal().astype(lo)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    bn = float(np.linalg.norm(b))
+    tol = rtol * bn
+    r_hi = b - A @ x
+    rn = float(np.linalg.norm(r_hi))
+    if rn <= tol:
+        return KrylovResult(x, 0, rn / bn if bn > 0 else rn, OK, [])
+    r = r_hi.astype(lo)
+    x_lo = np.zeros_like(r)
+    upd = delta * rn
+    z = (r / d_lo).astype(lo)
+    rz = float(np.dot(f64(r), f64(z)))
+    p = z.copy()
+    it = 0
+    replaced = []
+    while it < maxit:
+        q = (A_lo @ p).astype(lo)
+        pq = float(np.dot(f64(p), f64(q)))
+        if not pq > 0.0:
+            break
+        alpha = lo.type(rz / pq)
+        x_lo = (x_lo + alpha * p).astype(lo)
+        r = (r - alpha * q).astype(lo)
+        it += 1
+        rn_lo = float(np.sqrt(np.dot(f64(r), f64(r))))
+        if rn_lo <= tol or rn_lo <= upd:
+            x += f64(x_lo)
+            r_hi = b - A @ x
+            rn = float(np.linalg.norm(r_hi))
+            replaced.append(it)
+            if rn <= tol:
+                return KrylovResult(x, it, rn / bn, OK, replaced)
+            r = r_hi.astype(lo)
+            x_lo = np.zeros_like(r)
+            upd = delta * rn
+        z = (r / d_lo).astype(lo)
+        rz_new = float(np.dot(f64(r), f64(z)))
+        p = (z + lo.type(rz_new / rz) * p).astype(lo)
+        rz = rz_new
+    x += f64(x_lo)
+    rn = float(np.linalg.norm(b - A @ x))
+    return KrylovResult(x, it, rn / bn, OK if rn <= tol else NOTCONV, replaced)

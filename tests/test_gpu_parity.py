@@ -15,7 +15,7 @@ import torch
 
 import synth
 from gpu_util import T, csr_host, dev, device_mesh, rel, say
-from oracle import graph, ipcs, krylov, p1
+from oracle import graph, ipcs, krylov, p1, mixed
 
 pytestmark = pytest.mark.gpu
 
@@ -260,6 +260,12 @@ def test_pcg_mixed_meets_fp64_tolerance(oa, prob):
     assert out["iters"] <= 1.5 * ref.iters + 20, (out["iters"], ref.iters)
     xr = ref.x - ref.x.mean()
     assert rel(xg - xg.mean(), xr) < 1e-5
+    # the same reliable-update scheme in the oracle (FP32 recurrences, FP64
+    # replacements): iteration counts agree up to FP32 summation order
+    rr = mixed.reliable_pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8, delta=0.1)
+    say("mixed PCG iterations: GPU %d, oracle reliable-update %d, FP64 %d" % (out["iters"], rr.iters, ref.iters))
+    assert rr.status == krylov.OK
+    assert abs(out["iters"] - rr.iters) <= 0.15 * rr.iters + 5, (out["iters"], rr.iters)
 
 
 def test_bicgstab_mixed_meets_fp64_tolerance(oa):

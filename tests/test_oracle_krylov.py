@@ -99,3 +99,42 @@ def test_mixed_refinement_reaches_fp64_tolerance():
     assert rel < 1e-5
     rb = mixed.refine("bicgstab", A, b[0], st.U1[0], rtol=1e-10, inner_rtol=1e-4)
     assert rb.status == krylov.OK and rb.rel_res <= 1e-10
+
+
+def test_reliable_pcg_in_fp64_is_plain_pcg():
+    """With FP64 recurrences the residual replacements change r only by
+    rounding and keep the direction, so the iteration is Jacobi-PCG: the
+    same iteration count (within one) and the same answer.  A restart of the
+    direction at a replacement, or a wrong beta, costs many iterations."""
+    prob = synth.channel_flow("small")
+    S, st, A, b = _tent(prob)
+    rng = np.random.default_rng(21)
+    bphi = rng.normal(size=S.K.shape[0])
+    bphi -= bphi.mean()
+    x0 = rng.normal(size=bphi.size) * 0.1
+    ref = krylov.pcg(S.K, bphi, x0, rtol=1e-8)
+    r = mixed.reliable_pcg(S.K, bphi, x0, rtol=1e-8, delta=0.1, inner_dtype=np.float64)
+    assert r.status == krylov.OK and r.rel_res <= 1e-8
+    assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+    assert len(r.history) >= 7                       # one replacement per decade of 1e-8
+    assert np.linalg.norm(r.x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_reliable_pcg_fp32_reaches_fp64_tolerance():
+    prob = synth.channel_flow("small")
+    S, st, A, b = _tent(prob)
+    rng = np.random.default_rng(22)
+    bphi = rng.normal(size=S.K.shape[0])
+    bphi -= bphi.mean()
+    ref = krylov.pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-12)
+    r64 = krylov.pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8)
+    r = mixed.reliable_pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8)
+    assert r.status == krylov.OK
+    assert np.linalg.norm(bphi - S.K @ r.x) <= 1e-8 * np.linalg.norm(bphi)
+    assert r.iters <= 1.3 * r64.iters, (r.iters, r64.iters)
+    rel = np.linalg.norm((r.x - r.x.mean()) - (ref.x - ref.x.mean())) / np.linalg.norm(ref.x - ref.x.mean())
+    assert rel < 1e-5
+    # FP32 recurrences alone stall: without replacements the true residual
+    # cannot reach 1e-8 even though the recursive one does
+    rs = mixed.reliable_pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8, delta=0.0, maxit=3 * r64.iters)
+    assert rs.status == krylov.NOTCONV and rs.rel_res > 1e-7
