@@ -207,9 +207,10 @@ int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x,
               const oasis_krylov_opts *opt, void *ws, size_t ws_bytes,
               oasis_krylov_stats *stats);
 
-/* BiCGStab (van der Vorst) with left Jacobi preconditioning on an F64 CSR
- * matrix, for nrhs in {1,2,3} right-hand sides sharing A (one pass over A
- * per product for all of them).  b, x: device double [nrhs][n]; stats:
+/* BiCGStab (van der Vorst) with right Jacobi preconditioning (the iteration
+ * runs on A D^{-1} y = b, x = D^{-1} y, so its residual is the true one) on
+ * an F64 CSR matrix, for nrhs in {1,2,3} right-hand sides sharing A (one
+ * pass over A per product for all of them).  b, x: device double [nrhs][n]; stats:
  * host [nrhs].  On a breakdown the solve restarts once with r_hat = r.
  * Returns the worst status over the right-hand sides.  Synchronises. */
 int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, const double *b,

@@ -9,7 +9,7 @@ Readings taken where the paper is silent:
   atol = 0.  The recursively updated residual triggers the test, which is
   then confirmed with an explicit b - A x; if that fails the loop continues
   from the explicit residual.
-* BiCGStab uses left Jacobi preconditioning (the operator D^{-1} A, with D
+* BiCGStab uses right Jacobi preconditioning (the operator A D^{-1}, with D
   the diagonal of A after Dirichlet rows have been replaced by identity
   rows), shadow residual r_hat = r_0, and the early exit on ||s||.  On a
   breakdown (rho = 0, (r_hat, v) = 0 or omega = 0) it restarts once with
@@ -89,19 +89,19 @@ def pcg(A, b, x0, rtol=1e-8, maxit=10000, diag=None, history=False):
 
 
 def bicgstab(A, b, x0, rtol=1e-8, maxit=10000, diag=None, history=False):
-    """BiCGStab (van der Vorst) on the left-Jacobi-preconditioned system.
-
-    Works on r = D^{-1}(b - A x); convergence is judged on the unpreconditioned
-    residual ||D r||_2 = ||b - A x||_2."""
+    """BiCGStab (van der Vorst) with right Jacobi preconditioning: the
+    iteration runs on A D^{-1} y = b with x = D^{-1} y, written in x so that
+    p_hat = D^{-1} p and s_hat = D^{-1} s are the preconditioned directions.
+    Its residual r is the true residual b - A x."""
     d = A.diagonal() if diag is None else diag
     x = np.array(x0, dtype=np.float64, copy=True)
     bnorm = float(np.linalg.norm(b))
     tol = rtol * bnorm
-    r = (b - A @ x) / d
-    hist = [float(np.linalg.norm(d * r))] if history else []
+    r = b - A @ x
+    hist = [float(np.linalg.norm(r))] if history else []
     if not np.all(np.isfinite(r)):
         return KrylovResult(x, 0, float("nan"), NAN, hist)
-    if np.linalg.norm(d * r) <= tol:
+    if np.linalg.norm(r) <= tol:
         return KrylovResult(x, 0, _true_rel(A, b, x, bnorm), OK, hist)
     rhat = r.copy()
     rho_old = alpha = omega = 1.0
@@ -109,20 +109,22 @@ def bicgstab(A, b, x0, rtol=1e-8, maxit=10000, diag=None, history=False):
     p = np.zeros_like(x)
     restarted = False
     it = 0
+
+    def restart():
+        return r.copy(), 1.0, 1.0, 1.0, np.zeros_like(x), np.zeros_like(x)
+
     while it < maxit:
         rho = float(rhat @ r)
         if rho == 0.0:
             if restarted:
                 return KrylovResult(x, it, _true_rel(A, b, x, bnorm), BREAKDOWN, hist)
             restarted = True
-            rhat = r.copy()
-            rho_old = alpha = omega = 1.0
-            v[:] = 0.0
-            p[:] = 0.0
+            rhat, rho_old, alpha, omega, v, p = restart()
             continue
         beta = (rho / rho_old) * (alpha / omega)
         p = r + beta * (p - omega * v)
-        v = (A @ p) / d
+        ph = p / d
+        v = A @ ph
         rv = float(rhat @ v)
         if rv == 0.0 or not np.isfinite(rv):
             if not np.isfinite(rv):
@@ -130,28 +132,26 @@ def bicgstab(A, b, x0, rtol=1e-8, maxit=10000, diag=None, history=False):
             if restarted:
                 return KrylovResult(x, it, _true_rel(A, b, x, bnorm), BREAKDOWN, hist)
             restarted = True
-            rhat = r.copy()
-            rho_old = alpha = omega = 1.0
-            v[:] = 0.0
-            p[:] = 0.0
+            rhat, rho_old, alpha, omega, v, p = restart()
             continue
         alpha = rho / rv
         s = r - alpha * v
         it += 1
-        sn = float(np.linalg.norm(d * s))
+        sn = float(np.linalg.norm(s))
         if sn <= tol:
-            xs = x + alpha * p
+            xs = x + alpha * ph
             if np.linalg.norm(b - A @ xs) <= tol:
                 x = xs
                 if history:
                     hist.append(sn)
                 return KrylovResult(x, it, _true_rel(A, b, x, bnorm), OK, hist)
-        t = (A @ s) / d
+        sh = s / d
+        t = A @ sh
         tt = float(t @ t)
         omega = float(t @ s) / tt if tt > 0.0 else 0.0
-        x += alpha * p + omega * s
+        x += alpha * ph + omega * sh
         r = s - omega * t
-        rn = float(np.linalg.norm(d * r))
+        rn = float(np.linalg.norm(r))
         if history:
             hist.append(rn)
         if not np.isfinite(rn):
@@ -160,15 +160,12 @@ def bicgstab(A, b, x0, rtol=1e-8, maxit=10000, diag=None, history=False):
             r_true = b - A @ x
             if np.linalg.norm(r_true) <= tol:
                 return KrylovResult(x, it, _true_rel(A, b, x, bnorm), OK, hist)
-            r = r_true / d
+            r = r_true
         if omega == 0.0:
             if restarted:
                 return KrylovResult(x, it, _true_rel(A, b, x, bnorm), BREAKDOWN, hist)
             restarted = True
-            rhat = r.copy()
-            rho_old = alpha = omega = 1.0
-            v[:] = 0.0
-            p[:] = 0.0
+            rhat, rho_old, alpha, omega, v, p = restart()
             continue
         rho_old = rho
     return KrylovResult(x, it, _true_rel(A, b, x, bnorm), NOTCONV, hist)

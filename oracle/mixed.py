@@ -57,39 +57,40 @@ def _pcg32(A32, d32, r, rtol, maxit):
 
 
 def _bicgstab32(A32, d32, r0, rtol, maxit):
-    b = (r0.astype(np.float32) / d32).astype(np.float32)     # left Jacobi
-    dd = d32.astype(np.float64)
-    x = np.zeros_like(b)
-    r = b.copy()
+    """FP32 BiCGStab with right Jacobi preconditioning on A e = r0 (e0 = 0)."""
+    f64 = lambda a: a.astype(np.float64)  # noqa: E731
+    x = np.zeros(r0.size, dtype=np.float32)
+    r = r0.astype(np.float32)
     tol = rtol * float(np.linalg.norm(r0))
     rhat = r.copy()
     rho_old = alpha = omega = 1.0
-    v = np.zeros_like(b)
-    p = np.zeros_like(b)
+    v = np.zeros_like(r)
+    p = np.zeros_like(r)
     it = 0
-    f64 = lambda a: a.astype(np.float64)  # noqa: E731
     while it < maxit:
         rho = float(np.dot(f64(rhat), f64(r)))
         if rho == 0.0:
             break
         beta = (rho / rho_old) * (alpha / omega)
         p = (r + np.float32(beta) * (p - np.float32(omega) * v)).astype(np.float32)
-        v = ((A32 @ p) / d32).astype(np.float32)
+        ph = (p / d32).astype(np.float32)
+        v = (A32 @ ph).astype(np.float32)
         rv = float(np.dot(f64(rhat), f64(v)))
         if rv == 0.0:
             break
         alpha = rho / rv
         s = (r - np.float32(alpha) * v).astype(np.float32)
         it += 1
-        if np.linalg.norm(dd * f64(s)) <= tol:
-            x = (x + np.float32(alpha) * p).astype(np.float32)
+        if np.linalg.norm(f64(s)) <= tol:
+            x = (x + np.float32(alpha) * ph).astype(np.float32)
             break
-        t = ((A32 @ s) / d32).astype(np.float32)
+        sh = (s / d32).astype(np.float32)
+        t = (A32 @ sh).astype(np.float32)
         tt = float(np.dot(f64(t), f64(t)))
         omega = float(np.dot(f64(t), f64(s))) / tt if tt > 0 else 0.0
-        x = (x + np.float32(alpha) * p + np.float32(omega) * s).astype(np.float32)
+        x = (x + np.float32(alpha) * ph + np.float32(omega) * sh).astype(np.float32)
         r = (s - np.float32(omega) * t).astype(np.float32)
-        if np.linalg.norm(dd * f64(r)) <= tol or omega == 0.0:
+        if np.linalg.norm(f64(r)) <= tol or omega == 0.0:
             break
         rho_old = rho
     return x.astype(np.float64), it

@@ -8,9 +8,10 @@
 //      M/dt - C/2 - nu K/2 = 2M/dt - A is never stored: the explicit part of
 //      the right-hand side is evaluated row by row as (2M/dt - A) U^{n-1}.
 //   2  one pass per row: b^k = f_k M_L + (2M/dt - A) U^{k,n-1} - dP^k p*,
-//      Dirichlet rows (identity row, b = g), then the row is divided by its
-//      diagonal (left Jacobi) for the BiCGStab solve.
-//   3  BiCGStab for all velocity components at once (x0 = U^{k,n-1}).
+//      Dirichlet rows (identity row, b = g) and the diagonal D of A; then
+//      the columns are divided by D (right Jacobi: A D^{-1} y = b, x = y/D).
+//   3  BiCGStab for all velocity components at once (x0 = U^{k,n-1}, so
+//      y0 = D U^{k,n-1}); x = y / D afterwards.
 //   4  b_phi = -(1/dt) sum_k dP^k U^{k,I}, projected on 1-perp, symmetric
 //      Jacobi scaling, CG from phi_prev (or the better of phi_prev and a
 //      supplied guess).
@@ -48,26 +49,54 @@ __global__ __launch_bounds__(kBlock) void k_diag(int n, const int *__restrict__ 
     }
 }
 
-// sym: out_ij = a_ij / (s_i s_j);  row: out_ij = a_ij / d_i.  Optional FP32 copy.
+// kScaleSym: out_ij = a_ij / (s_i s_j) (symmetric Jacobi scaling);
+// kScaleCol: out_ij = a_ij / s_j (right Jacobi).  Optional FP32 copy.
+constexpr int kScaleSym = 1, kScaleCol = 2;
 __global__ __launch_bounds__(kBlock) void k_scale_matrix(int n, const int *__restrict__ rp,
                                                          const int *__restrict__ ci,
                                                          const double *__restrict__ a,
-                                                         const double *__restrict__ s, int sym,
+                                                         const double *__restrict__ s, int mode,
                                                          double *__restrict__ out,
                                                          float *__restrict__ out32) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const double si = s[i];
+        const double si = mode == kScaleSym ? s[i] : 1.0;
         for (int j = rp[i]; j < rp[i + 1]; ++j) {
-            const double v = sym ? a[j] / (si * s[ci[j]]) : a[j] / si;
+            const double v = a[j] / (si * s[ci[j]]);
             out[j] = v;
             if (out32) out32[j] = static_cast<float>(v);
         }
     }
 }
 
+// In place over the CSR entries: a_j /= d[col_j] (right Jacobi), FP32 copy.
+__global__ __launch_bounds__(kBlock) void k_colscale(long long nnz, const int *__restrict__ ci,
+                                                     const double *__restrict__ d, double *__restrict__ a,
+                                                     float *__restrict__ a32) {
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < nnz;
+         j += (long long)gridDim.x * blockDim.x) {
+        const double v = a[j] / d[ci[j]];
+        a[j] = v;
+        if (a32) a32[j] = static_cast<float>(v);
+    }
+}
+
+// x_k *= d (op 1) or x_k /= d (op 2) for up to 3 vectors, in place
+__global__ __launch_bounds__(kBlock) void k_scale3(int n, const double *__restrict__ d, int op, double *x0,
+                                                   double *x1, double *x2) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double di = d[i];
+        double *xs[3] = {x0, x1, x2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (xs[k]) xs[k][i] = op == 1 ? xs[k][i] * di : xs[k][i] / di;
+    }
+}
+
 // per-row vector set-up from a diagonal: mode 0 (CG): s = sqrt(d), w = d;
-// mode 1 (BiCGStab): s = d, w = d^2.  flag set if a diagonal is unusable.
+// mode 1 (BiCGStab, right Jacobi: its residual is the true one): s = d,
+// w = 1.  flag set if a diagonal is unusable.
 __global__ __launch_bounds__(kBlock) void k_diag_vectors(int n, const double *d, int mode, double *s,
                                                          double *w, float *w32, int *flag) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -75,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_vectors(int n, const double *d,
         const double v = d[i];
         if (mode == 0 ? !(v > 0.0) : !(v != 0.0) || !__builtin_isfinite(v)) atomicOr(flag, 1);
         s[i] = mode == 0 ? sqrt(v) : v;
-        w[i] = mode == 0 ? v : v * v;
+        w[i] = mode == 0 ? v : 1.0;
         if (w32) w32[i] = static_cast<float>(w[i]);
     }
 }
@@ -163,12 +192,12 @@ static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, 
 // ---------------------------------------------------------------------------
 // step kernels
 
-// Right-hand side, Dirichlet rows and left Jacobi scaling of A, one row per
+// Right-hand side, Dirichlet rows and the diagonal of A, one row per
 // lane group.  x0 of the velocity solve (U^{n-1}) is copied on the way.
 template <int D, int L>
 __global__ __launch_bounds__(kBlock) void k_tent_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ M,
-    double *__restrict__ A, float *__restrict__ A32, P3 dP, P3 U1, const double *__restrict__ p,
+    double *__restrict__ A, P3 dP, P3 U1, const double *__restrict__ p,
     const double *__restrict__ ML, const int *__restrict__ bc_index, const double *__restrict__ g,
     int nbc, double f0, double f1, double f2, double two_over_dt, double *__restrict__ b0,
     double *__restrict__ b1, double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1,
@@ -206,24 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
         diag = group_sum<L>(diag);
         const int q = bc_index[i];
         const double dd = q >= 0 ? 1.0 : diag;
-        const double inv = 1.0 / dd;
-        for (int j = s + lane; j < e; j += L) {
-            double a = A[j];
-            if (q >= 0) a = (ci[j] == i) ? 1.0 : 0.0;
-            a *= inv;
-            A[j] = a;
-            if (A32) A32[j] = static_cast<float>(a);
-        }
+        if (q >= 0)
+            for (int j = s + lane; j < e; j += L) A[j] = (ci[j] == i) ? 1.0 : 0.0;
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const double bk = q >= 0 ? g[k * nbc + q] : f[k] * ML[i] + acc[k] - accp[k];
-                bo[k][i] = bk * inv;
-                xo[k][i] = U1.p[k][i];
+                bo[k][i] = q >= 0 ? g[k * nbc + q] : f[k] * ML[i] + acc[k] - accp[k];
+                xo[k][i] = dd * U1.p[k][i];      // y0 = D x0 for the column-scaled system
             }
             dA[i] = dd;
-            wA[i] = dd * dd;
-            if (wA32) wA32[i] = static_cast<float>(dd * dd);
+            wA[i] = 1.0;
+            if (wA32) wA32[i] = 1.f;
         }
     }
 }
@@ -231,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
 // Row-gather form of step 1+2: every row assembles its own entries of
 // A = B + C(u_bar)/2 from the cells around its dof (the convection part of
 // Alg. 2's coefficient matrix), then forms the right-hand side, the
-// Dirichlet row and the left Jacobi scaling in the same pass.  One thread
+// Dirichlet row and the diagonal in the same pass.  One thread
 // owns one row; the row's columns and values live in MAXC registers and an
 // element contribution (column dof c, value v) is added to the slot whose
 // column equals c (a compile-time unrolled match).  The incident cells are
@@ -244,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
     const int *__restrict__ cells, const int *__restrict__ v2d, const double *__restrict__ X, P3 U1, P3 U2,
     const double *__restrict__ p, const double *__restrict__ ML, const int *__restrict__ bc_index,
     const double *__restrict__ g, int nbc, double f0, double f1, double f2, double two_over_dt,
-    double *__restrict__ A, float *__restrict__ A32, double *__restrict__ b0, double *__restrict__ b1,
+    double *__restrict__ A, double *__restrict__ b0, double *__restrict__ b1,
     double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1, double *__restrict__ x2,
     double *__restrict__ dA, double *__restrict__ wA, float *__restrict__ wA32) {
     constexpr int NV = D + 1;
@@ -323,26 +345,22 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
         }
         const int qb = bc_index[i];
         const double dd0 = qb >= 0 ? 1.0 : diag;
-        const double inv = 1.0 / dd0;
 #pragma unroll
         for (int q = 0; q < MAXC; ++q) {
             if (q < len) {
                 double v = a[q];
                 if (qb >= 0) v = (col[q] == i) ? 1.0 : 0.0;
-                v *= inv;
                 A[s + q] = v;
-                if (A32) A32[s + q] = static_cast<float>(v);
             }
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double bk = qb >= 0 ? g[k * nbc + qb] : f[k] * ML[i] + acc[k] - accp[k];
-            bo[k][i] = bk * inv;
-            xo[k][i] = U1.p[k][i];
+            bo[k][i] = qb >= 0 ? g[k * nbc + qb] : f[k] * ML[i] + acc[k] - accp[k];
+            xo[k][i] = dd0 * U1.p[k][i];      // y0 = D x0 for the column-scaled system
         }
         dA[i] = dd0;
-        wA[i] = dd0 * dd0;
-        if (wA32) wA32[i] = static_cast<float>(dd0 * dd0);
+        wA[i] = 1.0;
+        if (wA32) wA32[i] = 1.f;
     }
 }
 
@@ -643,7 +661,7 @@ static int ir_cg(hipStream_t s, int n, const int *rp, const int *ci, const doubl
     return out.status;
 }
 
-// BiCGStab for nr right-hand sides with FP32 inner solves (row-scaled system).
+// BiCGStab for nr right-hand sides with FP32 inner solves (column-scaled system).
 static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *ci,
                        const double *val, const float *val32, const double *w, const float *w32,
                        double *const *b, double *const *x, const KOpts &o, BiWork<float> &bw,
@@ -888,7 +906,7 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->B, h->dtmp);
     hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dtmp, 0, h->sK, h->wK, h->wK32,
                        h->flag + 1);
-    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->B, h->sK, 1,
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->B, h->sK, kScaleSym,
                        h->Ks, h->Ks32);
     hipLaunchKernelGGL(k_lincomb, dim3(gvec(nnz)), dim3(kBlock), 0, s, (long long)nnz, h->B, h->M,
                        1.0 / par->dt, h->B, 0.5 * par->nu);
@@ -968,7 +986,7 @@ extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const doubl
             if (which - OASIS_FORM_GRAD_X >= h->dim) return OASIS_EINVAL;
             *val = h->dP[which - OASIS_FORM_GRAD_X];
             return OASIS_OK;
-        case 100: *val = h->A; return OASIS_OK;      // last tentative matrix, row-scaled
+        case 100: *val = h->A; return OASIS_OK;      // last tentative matrix, column-scaled
         case 101: *val = h->dA; return OASIS_OK;     // its diagonal before scaling
         default: return OASIS_EINVAL;
     }
@@ -984,7 +1002,7 @@ static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_s
         U1.p[k] = st->U1[k];
     }
     const int grid = grid_for(n, kBlock / L, 1 << 20);
-    hipLaunchKernelGGL((k_tent_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A, h->A32,
+    hipLaunchKernelGGL((k_tent_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A,
                        dP, U1, st->p, h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1],
                        h->par.f[2], 2.0 / h->par.dt, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0],
                        x[1], D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
@@ -1003,7 +1021,7 @@ static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st,
     hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->B, h->M, dP,
                        h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, U1, U2, st->p, h->ML,
                        h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1], h->par.f[2], 2.0 / h->par.dt,
-                       h->A, h->A32, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0], x[1],
+                       h->A, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0], x[1],
                        D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
 }
 
@@ -1069,13 +1087,17 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         OASIS_TRY(scale_copy(s, h->nnz, h->A, h->B, 1.0));
         OASIS_TRY(assemble_colored(s, &h->mesh, h->rp, h->ci, h->A, OASIS_FORM_CONV, 0.5, U1, U2, 1.5, -0.5,
                                    nullptr));
-        // 2. right-hand sides, Dirichlet rows, scaling; x0 = U^{n-1}
+        // 2. right-hand sides, Dirichlet rows, diagonal; y0 = D U^{n-1}
         if (D == 3)
             launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
         else
             launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
         OASIS_TRY_LAUNCH();
     }
+    // right Jacobi: the solves run on A D^{-1} in y = D x
+    hipLaunchKernelGGL(k_colscale, dim3(grid_for(h->nnz, kBlock, 1 << 20)), dim3(kBlock), 0, s, (long long)h->nnz,
+                       h->ci, h->dA, h->A, h->mixed ? h->A32 : nullptr);
+    OASIS_TRY_LAUNCH();
     OASIS_TRY_HIP(hipEventRecord(h->ev[1], s));
     // 3. tentative velocity
     oasis_krylov_opts o{};
@@ -1091,6 +1113,8 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         rc_u = bicgstab_solve<double>(s, n, D, h->rp, h->ci, h->A, h->wA, h->bt, x, ko.rtol, ko.maxit, 0, false,
                                       h->bi, su);
     if (rc_u == OASIS_EHIP) return rc_u;
+    hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dA, 2, x[0], x[1], D > 2 ? x[2] : nullptr);
+    OASIS_TRY_LAUNCH();
     OASIS_TRY_HIP(hipEventRecord(h->ev[2], s));
     // 4. pressure correction
     int gd = 0;
@@ -1262,7 +1286,7 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
     hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.b);
     hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.b, 0, k.s, k.w, k.w32, k.flag);
-    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s, 1,
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s, kScaleSym,
                        k.val, k.val32);
     hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, b, k.s, 2, k.b);
     hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, x, k.s, 1, k.x);
@@ -1312,18 +1336,22 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
     hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.b);
     hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.b, 1, k.s, k.w, k.w32, k.flag);
-    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s, 0,
-                       k.val, k.val32);
-    double *xs[3];
-    for (int q = 0; q < nrhs; ++q) {
-        hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, b + (size_t)q * n, k.s, 2, k.bt[q]);
-        xs[q] = x + (size_t)q * n;
-    }
+    // right Jacobi: BiCGStab on A D^{-1} y = b, x = D^{-1} y
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s,
+                       kScaleCol, k.val, k.val32);
     OASIS_TRY_LAUNCH();
     int fl = 0;
     OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     OASIS_TRY_HIP(hipStreamSynchronize(s));
-    if (fl) return OASIS_EINVAL;
+    if (fl) return OASIS_EINVAL;     // x untouched
+    double *xs[3] = {nullptr, nullptr, nullptr};
+    for (int q = 0; q < nrhs; ++q) {
+        OASIS_TRY_HIP(hipMemcpyAsync(k.bt[q], b + (size_t)q * n, (size_t)n * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+        xs[q] = x + (size_t)q * n;
+    }
+    hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.s, 1, xs[0], xs[1], xs[2]);
+    OASIS_TRY_LAUNCH();
     const KOpts ko = kopts(opt);
     SolveOut so[3];
     int rc;
@@ -1334,6 +1362,8 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
         rc = bicgstab_solve<double>(s, n, nrhs, A->row_ptr, A->col_idx, k.val, k.w, k.bt, xs, ko.rtol, ko.maxit,
                                     ko.check_every, ko.time, k.bi, so);
     if (rc == OASIS_EHIP) return rc;
+    hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.s, 2, xs[0], xs[1], xs[2]);
+    OASIS_TRY_LAUNCH();
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < nrhs; ++q) fill_stats(so[q], stats + q);
     return rc;

@@ -5,8 +5,9 @@
 // nothing inside the loop:
 //   CG       : Ms = D^{-1/2} K D^{-1/2} (unit diagonal); same iterates as
 //              CG with z = D^{-1} r in exact arithmetic.
-//   BiCGStab : As = D^{-1} A (left Jacobi); residual norms are weighted so
-//              that the stopping test is on the unscaled ||b - A x||.
+//   BiCGStab : As = A D^{-1} (right Jacobi, iterate y = D x); its residual
+//              is the true b - A x.  The residual norms take per-row
+//              weights (1 here), so that other scalings can reuse the loop.
 //
 // Convergence is decided on the device.  Every kernel of an iteration
 // first sums the partials of the previous kernel (fixed order, identical in

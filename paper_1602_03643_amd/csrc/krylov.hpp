@@ -1,5 +1,5 @@
 // Internal Krylov solver interfaces (CG on a symmetrically scaled SPD
-// matrix, BiCGStab on a row-scaled matrix) shared by the standalone entry
+// matrix, BiCGStab on a column-scaled matrix) shared by the standalone entry
 // points and the IPCS step.
 #pragma once
 
@@ -72,7 +72,7 @@ int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, c
              const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
              CGWork<T> &w, SolveOut &out);
 
-// BiCGStab for nrhs systems with the row-scaled matrix As (left Jacobi).
+// BiCGStab for nrhs systems with the column-scaled matrix As (right Jacobi).
 template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,

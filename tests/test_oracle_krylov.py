@@ -138,3 +138,24 @@ def test_reliable_pcg_fp32_reaches_fp64_tolerance():
     # cannot reach 1e-8 even though the recursive one does
     rs = mixed.reliable_pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8, delta=0.0, maxit=3 * r64.iters)
     assert rs.status == krylov.NOTCONV and rs.rel_res > 1e-7
+
+
+def test_bicgstab_right_jacobi_is_plain_bicgstab_on_column_scaled_matrix():
+    """Right Jacobi preconditioning means BiCGStab on A D^{-1} in y = D x:
+    running the unpreconditioned method (diag = 1) on the explicitly
+    column-scaled matrix must give the same iterations and, after x = y/d,
+    the same solution.  Left preconditioning (D^{-1} A) fails this."""
+    prob = synth.channel_flow("small", seed=5)
+    S, st, A, b = _tent(prob)
+    d = A.diagonal()
+    Ac = (A @ sp.diags(1.0 / d)).tocsr()
+    for k in range(3):
+        r1 = krylov.bicgstab(A, b[k], st.U1[k], rtol=1e-10)
+        r2 = krylov.bicgstab(Ac, b[k], d * st.U1[k], rtol=1e-10, diag=np.ones_like(d))
+        assert r1.status == krylov.OK and r2.status == krylov.OK
+        assert r1.iters == r2.iters
+        assert np.linalg.norm(r1.x - r2.x / d) <= 1e-9 * np.linalg.norm(r1.x)
+    Al = (sp.diags(1.0 / d) @ A).tocsr()
+    x_left = krylov.bicgstab(Al, b[0] / d, st.U1[0], rtol=1e-10, maxit=3, diag=np.ones_like(d)).x
+    x_right = krylov.bicgstab(A, b[0], st.U1[0], rtol=1e-10, maxit=3).x
+    assert np.linalg.norm(x_left - x_right) > 1e-6 * np.linalg.norm(x_right)
