@@ -317,9 +317,17 @@ int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, const double *c
  * unscaled K is returned as scaled values plus sqrt of its diagonal, see
  * below) or _GRAD_X.. ; lumped mass via which = -1.  *scaled_diag_sqrt
  * (may be NULL) receives sqrt(diag K) for _STIFF, with K_ij = Ks_ij *
- * s_i * s_j. */
+ * s_i * s_j.  State of the last step: OASIS_INSPECT_A (the tentative
+ * matrix after Dirichlet rows, column-scaled: A_ij = val_ij * d_j),
+ * OASIS_INSPECT_DIAG_A (d = diag A, [n]), OASIS_INSPECT_RHS + k (the
+ * tentative right-hand side of component k, [n]).  Pointers stay valid
+ * for the handle's lifetime; their contents change with every step. */
 int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const double **val,
                       const double **scaled_diag_sqrt);
+
+#define OASIS_INSPECT_A 100
+#define OASIS_INSPECT_DIAG_A 101
+#define OASIS_INSPECT_RHS 102
 
 int oasis_ipcs_destroy(oasis_ipcs *h);
 

@@ -8,7 +8,8 @@ it has not been built.
 from . import _lib
 from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUNSUPPORTED, F32, F64,
                    FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, PSTART_PREV,
-                   PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, OasisError)
+                   PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS,
+                   OasisError)
 
 _lib.load()
 
@@ -19,4 +20,4 @@ __all__ = ["IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bicgstab",
            "colorize", "p1_pattern", "pcg", "rcm", "relabel", "spmv", "OasisError",
            "OK", "EINVAL", "EHIP", "ENOTCONV", "EBREAKDOWN", "ENAN", "EWORKSPACE", "EUNSUPPORTED", "F32", "F64",
            "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV", "PSTART_PREV",
-           "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS"]
+           "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS"]

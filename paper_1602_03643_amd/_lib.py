@@ -18,6 +18,7 @@ KRYLOV_TIME = 1
 KRYLOV_NULLSPACE_CONST = 2
 ASSEMBLE_ROWS, ASSEMBLE_COLORS = 0, 1
 PSTART_PREV, PSTART_ZERO = 0, 1
+INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS = 100, 101, 102
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
 

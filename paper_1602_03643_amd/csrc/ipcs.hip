@@ -763,6 +763,7 @@ struct oasis_ipcs {
     double *M = nullptr, *Ks = nullptr, *dP[3] = {nullptr, nullptr, nullptr}, *B = nullptr, *A = nullptr;
     float *A32 = nullptr, *Ks32 = nullptr;
     double *ML = nullptr, *sK = nullptr, *wK = nullptr, *dA = nullptr, *wA = nullptr, *dtmp = nullptr;
+    double *rtmp = nullptr;   // residual scratch of the warm-start guard
     float *wK32 = nullptr, *wA32 = nullptr, *vnull32 = nullptr, *xlo = nullptr;
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
@@ -804,6 +805,7 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
     h.dA = c.take<double>(n);
     h.wA = c.take<double>(n);
     h.dtmp = c.take<double>(n);
+    h.rtmp = c.take<double>(n);
     h.bc_index = c.take<int>(n);
     h.flag = c.take<int>(32);
     for (int k = 0; k < dim; ++k) {
@@ -986,8 +988,12 @@ extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const doubl
             if (which - OASIS_FORM_GRAD_X >= h->dim) return OASIS_EINVAL;
             *val = h->dP[which - OASIS_FORM_GRAD_X];
             return OASIS_OK;
-        case 100: *val = h->A; return OASIS_OK;      // last tentative matrix, column-scaled
-        case 101: *val = h->dA; return OASIS_OK;     // its diagonal before scaling
+        case OASIS_INSPECT_A: *val = h->A; return OASIS_OK;
+        case OASIS_INSPECT_DIAG_A: *val = h->dA; return OASIS_OK;
+        case OASIS_INSPECT_RHS: case OASIS_INSPECT_RHS + 1: case OASIS_INSPECT_RHS + 2:
+            if (which - OASIS_INSPECT_RHS >= h->dim) return OASIS_EINVAL;
+            *val = h->bt[which - OASIS_INSPECT_RHS];
+            return OASIS_OK;
         default: return OASIS_EINVAL;
     }
 }
@@ -1144,11 +1150,11 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         double wr_plain = 0, wr_guess = 0, wbb = 0;
         hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, phi_guess, h->sK, 1, h->xg);
         OASIS_TRY_LAUNCH();
-        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->bt[0], h->cg, &wr_guess, &wbb));
+        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->rtmp, h->cg, &wr_guess, &wbb));
         if (zero_start)
             wr_plain = wbb;
         else
-            OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->bt[0], h->cg, &wr_plain,
+            OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->rtmp, h->cg, &wr_plain,
                                   &wbb));
         if (std::isfinite(wr_guess) && wr_guess < wr_plain) {
             hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, h->xs, h->xg);

@@ -171,20 +171,31 @@ def channel(nx: int, ny: int, nz: int, beta: float = 2.0,
             delta = -displace_frac * lo[sel] + u * displace_frac * (lo[sel] + hi[sel])
             coords[mv[sel]] = base[mv[sel]] + delta
 
+        def touching(verts):   # cells with a vertex in verts
+            mark = np.zeros(nv, bool)
+            mark[verts] = True
+            return np.nonzero(mark[cells].any(axis=1))[0]
+
         draw(np.arange(mv.size))
+        vol = _signed_volumes_x6(coords, cells)
         for _ in range(10):
-            bad = _signed_volumes_x6(coords, cells) < quality_floor * vol0
+            bad = vol < quality_floor * vol0
             if not bad.any():
                 break
             verts = np.unique(cells[bad].ravel())
             sel = pos_in_mv[verts]
-            draw(sel[sel >= 0])
+            sel = sel[sel >= 0]
+            draw(sel)
+            t = touching(mv[sel])
+            vol[t] = _signed_volumes_x6(coords, cells[t])
         while True:
-            bad = _signed_volumes_x6(coords, cells) < quality_floor * vol0
+            bad = vol < quality_floor * vol0
             if not bad.any():
                 break
             verts = np.unique(cells[bad].ravel())
             coords[verts] = base[verts]
+            t = touching(verts)
+            vol[t] = _signed_volumes_x6(coords, cells[t])
 
     mx, mz = nx - 1, nz - 1
     dof = (ix % mx) + mx * (iy + ny * (iz % mz))
