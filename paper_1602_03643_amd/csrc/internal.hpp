@@ -120,9 +120,11 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *part, do
 // in the same order, so all blocks hold identical totals.
 // The loads are unrolled so that a thread issues all of its (at most
 // kMaxPartials / kBlock) loads at once: one cache round trip, not eight.
+// `stride` (>= NV) is the producer's values per block when the consumer
+// needs only its first NV.
 template <int NV>
 __device__ __forceinline__ void read_partials(const double *part, int nparts, double (&out)[NV],
-                                              double *lds) {
+                                              double *lds, int stride = NV) {
     constexpr int PER = kMaxPartials / kBlock;
     constexpr int U = NV <= 3 ? PER : 2;     // bound the registers held in flight
 #pragma unroll
@@ -133,7 +135,7 @@ __device__ __forceinline__ void read_partials(const double *part, int nparts, do
         for (int q = 0; q < U; ++q) {
             const int i = threadIdx.x + (q0 + q) * kBlock;
 #pragma unroll
-            for (int k = 0; k < NV; ++k) t[q][k] = i < nparts ? part[i * NV + k] : 0.0;
+            for (int k = 0; k < NV; ++k) t[q][k] = i < nparts ? part[i * stride + k] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < U; ++q)

@@ -76,14 +76,15 @@ __global__ __launch_bounds__(kBlock) void k_copy(int n, T *__restrict__ y, const
 // ---------------------------------------------------------------------------
 // CG kernels
 
-// r = b - Ms x; partials (r.r, sum wgt r^2, sum wgt b^2)
+// r = b - Ms x (r[row * rs]: rs = 2 writes the r of a residual/direction
+// pair); partials (r.r, sum wgt r^2, sum wgt b^2)
 template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ ci,
                                                     const T *__restrict__ val,
                                                     const T *__restrict__ wgt,
                                                     const T *__restrict__ b,
-                                                    const T *__restrict__ x, T *__restrict__ r,
+                                                    const T *__restrict__ x, T *__restrict__ r, int rs,
                                                     double *part) {
     __shared__ double lds[3 * kBlock / kWave];
     double acc[3] = {0.0, 0.0, 0.0};
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict
         [&](int row, int lane, T(&a)[1]) {
             if (lane == 0) {
                 const T ri = b[row] - a[0];
-                r[row] = ri;
+                r[static_cast<long long>(row) * rs] = ri;
                 const double rd = ri, bd = b[row], wd = wgt[row];
                 acc[0] += rd * rd;
                 acc[1] += wd * rd * rd;
@@ -124,42 +125,44 @@ __global__ __launch_bounds__(kBlock) void k_cg_finalize(const double *part, int 
     }
 }
 
-// r_lo = (float) r_hi, x_lo = 0; partials of r_lo in the k_cg_init layout
+// r_lo = (float) r_hi into the r of a residual/direction pair (the
+// direction is kept), x_lo = 0; partials (r.r, sum wgt r^2)
 __global__ __launch_bounds__(kBlock) void k_cg_cast(int n, const double *__restrict__ rhi,
                                                     const float *__restrict__ wgt,
-                                                    float *__restrict__ rlo, float *__restrict__ xlo,
+                                                    RP<float> *__restrict__ pr, float *__restrict__ xlo,
                                                     double *part) {
-    __shared__ double lds[3 * kBlock / kWave];
-    double acc[3] = {0.0, 0.0, 0.0};
+    __shared__ double lds[2 * kBlock / kWave];
+    double acc[2] = {0.0, 0.0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const float r = static_cast<float>(rhi[i]);
-        rlo[i] = r;
+        pr[i].r = r;
         xlo[i] = 0.f;
         const double rd = r;
         acc[0] += rd * rd;
         acc[1] += static_cast<double>(wgt[i]) * rd * rd;
     }
-    write_partials<3>(acc, part, lds);
+    write_partials<2>(acc, part, lds);
 }
 
 // Iteration part 1: convergence test on the incoming residual, direction
-// p_new = r + beta p_old (formed on the fly for the gathered operand),
-// q = Ms p_new, partial p_new.q.
+// p_new = r + beta p_old formed on the fly for the gathered operand (one
+// gather of the (r, p_old) pair per entry), q = Ms p_new, partial p_new.q.
+// partIn holds nIn blocks of `stride` values whose first two are
+// (r.r, sum wgt r^2).
 template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__ rp,
                                                   const int *__restrict__ ci,
                                                   const T *__restrict__ val,
-                                                  const T *__restrict__ r,
-                                                  const T *__restrict__ pold,
-                                                  T *__restrict__ pnew, T *__restrict__ q,
-                                                  const double *partIn, int nIn, CGState *st,
+                                                  const RP<T> *__restrict__ cur,
+                                                  RP<T> *__restrict__ nxt, T *__restrict__ q,
+                                                  const double *partIn, int nIn, int stride, CGState *st,
                                                   int it, int beta_zero, const T *__restrict__ vnull,
                                                   double *partOut) {
-    __shared__ double lds[3 * kBlock / kWave];
+    __shared__ double lds[2 * kBlock / kWave];
     if (block_read_flag(&st->flag)) return;
-    double v[3];
-    read_partials<3>(partIn, nIn, v, lds);
+    double v[2];
+    read_partials<2>(partIn, nIn, v, lds, stride);
     const double rr = v[0], wrr = v[1];
     int flag = 0;
     if (!finite(wrr) || !finite(rr))
@@ -182,19 +185,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
     double acc[2] = {0.0, 0.0};
     auto finish = [&](int row, int lane, T(&a)[1]) {
         if (lane == 0) {
-            const T pn = beta_zero ? r[row] : r[row] + bt * pold[row];
-            pnew[row] = pn;
+            const RP<T> me = cur[row];
+            const T pn = beta_zero ? me.r : me.r + bt * me.p;
+            nxt[row].p = pn;
             q[row] = a[0];
             acc[0] += static_cast<double>(pn) * static_cast<double>(a[0]);
             if (vnull) acc[1] += static_cast<double>(vnull[row]) * static_cast<double>(a[0]);
         }
     };
-    // a fresh direction never reads p_old (its buffer may hold stale values)
+    // a fresh direction never uses p_old (it may hold stale values)
     if (beta_zero)
         csr_rows<T, 1, C>(
             n, rp, ci, val,
             [&](int, int c, T vv, bool ok, T(&a)[1]) {
-                const T t = vv * r[c];
+                const T t = vv * cur[c].r;
                 a[0] += ok ? t : T(0);
             },
             finish);
@@ -202,22 +206,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
         csr_rows<T, 1, C>(
             n, rp, ci, val,
             [&](int, int c, T vv, bool ok, T(&a)[1]) {
-                const T t = vv * (r[c] + bt * pold[c]);
+                const RP<T> g = cur[c];
+                const T t = vv * (g.r + bt * g.p);
                 a[0] += ok ? t : T(0);
             },
             finish);
     write_partials<2>(acc, partOut, lds);
 }
 
-// Iteration part 2: alpha = r.r / p.q, x += alpha p, r -= alpha q,
-// partials (r.r, sum wgt r^2, 0).
+// Iteration part 2: alpha = r.r / p.q, x += alpha p, r_new = r - alpha q
+// into the pair that already holds p; partials (r_new.r_new, sum wgt r_new^2).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_p2(int n, T *__restrict__ r, const T *__restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_cg_p2(int n, const RP<T> *__restrict__ cur, RP<T> *__restrict__ nxt,
                                                   const T *__restrict__ q, T *__restrict__ x,
                                                   const T *__restrict__ wgt, const double *partIn,
                                                   int nIn, CGState *st, int it,
                                                   const T *__restrict__ vnull, double *partOut) {
-    __shared__ double lds[3 * kBlock / kWave];
+    __shared__ double lds[2 * kBlock / kWave];
     if (block_read_flag(&st->flag)) return;
     double v[2];
     read_partials<2>(partIn, nIn, v, lds);
@@ -231,26 +236,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_p2(int n, T *__restrict__ r, cons
     }
     const T a = static_cast<T>(st->rr[it & 1] / pq);
     const T cv = static_cast<T>(v[1]);    // (v.q) for a unit null vector v
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[2] = {0.0, 0.0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const T xi = x[i] + a * p[i];
+        RP<T> nx = nxt[i];
+        const T xi = x[i] + a * nx.p;
         const T qi = vnull ? q[i] - cv * vnull[i] : q[i];
-        const T ri = r[i] - a * qi;
+        const T ri = cur[i].r - a * qi;
         x[i] = xi;
-        r[i] = ri;
+        nx.r = ri;
+        nxt[i] = nx;
         const double rd = ri;
         acc[0] += rd * rd;
         acc[1] += static_cast<double>(wgt[i]) * rd * rd;
     }
-    write_partials<3>(acc, partOut, lds);
+    write_partials<2>(acc, partOut, lds);
 }
 
 template <typename T>
 void carve_cg(Carver &c, int n, CGWork<T> &w) {
-    w.r = c.take<T>(n);
-    w.p[0] = c.take<T>(n);
-    w.p[1] = c.take<T>(n);
+    w.pair[0] = c.take<RP<T>>(n);
+    w.pair[1] = c.take<RP<T>>(n);
     w.q = c.take<T>(n);
     w.partA = c.take<double>(3 * kMaxPartials);
     w.partB = c.take<double>(3 * kMaxPartials);
@@ -314,16 +320,17 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
     const int g2 = grid_for(n, kBlock, partial_cap());
     out = SolveOut();
-    auto residual = [&](int mode) -> int {
+    // explicit residual into the r of the pair that iteration `at` reads
+    auto residual = [&](int mode, int at) -> int {
         hipLaunchKernelGGL((k_cg_init<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                           b, x, w.r, w.partB);
+                           b, x, reinterpret_cast<T *>(w.pair[at & 1]), 2, w.partB);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
                            rtol * rtol, mode, 0.0);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
-    OASIS_TRY(residual(0));
+    OASIS_TRY(residual(0, 0));
     CGState h;
     ChunkTimer tm;
     OASIS_TRY(tm.init(time_kernel));
@@ -339,15 +346,16 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
             OASIS_TRY(tm.before(s));
-            hipLaunchKernelGGL((k_cg_p1<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, w.r,
-                               w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
-                               itj == restart_at ? g1 : g2, w.st, itj, itj == restart_at ? 1 : 0,
-                               static_cast<const T *>(nullptr), w.partA);
+            // after a restart the incoming partials are k_cg_init's (3 per block)
+            hipLaunchKernelGGL((k_cg_p1<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                               w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
+                               itj == restart_at ? g1 : g2, itj == restart_at ? 3 : 2, w.st, itj,
+                               itj == restart_at ? 1 : 0, static_cast<const T *>(nullptr), w.partA);
             OASIS_TRY_LAUNCH();
             OASIS_TRY(tm.after(s));
-            hipLaunchKernelGGL((k_cg_p2<T>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
-                               w.q, x, wgt, w.partA, g1, w.st, itj, static_cast<const T *>(nullptr),
-                               w.partB);
+            hipLaunchKernelGGL((k_cg_p2<T>), dim3(g2), dim3(kBlock), 0, s, n, w.pair[itj & 1],
+                               w.pair[(itj + 1) & 1], w.q, x, wgt, w.partA, g1, w.st, itj,
+                               static_cast<const T *>(nullptr), w.partB);
             OASIS_TRY_LAUNCH();
         }
         it += m;
@@ -357,7 +365,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         if (h.flag == 0) {
             if (it < maxit) continue;
             const double wbb = h.wbb, tol2 = h.tol2;
-            OASIS_TRY(residual(1));
+            OASIS_TRY(residual(1, it));
             OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
             OASIS_TRY_HIP(hipStreamSynchronize(s));
             out.iters = it;
@@ -368,7 +376,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         if (h.flag == 1) {
             const int itd = h.it_done;
             const double wbb = h.wbb, tol2 = h.tol2;
-            OASIS_TRY(residual(1));
+            OASIS_TRY(residual(1, itd));
             OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
             OASIS_TRY_HIP(hipStreamSynchronize(s));
             if (h.wrr <= tol2) {
@@ -426,15 +434,16 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     // FP64 residual of the FP64 accumulator, then its FP32 copy (x_lo = 0)
     auto replace = [&](int mode) -> int {
         hipLaunchKernelGGL((k_cg_init<double, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                           b, x, rhi, w.partB);
+                           b, x, rhi, 1, w.partB);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
                            rtol * rtol, mode, upd);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
-    auto cast = [&]() -> int {
-        hipLaunchKernelGGL(k_cg_cast, dim3(g2), dim3(kBlock), 0, s, n, rhi, wgt32, w.r, xlo, w.partB);
+    // into the r of the pair that iteration `at` reads; its direction stays
+    auto cast = [&](int at) -> int {
+        hipLaunchKernelGGL(k_cg_cast, dim3(g2), dim3(kBlock), 0, s, n, rhi, wgt32, w.pair[at & 1], xlo, w.partB);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
@@ -458,7 +467,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         out.rel_res = rel(h.wrr);
         return OASIS_OK;
     }
-    OASIS_TRY(cast());
+    OASIS_TRY(cast(0));
     ChunkTimer tm;
     OASIS_TRY(tm.init(time_kernel));
     const int chunk = check_every > 0 ? check_every : 32;
@@ -471,13 +480,14 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
             const int itj = it + j;
             OASIS_TRY(tm.before(s));
             hipLaunchKernelGGL((k_cg_p1<float, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val32,
-                               w.r, w.p[(itj + 1) & 1], w.p[itj & 1], w.q, w.partB,
-                               j == 0 ? nin : g2, w.st, itj, itj == restart_at ? 1 : 0, vnull,
+                               w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
+                               j == 0 ? nin : g2, 2, w.st, itj, itj == restart_at ? 1 : 0, vnull,
                                w.partA);
             OASIS_TRY_LAUNCH();
             OASIS_TRY(tm.after(s));
-            hipLaunchKernelGGL((k_cg_p2<float>), dim3(g2), dim3(kBlock), 0, s, n, w.r, w.p[itj & 1],
-                               w.q, xlo, wgt32, w.partA, g1, w.st, itj, vnull, w.partB);
+            hipLaunchKernelGGL((k_cg_p2<float>), dim3(g2), dim3(kBlock), 0, s, n, w.pair[itj & 1],
+                               w.pair[(itj + 1) & 1], w.q, xlo, wgt32, w.partA, g1, w.st, itj, vnull,
+                               w.partB);
             OASIS_TRY_LAUNCH();
         }
         it += m;
@@ -516,7 +526,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
             out.status = rc = OASIS_ENOTCONV;
             break;
         }
-        OASIS_TRY(cast());
+        OASIS_TRY(cast(at));
         it = at;
         nin = g2;
     }
@@ -539,7 +549,7 @@ int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double
                 CGWork<double> &w, double *wrr, double *wbb) {
     const int g1 = grid_for(n, rows_per_block<Cfg8x2x1>(), partial_cap());
     hipLaunchKernelGGL((k_cg_init<double, Cfg8x2x1>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                       b, x, r, w.partB);
+                       b, x, r, 1, w.partB);
     OASIS_TRY_LAUNCH();
     hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0, 0.0);
     OASIS_TRY_LAUNCH();

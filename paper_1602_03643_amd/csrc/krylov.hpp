@@ -19,8 +19,17 @@ struct CGState {
 };
 
 template <typename T>
+struct alignas(2 * sizeof(T)) RP {
+    T r, p;
+};
+
+template <typename T>
 struct CGWork {
-    T *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    // Residual and direction interleaved, so that the product kernel fetches
+    // both with one gather: iteration it reads pair[it & 1] = (r_it, p_{it-1})
+    // and writes p_it, then r_{it+1}, into pair[(it + 1) & 1].
+    RP<T> *pair[2] = {nullptr, nullptr};
+    T *q = nullptr;
     double *partA = nullptr, *partB = nullptr;
     CGState *st = nullptr;
 };
