@@ -259,14 +259,20 @@ def main():
     avg_ms, cnt = time_cg_kernel(oa, torch, handles[head], pat, prec, args.kernel_iters)
     kb = cg_kernel_bytes(pat.n, pat.nnz, vbytes)
     achieved = kb / (avg_ms * 1e-3) / 1e9
-    kname = "k_cg_p1<%s>" % ("double" if vbytes == 8 else "float")
+    # the ELL product kernel runs when every row has at most 16 entries (P1 on
+    # Kuhn-split hexahedra: at most 15) unless OASIS_ELL=0
+    # (FP32 iteration only)
+    ell = (os.environ.get("OASIS_ELL", "1") != "0" and vbytes == 4
+           and int((pat.row_ptr[1:] - pat.row_ptr[:-1]).max()) <= 16)
+    kname = "k_cg_p1%s<%s>" % ("_ell" if ell else "", "double" if vbytes == 8 else "float")
     traffic = pmc_traffic(kname) if args.size == "c129" else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
                 bytes_per_launch=kb, avg_launch_ms=avg_ms, launches_timed=cnt)
     avg64, _ = time_cg_kernel(oa, torch, handles[head], pat, oa.F64, args.kernel_iters)
     kb64 = cg_kernel_bytes(pat.n, pat.nnz, 8)
-    roof["fp64_kernel"] = dict(achieved=round(kb64 / (avg64 * 1e-3) / 1e9, 1), avg_launch_ms=avg64,
+    roof["fp64_kernel"] = dict(kernel="k_cg_p1<double>",
+                               achieved=round(kb64 / (avg64 * 1e-3) / 1e9, 1), avg_launch_ms=avg64,
                                bytes_per_launch=kb64)
     cpu = None
     if not args.no_cpu and "fp64" in results:

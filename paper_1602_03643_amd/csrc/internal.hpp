@@ -122,18 +122,18 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *part, do
 // kMaxPartials / kBlock) loads at once: one cache round trip, not eight.
 // `stride` (>= NV) is the producer's values per block when the consumer
 // needs only its first NV.
-template <int NV>
+template <int NV, int BS = kBlock>
 __device__ __forceinline__ void read_partials(const double *part, int nparts, double (&out)[NV],
                                               double *lds, int stride = NV) {
-    constexpr int PER = kMaxPartials / kBlock;
-    constexpr int U = NV <= 3 ? PER : 2;     // bound the registers held in flight
+    constexpr int PER = kMaxPartials / BS;
+    constexpr int U = NV <= 3 || PER < 2 ? PER : 2;     // bound the registers held in flight
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = 0.0;
     for (int q0 = 0; q0 < PER; q0 += U) {
         double t[U][NV];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int i = threadIdx.x + (q0 + q) * kBlock;
+            const int i = threadIdx.x + (q0 + q) * BS;
 #pragma unroll
             for (int k = 0; k < NV; ++k) t[q][k] = i < nparts ? part[i * stride + k] : 0.0;
         }

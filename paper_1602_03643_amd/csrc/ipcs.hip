@@ -764,6 +764,9 @@ struct oasis_ipcs {
     float *A32 = nullptr, *Ks32 = nullptr;
     double *ML = nullptr, *sK = nullptr, *wK = nullptr, *dA = nullptr, *wA = nullptr, *dtmp = nullptr;
     double *rtmp = nullptr;   // residual scratch of the warm-start guard
+    short *ecol = nullptr;    // ELL copy of the pressure matrix for the CG product:
+    double *eval = nullptr;   // FP64 values (FP64 mode) or
+    float *eval32 = nullptr;  // their FP32 rounding (mixed mode)
     float *wK32 = nullptr, *wA32 = nullptr, *vnull32 = nullptr, *xlo = nullptr;
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
@@ -785,6 +788,11 @@ struct oasis_ipcs {
 };
 
 static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, oasis_ipcs &h) {
+    h.ecol = c.take<short>((size_t)n * kEll);
+    if (mixed)
+        h.eval32 = c.take<float>((size_t)n * kEll);
+    else
+        h.eval = c.take<double>((size_t)n * kEll);
     h.M = c.take<double>(nnz);
     h.Ks = c.take<double>(nnz);
     for (int k = 0; k < dim; ++k) h.dP[k] = c.take<double>(nnz);
@@ -914,6 +922,20 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
                        1.0 / par->dt, h->B, 0.5 * par->nu);
     hipLaunchKernelGGL(k_row_sums, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->M, h->ML);
     if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
+    // ELL copy of the pressure matrix for the CG product when its rows and
+    // column offsets allow it (else the CSR product runs)
+    {
+        bool fits = false;
+        const int rc4 = csr_to_ell(s, n, row_ptr, col_idx, h->Ks, h->ecol, h->eval, h->eval32, h->flag + 24, &fits);
+        if (rc4 != OASIS_OK) return fail(rc4);
+        if (fits && h->mixed) {
+            h->cg32.ecol = h->ecol;
+            h->cg32.eval = h->eval32;
+        } else if (fits) {
+            h->cg.ecol = h->ecol;
+            h->cg.eval = h->eval;
+        }
+    }
     // row-gather assembly: dof -> cell lists and the longest row
     h->assembly = par->assembly == OASIS_ASSEMBLE_COLORS ? OASIS_ASSEMBLE_COLORS : OASIS_ASSEMBLE_ROWS;
     if (h->assembly == OASIS_ASSEMBLE_ROWS) {
@@ -1218,6 +1240,9 @@ struct KrylovWs {
     double *val, *s, *w, *b, *x, *rhi;
     float *val32, *w32, *vnull32, *xlo;
     int *flag;
+    short *ecol;        // ELL copy of the scaled matrix for the CG product
+    double *eval;       // (FP64 mode)
+    float *eval32;      // (mixed mode)
     CGWork<double> cg;
     CGWork<float> cg32;
     BiWork<double> bi;
@@ -1234,6 +1259,11 @@ static void carve_krylov(Carver &c, int n, int nnz, int nrhs, bool mixed, Krylov
     k.b = c.take<double>(n);
     k.x = c.take<double>(n);
     k.flag = c.take<int>(16);
+    k.ecol = c.take<short>((size_t)n * kEll);
+    if (mixed)
+        k.eval32 = c.take<float>((size_t)n * kEll);
+    else
+        k.eval = c.take<double>((size_t)n * kEll);
     for (int q = 0; q < nrhs; ++q) k.bt[q] = c.take<double>(n);
     carve_cg<double>(c, n, k.cg);
     carve_bi<double>(c, n, nrhs, k.bi);
@@ -1301,6 +1331,17 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     if (fl) return OASIS_EINVAL;
+    {
+        bool fits = false;
+        OASIS_TRY(csr_to_ell(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.eval, k.eval32, k.flag + 8, &fits));
+        if (fits && mixed) {
+            k.cg32.ecol = k.ecol;
+            k.cg32.eval = k.eval32;
+        } else if (fits) {
+            k.cg.ecol = k.ecol;
+            k.cg.eval = k.eval;
+        }
+    }
     const KOpts ko = kopts(opt);
     SolveOut so;
     int rc;

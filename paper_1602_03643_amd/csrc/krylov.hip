@@ -16,6 +16,7 @@
 // flag that makes the remaining launched kernels return at once.  The host
 // enqueues iterations in chunks and polls the small state block between
 // chunks; on a convergence candidate it confirms with an explicit residual.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -33,6 +34,14 @@ int spmv_cfg() {
         return (v >= 0 && v <= 4) ? v : 1;
     }();
     return cfg;
+}
+
+bool ell_enabled() {
+    static bool on = [] {
+        const char *e = std::getenv("OASIS_ELL");
+        return !(e && e[0] == '0');
+    }();
+    return on;
 }
 
 int partial_cap() {
@@ -150,8 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_cast(int n, const double *__restr
 // gather of the (r, p_old) pair per entry), q = Ms p_new, partial p_new.q.
 // partIn holds nIn blocks of `stride` values whose first two are
 // (r.r, sum wgt r^2).
-template <typename T, class C>
-__global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__ rp,
+template <typename T, class C, int BS>
+__global__ __launch_bounds__(BS) void k_cg_p1(int n, const int *__restrict__ rp,
                                                   const int *__restrict__ ci,
                                                   const T *__restrict__ val,
                                                   const RP<T> *__restrict__ cur,
@@ -159,10 +168,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
                                                   const double *partIn, int nIn, int stride, CGState *st,
                                                   int it, int beta_zero, const T *__restrict__ vnull,
                                                   double *partOut) {
-    __shared__ double lds[2 * kBlock / kWave];
+    __shared__ double lds[2 * BS / kWave];
     if (block_read_flag(&st->flag)) return;
     double v[2];
-    read_partials<2>(partIn, nIn, v, lds, stride);
+    read_partials<2, BS>(partIn, nIn, v, lds, stride);
     const double rr = v[0], wrr = v[1];
     int flag = 0;
     if (!finite(wrr) || !finite(rr))
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
         if (lane == 0) {
             const RP<T> me = cur[row];
             const T pn = beta_zero ? me.r : me.r + bt * me.p;
-            nxt[row].p = pn;
+            nxt[row] = RP<T>{me.r, pn};    // k_cg_p2 updates r in place
             q[row] = a[0];
             acc[0] += static_cast<double>(pn) * static_cast<double>(a[0]);
             if (vnull) acc[1] += static_cast<double>(vnull[row]) * static_cast<double>(a[0]);
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
     };
     // a fresh direction never uses p_old (it may hold stale values)
     if (beta_zero)
-        csr_rows<T, 1, C>(
+        csr_rows<T, 1, C, BS>(
             n, rp, ci, val,
             [&](int, int c, T vv, bool ok, T(&a)[1]) {
                 const T t = vv * cur[c].r;
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
             },
             finish);
     else
-        csr_rows<T, 1, C>(
+        csr_rows<T, 1, C, BS>(
             n, rp, ci, val,
             [&](int, int c, T vv, bool ok, T(&a)[1]) {
                 const RP<T> g = cur[c];
@@ -214,18 +223,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_p1(int n, const int *__restrict__
     write_partials<2>(acc, partOut, lds);
 }
 
-// Iteration part 2: alpha = r.r / p.q, x += alpha p, r_new = r - alpha q
-// into the pair that already holds p; partials (r_new.r_new, sum wgt r_new^2).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_p2(int n, const RP<T> *__restrict__ cur, RP<T> *__restrict__ nxt,
+// Iteration part 2: alpha = r.r / p.q, x += alpha p, r -= alpha q in the
+// pair (r, p_new) written by part 1; partials (r.r, sum wgt r^2).
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_cg_p2(int n, RP<T> *__restrict__ nxt,
                                                   const T *__restrict__ q, T *__restrict__ x,
                                                   const T *__restrict__ wgt, const double *partIn,
                                                   int nIn, CGState *st, int it,
                                                   const T *__restrict__ vnull, double *partOut) {
-    __shared__ double lds[2 * kBlock / kWave];
+    __shared__ double lds[2 * BS / kWave];
     if (block_read_flag(&st->flag)) return;
     double v[2];
-    read_partials<2>(partIn, nIn, v, lds);
+    read_partials<2, BS>(partIn, nIn, v, lds);
     const double pq = v[0];
     if (!(pq > 0.0) || !finite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p2(int n, const RP<T> *__restrict
         RP<T> nx = nxt[i];
         const T xi = x[i] + a * nx.p;
         const T qi = vnull ? q[i] - cv * vnull[i] : q[i];
-        const T ri = cur[i].r - a * qi;
+        const T ri = nx.r - a * qi;
         x[i] = xi;
         nx.r = ri;
         nxt[i] = nx;
@@ -251,6 +260,194 @@ __global__ __launch_bounds__(kBlock) void k_cg_p2(int n, const RP<T> *__restrict
         acc[1] += static_cast<double>(wgt[i]) * rd * rd;
     }
     write_partials<2>(acc, partOut, lds);
+}
+
+// Iteration part 1 on the ELL copy of the matrix: the same computation as
+// k_cg_p1.  L lanes share a row (each holds E = kEll / L entries, fetched
+// with 8-byte offset and 16-byte value loads) and a lane group works on R
+// rows at once, so that a lane has R * E pair gathers in flight.
+template <typename T, int BS, int L, int R>
+__global__ __launch_bounds__(BS) void k_cg_p1_ell(int n, const short *__restrict__ ecol,
+                                                  const T *__restrict__ eval,
+                                                  const RP<T> *__restrict__ cur,
+                                                  RP<T> *__restrict__ nxt, T *__restrict__ q,
+                                                  const double *partIn, int nIn, int stride, CGState *st,
+                                                  int it, int beta_zero, const T *__restrict__ vnull,
+                                                  double *partOut) {
+    constexpr int E = kEll / L;
+    static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
+    __shared__ double lds[2 * BS / kWave];
+    if (block_read_flag(&st->flag)) return;
+    double v[2];
+    read_partials<2, BS>(partIn, nIn, v, lds, stride);
+    const double rr = v[0], wrr = v[1];
+    int flag = 0;
+    if (!finite(wrr) || !finite(rr))
+        flag = 3;
+    else if (wrr <= st->tol2)
+        flag = 1;
+    else if (wrr <= st->upd2)
+        flag = 4;
+    if (flag) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->flag = flag;
+            st->it_done = it;
+            st->wrr = wrr;
+        }
+        return;
+    }
+    const double beta = beta_zero ? 0.0 : rr / st->rr[(it + 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
+    const T bt = static_cast<T>(beta);
+    double acc[2] = {0.0, 0.0};
+    const int lane = threadIdx.x & (L - 1);
+    const RowRange<L, BS> range(n);
+    for (long long row0 = range.first + range.gid * R; row0 < range.last; row0 += range.ngroups * R) {
+        int c[R][E];
+        T w[R][E];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            // a row past the end repeats the last one (loads stay valid; not written)
+            const long long row = row0 + r < range.last ? row0 + r : range.last - 1;
+            const long long base = row * kEll + lane * E;
+#pragma unroll
+            for (int g = 0; g < E / 4; ++g) {
+                const short4 d = *reinterpret_cast<const short4 *>(ecol + base + 4 * g);
+                c[r][4 * g] = ell_col(row, d.x, n);
+                c[r][4 * g + 1] = ell_col(row, d.y, n);
+                c[r][4 * g + 2] = ell_col(row, d.z, n);
+                c[r][4 * g + 3] = ell_col(row, d.w, n);
+                T t[4];
+                load4(eval + base + 4 * g, t);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[r][4 * g + k] = t[k];
+            }
+        }
+        T a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            a[r] = T(0);
+            if (beta_zero) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) a[r] += w[r][k] * cur[c[r][k]].r;
+            } else {
+                RP<T> gv[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) gv[k] = cur[c[r][k]];
+#pragma unroll
+                for (int k = 0; k < E; ++k) a[r] += w[r][k] * (gv[k].r + bt * gv[k].p);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            a[r] = group_sum<L>(a[r]);
+            const long long row = row0 + r;
+            if (lane == 0 && row < range.last) {
+                const RP<T> me = cur[row];
+                const T pn = beta_zero ? me.r : me.r + bt * me.p;
+                nxt[row] = RP<T>{me.r, pn};
+                q[row] = a[r];
+                acc[0] += static_cast<double>(pn) * static_cast<double>(a[r]);
+                if (vnull) acc[1] += static_cast<double>(vnull[row]) * static_cast<double>(a[r]);
+            }
+        }
+    }
+    write_partials<2>(acc, partOut, lds);
+}
+
+// ELL product shape, lanes per row x rows per group (env OASIS_ELL_SHAPE:
+// 41, 42, 21, 22, 11, 12).
+int ell_shape() {
+    static int v = [] {
+        const char *e = std::getenv("OASIS_ELL_SHAPE");
+        const int x = e ? std::atoi(e) : 21;
+        return (x == 41 || x == 42 || x == 21 || x == 22 || x == 11 || x == 12) ? x : 21;
+    }();
+    return v;
+}
+
+// Launch the ELL product kernel in the selected shape; returns its grid.
+template <typename T, int BS>
+static int launch_p1_ell(hipStream_t s, int n, const short *ecol, const T *eval, const RP<T> *cur, RP<T> *nxt,
+                         T *q, const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
+                         const T *vnull, double *partOut, bool grid_only = false) {
+    const int cap = kMaxPartials * kBlock / BS;
+    auto go = [&](auto kern, int rows_per_blk) {
+        const int g = grid_for(n, rows_per_blk, cap);
+        if (!grid_only)
+            hipLaunchKernelGGL(kern, dim3(g), dim3(BS), 0, s, n, ecol, eval, cur, nxt, q, partIn, nIn, stride, st,
+                               it, beta_zero, vnull, partOut);
+        return g;
+    };
+    switch (ell_shape()) {
+        case 41: return go(k_cg_p1_ell<T, BS, 4, 1>, BS / 4);
+        case 42: return go(k_cg_p1_ell<T, BS, 4, 2>, BS / 4 * 2);
+        case 22: return go(k_cg_p1_ell<T, BS, 2, 2>, BS / 2 * 2);
+        case 11: return go(k_cg_p1_ell<T, BS, 1, 1>, BS);
+        case 12: return go(k_cg_p1_ell<T, BS, 1, 2>, BS * 2);
+        default: return go(k_cg_p1_ell<T, BS, 2, 1>, BS / 2);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_row(int n, const int *__restrict__ rp, int *out) {
+    int m = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        m = max(m, rp[i + 1] - rp[i]);
+    for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
+}
+
+__global__ __launch_bounds__(kBlock) void k_csr_to_ell(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                       const double *__restrict__ val, short *__restrict__ ecol,
+                                                       double *__restrict__ eval, float *__restrict__ eval32,
+                                                       int *misfit) {
+    const long long half = n / 2;
+    int bad = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int s = rp[i], len = rp[i + 1] - s;
+        bad |= len > kEll ? 1 : 0;
+        for (int k = 0; k < kEll; ++k) {
+            long long d = 0;
+            double v = 0.0;
+            if (k < len) {
+                d = static_cast<long long>(ci[s + k]) - i;
+                if (d >= half) d -= n;
+                if (d < -half) d += n;
+                v = val[s + k];
+            }
+            const bool ok = d >= -32768 && d <= 32767;
+            bad |= ok ? 0 : 1;
+            ecol[i * kEll + k] = static_cast<short>(ok ? d : 0);
+            if (eval) eval[i * kEll + k] = v;
+            if (eval32) eval32[i * kEll + k] = static_cast<float>(v);
+        }
+    }
+    if (bad) atomicOr(misfit, 1);
+}
+
+int csr_max_row(hipStream_t s, int n, const int *rp, int *tmp, int *out) {
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kBlock), 0, s, 1, tmp, 0);
+    hipLaunchKernelGGL(k_max_row, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n, rp, tmp);
+    OASIS_TRY_LAUNCH();
+    OASIS_TRY_HIP(hipMemcpyAsync(out, tmp, sizeof(int), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    return OASIS_OK;
+}
+
+int csr_to_ell(hipStream_t s, int n, const int *rp, const int *ci, const double *val, short *ecol,
+               double *eval, float *eval32, int *tmp, bool *fits) {
+    if (!ecol || (!eval && !eval32) || !tmp || !fits) return OASIS_EINVAL;
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kBlock), 0, s, 1, tmp, 0);
+    hipLaunchKernelGGL(k_csr_to_ell, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, rp, ci, val, ecol,
+                       eval, eval32, tmp);
+    OASIS_TRY_LAUNCH();
+    int misfit = 1;
+    OASIS_TRY_HIP(hipMemcpyAsync(&misfit, tmp, sizeof(int), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    *fits = misfit == 0;
+    return OASIS_OK;
 }
 
 template <typename T>
@@ -313,19 +510,62 @@ struct ChunkTimer {
     }
 };
 
-template <typename T, class C>
+// Block size of the iteration kernels (env OASIS_CG_BLOCK = 256 or 1024).
+// 1024-thread blocks keep the occupancy with a quarter of the partial sums
+// but measure slower on the product kernel; 256 is the default.
+int cg_block() {
+    static int bs = [] {
+        const char *e = std::getenv("OASIS_CG_BLOCK");
+        const int v = e ? std::atoi(e) : 256;
+        return v == 1024 ? 1024 : 256;
+    }();
+    return bs;
+}
+
+// Upper bound on the grid of the elementwise update kernel (env
+// OASIS_CG_UPDATE_GRID): a streaming kernel needs fewer resident waves than
+// the gather-bound product, and fewer blocks mean fewer partial sums for
+// the product kernel to read.
+int cg_update_grid() {
+    static int g = [] {
+        const char *e = std::getenv("OASIS_CG_UPDATE_GRID");
+        const int v = e ? std::atoi(e) : kMaxPartials / 2;
+        return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
+    }();
+    return g;
+}
+
+// Grids of the iteration kernels with BS-thread blocks: at most
+// kMaxPartials * kBlock / BS blocks, which keeps the resident waves equal.
+template <int BS>
+struct CgGrids {
+    int p1, ell, p2;
+    template <class C>
+    static CgGrids make(int n) {
+        const int cap = kMaxPartials * kBlock / BS;
+        const int cap2 = std::min(cap, cg_update_grid() * kBlock / BS);
+        return CgGrids{grid_for(n, rows_per_block<C, BS>(), cap), grid_for(n, BS / kEllLanes, cap),
+                       grid_for(n, BS, cap2)};
+    }
+};
+
+template <typename T, class C, int BS>
 static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
                   CGWork<T> &w, SolveOut &out) {
-    const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
-    const int g2 = grid_for(n, kBlock, partial_cap());
+    const int gi = grid_for(n, rows_per_block<C>(), partial_cap());     // k_cg_init (kBlock threads)
+    const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
+    const bool ell = w.ecol && w.eval && ell_enabled();
+    const int g1 = ell ? launch_p1_ell<T, BS>(s, n, w.ecol, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
+                                              nullptr, 0, 0, nullptr, nullptr, true)
+                       : g.p1;
     out = SolveOut();
     // explicit residual into the r of the pair that iteration `at` reads
     auto residual = [&](int mode, int at) -> int {
-        hipLaunchKernelGGL((k_cg_init<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+        hipLaunchKernelGGL((k_cg_init<T, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
                            b, x, reinterpret_cast<T *>(w.pair[at & 1]), 2, w.partB);
         OASIS_TRY_LAUNCH();
-        hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
+        hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, gi, w.st,
                            rtol * rtol, mode, 0.0);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
@@ -345,17 +585,22 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         tm.chunk(it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
-            OASIS_TRY(tm.before(s));
             // after a restart the incoming partials are k_cg_init's (3 per block)
-            hipLaunchKernelGGL((k_cg_p1<T, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
-                               w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
-                               itj == restart_at ? g1 : g2, itj == restart_at ? 3 : 2, w.st, itj,
-                               itj == restart_at ? 1 : 0, static_cast<const T *>(nullptr), w.partA);
+            const bool fresh = itj == restart_at;
+            const int nin = fresh ? gi : g.p2, stride = fresh ? 3 : 2;
+            OASIS_TRY(tm.before(s));
+            if (ell)
+                launch_p1_ell<T, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
+                                     nin, stride, w.st, itj, fresh ? 1 : 0, static_cast<const T *>(nullptr),
+                                     w.partA);
+            else
+                hipLaunchKernelGGL((k_cg_p1<T, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val,
+                                   w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB, nin, stride, w.st, itj,
+                                   fresh ? 1 : 0, static_cast<const T *>(nullptr), w.partA);
             OASIS_TRY_LAUNCH();
             OASIS_TRY(tm.after(s));
-            hipLaunchKernelGGL((k_cg_p2<T>), dim3(g2), dim3(kBlock), 0, s, n, w.pair[itj & 1],
-                               w.pair[(itj + 1) & 1], w.q, x, wgt, w.partA, g1, w.st, itj,
-                               static_cast<const T *>(nullptr), w.partB);
+            hipLaunchKernelGGL((k_cg_p2<T, BS>), dim3(g.p2), dim3(BS), 0, s, n, w.pair[(itj + 1) & 1], w.q, x,
+                               wgt, w.partA, g1, w.st, itj, static_cast<const T *>(nullptr), w.partB);
             OASIS_TRY_LAUNCH();
         }
         it += m;
@@ -410,8 +655,11 @@ int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, c
              const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
              CGWork<T> &w, SolveOut &out) {
     return with_cfg([&](auto c) {
-        return cg_run<T, decltype(c)>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
-                                      time_kernel, w, out);
+        if (cg_block() == 256)
+            return cg_run<T, decltype(c), 256>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
+                                               time_kernel, w, out);
+        return cg_run<T, decltype(c), 1024>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel,
+                                            w, out);
     });
 }
 
@@ -421,34 +669,39 @@ __global__ __launch_bounds__(kBlock) void k_add_lo(int n, double *__restrict__ x
         x[i] += static_cast<double>(e[i]);
 }
 
-template <class C>
+template <class C, int BS>
 static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
                         const float *val32, const double *wgt, const float *wgt32,
                         const float *vnull, const double *b, double *x, double rtol, double delta,
                         int maxit, int check_every, bool time_kernel, CGWork<float> &w,
                         float *xlo, double *rhi, SolveOut &out) {
-    const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
-    const int g2 = grid_for(n, kBlock, partial_cap());
+    const int gi = grid_for(n, rows_per_block<C>(), partial_cap());     // k_cg_init (kBlock threads)
+    const int gv = grid_for(n, kBlock, partial_cap());                  // k_cg_cast, k_add_lo
+    const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
+    const bool ell = w.ecol && w.eval && ell_enabled();
+    const int g1 = ell ? launch_p1_ell<float, BS>(s, n, w.ecol, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
+                                                  nullptr, 0, 0, nullptr, nullptr, true)
+                       : g.p1;
     const double upd = delta * delta;
     out = SolveOut();
     // FP64 residual of the FP64 accumulator, then its FP32 copy (x_lo = 0)
     auto replace = [&](int mode) -> int {
-        hipLaunchKernelGGL((k_cg_init<double, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+        hipLaunchKernelGGL((k_cg_init<double, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
                            b, x, rhi, 1, w.partB);
         OASIS_TRY_LAUNCH();
-        hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st,
+        hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, gi, w.st,
                            rtol * rtol, mode, upd);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
     // into the r of the pair that iteration `at` reads; its direction stays
     auto cast = [&](int at) -> int {
-        hipLaunchKernelGGL(k_cg_cast, dim3(g2), dim3(kBlock), 0, s, n, rhi, wgt32, w.pair[at & 1], xlo, w.partB);
+        hipLaunchKernelGGL(k_cg_cast, dim3(gv), dim3(kBlock), 0, s, n, rhi, wgt32, w.pair[at & 1], xlo, w.partB);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
     auto fold = [&]() -> int {
-        hipLaunchKernelGGL(k_add_lo, dim3(g2), dim3(kBlock), 0, s, n, x, xlo);
+        hipLaunchKernelGGL(k_add_lo, dim3(gv), dim3(kBlock), 0, s, n, x, xlo);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
@@ -471,27 +724,30 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     ChunkTimer tm;
     OASIS_TRY(tm.init(time_kernel));
     const int chunk = check_every > 0 ? check_every : 32;
-    int it = 0, restart_at = 0, nin = g2;
+    int it = 0, restart_at = 0, nin = gv;     // partials of k_cg_cast first, then of k_cg_p2
     int rc = OASIS_OK;
     while (true) {
         const int m = std::min(chunk, maxit - it);
         tm.chunk(it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
+            const int ni = j == 0 ? nin : g.p2;
             OASIS_TRY(tm.before(s));
-            hipLaunchKernelGGL((k_cg_p1<float, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val32,
-                               w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
-                               j == 0 ? nin : g2, 2, w.st, itj, itj == restart_at ? 1 : 0, vnull,
-                               w.partA);
+            if (ell)
+                launch_p1_ell<float, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
+                                         w.partB, ni, 2, w.st, itj, itj == restart_at ? 1 : 0, vnull, w.partA);
+            else
+                hipLaunchKernelGGL((k_cg_p1<float, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val32,
+                                   w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB, ni, 2, w.st, itj,
+                                   itj == restart_at ? 1 : 0, vnull, w.partA);
             OASIS_TRY_LAUNCH();
             OASIS_TRY(tm.after(s));
-            hipLaunchKernelGGL((k_cg_p2<float>), dim3(g2), dim3(kBlock), 0, s, n, w.pair[itj & 1],
-                               w.pair[(itj + 1) & 1], w.q, xlo, wgt32, w.partA, g1, w.st, itj, vnull,
-                               w.partB);
+            hipLaunchKernelGGL((k_cg_p2<float, BS>), dim3(g.p2), dim3(BS), 0, s, n, w.pair[(itj + 1) & 1], w.q,
+                               xlo, wgt32, w.partA, g1, w.st, itj, vnull, w.partB);
             OASIS_TRY_LAUNCH();
         }
         it += m;
-        nin = g2;
+        nin = g.p2;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
         tm.commit(h, out);
@@ -528,7 +784,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         }
         OASIS_TRY(cast(at));
         it = at;
-        nin = g2;
+        nin = gv;
     }
     return rc;
 }
@@ -539,8 +795,11 @@ int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const dou
                    int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
                    SolveOut &out) {
     return with_cfg([&](auto c) {
-        return cg_mixed_run<decltype(c)>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, b, x, rtol, delta,
-                                         maxit, check_every, time_kernel, w, xlo, rhi, out);
+        if (cg_block() == 256)
+            return cg_mixed_run<decltype(c), 256>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, b, x, rtol, delta,
+                                                  maxit, check_every, time_kernel, w, xlo, rhi, out);
+        return cg_mixed_run<decltype(c), 1024>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, b, x, rtol, delta,
+                                               maxit, check_every, time_kernel, w, xlo, rhi, out);
     });
 }
 

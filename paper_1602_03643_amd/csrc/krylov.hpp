@@ -27,11 +27,16 @@ template <typename T>
 struct CGWork {
     // Residual and direction interleaved, so that the product kernel fetches
     // both with one gather: iteration it reads pair[it & 1] = (r_it, p_{it-1})
-    // and writes p_it, then r_{it+1}, into pair[(it + 1) & 1].
+    // and writes (r_it, p_it) into pair[(it + 1) & 1], whose r the update
+    // kernel then turns into r_{it+1}.
     RP<T> *pair[2] = {nullptr, nullptr};
     T *q = nullptr;
     double *partA = nullptr, *partB = nullptr;
     CGState *st = nullptr;
+    // optional ELL copy of the iteration matrix (set by the owner); the
+    // product kernel uses it when present
+    const short *ecol = nullptr;
+    const T *eval = nullptr;
 };
 
 struct BiState {
@@ -98,6 +103,17 @@ int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const dou
                    const double *b, double *x, double rtol, double delta, int maxit,
                    int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
                    SolveOut &out);
+
+// Longest row of a CSR pattern (synchronises; tmp: one device int).
+int csr_max_row(hipStream_t s, int n, const int *rp, int *tmp, int *out);
+
+// ELL copy of a CSR matrix with rows of at most kEll entries (see
+// spmv.hpp): ecol [n][kEll] 16-bit cyclic column offsets, and the values
+// as FP64 (eval) and/or their FP32 rounding (eval32); either value array
+// may be null, not both.  *fits (host) tells whether every offset fitted;
+// if not, the copy must not be used.  tmp: one device int.  Synchronises.
+int csr_to_ell(hipStream_t s, int n, const int *rp, const int *ci, const double *val, short *ecol,
+               double *eval, float *eval32, int *tmp, bool *fits);
 
 // Weighted residual of x for the scaled system: r = b - Ms x, returns
 // (sum wgt r^2, sum wgt b^2) on the host.  Uses w's buffers.

@@ -50,24 +50,36 @@ __device__ __forceinline__ T group_sum(T v) {
 // the whole moving window.
 constexpr int kXcds = 8;
 
-template <typename TA, int NR, class C, class Gather, class Finish>
+// Rows [first, last) walked by lane group gid of ngroups (groups of L
+// lanes), with the XCD-aware split when the grid allows it.
+template <int L, int BS = kBlock>
+struct RowRange {
+    long long first = 0, last = 0, gid = 0, ngroups = 1;
+    __device__ __forceinline__ explicit RowRange(int n) {
+        constexpr int GPB = BS / L;                   // groups per block
+        first = 0;
+        last = n;
+        if (xcd_mapping() && (gridDim.x % kXcds) == 0 && gridDim.x >= kXcds) {
+            const int x = blockIdx.x % kXcds;
+            const long long seg = (n + kXcds - 1) / kXcds;
+            first = x * seg;
+            last = first + seg < n ? first + seg : n;
+            gid = static_cast<long long>(blockIdx.x / kXcds) * GPB + threadIdx.x / L;
+            ngroups = static_cast<long long>(gridDim.x / kXcds) * GPB;
+        } else {
+            gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
+            ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
+        }
+    }
+};
+
+template <typename TA, int NR, class C, int BS = kBlock, class Gather, class Finish>
 __device__ __forceinline__ void csr_rows(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                          const TA *__restrict__ val, Gather gather, Finish finish) {
     constexpr int L = C::L, P = C::P, R = C::R;
-    constexpr int GPB = kBlock / L;                   // groups per block
     const int lane = threadIdx.x & (L - 1);
-    long long first = 0, last = n, gid, ngroups;
-    if (xcd_mapping() && (gridDim.x % kXcds) == 0 && gridDim.x >= kXcds) {
-        const int x = blockIdx.x % kXcds;
-        const long long seg = (n + kXcds - 1) / kXcds;
-        first = x * seg;
-        last = first + seg < n ? first + seg : n;
-        gid = static_cast<long long>(blockIdx.x / kXcds) * GPB + threadIdx.x / L;
-        ngroups = static_cast<long long>(gridDim.x / kXcds) * GPB;
-    } else {
-        gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
-        ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
-    }
+    const RowRange<L, BS> rr(n);
+    const long long first = rr.first, last = rr.last, gid = rr.gid, ngroups = rr.ngroups;
     for (long long row0 = first + gid * R; row0 < last; row0 += ngroups * R) {
         int s[R], e[R];
 #pragma unroll
@@ -104,6 +116,45 @@ __device__ __forceinline__ void csr_rows(int n, const int *__restrict__ rp, cons
     }
 }
 
+// ELL storage for matrices whose rows have at most kEll entries (P1 meshes
+// made of Kuhn-split hexahedra have at most 15): row i occupies entries
+// [kEll i, kEll i + kEll) of a column and a value array, padded with
+// (column i, value 0).  Columns are stored as 16-bit cyclic offsets
+// d = (c - i) taken into [-n/2, n/2), which fit whenever the matrix's
+// cyclic bandwidth is below 2^15 (the periodic channel's structured
+// numbering: one x-y layer; after RCM: about 1.3 layers).  kEll / 4 lanes
+// share a row; each fetches its 4 offsets with one 8-byte load and its 4
+// values with 16-byte loads (no row pointers).
+constexpr int kEll = 16;
+constexpr int kEllLanes = kEll / 4;
+
+__device__ __forceinline__ int ell_col(long long row, int d, int n) {
+    int c = static_cast<int>(row) + d;
+    c += c < 0 ? n : 0;
+    c -= c >= n ? n : 0;
+    return c;
+}
+
+__device__ __forceinline__ void load4(const float *__restrict__ p, float (&v)[4]) {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+}
+__device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0];
+    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+
+// Whether ELL product kernels are used when available (env OASIS_ELL=0
+// selects the CSR kernels, for comparisons).
+bool ell_enabled();
+
 // Row-iteration shapes compiled into the library (selected at run time).
 using Cfg4x4x1 = RowCfg<4, 4, 1>;
 using Cfg8x2x1 = RowCfg<8, 2, 1>;
@@ -116,8 +167,8 @@ int spmv_cfg();
 // Upper bound on producer grids (partials read by every consumer block).
 int partial_cap();
 
-template <class C>
-constexpr int rows_per_block() { return (kBlock / C::L) * C::R; }
+template <class C, int BS = kBlock>
+constexpr int rows_per_block() { return (BS / C::L) * C::R; }
 
 // Dispatch a callable templated on the row shape.
 template <class F>
