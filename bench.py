@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # hash differs from these files was taken on another kernel and is not used
 CG_KERNEL_SOURCES = ["paper_1602_03643_amd/csrc/krylov.hip", "paper_1602_03643_amd/csrc/krylov.hpp",
                      "paper_1602_03643_amd/csrc/spmv.hpp", "paper_1602_03643_amd/csrc/internal.hpp"]
-PMC_SUMMARY = "profiles/k_cg_p1_float_channel129_pmc.txt"
+PMC_SUMMARY = "profiles/k_cg_p1_ell_float_channel129_pmc.txt"
 
 
 def log(*a):
@@ -260,9 +260,9 @@ def main():
     kb = cg_kernel_bytes(pat.n, pat.nnz, vbytes)
     achieved = kb / (avg_ms * 1e-3) / 1e9
     # the ELL product kernel runs when every row has at most 16 entries (P1 on
-    # Kuhn-split hexahedra: at most 15) unless OASIS_ELL=0
-    # (FP32 iteration only)
-    ell = (os.environ.get("OASIS_ELL", "1") != "0" and vbytes == 4
+    # Kuhn-split hexahedra: at most 15; the 16-bit column offsets fit the
+    # periodic channel numbering) unless OASIS_ELL=0
+    ell = (os.environ.get("OASIS_ELL", "1") != "0"
            and int((pat.row_ptr[1:] - pat.row_ptr[:-1]).max()) <= 16)
     kname = "k_cg_p1%s<%s>" % ("_ell" if ell else "", "double" if vbytes == 8 else "float")
     traffic = pmc_traffic(kname) if args.size == "c129" else None
@@ -271,7 +271,7 @@ def main():
                 bytes_per_launch=kb, avg_launch_ms=avg_ms, launches_timed=cnt)
     avg64, _ = time_cg_kernel(oa, torch, handles[head], pat, oa.F64, args.kernel_iters)
     kb64 = cg_kernel_bytes(pat.n, pat.nnz, 8)
-    roof["fp64_kernel"] = dict(kernel="k_cg_p1<double>",
+    roof["fp64_kernel"] = dict(kernel="k_cg_p1%s<double>" % ("_ell" if ell else ""),
                                achieved=round(kb64 / (avg64 * 1e-3) / 1e9, 1), avg_launch_ms=avg64,
                                bytes_per_launch=kb64)
     cpu = None

@@ -69,15 +69,26 @@ __global__ __launch_bounds__(kBlock) void k_scale_matrix(int n, const int *__res
     }
 }
 
-// In place over the CSR entries: a_j /= d[col_j] (right Jacobi), FP32 copy.
-__global__ __launch_bounds__(kBlock) void k_colscale(long long nnz, const int *__restrict__ ci,
+// In place: a_ij /= d_j (right Jacobi), one row per kEll lanes, with the
+// optional FP32 CSR copy and the optional ELL values (e64 or e32; the
+// rows then have at most kEll entries, padding written as 0).
+__global__ __launch_bounds__(kBlock) void k_colscale(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                                      const double *__restrict__ d, double *__restrict__ a,
-                                                     float *__restrict__ a32) {
-    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < nnz;
-         j += (long long)gridDim.x * blockDim.x) {
-        const double v = a[j] / d[ci[j]];
-        a[j] = v;
-        if (a32) a32[j] = static_cast<float>(v);
+                                                     float *__restrict__ a32, double *__restrict__ e64,
+                                                     float *__restrict__ e32) {
+    const int k = threadIdx.x & (kEll - 1);
+    for (long long row = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / kEll; row < n;
+         row += (static_cast<long long>(gridDim.x) * blockDim.x) / kEll) {
+        const int s = rp[row], len = rp[row + 1] - s;
+        double v = 0.0;
+        for (int j = s + k; j < s + len; j += kEll) {
+            const double t = a[j] / d[ci[j]];
+            a[j] = t;
+            if (a32) a32[j] = static_cast<float>(t);
+            if (j == s + k) v = t;
+        }
+        if (e64) e64[row * kEll + k] = k < len ? v : 0.0;
+        if (e32) e32[row * kEll + k] = k < len ? static_cast<float>(v) : 0.f;
     }
 }
 
@@ -764,9 +775,12 @@ struct oasis_ipcs {
     float *A32 = nullptr, *Ks32 = nullptr;
     double *ML = nullptr, *sK = nullptr, *wK = nullptr, *dA = nullptr, *wA = nullptr, *dtmp = nullptr;
     double *rtmp = nullptr;   // residual scratch of the warm-start guard
-    short *ecol = nullptr;    // ELL copy of the pressure matrix for the CG product:
-    double *eval = nullptr;   // FP64 values (FP64 mode) or
+    short *ecol = nullptr;    // ELL column offsets of the shared pattern (when they fit)
+    double *eval = nullptr;   // ELL values of the pressure matrix: FP64 (FP64 mode) or
     float *eval32 = nullptr;  // their FP32 rounding (mixed mode)
+    double *eA = nullptr;     // ELL values of the column-scaled tentative matrix, per step:
+    float *eA32 = nullptr;    // FP64 (FP64 mode) or FP32 (mixed mode)
+    bool ell = false;         // the offsets fit
     float *wK32 = nullptr, *wA32 = nullptr, *vnull32 = nullptr, *xlo = nullptr;
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
@@ -789,10 +803,13 @@ struct oasis_ipcs {
 
 static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, oasis_ipcs &h) {
     h.ecol = c.take<short>((size_t)n * kEll);
-    if (mixed)
+    if (mixed) {
         h.eval32 = c.take<float>((size_t)n * kEll);
-    else
+        h.eA32 = c.take<float>((size_t)n * kEll);
+    } else {
         h.eval = c.take<double>((size_t)n * kEll);
+        h.eA = c.take<double>((size_t)n * kEll);
+    }
     h.M = c.take<double>(nnz);
     h.Ks = c.take<double>(nnz);
     for (int k = 0; k < dim; ++k) h.dP[k] = c.take<double>(nnz);
@@ -928,12 +945,15 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
         bool fits = false;
         const int rc4 = csr_to_ell(s, n, row_ptr, col_idx, h->Ks, h->ecol, h->eval, h->eval32, h->flag + 24, &fits);
         if (rc4 != OASIS_OK) return fail(rc4);
+        h->ell = fits;
         if (fits && h->mixed) {
-            h->cg32.ecol = h->ecol;
+            h->cg32.ecol = h->bi32.ecol = h->ecol;
             h->cg32.eval = h->eval32;
+            h->bi32.eval = h->eA32;
         } else if (fits) {
-            h->cg.ecol = h->ecol;
+            h->cg.ecol = h->bi.ecol = h->ecol;
             h->cg.eval = h->eval;
+            h->bi.eval = h->eA;
         }
     }
     // row-gather assembly: dof -> cell lists and the longest row
@@ -1122,10 +1142,15 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
             launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
         OASIS_TRY_LAUNCH();
     }
-    // right Jacobi: the solves run on A D^{-1} in y = D x
-    hipLaunchKernelGGL(k_colscale, dim3(grid_for(h->nnz, kBlock, 1 << 20)), dim3(kBlock), 0, s, (long long)h->nnz,
-                       h->ci, h->dA, h->A, h->mixed ? h->A32 : nullptr);
-    OASIS_TRY_LAUNCH();
+    // right Jacobi: the solves run on A D^{-1} in y = D x (ELL values for
+    // the Krylov products when the pattern fits, else the FP32 CSR copy)
+    {
+        const bool e = h->ell && ell_enabled();
+        hipLaunchKernelGGL(k_colscale, dim3(grid_for(n, kBlock / kEll, 1 << 20)), dim3(kBlock), 0, s, n, h->rp,
+                           h->ci, h->dA, h->A, h->mixed && !e ? h->A32 : nullptr, e ? h->eA : nullptr,
+                           e ? h->eA32 : nullptr);
+        OASIS_TRY_LAUNCH();
+    }
     OASIS_TRY_HIP(hipEventRecord(h->ev[1], s));
     // 3. tentative velocity
     oasis_krylov_opts o{};
@@ -1391,6 +1416,17 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
     OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     if (fl) return OASIS_EINVAL;     // x untouched
+    {
+        bool fits = false;
+        OASIS_TRY(csr_to_ell(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.eval, k.eval32, k.flag + 8, &fits));
+        if (fits && mixed) {
+            k.bi32.ecol = k.ecol;
+            k.bi32.eval = k.eval32;
+        } else if (fits) {
+            k.bi.ecol = k.ecol;
+            k.bi.eval = k.eval;
+        }
+    }
     double *xs[3] = {nullptr, nullptr, nullptr};
     for (int q = 0; q < nrhs; ++q) {
         OASIS_TRY_HIP(hipMemcpyAsync(k.bt[q], b + (size_t)q * n, (size_t)n * sizeof(double),

@@ -460,53 +460,54 @@ void carve_cg(Carver &c, int n, CGWork<T> &w) {
     w.st = c.take<CGState>(1);
 }
 
-// HIP-event timing of every direction+product launch of a chunk.  A launch
-// that finds the flag of an earlier iteration already raised returns at
-// once; when the chunk's state has been read back, only the launches of
+// HIP-event timing of every direction+product launch of a chunk: an event
+// pair brackets each launch, with no wait in between, so the launches run
+// back to back as in an untimed solve; the pairs are read when the chunk's
+// state is read back.  A launch that finds the flag of an earlier
+// iteration already raised returns at once; only the launches of
 // iterations before the flagged one (it_done) are counted.
 struct ChunkTimer {
     bool on = false;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int first = 0;
-    std::vector<float> ms;
+    std::vector<hipEvent_t> ev;     // 2 per launch of the largest chunk
+    int first = 0, used = 0;
     ~ChunkTimer() {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
-    int init(bool enable) {
+    int init(bool enable, int chunk) {
         on = enable;
         if (!on) return OASIS_OK;
-        OASIS_TRY_HIP(hipEventCreate(&e0));
-        OASIS_TRY_HIP(hipEventCreate(&e1));
+        ev.assign(2 * chunk, nullptr);
+        for (auto &e : ev) OASIS_TRY_HIP(hipEventCreate(&e));
         return OASIS_OK;
     }
     void chunk(int it) {
         first = it;
-        ms.clear();
+        used = 0;
     }
     int before(hipStream_t s) {
-        if (on) OASIS_TRY_HIP(hipEventRecord(e0, s));
+        if (on) OASIS_TRY_HIP(hipEventRecord(ev[2 * used], s));
         return OASIS_OK;
     }
     int after(hipStream_t s) {
         if (!on) return OASIS_OK;
-        OASIS_TRY_HIP(hipEventRecord(e1, s));
-        OASIS_TRY_HIP(hipEventSynchronize(e1));
-        float t = 0.f;
-        OASIS_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
-        ms.push_back(t);
+        OASIS_TRY_HIP(hipEventRecord(ev[2 * used + 1], s));
+        ++used;
         return OASIS_OK;
     }
-    // h: the state read back after the chunk
-    void commit(const CGState &h, SolveOut &out) {
-        if (!on) return;
-        const int lim = h.flag ? h.it_done : first + static_cast<int>(ms.size());
-        for (size_t j = 0; j < ms.size(); ++j)
-            if (first + static_cast<int>(j) < lim) {
-                out.kernel_ms += ms[j];
+    // h: the state read back after the chunk (the stream is synchronised)
+    int commit(const CGState &h, SolveOut &out) {
+        if (!on) return OASIS_OK;
+        const int lim = h.flag ? h.it_done : first + used;
+        for (int j = 0; j < used; ++j)
+            if (first + j < lim) {
+                float t = 0.f;
+                OASIS_TRY_HIP(hipEventElapsedTime(&t, ev[2 * j], ev[2 * j + 1]));
+                out.kernel_ms += t;
                 out.kernel_count += 1;
             }
-        ms.clear();
+        used = 0;
+        return OASIS_OK;
     }
 };
 
@@ -572,9 +573,9 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     };
     OASIS_TRY(residual(0, 0));
     CGState h;
-    ChunkTimer tm;
-    OASIS_TRY(tm.init(time_kernel));
     const int chunk = check_every > 0 ? check_every : 32;
+    ChunkTimer tm;
+    OASIS_TRY(tm.init(time_kernel, chunk));
     int it = 0, restart_at = 0;
     int rc = OASIS_OK;
     auto finish = [&](double wrr, double wbb) {
@@ -606,7 +607,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         it += m;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
-        tm.commit(h, out);
+        OASIS_TRY(tm.commit(h, out));
         if (h.flag == 0) {
             if (it < maxit) continue;
             const double wbb = h.wbb, tol2 = h.tol2;
@@ -721,9 +722,9 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         return OASIS_OK;
     }
     OASIS_TRY(cast(0));
-    ChunkTimer tm;
-    OASIS_TRY(tm.init(time_kernel));
     const int chunk = check_every > 0 ? check_every : 32;
+    ChunkTimer tm;
+    OASIS_TRY(tm.init(time_kernel, chunk));
     int it = 0, restart_at = 0, nin = gv;     // partials of k_cg_cast first, then of k_cg_p2
     int rc = OASIS_OK;
     while (true) {
@@ -750,7 +751,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         nin = g.p2;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
-        tm.commit(h, out);
+        OASIS_TRY(tm.commit(h, out));
         if (h.flag == 2 || h.flag == 3) {
             OASIS_TRY(fold());
             out.iters = h.it_done;
@@ -840,9 +841,7 @@ struct C3 {
 // r_k = b_k - As xsrc_k for k in mask_res; r_hat_k = r_k for k in mask_rhat;
 // partials (r_hat.r, sum wgt r^2, sum wgt b^2) for every k.
 template <typename T, int NR, class C>
-__global__ __launch_bounds__(kBlock) void k_bi_resid(int n, const int *__restrict__ rp,
-                                                     const int *__restrict__ ci,
-                                                     const T *__restrict__ val,
+__global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
                                                      const T *__restrict__ wgt, C3<T> b,
                                                      C3<T> xsrc, V3<T> r, V3<T> rhat, int mask_res,
                                                      int mask_rhat, double *part) {
@@ -850,8 +849,8 @@ __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, const int *__restric
     double acc[3 * NR];
 #pragma unroll
     for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
-    csr_rows<T, NR, C>(
-        n, rp, ci, val,
+    mat_rows<T, NR, C>(
+        n, m,
         [&](int, int c, T v, bool ok, T(&a)[NR]) {
 #pragma unroll
             for (int k = 0; k < NR; ++k)
@@ -914,9 +913,7 @@ __device__ __forceinline__ void bi_pause(BiGlobal *g, int phase, int it) {
 // part 1: tests on the incoming residual, p = r + beta (p - omega v),
 // v = As p, partial r_hat.v
 template <typename T, int NR, class C>
-__global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ rp,
-                                                 const int *__restrict__ ci,
-                                                 const T *__restrict__ val, C3<T> r, C3<T> rhat,
+__global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, C3<T> r, C3<T> rhat,
                                                  C3<T> pold, C3<T> vold, V3<T> pnew, V3<T> vnew,
                                                  const double *partIn, int nIn, BiState *st,
                                                  BiGlobal *glob, int it, double *partOut) {
@@ -964,8 +961,8 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ 
     double acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    csr_rows<T, NR, C>(
-        n, rp, ci, val,
+    mat_rows<T, NR, C>(
+        n, m,
         [&](int, int c, T vv, bool ok, T(&a)[NR]) {
 #pragma unroll
             for (int k = 0; k < NR; ++k)
@@ -991,9 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, const int *__restrict__ 
 // part 2: alpha = rho / (r_hat.v), s = r - alpha v, t = As s,
 // partials (t.s, t.t, sum wgt s^2)
 template <typename T, int NR, class C>
-__global__ __launch_bounds__(kBlock) void k_bi_2(int n, const int *__restrict__ rp,
-                                                 const int *__restrict__ ci,
-                                                 const T *__restrict__ val,
+__global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m,
                                                  const T *__restrict__ wgt, C3<T> r, C3<T> vv,
                                                  V3<T> s, V3<T> t, const double *partIn, int nIn,
                                                  BiState *st, BiGlobal *glob, int it,
@@ -1034,8 +1029,8 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, const int *__restrict__ 
     double acc[3 * NR];
 #pragma unroll
     for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
-    csr_rows<T, NR, C>(
-        n, rp, ci, val,
+    mat_rows<T, NR, C>(
+        n, m,
         [&](int, int c, T w, bool ok, T(&a)[NR]) {
 #pragma unroll
             for (int k = 0; k < NR; ++k)
@@ -1167,6 +1162,8 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
     const int g2 = grid_for(n, kBlock, partial_cap());
     const int gv = grid_for(n, kBlock, 4096);
+    const bool ell = w.ecol && w.eval && ell_enabled();
+    const Mat<T> mat{rp, ci, val, ell ? w.ecol : nullptr, ell ? w.eval : nullptr};
     C3<T> cb{}, cx{}, cr{}, crh{}, cs{}, ct{}, cp[2]{}, cvv[2]{};
     V3<T> vx{}, vr{}, vrh{}, vs{}, vt{}, vp[2]{}, vvv[2]{}, vxs{};
     for (int k = 0; k < NR; ++k) {
@@ -1213,7 +1210,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         return OASIS_OK;
     };
     auto resid = [&](int mask_res, int mask_rhat, C3<T> src) -> int {
-        hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
+        hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat, wgt,
                            cb, src, vr, vrh, mask_res, mask_rhat, w.part3);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
@@ -1271,7 +1268,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         while (launched < chunk && it < maxit) {
             if (phase == 1) {
                 if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
-                hipLaunchKernelGGL((k_bi_1<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                hipLaunchKernelGGL((k_bi_1<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
                                    cr, crh, cp[(it + 1) & 1], cvv[(it + 1) & 1], vp[it & 1],
                                    vvv[it & 1], w.part3, part3_count, w.st, w.glob, it, w.part1);
                 OASIS_TRY_LAUNCH();
@@ -1283,7 +1280,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                     out[0].kernel_ms += ms;
                     out[0].kernel_count += 1;
                 }
-                hipLaunchKernelGGL((k_bi_2<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                hipLaunchKernelGGL((k_bi_2<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
                                    wgt, cr, cvv[it & 1], vs, vt, w.part1, g1, w.st, w.glob, it,
                                    w.part2);
                 OASIS_TRY_LAUNCH();

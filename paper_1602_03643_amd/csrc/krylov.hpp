@@ -61,6 +61,9 @@ struct BiWork {
     double *part1, *part2, *part3;
     BiState *st;       // [3]
     BiGlobal *glob;
+    // optional ELL copy of the iteration matrix (set by the owner)
+    const short *ecol = nullptr;
+    const T *eval = nullptr;
 };
 
 struct SolveOut {

@@ -155,6 +155,63 @@ __device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[
 // selects the CSR kernels, for comparisons).
 bool ell_enabled();
 
+// The csr_rows contract on the ELL copy, L lanes per row: gather(j, c, v,
+// ok, acc) for each of the row's kEll stored entries (padding: c = row,
+// v = 0, ok = true) and finish(row, lane, acc) on all L lanes after the
+// butterfly.  Rows are walked grid-stride, so any grid covers them.
+template <typename TA, int NR, int L, int BS = kBlock, class Gather, class Finish>
+__device__ __forceinline__ void ell_rows(int n, const short *__restrict__ ecol, const TA *__restrict__ eval,
+                                         Gather gather, Finish finish) {
+    constexpr int E = kEll / L;
+    static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
+    const int lane = threadIdx.x & (L - 1);
+    const RowRange<L, BS> rr(n);
+    for (long long row = rr.first + rr.gid; row < rr.last; row += rr.ngroups) {
+        const long long base = row * kEll + lane * E;
+        int c[E];
+        TA w[E];
+#pragma unroll
+        for (int g = 0; g < E / 4; ++g) {
+            const short4 d = *reinterpret_cast<const short4 *>(ecol + base + 4 * g);
+            c[4 * g] = ell_col(row, d.x, n);
+            c[4 * g + 1] = ell_col(row, d.y, n);
+            c[4 * g + 2] = ell_col(row, d.z, n);
+            c[4 * g + 3] = ell_col(row, d.w, n);
+            TA t[4];
+            load4(eval + base + 4 * g, t);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[4 * g + k] = t[k];
+        }
+        TA acc[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = TA(0);
+#pragma unroll
+        for (int k = 0; k < E; ++k) gather(0, c[k], w[k], true, acc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = group_sum<L>(acc[k]);
+        finish(static_cast<int>(row), lane, acc);
+    }
+}
+
+// A matrix on the shared CSR pattern with an optional ELL copy (ecol and
+// eval both set) that products use instead.
+template <typename T>
+struct Mat {
+    const int *rp;
+    const int *ci;
+    const T *val;
+    const short *ecol;
+    const T *eval;
+};
+
+template <typename TA, int NR, class C, class Gather, class Finish>
+__device__ __forceinline__ void mat_rows(int n, const Mat<TA> &m, Gather gather, Finish finish) {
+    if (m.ecol)
+        ell_rows<TA, NR, 2>(n, m.ecol, m.eval, gather, finish);
+    else
+        csr_rows<TA, NR, C>(n, m.rp, m.ci, m.val, gather, finish);
+}
+
 // Row-iteration shapes compiled into the library (selected at run time).
 using Cfg4x4x1 = RowCfg<4, 4, 1>;
 using Cfg8x2x1 = RowCfg<8, 2, 1>;
