@@ -151,7 +151,9 @@ def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=
 
 def time_cg_kernel(oa, torch, h, pat, precision, iters=200):
     """Average duration of the CG direction+product kernel on the pressure
-    matrix of the benchmark mesh, bracketed by HIP events on its stream."""
+    matrix of the benchmark mesh: a standalone PCG runs `iters` iterations,
+    then its last product launch is repeated `iters` times back to back
+    between two HIP events on the launch stream."""
     Ks, _ = h.matrix(oa.FORM_STIFF)
     A = pat.with_values(Ks)
     n = pat.n

@@ -173,9 +173,15 @@ typedef struct {
                              (0 = 1e-4; tightened automatically for the last step) */
     int32_t max_outer;    /* F32 mode BiCGStab: cap on refinement steps (0 = 50) */
     int32_t check_every;  /* iterations launched between host convergence polls (0 = auto) */
-    int32_t flags;        /* OASIS_KRYLOV_TIME: time the dominant kernel with HIP events */
+    int32_t flags;        /* OASIS_KRYLOV_TIME, OASIS_KRYLOV_NULLSPACE_CONST */
 } oasis_krylov_opts;
 
+/* Kernel timing.  oasis_pcg: when the solve stops at maxit, its last
+ * direction+product launch (a full iteration's product work on the final
+ * state) is repeated maxit times back to back between two HIP events;
+ * kernel_ms is their total and kernel_count = maxit (0 when the solve
+ * stopped earlier).  oasis_bicgstab: every first-product launch of the
+ * FP64 iteration is bracketed by events. */
 #define OASIS_KRYLOV_TIME 1
 /* The matrix is singular with the constant vector as null space (pure
  * Neumann pressure matrix) and b is consistent.  In F32 mode the FP32
@@ -189,7 +195,7 @@ typedef struct {
     int32_t status;       /* OASIS_OK / ENOTCONV / EBREAKDOWN / ENAN */
     int32_t restarts;     /* BiCGStab breakdown restarts, residual replacements */
     double rel_res;       /* final true ||b - A x|| / ||b|| */
-    double kernel_ms;     /* OASIS_KRYLOV_TIME: summed time of the SpMV kernel */
+    double kernel_ms;     /* OASIS_KRYLOV_TIME: total time of the timed launches */
     int32_t kernel_count; /* number of timed launches */
     int32_t pad;
 } oasis_krylov_stats;

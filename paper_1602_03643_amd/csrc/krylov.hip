@@ -460,56 +460,39 @@ void carve_cg(Carver &c, int n, CGWork<T> &w) {
     w.st = c.take<CGState>(1);
 }
 
-// HIP-event timing of every direction+product launch of a chunk: an event
-// pair brackets each launch, with no wait in between, so the launches run
-// back to back as in an untimed solve; the pairs are read when the chunk's
-// state is read back.  A launch that finds the flag of an earlier
-// iteration already raised returns at once; only the launches of
-// iterations before the flagged one (it_done) are counted.
-struct ChunkTimer {
-    bool on = false;
-    std::vector<hipEvent_t> ev;     // 2 per launch of the largest chunk
-    int first = 0, used = 0;
-    ~ChunkTimer() {
-        for (auto e : ev)
-            if (e) (void)hipEventDestroy(e);
+// Kernel timing of a solve (time_kernel): when the solve has stopped at
+// maxit, the last iteration's state (a residual just recomputed, the flag
+// cleared, the previous direction and r.r in place) is a valid input for
+// one more direction+product launch; `launch` repeats that launch `reps`
+// times back to back between two events, so kernel_ms / kernel_count is
+// the kernel's duration without per-launch dispatch gaps.  Each repeat does
+// a full iteration's product work (same inputs, same outputs).
+template <class Launch>
+static int time_product(hipStream_t s, int reps, Launch launch, SolveOut &out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    OASIS_TRY_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return OASIS_EHIP;
     }
-    int init(bool enable, int chunk) {
-        on = enable;
-        if (!on) return OASIS_OK;
-        ev.assign(2 * chunk, nullptr);
-        for (auto &e : ev) OASIS_TRY_HIP(hipEventCreate(&e));
-        return OASIS_OK;
+    int rc = OASIS_OK;
+    float ms = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = OASIS_EHIP;
+    for (int i = 0; i < reps && rc == OASIS_OK; ++i) {
+        launch();
+        if (hipGetLastError() != hipSuccess) rc = OASIS_EHIP;
     }
-    void chunk(int it) {
-        first = it;
-        used = 0;
+    if (rc == OASIS_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = OASIS_EHIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == OASIS_OK) {
+        out.kernel_ms = ms;
+        out.kernel_count = reps;
     }
-    int before(hipStream_t s) {
-        if (on) OASIS_TRY_HIP(hipEventRecord(ev[2 * used], s));
-        return OASIS_OK;
-    }
-    int after(hipStream_t s) {
-        if (!on) return OASIS_OK;
-        OASIS_TRY_HIP(hipEventRecord(ev[2 * used + 1], s));
-        ++used;
-        return OASIS_OK;
-    }
-    // h: the state read back after the chunk (the stream is synchronised)
-    int commit(const CGState &h, SolveOut &out) {
-        if (!on) return OASIS_OK;
-        const int lim = h.flag ? h.it_done : first + used;
-        for (int j = 0; j < used; ++j)
-            if (first + j < lim) {
-                float t = 0.f;
-                OASIS_TRY_HIP(hipEventElapsedTime(&t, ev[2 * j], ev[2 * j + 1]));
-                out.kernel_ms += t;
-                out.kernel_count += 1;
-            }
-        used = 0;
-        return OASIS_OK;
-    }
-};
+    return rc;
+}
 
 // Block size of the iteration kernels (env OASIS_CG_BLOCK = 256 or 1024).
 // 1024-thread blocks keep the occupancy with a quarter of the partial sums
@@ -574,8 +557,6 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     OASIS_TRY(residual(0, 0));
     CGState h;
     const int chunk = check_every > 0 ? check_every : 32;
-    ChunkTimer tm;
-    OASIS_TRY(tm.init(time_kernel, chunk));
     int it = 0, restart_at = 0;
     int rc = OASIS_OK;
     auto finish = [&](double wrr, double wbb) {
@@ -583,13 +564,11 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     };
     while (true) {
         const int m = std::min(chunk, maxit - it);
-        tm.chunk(it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
             // after a restart the incoming partials are k_cg_init's (3 per block)
             const bool fresh = itj == restart_at;
             const int nin = fresh ? gi : g.p2, stride = fresh ? 3 : 2;
-            OASIS_TRY(tm.before(s));
             if (ell)
                 launch_p1_ell<T, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
                                      nin, stride, w.st, itj, fresh ? 1 : 0, static_cast<const T *>(nullptr),
@@ -599,7 +578,6 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                                    w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB, nin, stride, w.st, itj,
                                    fresh ? 1 : 0, static_cast<const T *>(nullptr), w.partA);
             OASIS_TRY_LAUNCH();
-            OASIS_TRY(tm.after(s));
             hipLaunchKernelGGL((k_cg_p2<T, BS>), dim3(g.p2), dim3(BS), 0, s, n, w.pair[(itj + 1) & 1], w.q, x,
                                wgt, w.partA, g1, w.st, itj, static_cast<const T *>(nullptr), w.partB);
             OASIS_TRY_LAUNCH();
@@ -607,7 +585,6 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         it += m;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
-        OASIS_TRY(tm.commit(h, out));
         if (h.flag == 0) {
             if (it < maxit) continue;
             const double wbb = h.wbb, tol2 = h.tol2;
@@ -617,6 +594,23 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             out.iters = it;
             finish(h.wrr, wbb);
             out.status = rc = (h.wrr <= tol2) ? OASIS_OK : OASIS_ENOTCONV;
+            if (time_kernel && rc == OASIS_ENOTCONV) {
+                // repeat iteration `it` on the residual just recomputed (k_cg_init's partials)
+                const int itj = it;
+                OASIS_TRY(time_product(
+                    s, maxit,
+                    [&] {
+                        if (ell)
+                            launch_p1_ell<T, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
+                                                 w.partB, gi, 3, w.st, itj, 0, static_cast<const T *>(nullptr),
+                                                 w.partA);
+                        else
+                            hipLaunchKernelGGL((k_cg_p1<T, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val,
+                                               w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB, gi, 3, w.st,
+                                               itj, 0, static_cast<const T *>(nullptr), w.partA);
+                    },
+                    out));
+            }
             break;
         }
         if (h.flag == 1) {
@@ -723,17 +717,13 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     }
     OASIS_TRY(cast(0));
     const int chunk = check_every > 0 ? check_every : 32;
-    ChunkTimer tm;
-    OASIS_TRY(tm.init(time_kernel, chunk));
     int it = 0, restart_at = 0, nin = gv;     // partials of k_cg_cast first, then of k_cg_p2
     int rc = OASIS_OK;
     while (true) {
         const int m = std::min(chunk, maxit - it);
-        tm.chunk(it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
             const int ni = j == 0 ? nin : g.p2;
-            OASIS_TRY(tm.before(s));
             if (ell)
                 launch_p1_ell<float, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
                                          w.partB, ni, 2, w.st, itj, itj == restart_at ? 1 : 0, vnull, w.partA);
@@ -742,7 +732,6 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
                                    w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB, ni, 2, w.st, itj,
                                    itj == restart_at ? 1 : 0, vnull, w.partA);
             OASIS_TRY_LAUNCH();
-            OASIS_TRY(tm.after(s));
             hipLaunchKernelGGL((k_cg_p2<float, BS>), dim3(g.p2), dim3(BS), 0, s, n, w.pair[(itj + 1) & 1], w.q,
                                xlo, wgt32, w.partA, g1, w.st, itj, vnull, w.partB);
             OASIS_TRY_LAUNCH();
@@ -751,7 +740,6 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         nin = g.p2;
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
-        OASIS_TRY(tm.commit(h, out));
         if (h.flag == 2 || h.flag == 3) {
             OASIS_TRY(fold());
             out.iters = h.it_done;
@@ -781,6 +769,21 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         if (at >= maxit) {
             out.iters = at;
             out.status = rc = OASIS_ENOTCONV;
+            if (time_kernel) {
+                // repeat iteration `at` (FP32 pair in place, k_cg_init's partials)
+                OASIS_TRY(time_product(
+                    s, maxit,
+                    [&] {
+                        if (ell)
+                            launch_p1_ell<float, BS>(s, n, w.ecol, w.eval, w.pair[at & 1], w.pair[(at + 1) & 1],
+                                                     w.q, w.partB, gi, 3, w.st, at, 0, vnull, w.partA);
+                        else
+                            hipLaunchKernelGGL((k_cg_p1<float, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val32,
+                                               w.pair[at & 1], w.pair[(at + 1) & 1], w.q, w.partB, gi, 3, w.st, at,
+                                               0, vnull, w.partA);
+                    },
+                    out));
+            }
             break;
         }
         OASIS_TRY(cast(at));

@@ -235,6 +235,33 @@ def test_ipcs_ten_steps_channel(oa):
     assert rel(p.cpu().numpy(), st.p) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pcg_kernel_timing_leaves_the_solve_unchanged(oa, precision):
+    """The timing mode repeats the last product launch after a solve that
+    stopped at maxit: it reports maxit timed launches and the returned x is
+    bit-for-bit that of an untimed solve."""
+    prob = synth.channel_flow("small", seed=3)
+    say("pcg timing", prob.name, precision)
+    S, st, A, b = _tent_problem(prob)
+    dm, pat, _ = device_mesh(prob.mesh)
+    Kp = pat.with_values(T(p1.on_pattern(S.K, csr_host(pat))))
+    rng = np.random.default_rng(12)
+    bphi = rng.normal(size=prob.mesh.n_dof)
+    bphi -= bphi.mean()
+    prec = oa.F64 if precision == "f64" else oa.F32
+    outs, xs = [], []
+    for timed in (False, True):
+        x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+        outs.append(oa.pcg(Kp, T(bphi), x, rtol=1e-30, maxit=40, precision=prec, time_kernel=timed,
+                           raise_on=False, nullspace_const=True))
+        xs.append(x)
+    assert outs[0]["rc"] == oa.ENOTCONV and outs[1]["rc"] == oa.ENOTCONV
+    assert outs[0]["kernel_count"] == 0
+    assert outs[1]["kernel_count"] == 40 and outs[1]["kernel_ms"] > 0
+    assert torch.equal(xs[0], xs[1])
+    assert outs[0]["iters"] == outs[1]["iters"] == 40
+
+
 # ---------------------------------------------------------------------------
 # mixed precision: FP32 iterations, FP64 refinement.  The answer is any x
 # whose FP64 true residual meets rtol; the oracle recomputes that residual
