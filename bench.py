@@ -40,18 +40,25 @@ HBM_PEAK_GBS = 8000.0
 # hash differs from these files was taken on another kernel and is not used
 CG_KERNEL_SOURCES = ["paper_1602_03643_amd/csrc/krylov.hip", "paper_1602_03643_amd/csrc/krylov.hpp",
                      "paper_1602_03643_amd/csrc/spmv.hpp", "paper_1602_03643_amd/csrc/internal.hpp"]
-PMC_SUMMARY = "profiles/k_cg_p1_ell_float_channel129_pmc.txt"
+PMC_SUMMARY = "profiles/k_cg_sr_float_channel129_pmc.txt"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cg_kernel_bytes(n, nnz, vbytes):
-    """Algorithmic bytes of one CG direction+product launch (k_cg_p1):
-    values + column indices + row pointers, gathers of r and p_old, writes of
-    p_new and q (each vector once)."""
-    return vbytes * nnz + 4 * nnz + 4 * (n + 1) + 2 * vbytes * n + 2 * vbytes * n
+def cg_kernel_bytes(n, nnz, vbytes, single_reduction=False, projected=False):
+    """Algorithmic bytes of one launch of the CG product kernel, with the
+    matrix counted as CSR (values + column indices + row pointers) and every
+    vector once.  Two-kernel iteration (k_cg_p1): gathers of r and p_old,
+    writes of p_new and q.  Single-reduction iteration (k_cg_sr, the whole
+    iteration): the record (r, w, s, p) read and written, x read and
+    written, the norm weights read and, for a singular matrix, the null
+    vector read."""
+    mat = vbytes * nnz + 4 * nnz + 4 * (n + 1)
+    if not single_reduction:
+        return mat + 2 * vbytes * n + 2 * vbytes * n
+    return mat + (4 + 4 + 2 + 1 + (1 if projected else 0)) * vbytes * n
 
 
 def step_bytes_model(n, nnz, iters_u, iters_p, dim=3):
@@ -150,10 +157,12 @@ def run_variant(oa, torch, pr, dm, pat, precision, steps, warmup, tag, assembly=
 
 
 def time_cg_kernel(oa, torch, h, pat, precision, iters=200):
-    """Average duration of the CG direction+product kernel on the pressure
-    matrix of the benchmark mesh: a standalone PCG runs `iters` iterations,
-    then its last product launch is repeated `iters` times back to back
-    between two HIP events on the launch stream."""
+    """Average duration of the CG product kernel on the pressure matrix of
+    the benchmark mesh (k_cg_sr, a whole iteration, for FP32 values;
+    k_cg_p1_ell, the direction + product part, for FP64 ones): a standalone
+    PCG on the singular matrix runs `iters` iterations, then its last
+    product launch is repeated `iters` times back to back between two HIP
+    events on the launch stream."""
     Ks, _ = h.matrix(oa.FORM_STIFF)
     A = pat.with_values(Ks)
     n = pat.n
@@ -259,21 +268,33 @@ def main():
     prec = oa.F64 if head.startswith("fp64") else oa.F32
     vbytes = 8 if prec == oa.F64 else 4
     avg_ms, cnt = time_cg_kernel(oa, torch, handles[head], pat, prec, args.kernel_iters)
-    kb = cg_kernel_bytes(pat.n, pat.nnz, vbytes)
-    achieved = kb / (avg_ms * 1e-3) / 1e9
-    # the ELL product kernel runs when every row has at most 16 entries (P1 on
+    # the ELL kernels run when every row has at most 16 entries (P1 on
     # Kuhn-split hexahedra: at most 15; the 16-bit column offsets fit the
-    # periodic channel numbering) unless OASIS_ELL=0
+    # periodic channel numbering) unless OASIS_ELL=0; on the ELL copy the
+    # FP32 iteration is the single-reduction kernel unless OASIS_CG_SR=0
+    # (OASIS_CG_SR=1 selects it for FP64 values too)
     ell = (os.environ.get("OASIS_ELL", "1") != "0"
            and int((pat.row_ptr[1:] - pat.row_ptr[:-1]).max()) <= 16)
-    kname = "k_cg_p1%s<%s>" % ("_ell" if ell else "", "double" if vbytes == 8 else "float")
+    sr_mode = os.environ.get("OASIS_CG_SR", "")
+
+    def kernel_of(vb):
+        sr = ell and (sr_mode == "1" or (sr_mode != "0" and vb == 4))
+        if sr:
+            return "k_cg_sr<%s>" % ("double" if vb == 8 else "float"), True
+        return "k_cg_p1%s<%s>" % ("_ell" if ell else "", "double" if vb == 8 else "float"), False
+
+    kname, sr = kernel_of(vbytes)
+    # the FP32 standalone solve projects out the null vector, the FP64 one does not
+    kb = cg_kernel_bytes(pat.n, pat.nnz, vbytes, sr, projected=vbytes == 4)
+    achieved = kb / (avg_ms * 1e-3) / 1e9
     traffic = pmc_traffic(kname) if args.size == "c129" else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
                 bytes_per_launch=kb, avg_launch_ms=avg_ms, launches_timed=cnt)
     avg64, _ = time_cg_kernel(oa, torch, handles[head], pat, oa.F64, args.kernel_iters)
-    kb64 = cg_kernel_bytes(pat.n, pat.nnz, 8)
-    roof["fp64_kernel"] = dict(kernel="k_cg_p1%s<double>" % ("_ell" if ell else ""),
+    kname64, sr64 = kernel_of(8)
+    kb64 = cg_kernel_bytes(pat.n, pat.nnz, 8, sr64)
+    roof["fp64_kernel"] = dict(kernel=kname64,
                                achieved=round(kb64 / (avg64 * 1e-3) / 1e9, 1), avg_launch_ms=avg64,
                                bytes_per_launch=kb64)
     cpu = None

@@ -177,11 +177,12 @@ typedef struct {
 } oasis_krylov_opts;
 
 /* Kernel timing.  oasis_pcg: when the solve stops at maxit, its last
- * direction+product launch (a full iteration's product work on the final
- * state) is repeated maxit times back to back between two HIP events;
+ * product launch is repeated maxit times back to back between two HIP
+ * events: in F32 mode the whole single-reduction iteration (its iterate
+ * update goes to scratch memory), in F64 mode the direction+product kernel.
  * kernel_ms is their total and kernel_count = maxit (0 when the solve
- * stopped earlier).  oasis_bicgstab: every first-product launch of the
- * FP64 iteration is bracketed by events. */
+ * stopped earlier); x is unchanged by the repeats.  oasis_bicgstab: every
+ * first-product launch of the FP64 iteration is bracketed by events. */
 #define OASIS_KRYLOV_TIME 1
 /* The matrix is singular with the constant vector as null space (pure
  * Neumann pressure matrix) and b is consistent.  In F32 mode the FP32

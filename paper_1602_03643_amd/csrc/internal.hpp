@@ -118,17 +118,21 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *part, do
 
 // Consumer side: every block sums the nparts partials of the previous kernel
 // in the same order, so all blocks hold identical totals.
-// The loads are unrolled so that a thread issues all of its (at most
-// kMaxPartials / kBlock) loads at once: one cache round trip, not eight.
-// `stride` (>= NV) is the producer's values per block when the consumer
-// needs only its first NV.
+// For up to three values per block the loads are unrolled so that a thread
+// issues all of its (at most kMaxPartials / kBlock) loads at once: one
+// cache round trip, not eight.  Wider partials are read two blocks at a
+// time, in rounds that are kept apart so that the registers held in flight
+// stay bounded (the kernel's register count, and so its occupancy, is the
+// maximum over all of its code).  `stride` (>= NV) is the producer's values
+// per block when the consumer needs only its first NV.
 template <int NV, int BS = kBlock>
 __device__ __forceinline__ void read_partials(const double *part, int nparts, double (&out)[NV],
                                               double *lds, int stride = NV) {
     constexpr int PER = kMaxPartials / BS;
-    constexpr int U = NV <= 3 || PER < 2 ? PER : 2;     // bound the registers held in flight
+    constexpr int U = NV <= 3 || PER < 2 ? PER : 2;
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = 0.0;
+#pragma unroll 1
     for (int q0 = 0; q0 < PER; q0 += U) {
         double t[U][NV];
 #pragma unroll

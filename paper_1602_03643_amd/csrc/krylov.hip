@@ -68,6 +68,15 @@ __device__ __forceinline__ int block_read_flag(const int *p) {
 // ---------------------------------------------------------------------------
 // vector helpers
 
+// a*b + c and c - a*b with a single rounding, so that a value formed once
+// for a gathered column and once for the thread's own row is the same.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T>
+__device__ __forceinline__ T fmsub(T c, T a, T b) {
+    return fmadd(-a, b, c);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(int n, T *x, T v) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -134,18 +143,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_finalize(const double *part, int 
     }
 }
 
-// r_lo = (float) r_hi into the r of a residual/direction pair (the
-// direction is kept), x_lo = 0; partials (r.r, sum wgt r^2)
+// r_lo = (float) r_hi into the residual of a record of rs floats (the rest
+// of the record is kept), x_lo = 0; partials (r.r, sum wgt r^2)
 __global__ __launch_bounds__(kBlock) void k_cg_cast(int n, const double *__restrict__ rhi,
-                                                    const float *__restrict__ wgt,
-                                                    RP<float> *__restrict__ pr, float *__restrict__ xlo,
-                                                    double *part) {
+                                                    const float *__restrict__ wgt, float *__restrict__ rlo,
+                                                    int rs, float *__restrict__ xlo, double *part) {
     __shared__ double lds[2 * kBlock / kWave];
     double acc[2] = {0.0, 0.0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const float r = static_cast<float>(rhi[i]);
-        pr[i].r = r;
+        rlo[i * rs] = r;
         xlo[i] = 0.f;
         const double rd = r;
         acc[0] += rd * rd;
@@ -389,6 +397,246 @@ static int launch_p1_ell(hipStream_t s, int n, const short *ecol, const T *eval,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-reduction CG on the ELL copy (the recurrences of Chronopoulos and
+// Gear).  With w = Ms r and s = Ms p carried as vectors, an iteration
+//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1},
+//   x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i, w_{i+1} = Ms r_{i+1}
+// is one pass over the matrix, and every scalar it needs comes from one set
+// of partial sums written by the previous pass:
+//   beta_i = (r_i.r_i) / (r_{i-1}.r_{i-1}),  alpha_i = (r_i.r_i) / (p_i.s_i),
+//   p_i.s_i = r_i.w_i + beta_i (r_i.s_{i-1} + p_{i-1}.w_i) + beta_i^2 p_{i-1}.s_{i-1}.
+// Row i's product gathers r_{i+1} of its columns, formed on the fly from the
+// gathered record (r, w, s) with the same roundings as in the owning row.
+// In exact arithmetic the iterates are those of Hestenes-Stiefel CG.
+//
+// With a null vector v (singular matrix) each row projects w and s,
+// w - (v.w) v, in its own update; the gathered operand leaves that term out,
+// whose product (v.w) Ms v is second order in the rounding of Ms.
+
+// Partials per block: r.r, sum wgt r^2, r.w, r.s + p.w, p.s, v.w, v.s
+// (of the record just written).
+constexpr int kSr = 7;
+
+template <typename T>
+__device__ __forceinline__ void sr_partials(double (&acc)[kSr], const Q4<T> &o, double wd, double vd) {
+    const double r = o.r, w = o.w, s = o.s, p = o.p;
+    acc[0] += r * r;
+    acc[1] += wd * r * r;
+    acc[2] += r * w;
+    acc[3] += r * s + p * w;
+    acc[4] += p * s;
+    acc[5] += vd * w;
+    acc[6] += vd * s;
+}
+
+// Offsets and values of one lane's E entries of an ELL row.
+template <typename T, int E>
+__device__ __forceinline__ void ell_lane(long long row, int lane, int n, const short *__restrict__ ecol,
+                                         const T *__restrict__ eval, int (&c)[E], T (&w)[E]) {
+    const long long base = row * kEll + lane * E;
+#pragma unroll
+    for (int g = 0; g < E / 4; ++g) {
+        const short4 d = *reinterpret_cast<const short4 *>(ecol + base + 4 * g);
+        c[4 * g] = ell_col(row, d.x, n);
+        c[4 * g + 1] = ell_col(row, d.y, n);
+        c[4 * g + 2] = ell_col(row, d.z, n);
+        c[4 * g + 3] = ell_col(row, d.w, n);
+        T t[4];
+        load4(eval + base + 4 * g, t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[4 * g + k] = t[k];
+    }
+}
+
+// One iteration (see above).  Convergence tests on the incoming residual
+// as in k_cg_p1; a non-positive p.s is a breakdown.
+template <typename T, int BS, int L, bool PROJ>
+__global__ __launch_bounds__(BS) void k_cg_sr(int n, const short *__restrict__ ecol, const T *__restrict__ eval,
+                                              const Q4<T> *__restrict__ cur, Q4<T> *__restrict__ nxt,
+                                              T *__restrict__ x, const T *__restrict__ wgt,
+                                              const T *__restrict__ vnull, const double *partIn, int nIn,
+                                              CGState *st, int it, int beta_zero, double *partOut) {
+    constexpr int E = kEll / L;
+    static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
+    __shared__ double lds[kSr * BS / kWave];
+    if (block_read_flag(&st->flag)) return;
+    double v[kSr];
+    read_partials<kSr, BS>(partIn, nIn, v, lds);
+    const double rr = v[0], wrr = v[1];
+    int flag = 0;
+    double beta = 0.0, ps = 0.0;
+    if (!finite(wrr) || !finite(rr)) {
+        flag = 3;
+    } else if (wrr <= st->tol2) {
+        flag = 1;
+    } else if (wrr <= st->upd2) {
+        flag = 4;
+    } else {
+        beta = beta_zero ? 0.0 : rr / st->rr[(it + 1) & 1];
+        ps = v[2] + beta * (v[3] + beta * v[4]);
+        if (!finite(ps))
+            flag = 3;
+        else if (!(ps > 0.0))
+            flag = 2;
+    }
+    if (flag) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->flag = flag;
+            st->it_done = it;
+            st->wrr = wrr;
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
+    const T al = static_cast<T>(rr / ps), bt = static_cast<T>(beta);
+    const T cw = static_cast<T>(v[5]), cs = static_cast<T>(v[6]);
+    double acc[kSr];
+#pragma unroll
+    for (int k = 0; k < kSr; ++k) acc[k] = 0.0;
+    const int lane = threadIdx.x & (L - 1);
+    const RowRange<L, BS> range(n);
+    for (long long row = range.first + range.gid; row < range.last; row += range.ngroups) {
+        int c[E];
+        T w[E];
+        ell_lane<T, E>(row, lane, n, ecol, eval, c, w);
+        Q4<T> g[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) g[k] = cur[c[k]];
+        T a = T(0);
+#pragma unroll
+        for (int k = 0; k < E; ++k) a += w[k] * fmsub(g[k].r, al, fmadd(bt, g[k].s, g[k].w));
+        a = group_sum<L>(a);
+        if (lane == 0) {
+            const Q4<T> me = cur[row];
+            const T vr = PROJ ? vnull[row] : T(0);
+            const T wp = PROJ ? fmsub(me.w, cw, vr) : me.w;
+            const T sp = PROJ ? fmsub(me.s, cs, vr) : me.s;
+            Q4<T> o;
+            o.s = fmadd(bt, sp, wp);
+            o.p = fmadd(bt, me.p, me.r);
+            o.r = fmsub(me.r, al, o.s);
+            o.w = a;
+            x[row] = fmadd(al, o.p, x[row]);
+            nxt[row] = o;
+            sr_partials<T>(acc, o, static_cast<double>(wgt[row]), static_cast<double>(vr));
+        }
+    }
+    write_partials<kSr>(acc, partOut, lds);
+}
+
+// Start of a single-reduction run on the residual in rec: w = Ms r and, with
+// keep != 0, s = Ms p for the direction kept (p itself unchanged);
+// otherwise s = p = 0.  The record is updated in place (the gathered fields
+// r and, with keep, p are not written); the partials are those the first
+// iteration reads.
+template <typename T, int BS, int L>
+__global__ __launch_bounds__(BS) void k_cg_sr_start(int n, const short *__restrict__ ecol,
+                                                    const T *__restrict__ eval, Q4<T> *rec,
+                                                    const T *__restrict__ wgt, const T *__restrict__ vnull,
+                                                    int keep, double *partOut) {
+    constexpr int E = kEll / L;
+    __shared__ double lds[kSr * BS / kWave];
+    double acc[kSr];
+#pragma unroll
+    for (int k = 0; k < kSr; ++k) acc[k] = 0.0;
+    const int lane = threadIdx.x & (L - 1);
+    const RowRange<L, BS> range(n);
+    for (long long row = range.first + range.gid; row < range.last; row += range.ngroups) {
+        int c[E];
+        T w[E];
+        ell_lane<T, E>(row, lane, n, ecol, eval, c, w);
+        T ar = T(0), ap = T(0);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const Q4<T> g = rec[c[k]];
+            ar += w[k] * g.r;
+            ap += w[k] * g.p;
+        }
+        ar = group_sum<L>(ar);
+        ap = group_sum<L>(ap);
+        if (lane == 0) {
+            Q4<T> o;
+            o.r = rec[row].r;
+            o.w = ar;
+            o.s = keep ? ap : T(0);
+            o.p = keep ? rec[row].p : T(0);
+            rec[row].w = o.w;
+            rec[row].s = o.s;
+            if (!keep) rec[row].p = T(0);
+            sr_partials<T>(acc, o, static_cast<double>(wgt[row]), vnull ? static_cast<double>(vnull[row]) : 0.0);
+        }
+    }
+    write_partials<kSr>(acc, partOut, lds);
+}
+
+// Lanes per row of the single-reduction kernels (env OASIS_SR_LANES = 2
+// or 4; 2 measures faster for both record widths).
+int sr_lanes() {
+    static int v = [] {
+        const char *e = std::getenv("OASIS_SR_LANES");
+        const int x = e ? std::atoi(e) : 2;
+        return x == 4 ? 4 : 2;
+    }();
+    return v;
+}
+
+// Grid cap of the single-reduction kernels (env OASIS_SR_GRID): every block
+// of an iteration reads all partials of the previous one, kSr per block.
+int sr_grid_cap() {
+    static int g = [] {
+        const char *e = std::getenv("OASIS_SR_GRID");
+        const int v = e ? std::atoi(e) : kMaxPartials / 2;
+        return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
+    }();
+    return g;
+}
+
+// Single-reduction CG on the ELL copy in rec / the workspace partials.
+// Used by cg_run and cg_mixed_run when the ELL copy is present.
+template <typename T>
+struct SrLoop {
+    static constexpr int BS = kBlock;
+    hipStream_t s;
+    int n;
+    const short *ecol;
+    const T *eval;
+    const T *wgt, *vnull;
+    CGWork<T> *w;
+    int lanes, grid;
+    SrLoop(hipStream_t s_, int n_, CGWork<T> &w_, const T *wgt_, const T *vnull_)
+        : s(s_), n(n_), ecol(w_.ecol), eval(w_.eval), wgt(wgt_), vnull(vnull_), w(&w_) {
+        lanes = sr_lanes();
+        grid = grid_for(n, BS / lanes, std::min(kMaxPartials, sr_grid_cap()));
+    }
+    double *part(int it) const { return (it & 1) ? w->partA : w->partB; }
+    // partials for iteration `at`, written into part(at)
+    int start(int at, bool keep) {
+        if (lanes == 4)
+            hipLaunchKernelGGL((k_cg_sr_start<T, BS, 4>), dim3(grid), dim3(BS), 0, s, n, ecol, eval,
+                               w->rec[at & 1], wgt, vnull, keep ? 1 : 0, part(at));
+        else
+            hipLaunchKernelGGL((k_cg_sr_start<T, BS, 2>), dim3(grid), dim3(BS), 0, s, n, ecol, eval,
+                               w->rec[at & 1], wgt, vnull, keep ? 1 : 0, part(at));
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    }
+    template <int L, bool PROJ>
+    void go(int it, int beta_zero, T *x) {
+        hipLaunchKernelGGL((k_cg_sr<T, BS, L, PROJ>), dim3(grid), dim3(BS), 0, s, n, ecol, eval,
+                           w->rec[it & 1], w->rec[(it + 1) & 1], x, wgt, vnull, part(it), grid, w->st, it,
+                           beta_zero, part(it + 1));
+    }
+    void iterate(int it, int beta_zero, T *x) {
+        if (lanes == 4) {
+            if (vnull) return go<4, true>(it, beta_zero, x);
+            return go<4, false>(it, beta_zero, x);
+        }
+        if (vnull) return go<2, true>(it, beta_zero, x);
+        return go<2, false>(it, beta_zero, x);
+    }
+};
+
 __global__ __launch_bounds__(kBlock) void k_max_row(int n, const int *__restrict__ rp, int *out) {
     int m = 0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -452,12 +700,27 @@ int csr_to_ell(hipStream_t s, int n, const int *rp, const int *ci, const double 
 
 template <typename T>
 void carve_cg(Carver &c, int n, CGWork<T> &w) {
-    w.pair[0] = c.take<RP<T>>(n);
-    w.pair[1] = c.take<RP<T>>(n);
+    for (int k = 0; k < 2; ++k) {
+        w.rec[k] = c.take<Q4<T>>(n);
+        w.pair[k] = reinterpret_cast<RP<T> *>(w.rec[k]);
+    }
     w.q = c.take<T>(n);
-    w.partA = c.take<double>(3 * kMaxPartials);
-    w.partB = c.take<double>(3 * kMaxPartials);
+    w.partA = c.take<double>(kSr * kMaxPartials);
+    w.partB = c.take<double>(kSr * kMaxPartials);
     w.st = c.take<CGState>(1);
+}
+
+// Single-reduction iterations on the ELL copy.  Their gathered record is
+// (r, w, s) rather than (r, p): with FP32 values the one pass beats the two
+// (the update pass is gone), with FP64 values the wider gathers cost more
+// than that pass.  Default: FP32 only; env OASIS_CG_SR = 0 (never) or 1
+// (both widths).
+bool sr_enabled(int tbytes) {
+    static int mode = [] {
+        const char *e = std::getenv("OASIS_CG_SR");
+        return e ? std::atoi(e) : -1;
+    }();
+    return mode == 1 || (mode != 0 && tbytes == 4);
 }
 
 // Kernel timing of a solve (time_kernel): when the solve has stopped at
@@ -540,14 +803,17 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     const int gi = grid_for(n, rows_per_block<C>(), partial_cap());     // k_cg_init (kBlock threads)
     const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
     const bool ell = w.ecol && w.eval && ell_enabled();
+    const bool sr = ell && sr_enabled(sizeof(T));
+    SrLoop<T> loop(s, n, w, wgt, nullptr);
     const int g1 = ell ? launch_p1_ell<T, BS>(s, n, w.ecol, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
                                               nullptr, 0, 0, nullptr, nullptr, true)
                        : g.p1;
     out = SolveOut();
-    // explicit residual into the r of the pair that iteration `at` reads
+    // explicit residual into the r of the record that iteration `at` reads
     auto residual = [&](int mode, int at) -> int {
+        T *r = sr ? reinterpret_cast<T *>(w.rec[at & 1]) : reinterpret_cast<T *>(w.pair[at & 1]);
         hipLaunchKernelGGL((k_cg_init<T, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                           b, x, reinterpret_cast<T *>(w.pair[at & 1]), 2, w.partB);
+                           b, x, r, sr ? 4 : 2, w.partB);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, gi, w.st,
                            rtol * rtol, mode, 0.0);
@@ -555,6 +821,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         return OASIS_OK;
     };
     OASIS_TRY(residual(0, 0));
+    if (sr) OASIS_TRY(loop.start(0, false));
     CGState h;
     const int chunk = check_every > 0 ? check_every : 32;
     int it = 0, restart_at = 0;
@@ -568,6 +835,11 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             const int itj = it + j;
             // after a restart the incoming partials are k_cg_init's (3 per block)
             const bool fresh = itj == restart_at;
+            if (sr) {
+                loop.iterate(itj, fresh ? 1 : 0, x);
+                OASIS_TRY_LAUNCH();
+                continue;
+            }
             const int nin = fresh ? gi : g.p2, stride = fresh ? 3 : 2;
             if (ell)
                 launch_p1_ell<T, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
@@ -594,7 +866,12 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             out.iters = it;
             finish(h.wrr, wbb);
             out.status = rc = (h.wrr <= tol2) ? OASIS_OK : OASIS_ENOTCONV;
-            if (time_kernel && rc == OASIS_ENOTCONV) {
+            if (time_kernel && rc == OASIS_ENOTCONV && sr) {
+                // repeat iteration `it` from the residual just recomputed; x
+                // is left alone (the repeats advance a scratch copy)
+                OASIS_TRY(loop.start(it, false));
+                OASIS_TRY(time_product(s, maxit, [&] { loop.iterate(it, 1, w.q); }, out));
+            } else if (time_kernel && rc == OASIS_ENOTCONV) {
                 // repeat iteration `it` on the residual just recomputed (k_cg_init's partials)
                 const int itj = it;
                 OASIS_TRY(time_product(
@@ -635,6 +912,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                 out.status = rc = OASIS_ENOTCONV;
                 break;
             }
+            if (sr) OASIS_TRY(loop.start(itd, false));
             continue;
         }
         out.iters = h.it_done;
@@ -674,6 +952,8 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     const int gv = grid_for(n, kBlock, partial_cap());                  // k_cg_cast, k_add_lo
     const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
     const bool ell = w.ecol && w.eval && ell_enabled();
+    const bool sr = ell && sr_enabled(4);
+    SrLoop<float> loop(s, n, w, wgt32, vnull);
     const int g1 = ell ? launch_p1_ell<float, BS>(s, n, w.ecol, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
                                                   nullptr, 0, 0, nullptr, nullptr, true)
                        : g.p1;
@@ -689,10 +969,13 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
-    // into the r of the pair that iteration `at` reads; its direction stays
-    auto cast = [&](int at) -> int {
-        hipLaunchKernelGGL(k_cg_cast, dim3(gv), dim3(kBlock), 0, s, n, rhi, wgt32, w.pair[at & 1], xlo, w.partB);
+    // into the r of the record that iteration `at` reads; its direction stays
+    // (the single-reduction start then forms Ms r and Ms p of the record)
+    auto cast = [&](int at, bool keep) -> int {
+        float *r = sr ? reinterpret_cast<float *>(w.rec[at & 1]) : reinterpret_cast<float *>(w.pair[at & 1]);
+        hipLaunchKernelGGL(k_cg_cast, dim3(gv), dim3(kBlock), 0, s, n, rhi, wgt32, r, sr ? 4 : 2, xlo, w.partB);
         OASIS_TRY_LAUNCH();
+        if (sr) OASIS_TRY(loop.start(at, keep));
         return OASIS_OK;
     };
     auto fold = [&]() -> int {
@@ -715,7 +998,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         out.rel_res = rel(h.wrr);
         return OASIS_OK;
     }
-    OASIS_TRY(cast(0));
+    OASIS_TRY(cast(0, false));
     const int chunk = check_every > 0 ? check_every : 32;
     int it = 0, restart_at = 0, nin = gv;     // partials of k_cg_cast first, then of k_cg_p2
     int rc = OASIS_OK;
@@ -723,6 +1006,11 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         const int m = std::min(chunk, maxit - it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
+            if (sr) {
+                loop.iterate(itj, itj == restart_at ? 1 : 0, xlo);
+                OASIS_TRY_LAUNCH();
+                continue;
+            }
             const int ni = j == 0 ? nin : g.p2;
             if (ell)
                 launch_p1_ell<float, BS>(s, n, w.ecol, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
@@ -769,7 +1057,12 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         if (at >= maxit) {
             out.iters = at;
             out.status = rc = OASIS_ENOTCONV;
-            if (time_kernel) {
+            if (time_kernel && sr) {
+                // repeat iteration `at` from the replaced residual; x_lo is
+                // left alone (the repeats advance a scratch copy)
+                OASIS_TRY(cast(at, true));
+                OASIS_TRY(time_product(s, maxit, [&] { loop.iterate(at, 0, w.q); }, out));
+            } else if (time_kernel) {
                 // repeat iteration `at` (FP32 pair in place, k_cg_init's partials)
                 OASIS_TRY(time_product(
                     s, maxit,
@@ -786,7 +1079,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
             }
             break;
         }
-        OASIS_TRY(cast(at));
+        OASIS_TRY(cast(at, true));
         it = at;
         nin = gv;
     }
@@ -840,13 +1133,22 @@ template <typename T>
 struct C3 {
     const T *p[3];
 };
+template <typename T>
+struct W3 {
+    RW<T> *p[3];
+};
+template <typename T>
+struct CW3 {
+    const RW<T> *p[3];
+};
 
 // r_k = b_k - As xsrc_k for k in mask_res; r_hat_k = r_k for k in mask_rhat;
-// partials (r_hat.r, sum wgt r^2, sum wgt b^2) for every k.
+// partials (r_hat.r, sum wgt r^2, sum wgt b^2) for every k.  The residual
+// is the first half of the (r, u) pair; u is left as it is.
 template <typename T, int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
                                                      const T *__restrict__ wgt, C3<T> b,
-                                                     C3<T> xsrc, V3<T> r, V3<T> rhat, int mask_res,
+                                                     C3<T> xsrc, W3<T> ru, V3<T> rhat, int mask_res,
                                                      int mask_rhat, double *part) {
     __shared__ double lds[9 * kBlock / kWave];
     double acc[3 * NR];
@@ -870,9 +1172,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
                 T rk;
                 if ((mask_res >> k) & 1) {
                     rk = b.p[k][row] - a[k];
-                    r.p[k][row] = rk;
+                    ru.p[k][row].r = rk;
                 } else {
-                    rk = r.p[k][row];
+                    rk = ru.p[k][row].r;
                 }
                 T hk;
                 if ((mask_rhat >> k) & 1) {
@@ -913,13 +1215,15 @@ __device__ __forceinline__ void bi_pause(BiGlobal *g, int phase, int it) {
     g->pause = 1;
 }
 
-// part 1: tests on the incoming residual, p = r + beta (p - omega v),
-// v = As p, partial r_hat.v
+// part 1: tests on the incoming residual, p = r + beta u (u = p_old -
+// omega v_old, formed by part 3), v = As p, partial r_hat.v.  Writes p and
+// the (r, v) pairs that part 2 gathers; reads nothing it writes, so a
+// relaunch after a pause recomputes the same values.
 template <typename T, int NR, class C>
-__global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, C3<T> r, C3<T> rhat,
-                                                 C3<T> pold, C3<T> vold, V3<T> pnew, V3<T> vnew,
-                                                 const double *partIn, int nIn, BiState *st,
-                                                 BiGlobal *glob, int it, double *partOut) {
+__global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, CW3<T> ru, C3<T> rhat,
+                                                 V3<T> p, W3<T> rv, const double *partIn, int nIn,
+                                                 BiState *st, BiGlobal *glob, int it,
+                                                 double *partOut) {
     __shared__ double lds[9 * kBlock / kWave];
     if (block_read_flag(&glob->pause)) return;
     double v[3 * NR];
@@ -950,12 +1254,11 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, C3<T> r, C3<T>
         }
         return;
     }
-    T beta[NR], om[NR];
+    T beta[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         const double rr = v[3 * k];
         beta[k] = static_cast<T>((rr / st[k].rho[prev]) * (st[k].alpha[prev] / st[k].omega[prev]));
-        om[k] = static_cast<T>(st[k].omega[prev]);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int k = 0; k < NR; ++k)
@@ -970,7 +1273,8 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, C3<T> r, C3<T>
 #pragma unroll
             for (int k = 0; k < NR; ++k)
                 if ((active >> k) & 1) {
-                    const T t = vv * (r.p[k][c] + beta[k] * (pold.p[k][c] - om[k] * vold.p[k][c]));
+                    const RW<T> g = ru.p[k][c];
+                    const T t = vv * fmadd(beta[k], g.w, g.r);
                     a[k] += ok ? t : T(0);
                 }
         },
@@ -979,9 +1283,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, C3<T> r, C3<T>
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 if (!((active >> k) & 1)) continue;
-                const T pn = r.p[k][row] + beta[k] * (pold.p[k][row] - om[k] * vold.p[k][row]);
-                pnew.p[k][row] = pn;
-                vnew.p[k][row] = a[k];
+                const RW<T> me = ru.p[k][row];
+                p.p[k][row] = fmadd(beta[k], me.w, me.r);
+                rv.p[k][row] = RW<T>{me.r, a[k]};
                 acc[k] += static_cast<double>(rhat.p[k][row]) * static_cast<double>(a[k]);
             }
         });
@@ -989,11 +1293,11 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, C3<T> r, C3<T>
 }
 
 // part 2: alpha = rho / (r_hat.v), s = r - alpha v, t = As s,
-// partials (t.s, t.t, sum wgt s^2)
+// partials (t.s, t.t, sum wgt s^2).  s itself is not stored: part 3 forms
+// it again from the same (r, v) pair with the same rounding.
 template <typename T, int NR, class C>
-__global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m,
-                                                 const T *__restrict__ wgt, C3<T> r, C3<T> vv,
-                                                 V3<T> s, V3<T> t, const double *partIn, int nIn,
+__global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m, const T *__restrict__ wgt,
+                                                 CW3<T> rv, V3<T> t, const double *partIn, int nIn,
                                                  BiState *st, BiGlobal *glob, int it,
                                                  double *partOut) {
     __shared__ double lds[9 * kBlock / kWave];
@@ -1038,8 +1342,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m,
 #pragma unroll
             for (int k = 0; k < NR; ++k)
                 if ((active >> k) & 1) {
-                    const T t = w * (r.p[k][c] - al[k] * vv.p[k][c]);
-                    a[k] += ok ? t : T(0);
+                    const RW<T> g = rv.p[k][c];
+                    const T tk = w * fmsub(g.r, al[k], g.w);
+                    a[k] += ok ? tk : T(0);
                 }
         },
         [&](int row, int lane, T(&a)[NR]) {
@@ -1048,8 +1353,8 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m,
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 if (!((active >> k) & 1)) continue;
-                const T sn = r.p[k][row] - al[k] * vv.p[k][row];
-                s.p[k][row] = sn;
+                const RW<T> me = rv.p[k][row];
+                const T sn = fmsub(me.r, al[k], me.w);
                 t.p[k][row] = a[k];
                 const double sd = sn, td = a[k];
                 acc[3 * k + 0] += td * sd;
@@ -1060,13 +1365,15 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m,
     write_partials<3 * NR>(acc, partOut, lds);
 }
 
-// part 3: s-stage test, omega = (t.s)/(t.t), x += alpha p + omega s,
-// r = s - omega t, partials (r_hat.r, sum wgt r^2, 0)
+// part 3: s-stage test, omega = (t.s)/(t.t), s = r - alpha v,
+// x += alpha p + omega s, r = s - omega t and u = p - omega v for the next
+// direction; partials (r_hat.r, sum wgt r^2, 0)
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void k_bi_3(int n, const T *__restrict__ wgt, V3<T> x,
-                                                 V3<T> r, C3<T> rhat, C3<T> p, C3<T> s, C3<T> t,
-                                                 const double *partIn, int nIn, BiState *st,
-                                                 BiGlobal *glob, int it, double *partOut) {
+                                                 W3<T> ru, C3<T> rhat, C3<T> p, CW3<T> rv,
+                                                 C3<T> t, const double *partIn, int nIn,
+                                                 BiState *st, BiGlobal *glob, int it,
+                                                 double *partOut) {
     __shared__ double lds[9 * kBlock / kWave];
     if (block_read_flag(&glob->pause)) return;
     double v[3 * NR];
@@ -1112,10 +1419,12 @@ __global__ __launch_bounds__(kBlock) void k_bi_3(int n, const T *__restrict__ wg
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             if (!((active >> k) & 1)) continue;
-            const T sk = s.p[k][i];
-            x.p[k][i] = x.p[k][i] + al[k] * p.p[k][i] + om[k] * sk;
-            const T rk = sk - om[k] * t.p[k][i];
-            r.p[k][i] = rk;
+            const RW<T> g = rv.p[k][i];
+            const T sk = fmsub(g.r, al[k], g.w);
+            const T pk = p.p[k][i];
+            x.p[k][i] = x.p[k][i] + al[k] * pk + om[k] * sk;
+            const T rk = fmsub(sk, om[k], t.p[k][i]);
+            ru.p[k][i] = RW<T>{rk, fmsub(pk, om[k], g.w)};
             const double rd = rk;
             acc[3 * k + 0] += static_cast<double>(rhat.p[k][i]) * rd;
             acc[3 * k + 1] += wd * rd * rd;
@@ -1137,17 +1446,22 @@ __global__ __launch_bounds__(kBlock) void k_bi_xs(int n, C3<T> x, C3<T> p, V3<T>
     }
 }
 
+// u = 0 in every (r, u) pair: the next direction is the residual itself
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero_u(int n, RW<T> *ru) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        ru[i].w = T(0);
+}
+
 template <typename T>
 void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
     std::memset(&w, 0, sizeof(w));
     for (int k = 0; k < nrhs; ++k) {
-        w.r[k] = c.take<T>(n);
+        w.ru[k] = c.take<RW<T>>(n);
+        w.rv[k] = c.take<RW<T>>(n);
+        w.p[k] = c.take<T>(n);
         w.rhat[k] = c.take<T>(n);
-        w.p[0][k] = c.take<T>(n);
-        w.p[1][k] = c.take<T>(n);
-        w.v[0][k] = c.take<T>(n);
-        w.v[1][k] = c.take<T>(n);
-        w.s[k] = c.take<T>(n);
         w.t[k] = c.take<T>(n);
         w.xs[k] = c.take<T>(n);
     }
@@ -1167,21 +1481,20 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     const int gv = grid_for(n, kBlock, 4096);
     const bool ell = w.ecol && w.eval && ell_enabled();
     const Mat<T> mat{rp, ci, val, ell ? w.ecol : nullptr, ell ? w.eval : nullptr};
-    C3<T> cb{}, cx{}, cr{}, crh{}, cs{}, ct{}, cp[2]{}, cvv[2]{};
-    V3<T> vx{}, vr{}, vrh{}, vs{}, vt{}, vp[2]{}, vvv[2]{}, vxs{};
+    C3<T> cb{}, cx{}, crh{}, ct{}, cp{};
+    V3<T> vx{}, vrh{}, vt{}, vp{}, vxs{};
+    CW3<T> cru{}, crv{};
+    W3<T> vru{}, vrv{};
     for (int k = 0; k < NR; ++k) {
         cb.p[k] = b[k];
         cx.p[k] = x[k];
         vx.p[k] = x[k];
-        cr.p[k] = vr.p[k] = w.r[k];
+        cru.p[k] = vru.p[k] = w.ru[k];
+        crv.p[k] = vrv.p[k] = w.rv[k];
         crh.p[k] = vrh.p[k] = w.rhat[k];
-        cs.p[k] = vs.p[k] = w.s[k];
         ct.p[k] = vt.p[k] = w.t[k];
+        cp.p[k] = vp.p[k] = w.p[k];
         vxs.p[k] = w.xs[k];
-        for (int q = 0; q < 2; ++q) {
-            cp[q].p[k] = vp[q].p[k] = w.p[q][k];
-            cvv[q].p[k] = vvv[q].p[k] = w.v[q][k];
-        }
     }
     BiState hs[3];
     BiGlobal hg{};
@@ -1204,17 +1517,13 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         return OASIS_OK;
     };
     auto zero_dirs = [&](int k) -> int {
-        for (int q = 0; q < 2; ++q) {
-            hipLaunchKernelGGL((k_fill<T>), dim3(gv), dim3(kBlock), 0, s, n, w.p[q][k], T(0));
-            OASIS_TRY_LAUNCH();
-            hipLaunchKernelGGL((k_fill<T>), dim3(gv), dim3(kBlock), 0, s, n, w.v[q][k], T(0));
-            OASIS_TRY_LAUNCH();
-        }
+        hipLaunchKernelGGL((k_zero_u<T>), dim3(gv), dim3(kBlock), 0, s, n, w.ru[k]);
+        OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
     auto resid = [&](int mask_res, int mask_rhat, C3<T> src) -> int {
         hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat, wgt,
-                           cb, src, vr, vrh, mask_res, mask_rhat, w.part3);
+                           cb, src, vru, vrh, mask_res, mask_rhat, w.part3);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
@@ -1272,8 +1581,8 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             if (phase == 1) {
                 if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
                 hipLaunchKernelGGL((k_bi_1<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
-                                   cr, crh, cp[(it + 1) & 1], cvv[(it + 1) & 1], vp[it & 1],
-                                   vvv[it & 1], w.part3, part3_count, w.st, w.glob, it, w.part1);
+                                   cru, crh, vp, vrv, w.part3, part3_count, w.st, w.glob, it,
+                                   w.part1);
                 OASIS_TRY_LAUNCH();
                 if (time_kernel) {
                     OASIS_TRY_HIP(hipEventRecord(e1, s));
@@ -1284,12 +1593,11 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                     out[0].kernel_count += 1;
                 }
                 hipLaunchKernelGGL((k_bi_2<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
-                                   wgt, cr, cvv[it & 1], vs, vt, w.part1, g1, w.st, w.glob, it,
-                                   w.part2);
+                                   wgt, crv, vt, w.part1, g1, w.st, w.glob, it, w.part2);
                 OASIS_TRY_LAUNCH();
             }
-            hipLaunchKernelGGL((k_bi_3<T, NR>), dim3(g2), dim3(kBlock), 0, s, n, wgt, vx, vr, crh,
-                               cp[it & 1], cs, ct, w.part2, g1, w.st, w.glob, it, w.part3);
+            hipLaunchKernelGGL((k_bi_3<T, NR>), dim3(g2), dim3(kBlock), 0, s, n, wgt, vx, vru, crh,
+                               cp, crv, ct, w.part2, g1, w.st, w.glob, it, w.part3);
             OASIS_TRY_LAUNCH();
             part3_count = g2;
             phase = 1;
@@ -1359,7 +1667,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             int cands = 0;
             for (int k = 0; k < NR; ++k)
                 if (hs[k].active && hs[k].event == 5) cands |= 1 << k;
-            hipLaunchKernelGGL((k_bi_xs<T, NR>), dim3(gv), dim3(kBlock), 0, s, n, cx, cp[pit & 1], vxs,
+            hipLaunchKernelGGL((k_bi_xs<T, NR>), dim3(gv), dim3(kBlock), 0, s, n, cx, cp, vxs,
                                w.st, pit, cands);
             OASIS_TRY_LAUNCH();
             C3<T> src = cx;

@@ -23,12 +23,24 @@ struct alignas(2 * sizeof(T)) RP {
     T r, p;
 };
 
+// One row of the single-reduction CG state: residual r, its product
+// w = Ms r, the direction's product s = Ms p and the direction p.
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+    T r, w, s, p;
+};
+
 template <typename T>
 struct CGWork {
-    // Residual and direction interleaved, so that the product kernel fetches
-    // both with one gather: iteration it reads pair[it & 1] = (r_it, p_{it-1})
-    // and writes (r_it, p_it) into pair[(it + 1) & 1], whose r the update
-    // kernel then turns into r_{it+1}.
+    // ELL path (single-reduction CG, one kernel per iteration): iteration it
+    // reads rec[it & 1] = (r_it, Ms r_it, s_{it-1}, p_{it-1}) and writes
+    // (r_{it+1}, Ms r_{it+1}, s_it, p_it) into rec[(it + 1) & 1].
+    Q4<T> *rec[2] = {nullptr, nullptr};
+    // CSR path (two kernels per iteration), in the same memory: residual and
+    // direction interleaved, so that the product kernel fetches both with
+    // one gather: iteration it reads pair[it & 1] = (r_it, p_{it-1}) and
+    // writes (r_it, p_it) into pair[(it + 1) & 1], whose r the update kernel
+    // then turns into r_{it+1}.
     RP<T> *pair[2] = {nullptr, nullptr};
     T *q = nullptr;
     double *partA = nullptr, *partB = nullptr;
@@ -55,9 +67,21 @@ struct BiGlobal {
     int pad;
 };
 
+// A residual interleaved with a companion vector (BiCGStab's u or v).
+template <typename T>
+struct alignas(2 * sizeof(T)) RW {
+    T r, w;
+};
+
 template <typename T>
 struct BiWork {
-    T *r[3], *rhat[3], *p[2][3], *v[2][3], *s[3], *t[3], *xs[3];
+    // Per right-hand side: ru = (r, u) with u = p - omega v, the part of
+    // the next direction beyond r (formed by the update kernel, so the first
+    // product gathers one pair per entry); rv = (r, v) written by the first
+    // product for the second; the direction p, r_hat, s, t and the s-stage
+    // candidate iterate xs.
+    RW<T> *ru[3], *rv[3];
+    T *p[3], *rhat[3], *s[3], *t[3], *xs[3];
     double *part1, *part2, *part3;
     BiState *st;       // [3]
     BiGlobal *glob;
