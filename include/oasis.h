@@ -198,7 +198,9 @@ typedef struct {
     double rel_res;       /* final true ||b - A x|| / ||b|| */
     double kernel_ms;     /* OASIS_KRYLOV_TIME: total time of the timed launches */
     int32_t kernel_count; /* number of timed launches */
-    int32_t pad;
+    int32_t ell_patterns; /* column storage the products used: > 0 the number of distinct
+                             per-row offset lists of the ELL dictionary, -1 per-entry
+                             16-bit ELL offsets, 0 CSR */
 } oasis_krylov_stats;
 
 /* Workspace for oasis_pcg / oasis_bicgstab with nrhs right-hand sides. */

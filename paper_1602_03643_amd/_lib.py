@@ -48,7 +48,7 @@ class KrylovOpts(C.Structure):
 
 class KrylovStats(C.Structure):
     _fields_ = [("iters", i32), ("outer_iters", i32), ("status", i32), ("restarts", i32),
-                ("rel_res", f64), ("kernel_ms", f64), ("kernel_count", i32), ("pad", i32)]
+                ("rel_res", f64), ("kernel_ms", f64), ("kernel_count", i32), ("ell_patterns", i32)]
 
 
 class IpcsParams(C.Structure):

@@ -205,7 +205,8 @@ def _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kerne
 
 def _stats(st):
     return dict(iters=st.iters, outer_iters=st.outer_iters, status=st.status, restarts=st.restarts,
-                rel_res=st.rel_res, kernel_ms=st.kernel_ms, kernel_count=st.kernel_count)
+                rel_res=st.rel_res, kernel_ms=st.kernel_ms, kernel_count=st.kernel_count,
+                ell_patterns=st.ell_patterns)
 
 
 def pcg(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=0.1, max_outer=50,

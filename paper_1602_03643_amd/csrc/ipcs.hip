@@ -776,6 +776,9 @@ struct oasis_ipcs {
     double *ML = nullptr, *sK = nullptr, *wK = nullptr, *dA = nullptr, *wA = nullptr, *dtmp = nullptr;
     double *rtmp = nullptr;   // residual scratch of the warm-start guard
     short *ecol = nullptr;    // ELL column offsets of the shared pattern (when they fit)
+    unsigned short *pid = nullptr;   // their pattern dictionary: id per row,
+    short *ptab = nullptr;           // offset lists
+    EllCols cols;             // what the ELL products use (none when the offsets do not fit)
     double *eval = nullptr;   // ELL values of the pressure matrix: FP64 (FP64 mode) or
     float *eval32 = nullptr;  // their FP32 rounding (mixed mode)
     double *eA = nullptr;     // ELL values of the column-scaled tentative matrix, per step:
@@ -801,8 +804,28 @@ struct oasis_ipcs {
     size_t ws_bytes = 0;
 };
 
+// ELL copy of a matrix on a CSR pattern and the pattern dictionary of its
+// offsets; *cols receives the columns the products use (none when the
+// offsets do not fit, and the products then run on CSR).  Synchronises.
+static int ell_setup(hipStream_t s, int n, const int *rp, const int *ci, const double *val, short *ecol,
+                     unsigned short *pid, short *ptab, double *eval, float *eval32, int *tmp, EllCols *cols,
+                     int *storage = nullptr) {
+    bool fits = false;
+    *cols = EllCols{};
+    if (storage) *storage = 0;
+    OASIS_TRY(csr_to_ell(s, n, rp, ci, val, ecol, eval, eval32, tmp, &fits));
+    if (!fits) return OASIS_OK;
+    int npat = 0;
+    OASIS_TRY(ell_dictionary(s, n, ecol, pid, ptab, &npat));
+    *cols = ell_cols(ecol, pid, ptab, npat);
+    if (storage && ell_enabled()) *storage = npat > 0 ? npat : -1;
+    return OASIS_OK;
+}
+
 static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, oasis_ipcs &h) {
     h.ecol = c.take<short>((size_t)n * kEll);
+    h.pid = c.take<unsigned short>(n);
+    h.ptab = c.take<short>((size_t)kMaxEllPatterns * kEll);
     if (mixed) {
         h.eval32 = c.take<float>((size_t)n * kEll);
         h.eA32 = c.take<float>((size_t)n * kEll);
@@ -942,16 +965,17 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     // ELL copy of the pressure matrix for the CG product when its rows and
     // column offsets allow it (else the CSR product runs)
     {
-        bool fits = false;
-        const int rc4 = csr_to_ell(s, n, row_ptr, col_idx, h->Ks, h->ecol, h->eval, h->eval32, h->flag + 24, &fits);
+        const int rc4 = ell_setup(s, n, row_ptr, col_idx, h->Ks, h->ecol, h->pid, h->ptab, h->eval, h->eval32,
+                                  h->flag + 24, &h->cols);
         if (rc4 != OASIS_OK) return fail(rc4);
+        const bool fits = h->cols.any();
         h->ell = fits;
         if (fits && h->mixed) {
-            h->cg32.ecol = h->bi32.ecol = h->ecol;
+            h->cg32.cols = h->bi32.cols = h->cols;
             h->cg32.eval = h->eval32;
             h->bi32.eval = h->eA32;
         } else if (fits) {
-            h->cg.ecol = h->bi.ecol = h->ecol;
+            h->cg.cols = h->bi.cols = h->cols;
             h->cg.eval = h->eval;
             h->bi.eval = h->eA;
         }
@@ -1265,7 +1289,9 @@ struct KrylovWs {
     double *val, *s, *w, *b, *x, *rhi;
     float *val32, *w32, *vnull32, *xlo;
     int *flag;
-    short *ecol;        // ELL copy of the scaled matrix for the CG product
+    short *ecol;        // ELL copy of the scaled matrix for the Krylov products
+    unsigned short *pid;
+    short *ptab;
     double *eval;       // (FP64 mode)
     float *eval32;      // (mixed mode)
     CGWork<double> cg;
@@ -1285,6 +1311,8 @@ static void carve_krylov(Carver &c, int n, int nnz, int nrhs, bool mixed, Krylov
     k.x = c.take<double>(n);
     k.flag = c.take<int>(16);
     k.ecol = c.take<short>((size_t)n * kEll);
+    k.pid = c.take<unsigned short>(n);
+    k.ptab = c.take<short>((size_t)kMaxEllPatterns * kEll);
     if (mixed)
         k.eval32 = c.take<float>((size_t)n * kEll);
     else
@@ -1314,7 +1342,7 @@ extern "C" int oasis_krylov_workspace_size(int32_t n, int32_t nnz, int32_t nrhs,
     return OASIS_OK;
 }
 
-static void fill_stats(const SolveOut &o, oasis_krylov_stats *st) {
+static void fill_stats(const SolveOut &o, int ell_storage, oasis_krylov_stats *st) {
     st->iters = o.iters;
     st->outer_iters = o.outer;
     st->status = o.status;
@@ -1322,7 +1350,7 @@ static void fill_stats(const SolveOut &o, oasis_krylov_stats *st) {
     st->rel_res = o.rel_res;
     st->kernel_ms = o.kernel_ms;
     st->kernel_count = o.kernel_count;
-    st->pad = 0;
+    st->ell_patterns = ell_storage;
 }
 
 static int check_opts(const oasis_krylov_opts *o) {
@@ -1356,14 +1384,16 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     if (fl) return OASIS_EINVAL;
+    int ell_storage = 0;
     {
-        bool fits = false;
-        OASIS_TRY(csr_to_ell(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.eval, k.eval32, k.flag + 8, &fits));
-        if (fits && mixed) {
-            k.cg32.ecol = k.ecol;
+        EllCols cols;
+        OASIS_TRY(ell_setup(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.pid, k.ptab, k.eval, k.eval32,
+                            k.flag + 8, &cols, &ell_storage));
+        if (cols.any() && mixed) {
+            k.cg32.cols = cols;
             k.cg32.eval = k.eval32;
-        } else if (fits) {
-            k.cg.ecol = k.ecol;
+        } else if (cols.any()) {
+            k.cg.cols = cols;
             k.cg.eval = k.eval;
         }
     }
@@ -1387,7 +1417,7 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.x, k.s, 2, x);
     OASIS_TRY_LAUNCH();
     OASIS_TRY_HIP(hipStreamSynchronize(s));
-    fill_stats(so, stats);
+    fill_stats(so, ell_storage, stats);
     return rc;
 }
 
@@ -1416,14 +1446,16 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
     OASIS_TRY_HIP(hipMemcpyAsync(&fl, k.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     if (fl) return OASIS_EINVAL;     // x untouched
+    int ell_storage = 0;
     {
-        bool fits = false;
-        OASIS_TRY(csr_to_ell(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.eval, k.eval32, k.flag + 8, &fits));
-        if (fits && mixed) {
-            k.bi32.ecol = k.ecol;
+        EllCols cols;
+        OASIS_TRY(ell_setup(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.pid, k.ptab, k.eval, k.eval32,
+                            k.flag + 8, &cols, &ell_storage));
+        if (cols.any() && mixed) {
+            k.bi32.cols = cols;
             k.bi32.eval = k.eval32;
-        } else if (fits) {
-            k.bi.ecol = k.ecol;
+        } else if (cols.any()) {
+            k.bi.cols = cols;
             k.bi.eval = k.eval;
         }
     }
@@ -1448,6 +1480,6 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
     hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.s, 2, xs[0], xs[1], xs[2]);
     OASIS_TRY_LAUNCH();
     OASIS_TRY_HIP(hipStreamSynchronize(s));
-    for (int q = 0; q < nrhs; ++q) fill_stats(so[q], stats + q);
+    for (int q = 0; q < nrhs; ++q) fill_stats(so[q], ell_storage, stats + q);
     return rc;
 }

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "internal.hpp"
+#include "spmv.hpp"
 
 namespace oasis {
 
@@ -47,7 +48,7 @@ struct CGWork {
     CGState *st = nullptr;
     // optional ELL copy of the iteration matrix (set by the owner); the
     // product kernel uses it when present
-    const short *ecol = nullptr;
+    EllCols cols;
     const T *eval = nullptr;
 };
 
@@ -86,7 +87,7 @@ struct BiWork {
     BiState *st;       // [3]
     BiGlobal *glob;
     // optional ELL copy of the iteration matrix (set by the owner)
-    const short *ecol = nullptr;
+    EllCols cols;
     const T *eval = nullptr;
 };
 
@@ -141,6 +142,31 @@ int csr_max_row(hipStream_t s, int n, const int *rp, int *tmp, int *out);
 // if not, the copy must not be used.  tmp: one device int.  Synchronises.
 int csr_to_ell(hipStream_t s, int n, const int *rp, const int *ci, const double *val, short *ecol,
                double *eval, float *eval32, int *tmp, bool *fits);
+
+// Most distinct offset lists an ELL pattern dictionary holds.
+constexpr int kMaxEllPatterns = 4096;
+
+// Pattern dictionary of an ELL copy's offsets (ecol, as written by
+// csr_to_ell): pid [n] receives each row's pattern id and ptab
+// [kMaxEllPatterns][kEll] the distinct offset lists, numbered in order of
+// first occurrence.  *npat = their number, or 0 when there are more than
+// min(kMaxEllPatterns, n / 8) (pid and ptab then must not be used) or the
+// dictionary is switched off (env OASIS_ELL_DICT=0).  Host work on a copy
+// of ecol; synchronises.
+int ell_dictionary(hipStream_t s, int n, const short *ecol, unsigned short *pid, short *ptab, int *npat);
+
+// The columns of an ELL copy: the dictionary when it was built, else the
+// per-entry offsets.
+inline EllCols ell_cols(const short *ecol, const unsigned short *pid, const short *ptab, int npat) {
+    EllCols c;
+    if (npat > 0) {
+        c.pid = pid;
+        c.ptab = ptab;
+    } else {
+        c.ecol = ecol;
+    }
+    return c;
+}
 
 // Weighted residual of x for the scaled system: r = b - Ms x, returns
 // (sum wgt r^2, sum wgt b^2) on the host.  Uses w's buffers.

@@ -128,6 +128,20 @@ __device__ __forceinline__ void csr_rows(int n, const int *__restrict__ rp, cons
 constexpr int kEll = 16;
 constexpr int kEllLanes = kEll / 4;
 
+// Column offsets of an ELL copy: per entry (ecol, n x kEll), or per row
+// through a dictionary (pid: pattern id of each row; ptab: kEll offsets per
+// pattern) when the rows share few distinct offset lists, as on structured
+// meshes, where the offsets then cost 2 bytes per row instead of 32.
+struct EllCols {
+    const short *ecol = nullptr;
+    const unsigned short *pid = nullptr;
+    const short *ptab = nullptr;
+    __host__ __device__ bool any() const { return ecol != nullptr || pid != nullptr; }
+    __device__ __forceinline__ const short *offsets(long long row) const {
+        return pid ? ptab + static_cast<int>(pid[row]) * kEll : ecol + row * kEll;
+    }
+};
+
 __device__ __forceinline__ int ell_col(long long row, int d, int n) {
     int c = static_cast<int>(row) + d;
     c += c < 0 ? n : 0;
@@ -159,55 +173,69 @@ bool ell_enabled();
 // ok, acc) for each of the row's kEll stored entries (padding: c = row,
 // v = 0, ok = true) and finish(row, lane, acc) on all L lanes after the
 // butterfly.  Rows are walked grid-stride, so any grid covers them.
+// Offsets (decoded to columns) and values of one lane's E entries of row
+// `row` of an ELL copy.
+template <typename TA, int E>
+__device__ __forceinline__ void ell_fetch(long long row, int lane, int n, const EllCols &cols,
+                                          const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
+    const long long base = row * kEll + lane * E;
+    const short *off = cols.offsets(row) + lane * E;
+#pragma unroll
+    for (int g = 0; g < E / 4; ++g) {
+        const short4 d = *reinterpret_cast<const short4 *>(off + 4 * g);
+        c[4 * g] = ell_col(row, d.x, n);
+        c[4 * g + 1] = ell_col(row, d.y, n);
+        c[4 * g + 2] = ell_col(row, d.z, n);
+        c[4 * g + 3] = ell_col(row, d.w, n);
+        TA t[4];
+        load4(eval + base + 4 * g, t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[4 * g + k] = t[k];
+    }
+}
+
+// The row loop is software-pipelined: the next row's offsets and values are
+// fetched while this row's gathers are in flight.
 template <typename TA, int NR, int L, int BS = kBlock, class Gather, class Finish>
-__device__ __forceinline__ void ell_rows(int n, const short *__restrict__ ecol, const TA *__restrict__ eval,
+__device__ __forceinline__ void ell_rows(int n, const EllCols &cols, const TA *__restrict__ eval,
                                          Gather gather, Finish finish) {
     constexpr int E = kEll / L;
     static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
     const int lane = threadIdx.x & (L - 1);
     const RowRange<L, BS> rr(n);
-    for (long long row = rr.first + rr.gid; row < rr.last; row += rr.ngroups) {
-        const long long base = row * kEll + lane * E;
-        int c[E];
-        TA w[E];
-#pragma unroll
-        for (int g = 0; g < E / 4; ++g) {
-            const short4 d = *reinterpret_cast<const short4 *>(ecol + base + 4 * g);
-            c[4 * g] = ell_col(row, d.x, n);
-            c[4 * g + 1] = ell_col(row, d.y, n);
-            c[4 * g + 2] = ell_col(row, d.z, n);
-            c[4 * g + 3] = ell_col(row, d.w, n);
-            TA t[4];
-            load4(eval + base + 4 * g, t);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) w[4 * g + k] = t[k];
-        }
+    long long row = rr.first + rr.gid;
+    int c[E];
+    TA w[E];
+    if (row < rr.last) ell_fetch<TA, E>(row, lane, n, cols, eval, c, w);
+    for (; row < rr.last; row += rr.ngroups) {
         TA acc[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[k] = TA(0);
 #pragma unroll
         for (int k = 0; k < E; ++k) gather(0, c[k], w[k], true, acc);
+        const long long nrow = row + rr.ngroups;
+        if (nrow < rr.last) ell_fetch<TA, E>(nrow, lane, n, cols, eval, c, w);
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[k] = group_sum<L>(acc[k]);
         finish(static_cast<int>(row), lane, acc);
     }
 }
 
-// A matrix on the shared CSR pattern with an optional ELL copy (ecol and
-// eval both set) that products use instead.
+// A matrix on the shared CSR pattern with an optional ELL copy (columns
+// and eval both set) that products use instead.
 template <typename T>
 struct Mat {
     const int *rp;
     const int *ci;
     const T *val;
-    const short *ecol;
+    EllCols cols;
     const T *eval;
 };
 
 template <typename TA, int NR, class C, class Gather, class Finish>
 __device__ __forceinline__ void mat_rows(int n, const Mat<TA> &m, Gather gather, Finish finish) {
-    if (m.ecol)
-        ell_rows<TA, NR, 2>(n, m.ecol, m.eval, gather, finish);
+    if (m.eval)
+        ell_rows<TA, NR, 2>(n, m.cols, m.eval, gather, finish);
     else
         csr_rows<TA, NR, C>(n, m.rp, m.ci, m.val, gather, finish);
 }
