@@ -411,7 +411,7 @@ __device__ __forceinline__ void sr_partials(double (&acc)[kSr], const Q4<T> &o, 
 
 // One iteration (see above).  Convergence tests on the incoming residual
 // as in k_cg_p1; a non-positive p.s is a breakdown.
-template <typename T, int BS, int L, bool PROJ, bool PIPE>
+template <typename T, int BS, int L, bool PROJ>
 __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__restrict__ eval,
                                               const Q4<T> *__restrict__ cur, Q4<T> *__restrict__ nxt,
                                               T *__restrict__ x, const T *__restrict__ wgt,
@@ -456,24 +456,21 @@ __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__re
     for (int k = 0; k < kSr; ++k) acc[k] = 0.0;
     const int lane = threadIdx.x & (L - 1);
     const RowRange<L, BS> range(n);
-    // PIPE: the next row's offsets and values are fetched while this row's
-    // gathers are in flight (one more set of registers).
+    // software-pipelined: the next row's offsets and values are fetched
+    // while this row's gathers are in flight
     long long row = range.first + range.gid;
     int c[E];
     T w[E];
-    if (PIPE && row < range.last) ell_fetch<T, E>(row, lane, n, cols, eval, c, w);
+    if (row < range.last) ell_fetch<T, E>(row, lane, n, cols, eval, c, w);
     for (; row < range.last; row += range.ngroups) {
-        if (!PIPE) ell_fetch<T, E>(row, lane, n, cols, eval, c, w);
         Q4<T> g[E];
 #pragma unroll
         for (int k = 0; k < E; ++k) g[k] = cur[c[k]];
         T a = T(0);
 #pragma unroll
         for (int k = 0; k < E; ++k) a += w[k] * fmsub(g[k].r, al, fmadd(bt, g[k].s, g[k].w));
-        if (PIPE) {
-            const long long nrow = row + range.ngroups;
-            if (nrow < range.last) ell_fetch<T, E>(nrow, lane, n, cols, eval, c, w);
-        }
+        const long long nrow = row + range.ngroups;
+        if (nrow < range.last) ell_fetch<T, E>(nrow, lane, n, cols, eval, c, w);
         a = group_sum<L>(a);
         if (lane == 0) {
             const Q4<T> me = cur[row];
@@ -538,28 +535,6 @@ __global__ __launch_bounds__(BS) void k_cg_sr_start(int n, EllCols cols,
     write_partials<kSr>(acc, partOut, lds);
 }
 
-// Lanes per row of the single-reduction kernels (env OASIS_SR_LANES = 2
-// or 4; 2 measures faster for both record widths).
-int sr_lanes() {
-    static int v = [] {
-        const char *e = std::getenv("OASIS_SR_LANES");
-        const int x = e ? std::atoi(e) : 2;
-        return x == 4 ? 4 : 2;
-    }();
-    return v;
-}
-
-// Software-pipelined row loop of the single-reduction iteration (env
-// OASIS_SR_PIPE=0 switches it off): 41.9 against 45.8 us per iteration at
-// 1.6M rows with the offset dictionary.
-int sr_pipe() {
-    static int v = [] {
-        const char *e = std::getenv("OASIS_SR_PIPE");
-        return e && e[0] == '0' ? 0 : 1;
-    }();
-    return v;
-}
-
 // Grid cap of the single-reduction kernels (env OASIS_SR_GRID): every block
 // of an iteration reads all partials of the previous one, kSr per block.
 int sr_grid_cap() {
@@ -575,49 +550,37 @@ int sr_grid_cap() {
 // Used by cg_run and cg_mixed_run when the ELL copy is present.
 template <typename T>
 struct SrLoop {
-    static constexpr int BS = kBlock;
+    static constexpr int BS = kBlock, L = 2;
     hipStream_t s;
     int n;
     EllCols cols;
     const T *eval;
     const T *wgt, *vnull;
     CGWork<T> *w;
-    int lanes, grid;
+    int grid;
     SrLoop(hipStream_t s_, int n_, CGWork<T> &w_, const T *wgt_, const T *vnull_)
         : s(s_), n(n_), cols(w_.cols), eval(w_.eval), wgt(wgt_), vnull(vnull_), w(&w_) {
-        lanes = sr_lanes();
-        grid = grid_for(n, BS / lanes, std::min(kMaxPartials, sr_grid_cap()));
+        grid = grid_for(n, BS / L, std::min(kMaxPartials, sr_grid_cap()));
     }
     double *part(int it) const { return (it & 1) ? w->partA : w->partB; }
     // partials for iteration `at`, written into part(at)
     int start(int at, bool keep) {
-        if (lanes == 4)
-            hipLaunchKernelGGL((k_cg_sr_start<T, BS, 4>), dim3(grid), dim3(BS), 0, s, n, cols, eval,
-                               w->rec[at & 1], wgt, vnull, keep ? 1 : 0, part(at));
-        else
-            hipLaunchKernelGGL((k_cg_sr_start<T, BS, 2>), dim3(grid), dim3(BS), 0, s, n, cols, eval,
-                               w->rec[at & 1], wgt, vnull, keep ? 1 : 0, part(at));
+        hipLaunchKernelGGL((k_cg_sr_start<T, BS, L>), dim3(grid), dim3(BS), 0, s, n, cols, eval, w->rec[at & 1],
+                           wgt, vnull, keep ? 1 : 0, part(at));
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     }
-    template <int L, bool PROJ, bool PIPE>
-    void go3(int it, int beta_zero, T *x) {
-        hipLaunchKernelGGL((k_cg_sr<T, BS, L, PROJ, PIPE>), dim3(grid), dim3(BS), 0, s, n, cols, eval,
-                           w->rec[it & 1], w->rec[(it + 1) & 1], x, wgt, vnull, part(it), grid, w->st, it,
-                           beta_zero, part(it + 1));
-    }
-    template <int L, bool PROJ>
+    template <bool PROJ>
     void go(int it, int beta_zero, T *x) {
-        if (sr_pipe()) return go3<L, PROJ, true>(it, beta_zero, x);
-        return go3<L, PROJ, false>(it, beta_zero, x);
+        hipLaunchKernelGGL((k_cg_sr<T, BS, L, PROJ>), dim3(grid), dim3(BS), 0, s, n, cols, eval, w->rec[it & 1],
+                           w->rec[(it + 1) & 1], x, wgt, vnull, part(it), grid, w->st, it, beta_zero,
+                           part(it + 1));
     }
     void iterate(int it, int beta_zero, T *x) {
-        if (lanes == 4) {
-            if (vnull) return go<4, true>(it, beta_zero, x);
-            return go<4, false>(it, beta_zero, x);
-        }
-        if (vnull) return go<2, true>(it, beta_zero, x);
-        return go<2, false>(it, beta_zero, x);
+        if (vnull)
+            go<true>(it, beta_zero, x);
+        else
+            go<false>(it, beta_zero, x);
     }
 };
 
