@@ -191,12 +191,19 @@ __global__ __launch_bounds__(kBlock) void k_unit_f32(int n, const double *__rest
         out32[i] = static_cast<float>(x[i] * inv);
 }
 
-static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, float *out) {
+// out = x / ||x|| in FP32; *norm2 (host) = ||x||^2 (synchronises).
+static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, float *out, double *norm2) {
     const int g = grid_for(n, kBlock);
     hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(kBlock), 0, s, n, x, part);
     OASIS_TRY_LAUNCH();
     hipLaunchKernelGGL(k_unit_f32, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, x, part, g, out);
     OASIS_TRY_LAUNCH();
+    std::vector<double> h(g);
+    OASIS_TRY_HIP(hipMemcpyAsync(h.data(), part, g * sizeof(double), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : h) t += v;
+    *norm2 = t;
     return OASIS_OK;
 }
 
@@ -785,6 +792,7 @@ struct oasis_ipcs {
     float *eA32 = nullptr;    // FP64 (FP64 mode) or FP32 (mixed mode)
     bool ell = false;         // the offsets fit
     float *wK32 = nullptr, *wA32 = nullptr, *vnull32 = nullptr, *xlo = nullptr;
+    double vscale = 0.0;      // ||s||^2: the pressure norm weights are vscale * vnull32^2
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
     int *iptr = nullptr, *inc = nullptr, *icnt = nullptr, *itmp = nullptr;
@@ -1001,7 +1009,9 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
         }
     }
     // the scaled pressure matrix has null vector s = sqrt(diag K) (K 1 = 0)
-    if (h->mixed && unit_vector_f32(s, n, h->sK, h->red, h->vnull32) != OASIS_OK) return fail(OASIS_EHIP);
+    // with it, the norm weights d = s^2 of the FP32 iterations are ||s||^2 v^2
+    if (h->mixed && unit_vector_f32(s, n, h->sK, h->red, h->vnull32, &h->vscale) != OASIS_OK)
+        return fail(OASIS_EHIP);
     int fl[3] = {0, 0, 0};
     if (hipMemcpyAsync(fl, h->flag, sizeof(fl), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -1238,7 +1248,8 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     SolveOut sp;
     int rc_p;
     if (h->mixed)
-        rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->bs, h->xs,
+        rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->vscale, h->bs,
+                              h->xs,
                               ko.rtol, reliable_delta(0.0), ko.maxit, 0, false, h->cg32, h->xlo,
                               h->rhi, sp);
     else
@@ -1402,11 +1413,12 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     int rc;
     if (mixed) {
         const float *vn = nullptr;
+        double vscale = 0.0;
         if (opt->flags & OASIS_KRYLOV_NULLSPACE_CONST) {
-            OASIS_TRY(unit_vector_f32(s, n, k.s, k.ir.part, k.vnull32));
+            OASIS_TRY(unit_vector_f32(s, n, k.s, k.ir.part, k.vnull32, &vscale));
             vn = k.vnull32;
         }
-        rc = cg_mixed_solve(s, n, A->row_ptr, A->col_idx, k.val, k.val32, k.w, k.w32, vn, k.b, k.x, ko.rtol,
+        rc = cg_mixed_solve(s, n, A->row_ptr, A->col_idx, k.val, k.val32, k.w, k.w32, vn, vscale, k.b, k.x, ko.rtol,
                             reliable_delta(opt->inner_rtol), ko.maxit, ko.check_every, ko.time, k.cg32, k.xlo,
                             k.rhi, so);
     }

@@ -415,8 +415,8 @@ template <typename T, int BS, int L, bool PROJ>
 __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__restrict__ eval,
                                               const Q4<T> *__restrict__ cur, Q4<T> *__restrict__ nxt,
                                               T *__restrict__ x, const T *__restrict__ wgt,
-                                              const T *__restrict__ vnull, const double *partIn, int nIn,
-                                              CGState *st, int it, int beta_zero, double *partOut) {
+                                              const T *__restrict__ vnull, double vscale, const double *partIn,
+                                              int nIn, CGState *st, int it, int beta_zero, double *partOut) {
     constexpr int E = kEll / L;
     static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
     __shared__ double lds[kSr * BS / kWave];
@@ -484,7 +484,8 @@ __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__re
             o.w = a;
             x[row] = fmadd(al, o.p, x[row]);
             nxt[row] = o;
-            sr_partials<T>(acc, o, static_cast<double>(wgt[row]), static_cast<double>(vr));
+            const double vd = vr;
+            sr_partials<T>(acc, o, wgt ? static_cast<double>(wgt[row]) : vscale * vd * vd, vd);
         }
     }
     write_partials<kSr>(acc, partOut, lds);
@@ -499,7 +500,7 @@ template <typename T, int BS, int L>
 __global__ __launch_bounds__(BS) void k_cg_sr_start(int n, EllCols cols,
                                                     const T *__restrict__ eval, Q4<T> *rec,
                                                     const T *__restrict__ wgt, const T *__restrict__ vnull,
-                                                    int keep, double *partOut) {
+                                                    double vscale, int keep, double *partOut) {
     constexpr int E = kEll / L;
     __shared__ double lds[kSr * BS / kWave];
     double acc[kSr];
@@ -529,7 +530,8 @@ __global__ __launch_bounds__(BS) void k_cg_sr_start(int n, EllCols cols,
             rec[row].w = o.w;
             rec[row].s = o.s;
             if (!keep) rec[row].p = T(0);
-            sr_partials<T>(acc, o, static_cast<double>(wgt[row]), vnull ? static_cast<double>(vnull[row]) : 0.0);
+            const double vd = vnull ? static_cast<double>(vnull[row]) : 0.0;
+            sr_partials<T>(acc, o, wgt ? static_cast<double>(wgt[row]) : vscale * vd * vd, vd);
         }
     }
     write_partials<kSr>(acc, partOut, lds);
@@ -556,24 +558,28 @@ struct SrLoop {
     EllCols cols;
     const T *eval;
     const T *wgt, *vnull;
+    double vscale;
     CGWork<T> *w;
     int grid;
-    SrLoop(hipStream_t s_, int n_, CGWork<T> &w_, const T *wgt_, const T *vnull_)
-        : s(s_), n(n_), cols(w_.cols), eval(w_.eval), wgt(wgt_), vnull(vnull_), w(&w_) {
+    // vscale > 0 (with vnull): the norm weights are vscale * vnull^2 and are
+    // formed in the kernels instead of read from wgt
+    SrLoop(hipStream_t s_, int n_, CGWork<T> &w_, const T *wgt_, const T *vnull_, double vscale_)
+        : s(s_), n(n_), cols(w_.cols), eval(w_.eval), wgt(vnull_ && vscale_ > 0.0 ? nullptr : wgt_),
+          vnull(vnull_), vscale(vnull_ && vscale_ > 0.0 ? vscale_ : 0.0), w(&w_) {
         grid = grid_for(n, BS / L, std::min(kMaxPartials, sr_grid_cap()));
     }
     double *part(int it) const { return (it & 1) ? w->partA : w->partB; }
     // partials for iteration `at`, written into part(at)
     int start(int at, bool keep) {
         hipLaunchKernelGGL((k_cg_sr_start<T, BS, L>), dim3(grid), dim3(BS), 0, s, n, cols, eval, w->rec[at & 1],
-                           wgt, vnull, keep ? 1 : 0, part(at));
+                           wgt, vnull, vscale, keep ? 1 : 0, part(at));
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     }
     template <bool PROJ>
     void go(int it, int beta_zero, T *x) {
         hipLaunchKernelGGL((k_cg_sr<T, BS, L, PROJ>), dim3(grid), dim3(BS), 0, s, n, cols, eval, w->rec[it & 1],
-                           w->rec[(it + 1) & 1], x, wgt, vnull, part(it), grid, w->st, it, beta_zero,
+                           w->rec[(it + 1) & 1], x, wgt, vnull, vscale, part(it), grid, w->st, it, beta_zero,
                            part(it + 1));
     }
     void iterate(int it, int beta_zero, T *x) {
@@ -785,7 +791,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
     const bool ell = w.cols.any() && w.eval && ell_enabled();
     const bool sr = ell && sr_enabled(sizeof(T));
-    SrLoop<T> loop(s, n, w, wgt, nullptr);
+    SrLoop<T> loop(s, n, w, wgt, nullptr, 0.0);
     const int g1 = ell ? launch_p1_ell<T, BS>(s, n, w.cols, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
                                               nullptr, 0, 0, nullptr, nullptr, true)
                        : g.p1;
@@ -926,7 +932,7 @@ __global__ __launch_bounds__(kBlock) void k_add_lo(int n, double *__restrict__ x
 template <class C, int BS>
 static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
                         const float *val32, const double *wgt, const float *wgt32,
-                        const float *vnull, const double *b, double *x, double rtol, double delta,
+                        const float *vnull, double vscale, const double *b, double *x, double rtol, double delta,
                         int maxit, int check_every, bool time_kernel, CGWork<float> &w,
                         float *xlo, double *rhi, SolveOut &out) {
     const int gi = grid_for(n, rows_per_block<C>(), partial_cap());     // k_cg_init (kBlock threads)
@@ -934,7 +940,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
     const bool ell = w.cols.any() && w.eval && ell_enabled();
     const bool sr = ell && sr_enabled(4);
-    SrLoop<float> loop(s, n, w, wgt32, vnull);
+    SrLoop<float> loop(s, n, w, wgt32, vnull, vscale);
     const int g1 = ell ? launch_p1_ell<float, BS>(s, n, w.cols, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
                                                   nullptr, 0, 0, nullptr, nullptr, true)
                        : g.p1;
@@ -1069,15 +1075,15 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
 
 int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
                    const float *val32, const double *wgt, const float *wgt32, const float *vnull,
-                   const double *b, double *x, double rtol, double delta, int maxit,
+                   double vscale, const double *b, double *x, double rtol, double delta, int maxit,
                    int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
                    SolveOut &out) {
     return with_cfg([&](auto c) {
         if (cg_block() == 256)
-            return cg_mixed_run<decltype(c), 256>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, b, x, rtol, delta,
-                                                  maxit, check_every, time_kernel, w, xlo, rhi, out);
-        return cg_mixed_run<decltype(c), 1024>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, b, x, rtol, delta,
-                                               maxit, check_every, time_kernel, w, xlo, rhi, out);
+            return cg_mixed_run<decltype(c), 256>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, vscale, b, x, rtol,
+                                                  delta, maxit, check_every, time_kernel, w, xlo, rhi, out);
+        return cg_mixed_run<decltype(c), 1024>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, vscale, b, x, rtol,
+                                               delta, maxit, check_every, time_kernel, w, xlo, rhi, out);
     });
 }
 

@@ -125,10 +125,13 @@ int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci,
 // FP64 residual b - Ms x that replaces the FP32 one whenever the latter has
 // dropped by `delta` since the last replacement (the search direction is
 // kept).  vnull (nullable): unit-norm null vector of Ms, projected out of
-// the FP32 residual updates.
+// the FP32 residual updates.  vscale > 0 states that the norm weights are
+// vscale * vnull^2 (Ms = D^-1/2 K D^-1/2 with K 1 = 0: weights d = s^2 and
+// vnull = s / ||s||, vscale = ||s||^2); the single-reduction iterations then
+// form them from vnull instead of reading wgt32.
 int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
                    const float *val32, const double *wgt, const float *wgt32, const float *vnull,
-                   const double *b, double *x, double rtol, double delta, int maxit,
+                   double vscale, const double *b, double *x, double rtol, double delta, int maxit,
                    int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
                    SolveOut &out);
 
