@@ -1120,14 +1120,6 @@ template <typename T>
 struct C3 {
     const T *p[3];
 };
-template <typename T>
-struct W3 {
-    RW<T> *p[3];
-};
-template <typename T>
-struct CW3 {
-    const RW<T> *p[3];
-};
 
 // r_k = b_k - As xsrc_k for k in mask_res; r_hat_k = r_k for k in mask_rhat;
 // partials (r_hat.r, sum wgt r^2, sum wgt b^2) for every k.  The residual
@@ -1135,7 +1127,7 @@ struct CW3 {
 template <typename T, int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
                                                      const T *__restrict__ wgt, C3<T> b,
-                                                     C3<T> xsrc, W3<T> ru, V3<T> rhat, int mask_res,
+                                                     C3<T> xsrc, RW<T> *ru, V3<T> rhat, int mask_res,
                                                      int mask_rhat, double *part) {
     __shared__ double lds[9 * kBlock / kWave];
     double acc[3 * NR];
@@ -1144,12 +1136,14 @@ __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
     mat_rows<T, NR, C>(
         n, m,
         [&](int, int c, T v, bool ok, T(&a)[NR]) {
+            // every right-hand side is gathered (no branch per k, so that the
+            // loads of all of them are in flight together); finish uses
+            // only those in mask_res
 #pragma unroll
-            for (int k = 0; k < NR; ++k)
-                if ((mask_res >> k) & 1) {
-                    const T t = v * xsrc.p[k][c];
-                    a[k] += ok ? t : T(0);
-                }
+            for (int k = 0; k < NR; ++k) {
+                const T t = v * xsrc.p[k][c];
+                a[k] += ok ? t : T(0);
+            }
         },
         [&](int row, int lane, T(&a)[NR]) {
             if (lane != 0) return;
@@ -1159,9 +1153,9 @@ __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
                 T rk;
                 if ((mask_res >> k) & 1) {
                     rk = b.p[k][row] - a[k];
-                    ru.p[k][row].r = rk;
+                    ru[(long long)row * NR + k].r = rk;
                 } else {
-                    rk = ru.p[k][row].r;
+                    rk = ru[(long long)row * NR + k].r;
                 }
                 T hk;
                 if ((mask_rhat >> k) & 1) {
@@ -1207,8 +1201,8 @@ __device__ __forceinline__ void bi_pause(BiGlobal *g, int phase, int it) {
 // the (r, v) pairs that part 2 gathers; reads nothing it writes, so a
 // relaunch after a pause recomputes the same values.
 template <typename T, int NR, class C>
-__global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, CW3<T> ru, C3<T> rhat,
-                                                 V3<T> p, W3<T> rv, const double *partIn, int nIn,
+__global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, const RW<T> *ru, C3<T> rhat,
+                                                 V3<T> p, RW<T> *rv, const double *partIn, int nIn,
                                                  BiState *st, BiGlobal *glob, int it,
                                                  double *partOut) {
     __shared__ double lds[9 * kBlock / kWave];
@@ -1257,23 +1251,31 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, CW3<T> ru, C3<
     mat_rows<T, NR, C>(
         n, m,
         [&](int, int c, T vv, bool ok, T(&a)[NR]) {
+            // all right-hand sides, active or not: branch-free, so that the
+            // gathers of one entry are issued together (finish discards the
+            // inactive ones)
 #pragma unroll
-            for (int k = 0; k < NR; ++k)
-                if ((active >> k) & 1) {
-                    const RW<T> g = ru.p[k][c];
-                    const T t = vv * fmadd(beta[k], g.w, g.r);
-                    a[k] += ok ? t : T(0);
-                }
+            for (int k = 0; k < NR; ++k) {
+                const RW<T> g = ru[(long long)c * NR + k];
+                const T t = vv * fmadd(beta[k], g.w, g.r);
+                a[k] += ok ? t : T(0);
+            }
         },
         [&](int row, int lane, T(&a)[NR]) {
             if (lane != 0) return;
+            RW<T> me[NR];
+            T hk[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                me[k] = ru[(long long)row * NR + k];
+                hk[k] = rhat.p[k][row];
+            }
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 if (!((active >> k) & 1)) continue;
-                const RW<T> me = ru.p[k][row];
-                p.p[k][row] = fmadd(beta[k], me.w, me.r);
-                rv.p[k][row] = RW<T>{me.r, a[k]};
-                acc[k] += static_cast<double>(rhat.p[k][row]) * static_cast<double>(a[k]);
+                p.p[k][row] = fmadd(beta[k], me[k].w, me[k].r);
+                rv[(long long)row * NR + k] = RW<T>{me[k].r, a[k]};
+                acc[k] += static_cast<double>(hk[k]) * static_cast<double>(a[k]);
             }
         });
     write_partials<NR>(acc, partOut, lds);
@@ -1284,7 +1286,7 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, CW3<T> ru, C3<
 // it again from the same (r, v) pair with the same rounding.
 template <typename T, int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m, const T *__restrict__ wgt,
-                                                 CW3<T> rv, V3<T> t, const double *partIn, int nIn,
+                                                 const RW<T> *rv, V3<T> t, const double *partIn, int nIn,
                                                  BiState *st, BiGlobal *glob, int it,
                                                  double *partOut) {
     __shared__ double lds[9 * kBlock / kWave];
@@ -1326,21 +1328,24 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m, const T *__res
     mat_rows<T, NR, C>(
         n, m,
         [&](int, int c, T w, bool ok, T(&a)[NR]) {
+            // branch-free over the right-hand sides (see k_bi_1)
 #pragma unroll
-            for (int k = 0; k < NR; ++k)
-                if ((active >> k) & 1) {
-                    const RW<T> g = rv.p[k][c];
-                    const T tk = w * fmsub(g.r, al[k], g.w);
-                    a[k] += ok ? tk : T(0);
-                }
+            for (int k = 0; k < NR; ++k) {
+                const RW<T> g = rv[(long long)c * NR + k];
+                const T tk = w * fmsub(g.r, al[k], g.w);
+                a[k] += ok ? tk : T(0);
+            }
         },
         [&](int row, int lane, T(&a)[NR]) {
             if (lane != 0) return;
             const double wd = wgt[row];
+            RW<T> mv[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) mv[k] = rv[(long long)row * NR + k];
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 if (!((active >> k) & 1)) continue;
-                const RW<T> me = rv.p[k][row];
+                const RW<T> me = mv[k];
                 const T sn = fmsub(me.r, al[k], me.w);
                 t.p[k][row] = a[k];
                 const double sd = sn, td = a[k];
@@ -1357,7 +1362,7 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m, const T *__res
 // direction; partials (r_hat.r, sum wgt r^2, 0)
 template <typename T, int NR>
 __global__ __launch_bounds__(kBlock) void k_bi_3(int n, const T *__restrict__ wgt, V3<T> x,
-                                                 W3<T> ru, C3<T> rhat, C3<T> p, CW3<T> rv,
+                                                 RW<T> *ru, C3<T> rhat, C3<T> p, const RW<T> *rv,
                                                  C3<T> t, const double *partIn, int nIn,
                                                  BiState *st, BiGlobal *glob, int it,
                                                  double *partOut) {
@@ -1403,18 +1408,30 @@ __global__ __launch_bounds__(kBlock) void k_bi_3(int n, const T *__restrict__ wg
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const double wd = wgt[i];
+        // loads for every right-hand side first (no branch per k, so they are
+        // in flight together); stores and partials only for the active ones
+        RW<T> g[NR];
+        T pk[NR], tk[NR], xk[NR], hk[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-            if (!((active >> k) & 1)) continue;
-            const RW<T> g = rv.p[k][i];
-            const T sk = fmsub(g.r, al[k], g.w);
-            const T pk = p.p[k][i];
-            x.p[k][i] = x.p[k][i] + al[k] * pk + om[k] * sk;
-            const T rk = fmsub(sk, om[k], t.p[k][i]);
-            ru.p[k][i] = RW<T>{rk, fmsub(pk, om[k], g.w)};
-            const double rd = rk;
-            acc[3 * k + 0] += static_cast<double>(rhat.p[k][i]) * rd;
-            acc[3 * k + 1] += wd * rd * rd;
+            g[k] = rv[i * NR + k];
+            pk[k] = p.p[k][i];
+            tk[k] = t.p[k][i];
+            xk[k] = x.p[k][i];
+            hk[k] = rhat.p[k][i];
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const bool on = (active >> k) & 1;
+            const T sk = fmsub(g[k].r, al[k], g[k].w);
+            const T rk = fmsub(sk, om[k], tk[k]);
+            if (on) {
+                x.p[k][i] = xk[k] + al[k] * pk[k] + om[k] * sk;
+                ru[i * NR + k] = RW<T>{rk, fmsub(pk[k], om[k], g[k].w)};
+                const double rd = rk;
+                acc[3 * k + 0] += static_cast<double>(hk[k]) * rd;
+                acc[3 * k + 1] += wd * rd * rd;
+            }
         }
     }
     write_partials<3 * NR>(acc, partOut, lds);
@@ -1435,18 +1452,18 @@ __global__ __launch_bounds__(kBlock) void k_bi_xs(int n, C3<T> x, C3<T> p, V3<T>
 
 // u = 0 in every (r, u) pair: the next direction is the residual itself
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_zero_u(int n, RW<T> *ru) {
+__global__ __launch_bounds__(kBlock) void k_zero_u(int n, RW<T> *ru, int nr, int k) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
-        ru[i].w = T(0);
+        ru[i * nr + k].w = T(0);
 }
 
 template <typename T>
 void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
     std::memset(&w, 0, sizeof(w));
+    w.ru = c.take<RW<T>>((size_t)n * nrhs);
+    w.rv = c.take<RW<T>>((size_t)n * nrhs);
     for (int k = 0; k < nrhs; ++k) {
-        w.ru[k] = c.take<RW<T>>(n);
-        w.rv[k] = c.take<RW<T>>(n);
         w.p[k] = c.take<T>(n);
         w.rhat[k] = c.take<T>(n);
         w.t[k] = c.take<T>(n);
@@ -1470,14 +1487,10 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     const Mat<T> mat{rp, ci, val, ell ? w.cols : EllCols{}, ell ? w.eval : nullptr};
     C3<T> cb{}, cx{}, crh{}, ct{}, cp{};
     V3<T> vx{}, vrh{}, vt{}, vp{}, vxs{};
-    CW3<T> cru{}, crv{};
-    W3<T> vru{}, vrv{};
     for (int k = 0; k < NR; ++k) {
         cb.p[k] = b[k];
         cx.p[k] = x[k];
         vx.p[k] = x[k];
-        cru.p[k] = vru.p[k] = w.ru[k];
-        crv.p[k] = vrv.p[k] = w.rv[k];
         crh.p[k] = vrh.p[k] = w.rhat[k];
         ct.p[k] = vt.p[k] = w.t[k];
         cp.p[k] = vp.p[k] = w.p[k];
@@ -1504,13 +1517,13 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         return OASIS_OK;
     };
     auto zero_dirs = [&](int k) -> int {
-        hipLaunchKernelGGL((k_zero_u<T>), dim3(gv), dim3(kBlock), 0, s, n, w.ru[k]);
+        hipLaunchKernelGGL((k_zero_u<T>), dim3(gv), dim3(kBlock), 0, s, n, w.ru, NR, k);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
     auto resid = [&](int mask_res, int mask_rhat, C3<T> src) -> int {
         hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat, wgt,
-                           cb, src, vru, vrh, mask_res, mask_rhat, w.part3);
+                           cb, src, w.ru, vrh, mask_res, mask_rhat, w.part3);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
@@ -1568,7 +1581,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             if (phase == 1) {
                 if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
                 hipLaunchKernelGGL((k_bi_1<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
-                                   cru, crh, vp, vrv, w.part3, part3_count, w.st, w.glob, it,
+                                   w.ru, crh, vp, w.rv, w.part3, part3_count, w.st, w.glob, it,
                                    w.part1);
                 OASIS_TRY_LAUNCH();
                 if (time_kernel) {
@@ -1580,11 +1593,11 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                     out[0].kernel_count += 1;
                 }
                 hipLaunchKernelGGL((k_bi_2<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
-                                   wgt, crv, vt, w.part1, g1, w.st, w.glob, it, w.part2);
+                                   wgt, w.rv, vt, w.part1, g1, w.st, w.glob, it, w.part2);
                 OASIS_TRY_LAUNCH();
             }
-            hipLaunchKernelGGL((k_bi_3<T, NR>), dim3(g2), dim3(kBlock), 0, s, n, wgt, vx, vru, crh,
-                               cp, crv, ct, w.part2, g1, w.st, w.glob, it, w.part3);
+            hipLaunchKernelGGL((k_bi_3<T, NR>), dim3(g2), dim3(kBlock), 0, s, n, wgt, vx, w.ru, crh,
+                               cp, w.rv, ct, w.part2, g1, w.st, w.glob, it, w.part3);
             OASIS_TRY_LAUNCH();
             part3_count = g2;
             phase = 1;

@@ -76,13 +76,16 @@ struct alignas(2 * sizeof(T)) RW {
 
 template <typename T>
 struct BiWork {
-    // Per right-hand side: ru = (r, u) with u = p - omega v, the part of
-    // the next direction beyond r (formed by the update kernel, so the first
-    // product gathers one pair per entry); rv = (r, v) written by the first
-    // product for the second; the direction p, r_hat, s, t and the s-stage
+    // ru = (r, u) with u = p - omega v, the part of the next direction
+    // beyond r (formed by the update kernel, so the first product gathers
+    // one pair per entry and right-hand side); rv = (r, v) written by the
+    // first product for the second.  Both hold the pairs of all nr
+    // right-hand sides of a row together (right-hand side k of row i at
+    // i * nr + k), so that a gathered column's pairs share a cache line.
+    // Per right-hand side: the direction p, r_hat, t and the s-stage
     // candidate iterate xs.
-    RW<T> *ru[3], *rv[3];
-    T *p[3], *rhat[3], *s[3], *t[3], *xs[3];
+    RW<T> *ru, *rv;
+    T *p[3], *rhat[3], *t[3], *xs[3];
     double *part1, *part2, *part3;
     BiState *st;       // [3]
     BiGlobal *glob;
