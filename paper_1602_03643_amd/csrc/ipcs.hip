@@ -268,30 +268,37 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
     }
 }
 
-// Row-gather form of step 1+2: every row assembles its own entries of
+// u_bar = 1.5 U^{n-1} - 0.5 U^{n-2} (Alg. 2), interleaved per dof
+// ([n][4] in 3D, [n][2] in 2D) for the assembly's per-vertex gathers.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ubar(int n, P3 U1, P3 U2, double *__restrict__ ubar) {
+    constexpr int UW = D == 3 ? 4 : 2;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) ubar[i * UW + c] = 1.5 * U1.p[c][i] - 0.5 * U2.p[c][i];
+        if (D == 3) ubar[i * UW + 3] = 0.0;
+    }
+}
+
+// Row-gather form of step 1: every row assembles its own entries of
 // A = B + C(u_bar)/2 from the cells around its dof (the convection part of
-// Alg. 2's coefficient matrix), then forms the right-hand side, the
-// Dirichlet row and the diagonal in the same pass.  One thread
-// owns one row; the row's columns and values live in MAXC registers and an
-// element contribution (column dof c, value v) is added to the slot whose
-// column equals c (a compile-time unrolled match).  The incident cells are
-// visited in ascending order, so the sums are deterministic; no other
-// thread writes the row, so no atomics and no colouring are needed.
+// Alg. 2's coefficient matrix); k_tent_rows then forms the right-hand side,
+// the Dirichlet row and the diagonal.  One thread owns one row; the row's
+// columns and values live in MAXC registers and an element contribution
+// (column dof c, value v) is added to the slot whose column equals c (a
+// compile-time unrolled match).  The incident cells are visited in
+// ascending order, so the sums are deterministic; no other thread writes
+// the row, so no atomics and no colouring are needed.
 template <int D, int MAXC>
 __global__ __launch_bounds__(kBlock) void k_asm_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ B,
-    const double *__restrict__ M, P3 dP, const int *__restrict__ iptr, const int *__restrict__ inc,
-    const int *__restrict__ cells, const int *__restrict__ v2d, const double *__restrict__ X, P3 U1, P3 U2,
-    const double *__restrict__ p, const double *__restrict__ ML, const int *__restrict__ bc_index,
-    const double *__restrict__ g, int nbc, double f0, double f1, double f2, double two_over_dt,
-    double *__restrict__ A, double *__restrict__ b0, double *__restrict__ b1,
-    double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1, double *__restrict__ x2,
-    double *__restrict__ dA, double *__restrict__ wA, float *__restrict__ wA32) {
+    const int *__restrict__ iptr, const int *__restrict__ inc, const int *__restrict__ cells,
+    const int *__restrict__ v2d, const double *__restrict__ X, const double *__restrict__ ubar,
+    double *__restrict__ A) {
     constexpr int NV = D + 1;
+    constexpr int UW = D == 3 ? 4 : 2;                  // u_bar row width
     constexpr double mfac = 0.5 / ((D + 1) * (D + 2));   // C/2 and the mass-moment factor
-    double *bo[3] = {b0, b1, b2};
-    double *xo[3] = {x0, x1, x2};
-    const double f[3] = {f0, f1, f2};
     for (long long row = blockIdx.x * (long long)blockDim.x + threadIdx.x; row < n;
          row += (long long)gridDim.x * blockDim.x) {
         const int i = static_cast<int>(row);
@@ -315,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     x[k][c] = X[(long long)v * D + c];
-                    ub[k][c] = 1.5 * U1.p[c][dd[k]] - 0.5 * U2.p[c][dd[k]];
+                    ub[k][c] = ubar[(long long)dd[k] * UW + c];
                 }
             }
             Elem<D> e;
@@ -343,42 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                 for (int q = 0; q < MAXC; ++q) a[q] += (col[q] == target) ? v : 0.0;
             }
         }
-        // right-hand side (2M/dt - A) U^{n-1} - dP^k p*, Dirichlet row, scaling
-        double acc[D], accp[D], diag = 0.0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] = accp[k] = 0.0;
-#pragma unroll
-        for (int q = 0; q < MAXC; ++q) {
-            if (q < len) {
-                const int c = col[q];
-                const double coef = two_over_dt * M[s + q] - a[q];
-                const double pc = p[c];
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    acc[k] += coef * U1.p[k][c];
-                    accp[k] += dP.p[k][s + q] * pc;
-                }
-                if (c == i) diag = a[q];
-            }
-        }
-        const int qb = bc_index[i];
-        const double dd0 = qb >= 0 ? 1.0 : diag;
-#pragma unroll
-        for (int q = 0; q < MAXC; ++q) {
-            if (q < len) {
-                double v = a[q];
-                if (qb >= 0) v = (col[q] == i) ? 1.0 : 0.0;
-                A[s + q] = v;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            bo[k][i] = qb >= 0 ? g[k * nbc + qb] : f[k] * ML[i] + acc[k] - accp[k];
-            xo[k][i] = dd0 * U1.p[k][i];      // y0 = D x0 for the column-scaled system
-        }
-        dA[i] = dd0;
-        wA[i] = 1.0;
-        if (wA32) wA32[i] = 1.f;
+        for (int q = 0; q < MAXC; ++q)
+            if (q < len) A[s + q] = a[q];
     }
 }
 
@@ -797,6 +771,7 @@ struct oasis_ipcs {
     int *bc_index = nullptr, *flag = nullptr;
     int *iptr = nullptr, *inc = nullptr, *icnt = nullptr, *itmp = nullptr;
     int assembly = OASIS_ASSEMBLE_ROWS, maxc = 16;
+    double *ubar = nullptr;   // per step u_bar, interleaved ([n][D == 3 ? 4 : 2])
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
     double *bphi = nullptr, *bs = nullptr, *xs = nullptr, *xg = nullptr, *red = nullptr;
     CGWork<double> cg;
@@ -874,6 +849,7 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
     h.xg = c.take<double>(n);
     h.red = c.take<double>(2 * kMaxPartials);
     const int nmax = std::max(n, ncell);
+    h.ubar = c.take<double>((size_t)n * (dim == 3 ? 4 : 2));
     h.iptr = c.take<int>((size_t)n + 1);
     h.inc = c.take<int>((size_t)ncell * (dim + 1));
     h.icnt = c.take<int>((size_t)nmax + 1);
@@ -1093,18 +1069,17 @@ static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_s
 template <int D, int MAXC>
 static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g, double *const *x) {
     const int n = h->n;
-    P3 dP{}, U1{}, U2{};
+    P3 U1{}, U2{};
     for (int k = 0; k < D; ++k) {
-        dP.p[k] = h->dP[k];
         U1.p[k] = st->U1[k];
         U2.p[k] = st->U2[k];
     }
+    hipLaunchKernelGGL((k_ubar<D>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
     const int grid = grid_for(n, kBlock, 1 << 20);
-    hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->B, h->M, dP,
-                       h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, U1, U2, st->p, h->ML,
-                       h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1], h->par.f[2], 2.0 / h->par.dt,
-                       h->A, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0], x[1],
-                       D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
+    hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->B, h->iptr,
+                       h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+    // right-hand sides, Dirichlet rows, diagonal and y0 (8 lanes per row)
+    launch_step_kernels_tent<D, 8>(s, h, st, g, x);
 }
 
 template <int D, int L>
