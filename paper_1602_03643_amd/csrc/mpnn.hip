@@ -242,16 +242,37 @@ __device__ __forceinline__ void agg8(int i, int f0, const int *__restrict__ rp, 
     float acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.f;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        const int j = ci[e];
-        if (j == i) continue;
-        const float w = static_cast<float>(scale_by_j ? Ks[e] * s[j] : Ks[e]);
-        const uint4 q = *reinterpret_cast<const uint4 *>(V + (size_t)j * kHid + f0);
-        const unsigned qq[4] = {q.x, q.y, q.z, q.w};
+    // edges in chunks of U: all loads of a chunk come from clamped (valid)
+    // addresses and are issued together, then the chunk is accumulated in
+    // edge order (the same sums as one edge at a time)
+    constexpr int U = 8;
+    const int e0 = rp[i], len = rp[i + 1] - e0;
+    for (int c0 = 0; c0 < len; c0 += U) {
+        int j[U];
+        double kv[U];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            acc[2 * k] += w * bf2f(static_cast<unsigned short>(qq[k] & 0xffffu));
-            acc[2 * k + 1] += w * bf2f(static_cast<unsigned short>(qq[k] >> 16));
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + (c0 + u < len ? c0 + u : len - 1);
+            j[u] = ci[e];
+            kv[u] = Ks[e];
+        }
+        uint4 q[U];
+        double sj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            q[u] = *reinterpret_cast<const uint4 *>(V + (size_t)j[u] * kHid + f0);
+            sj[u] = scale_by_j ? s[j[u]] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c0 + u >= len || j[u] == i) continue;
+            const float w = static_cast<float>(scale_by_j ? kv[u] * sj[u] : kv[u]);
+            const unsigned qq[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc[2 * k] += w * bf2f(static_cast<unsigned short>(qq[k] & 0xffffu));
+                acc[2 * k + 1] += w * bf2f(static_cast<unsigned short>(qq[k] >> 16));
+            }
         }
     }
 #pragma unroll
