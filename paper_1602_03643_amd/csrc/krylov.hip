@@ -199,7 +199,11 @@ __global__ __launch_bounds__(BS) void k_cg_p1(int n, const int *__restrict__ rp,
         return;
     }
     const double beta = beta_zero ? 0.0 : rr / st->rr[(it + 1) & 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr[it & 1] = rr;
+        st->wrr_it = wrr;
+        st->it_last = it;
+    }
     const T bt = static_cast<T>(beta);
     double acc[2] = {0.0, 0.0};
     auto finish = [&](int row, int lane, T(&a)[1]) {
@@ -307,7 +311,11 @@ __global__ __launch_bounds__(BS) void k_cg_p1_ell(int n, EllCols cols,
         return;
     }
     const double beta = beta_zero ? 0.0 : rr / st->rr[(it + 1) & 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr[it & 1] = rr;
+        st->wrr_it = wrr;
+        st->it_last = it;
+    }
     const T bt = static_cast<T>(beta);
     double acc[2] = {0.0, 0.0};
     const int lane = threadIdx.x & (L - 1);
@@ -448,7 +456,11 @@ __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__re
         }
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr[it & 1] = rr;
+        st->wrr_it = wrr;
+        st->it_last = it;
+    }
     const T al = static_cast<T>(rr / ps), bt = static_cast<T>(beta);
     const T cw = static_cast<T>(v[5]), cs = static_cast<T>(v[6]);
     double acc[kSr];
@@ -783,6 +795,47 @@ struct CgGrids {
     }
 };
 
+// Iterations to launch before the next host poll of the CG state.  With
+// check_every > 0 that fixed number; otherwise estimated from the rate at
+// which log(wrr) has fallen since the last restart of the recurrence, so
+// that the poll comes just before the next event (a residual replacement
+// at upd2, convergence at tol2): fewer polls than a fixed chunk, and few
+// launches after the event that return at once.  Within [8, 256]; 32
+// before any rate is known.
+struct ChunkPlan {
+    int fixed;
+    double rate = 0.0;            // d log(wrr) / d iteration, < 0 once known
+    double w0 = 0.0;
+    int it0 = -1;
+    int next = 32;
+    explicit ChunkPlan(int check_every) : fixed(check_every) {
+        if (fixed > 0) next = fixed;
+    }
+    void plan(double wrr, double target) {
+        if (fixed > 0) return;
+        if (!(rate < 0.0) || !(wrr > 0.0) || !(target > 0.0)) {
+            next = 32;
+            return;
+        }
+        const double k = std::log(target / wrr) / rate;
+        next = static_cast<int>(std::min(256.0, std::max(8.0, 0.85 * k)));
+    }
+    // a new recurrence starts at iteration it from weighted residual wrr
+    void restart(double wrr, int it, double target) {
+        w0 = wrr;
+        it0 = it;
+        plan(wrr, target);
+    }
+    // state seen at a poll: the residual entering iteration it_last
+    void observe(double wrr, int it_last, double target) {
+        if (it0 >= 0 && it_last > it0 && wrr > 0.0 && w0 > 0.0) {
+            const double r = std::log(wrr / w0) / (it_last - it0);
+            if (r < 0.0) rate = r;
+        }
+        plan(wrr, target);
+    }
+};
+
 template <typename T, class C, int BS>
 static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
@@ -810,14 +863,17 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     OASIS_TRY(residual(0, 0));
     if (sr) OASIS_TRY(loop.start(0, false));
     CGState h;
-    const int chunk = check_every > 0 ? check_every : 32;
+    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    ChunkPlan plan(check_every);
+    plan.restart(h.wrr, 0, h.tol2);
     int it = 0, restart_at = 0;
     int rc = OASIS_OK;
     auto finish = [&](double wrr, double wbb) {
         out.rel_res = wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr);
     };
     while (true) {
-        const int m = std::min(chunk, maxit - it);
+        const int m = std::min(plan.next, maxit - it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
             // after a restart the incoming partials are k_cg_init's (3 per block)
@@ -845,7 +901,10 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
         if (h.flag == 0) {
-            if (it < maxit) continue;
+            if (it < maxit) {
+                plan.observe(h.wrr_it, h.it_last, h.tol2);
+                continue;
+            }
             const double wbb = h.wbb, tol2 = h.tol2;
             OASIS_TRY(residual(1, it));
             OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -900,6 +959,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                 break;
             }
             if (sr) OASIS_TRY(loop.start(itd, false));
+            plan.restart(h.wrr, itd, tol2);
             continue;
         }
         out.iters = h.it_done;
@@ -986,11 +1046,12 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         return OASIS_OK;
     }
     OASIS_TRY(cast(0, false));
-    const int chunk = check_every > 0 ? check_every : 32;
+    ChunkPlan plan(check_every);
+    plan.restart(h.wrr, 0, std::max(h.upd2, tol2));
     int it = 0, restart_at = 0, nin = gv;     // partials of k_cg_cast first, then of k_cg_p2
     int rc = OASIS_OK;
     while (true) {
-        const int m = std::min(chunk, maxit - it);
+        const int m = std::min(plan.next, maxit - it);
         for (int j = 0; j < m; ++j) {
             const int itj = it + j;
             if (sr) {
@@ -1022,7 +1083,10 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
             out.rel_res = NAN;
             break;
         }
-        if (h.flag == 0 && it < maxit) continue;
+        if (h.flag == 0 && it < maxit) {
+            plan.observe(h.wrr_it, h.it_last, std::max(h.upd2, tol2));
+            continue;
+        }
         // replacement: fold x_lo into x, FP64 residual, test, FP32 copy
         const int at = h.flag == 0 ? it : h.it_done;
         OASIS_TRY(fold());
@@ -1067,6 +1131,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
             break;
         }
         OASIS_TRY(cast(at, true));
+        plan.restart(h.wrr, at, std::max(h.upd2, tol2));
         it = at;
         nin = gv;
     }

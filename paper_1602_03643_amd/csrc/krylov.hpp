@@ -17,6 +17,9 @@ struct CGState {
     int flag;          // 0 running, 1 converged candidate, 2 breakdown, 3 non-finite,
                        // 4 residual replacement due (mixed precision)
     int it_done;       // iteration index at which flag was raised
+    double wrr_it;     // weighted r.r entering iteration it_last (the last one that ran)
+    int it_last;
+    int pad;
 };
 
 template <typename T>
