@@ -317,7 +317,8 @@ int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
  * prediction only if its initial residual is below that of the plain start
  * (par->pressure_start); the solve still stops at the same rtol.  params: device float
  * [OASIS_MPNN_NPARAM]; coords: device double [n_dof][dim]; ws: at least
- * oasis_mpnn_workspace_size(n_dof) bytes.  All three are kept by reference. */
+ * oasis_mpnn_workspace_size(n_dof) bytes.  All three are kept by reference.
+ * The step's forward pass keeps no activations in ws (it is inference only). */
 int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, const double *coords,
                              void *ws, size_t ws_bytes);
 

@@ -25,6 +25,7 @@
 
 #include "assemble.hpp"
 #include "krylov.hpp"
+#include "mpnn.hpp"
 #include "p1.hpp"
 #include "spmv.hpp"
 
@@ -370,10 +371,19 @@ __global__ __launch_bounds__(kBlock) void k_div_rows(int n, const int *__restric
     for (long long row = gid; row < n; row += ngroups) {
         const int s = rp[row], e = rp[row + 1];
         double acc = 0.0;
-        for (int j = s + lane; j < e; j += L) {
-            const int c = ci[j];
+        // two entries per lane and pass, the second from a clamped index,
+        // so that both entries' loads are in flight together
+        for (int j0 = s + lane; j0 < e; j0 += 2 * L) {
+            const bool ok1 = j0 + L < e;
+            const int j1 = ok1 ? j0 + L : j0;
+            const int c0 = ci[j0], c1 = ci[j1];
+            double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc += dP.p[k][j] * UI.p[k][c];
+            for (int k = 0; k < D; ++k) {
+                t0 += dP.p[k][j0] * UI.p[k][c0];
+                t1 += dP.p[k][j1] * UI.p[k][c1];
+            }
+            acc += t0 + (ok1 ? t1 : 0.0);
         }
         acc = group_sum<L>(acc);
         if (lane == 0) {
@@ -469,10 +479,16 @@ __global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__rest
         double acc[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] = 0.0;
-        for (int j = s + lane; j < e; j += L) {
-            const double f = phi[ci[j]];
+        // two entries per lane and pass (see k_div_rows)
+        for (int j0 = s + lane; j0 < e; j0 += 2 * L) {
+            const bool ok1 = j0 + L < e;
+            const int j1 = ok1 ? j0 + L : j0;
+            const double f0 = phi[ci[j0]], f1 = phi[ci[j1]];
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc[k] += dP.p[k][j] * f;
+            for (int k = 0; k < D; ++k) {
+                const double a0 = dP.p[k][j0] * f0, a1 = dP.p[k][j1] * f1;
+                acc[k] += a0 + (ok1 ? a1 : 0.0);
+            }
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] = group_sum<L>(acc[k]);
@@ -1197,8 +1213,8 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     if (!phi_guess && h->ws_params) {
         // learned warm start from the projected right-hand side and phi_prev
         oasis_csr Kc{n, h->nnz, h->rp, h->ci, h->Ks, OASIS_F64};
-        OASIS_TRY(oasis_mpnn_forward(stream, &Kc, h->sK, D, h->ws_coords, h->bphi, st->phi, h->ws_params,
-                                     h->dtmp, nullptr, h->ws_mem, h->ws_bytes));
+        OASIS_TRY(mpnn_infer(stream, &Kc, h->sK, D, h->ws_coords, h->bphi, st->phi, h->ws_params, h->dtmp,
+                             h->ws_mem, h->ws_bytes));
         phi_guess = h->dtmp;
     }
     if (phi_guess) {

@@ -23,6 +23,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "mpnn.hpp"
 #include "spmv.hpp"
 
 namespace oasis {
@@ -289,7 +290,10 @@ __device__ __forceinline__ void load_layer_weights(const float *__restrict__ P, 
     }
 }
 
-template <bool LAST>
+// STORE: keep the activations (aggregate, pre-activation, and the last
+// layer's output) for the backward pass; inference needs only the hidden
+// state that the next layer reads.
+template <bool LAST, bool STORE>
 __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__restrict__ rp,
                                                      const int *__restrict__ ci, const double *__restrict__ Ks,
                                                      const double *__restrict__ s, const float *__restrict__ P,
@@ -330,7 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__
                     T[ln][kHid + f0 + 2 * k] = static_cast<unsigned short>(lo);
                     T[ln][kHid + f0 + 2 * k + 1] = static_cast<unsigned short>(hi);
                 }
-                *reinterpret_cast<uint4 *>(Aout + (size_t)i * kHid + f0) = make_uint4(av[0], av[1], av[2], av[3]);
+                if (STORE)
+                    *reinterpret_cast<uint4 *>(Aout + (size_t)i * kHid + f0) = make_uint4(av[0], av[1], av[2], av[3]);
             } else {
                 for (int k = 0; k < 8; ++k) {
                     T[ln][f0 + k] = 0;
@@ -369,8 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__
                 const float z = acc[nt][q] + cvec[o];
                 const float hn = bf2f(T[ln][o]) + fmaxf(z, 0.f);
                 if (i < n) {
-                    Zout[(size_t)i * kHid + o] = f2bf(z);
-                    Hout[(size_t)i * kHid + o] = f2bf(hn);
+                    if (STORE) Zout[(size_t)i * kHid + o] = f2bf(z);
+                    if (STORE || !LAST) Hout[(size_t)i * kHid + o] = f2bf(hn);
                 }
                 if (LAST) dpart[q] += bf2f(f2bf(hn)) * wd[o];
             }
@@ -677,9 +682,9 @@ static int mp_check(const oasis_csr *Ks, const double *s, void *ws) {
     return OASIS_OK;
 }
 
-extern "C" int oasis_mpnn_forward(void *stream, const oasis_csr *Ks, const double *s, int32_t dim,
-                                  const double *coords, const double *b_phi, const double *phi_prev,
-                                  const float *params, double *guess, float *delta, void *ws, size_t ws_bytes) {
+static int mp_forward(void *stream, const oasis_csr *Ks, const double *s, int32_t dim, const double *coords,
+                      const double *b_phi, const double *phi_prev, const float *params, double *guess,
+                      float *delta, void *ws, size_t ws_bytes, bool store) {
     OASIS_TRY(mp_check(Ks, s, ws));
     if (!b_phi || !phi_prev || !params || dim < 0 || dim > 3 || (dim > 0 && !coords)) return OASIS_EINVAL;
     const int n = Ks->n;
@@ -702,21 +707,36 @@ extern "C" int oasis_mpnn_forward(void *stream, const oasis_csr *Ks, const doubl
     for (int l = 0; l < kLayers; ++l) {
         const bool last = l == kLayers - 1;
         float *dl = delta ? delta : w.delta;
+        auto go = [&](auto kern, float *d, double *g) {
+            hipLaunchKernelGGL(kern, dim3(gt), dim3(kBlock), 0, st, n, l, Ks->row_ptr, Ks->col_idx, val, s, params,
+                               w.H[l], w.Ag[l], w.Z[l + 1], w.H[l + 1], d, g, phi_prev, w.scal);
+        };
         if (last)
-            hipLaunchKernelGGL(k_mp_layer<true>, dim3(gt), dim3(kBlock), 0, st, n, l, Ks->row_ptr, Ks->col_idx, val,
-                               s, params, w.H[l], w.Ag[l], w.Z[l + 1], w.H[l + 1], dl, guess, phi_prev, w.scal);
+            store ? go(k_mp_layer<true, true>, dl, guess) : go(k_mp_layer<true, false>, dl, guess);
         else
-            hipLaunchKernelGGL(k_mp_layer<false>, dim3(gt), dim3(kBlock), 0, st, n, l, Ks->row_ptr, Ks->col_idx,
-                               val, s, params, w.H[l], w.Ag[l], w.Z[l + 1], w.H[l + 1], (float *)nullptr,
-                               (double *)nullptr, phi_prev, w.scal);
+            store ? go(k_mp_layer<false, true>, nullptr, nullptr) : go(k_mp_layer<false, false>, nullptr, nullptr);
         OASIS_TRY_LAUNCH();
     }
-    if (delta) {
+    if (delta && store) {
         // keep the workspace copy for the backward pass
         OASIS_TRY_HIP(hipMemcpyAsync(w.delta, delta, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
     }
     return OASIS_OK;
 }
+
+extern "C" int oasis_mpnn_forward(void *stream, const oasis_csr *Ks, const double *s, int32_t dim,
+                                  const double *coords, const double *b_phi, const double *phi_prev,
+                                  const float *params, double *guess, float *delta, void *ws, size_t ws_bytes) {
+    return mp_forward(stream, Ks, s, dim, coords, b_phi, phi_prev, params, guess, delta, ws, ws_bytes, true);
+}
+
+namespace oasis {
+int mpnn_infer(void *stream, const oasis_csr *Ks, const double *s, int32_t dim, const double *coords,
+               const double *b_phi, const double *phi_prev, const float *params, double *guess, void *ws,
+               size_t ws_bytes) {
+    return mp_forward(stream, Ks, s, dim, coords, b_phi, phi_prev, params, guess, nullptr, ws, ws_bytes, false);
+}
+}  // namespace oasis
 
 extern "C" int oasis_mpnn_backward(void *stream, const oasis_csr *Ks, const double *s, const double *phi,
                                    const double *phi_prev, const float *params, float *grad, double *loss_out,
