@@ -295,6 +295,33 @@ def test_pcg_mixed_meets_fp64_tolerance(oa, prob):
     assert abs(out["iters"] - rr.iters) <= 0.15 * rr.iters + 5, (out["iters"], rr.iters)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pcg_poll_schedule_does_not_change_the_solve(oa, precision):
+    """The host polls the device-side convergence state between chunks of
+    launched iterations (sized from the observed convergence rate by
+    default, or every check_every iterations); launches after a raised flag
+    return at once, so the iterate, the iteration count and the replacement
+    count must be bit-for-bit the same for any schedule."""
+    prob = synth.channel_flow((33, 33, 25), seed=2)
+    say("pcg poll schedule", prob.name, precision)
+    S, st, A, b = _tent_problem(prob)
+    dm, pat, _ = device_mesh(prob.mesh)
+    Kp = pat.with_values(T(p1.on_pattern(S.K, csr_host(pat))))
+    rng = np.random.default_rng(31)
+    bphi = rng.normal(size=prob.mesh.n_dof)
+    bphi -= bphi.mean()
+    prec = oa.F64 if precision == "f64" else oa.F32
+    outs, xs = [], []
+    for every in (0, 1, 7, 64):
+        x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+        outs.append(oa.pcg(Kp, T(bphi), x, rtol=1e-9, precision=prec, nullspace_const=True, check_every=every))
+        xs.append(x)
+    for o, x in zip(outs[1:], xs[1:]):
+        assert o["rc"] == outs[0]["rc"] == 0
+        assert o["iters"] == outs[0]["iters"] and o["restarts"] == outs[0]["restarts"], (o, outs[0])
+        assert torch.equal(x, xs[0])
+
+
 def test_bicgstab_mixed_meets_fp64_tolerance(oa):
     prob = synth.channel_flow("small", seed=5)
     say("bicgstab mixed", prob.name)
