@@ -792,13 +792,12 @@ int cg_update_grid() {
 // kMaxPartials * kBlock / BS blocks, which keeps the resident waves equal.
 template <int BS>
 struct CgGrids {
-    int p1, ell, p2;
+    int p1, p2;
     template <class C>
     static CgGrids make(int n) {
         const int cap = kMaxPartials * kBlock / BS;
         const int cap2 = std::min(cap, cg_update_grid() * kBlock / BS);
-        return CgGrids{grid_for(n, rows_per_block<C, BS>(), cap), grid_for(n, BS / kEllLanes, cap),
-                       grid_for(n, BS, cap2)};
+        return CgGrids{grid_for(n, rows_per_block<C, BS>(), cap), grid_for(n, BS, cap2)};
     }
 };
 

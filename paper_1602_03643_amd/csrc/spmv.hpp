@@ -122,11 +122,10 @@ __device__ __forceinline__ void csr_rows(int n, const int *__restrict__ rp, cons
 // (column i, value 0).  Columns are stored as 16-bit cyclic offsets
 // d = (c - i) taken into [-n/2, n/2), which fit whenever the matrix's
 // cyclic bandwidth is below 2^15 (the periodic channel's structured
-// numbering: one x-y layer; after RCM: about 1.3 layers).  kEll / 4 lanes
-// share a row; each fetches its 4 offsets with one 8-byte load and its 4
-// values with 16-byte loads (no row pointers).
+// numbering: one x-y layer; after RCM: about 1.3 layers).  The product
+// loops give each of L lanes of a row kEll / L consecutive entries,
+// fetched with 8-byte offset and 16-byte value loads (no row pointers).
 constexpr int kEll = 16;
-constexpr int kEllLanes = kEll / 4;
 
 // Column offsets of an ELL copy: per entry (ecol, n x kEll), or per row
 // through a dictionary (pid: pattern id of each row; ptab: kEll offsets per
