@@ -506,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__rest
 template <int NR, class C>
 __global__ __launch_bounds__(kBlock) void k_ir_resid(int n, const int *__restrict__ rp,
                                                      const int *__restrict__ ci,
-                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ val, EllCols cols,
                                                      const double *__restrict__ w, P3 b, P3 x,
                                                      float *r0, float *r1, float *r2, double *part) {
     __shared__ double lds[6 * kBlock / kWave];
@@ -514,27 +514,30 @@ __global__ __launch_bounds__(kBlock) void k_ir_resid(int n, const int *__restric
     double acc2[2 * NR];
 #pragma unroll
     for (int k = 0; k < 2 * NR; ++k) acc2[k] = 0.0;
-    csr_rows<double, NR, C>(
-        n, rp, ci, val,
-        [&](int, int c, double v, bool ok, double(&a)[NR]) {
+    auto gather = [&](int, int c, double v, bool ok, double(&a)[NR]) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const double t = v * x.p[k][c];
-                a[k] += ok ? t : 0.0;
-            }
-        },
-        [&](int row, int lane, double(&a)[NR]) {
-            if (lane != 0) return;
-            const double wd = w[row];
+        for (int k = 0; k < NR; ++k) {
+            const double t = v * x.p[k][c];
+            a[k] += ok ? t : 0.0;
+        }
+    };
+    auto finish = [&](int row, int lane, double(&a)[NR]) {
+        if (lane != 0) return;
+        const double wd = w[row];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const double bk = b.p[k][row];
-                const double r = bk - a[k];
-                ro[k][row] = static_cast<float>(r);
-                acc2[2 * k] += wd * r * r;
-                acc2[2 * k + 1] += wd * bk * bk;
-            }
-        });
+        for (int k = 0; k < NR; ++k) {
+            const double bk = b.p[k][row];
+            const double r = bk - a[k];
+            ro[k][row] = static_cast<float>(r);
+            acc2[2 * k] += wd * r * r;
+            acc2[2 * k + 1] += wd * bk * bk;
+        }
+    };
+    // the CSR values with an ELL copy's columns when there is one
+    if (cols.any())
+        csr_cols_rows<double, NR, 2>(n, rp, val, cols, gather, finish);
+    else
+        csr_rows<double, NR, C>(n, rp, ci, val, gather, finish);
     write_partials<2 * NR>(acc2, part, lds);
 }
 
@@ -586,22 +589,22 @@ static void carve_ir(Carver &c, int n, int nr, IRBufs &ir) {
 }
 
 static int ir_outer_resid(hipStream_t s, int n, int nr, const int *rp, const int *ci,
-                          const double *val, const double *w, P3 b, P3 x, IRBufs &ir,
+                          const double *val, const EllCols &cols, const double *w, P3 b, P3 x, IRBufs &ir,
                           double *host_sums) {
     using L = Cfg8x2x1;
     const int g = grid_for(n, rows_per_block<L>(), partial_cap());
     if (nr == 1) {
-        hipLaunchKernelGGL((k_ir_resid<1, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
+        hipLaunchKernelGGL((k_ir_resid<1, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, cols, w, b, x,
                            ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL((k_sum_to<2>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
     } else if (nr == 2) {
-        hipLaunchKernelGGL((k_ir_resid<2, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
+        hipLaunchKernelGGL((k_ir_resid<2, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, cols, w, b, x,
                            ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL((k_sum_to<4>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
     } else {
-        hipLaunchKernelGGL((k_ir_resid<3, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, w, b, x,
+        hipLaunchKernelGGL((k_ir_resid<3, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, cols, w, b, x,
                            ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL((k_sum_to<6>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
@@ -634,7 +637,7 @@ static int ir_cg(hipStream_t s, int n, const int *rp, const int *ci, const doubl
     double hs[2];
     int total = 0;
     for (int outer = 0;; ++outer) {
-        OASIS_TRY(ir_outer_resid(s, n, 1, rp, ci, val, w, pb, px, ir, hs));
+        OASIS_TRY(ir_outer_resid(s, n, 1, rp, ci, val, ell_enabled() ? cw.cols : EllCols{}, w, pb, px, ir, hs));
         out.rel_res = hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : std::sqrt(hs[0]);
         if (!std::isfinite(hs[0])) {
             out.status = OASIS_ENAN;
@@ -685,7 +688,7 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
     bool done[3] = {false, false, false};
     double hs[6];
     for (int outer = 0;; ++outer) {
-        OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, w, pb, px, ir, hs));
+        OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, ell_enabled() ? bw.cols : EllCols{}, w, pb, px, ir, hs));
         int active[3], na = 0;
         for (int k = 0; k < nr; ++k) {
             if (done[k]) continue;

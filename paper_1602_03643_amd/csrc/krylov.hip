@@ -103,33 +103,38 @@ __global__ __launch_bounds__(kBlock) void k_copy(int n, T *__restrict__ y, const
 // ---------------------------------------------------------------------------
 // CG kernels
 
-// r = b - Ms x (r[row * rs]: rs = 2 writes the r of a residual/direction
-// pair); partials (r.r, sum wgt r^2, sum wgt b^2)
+// r = b - Ms x (r[row * rs]: rs = 2 or 4 writes the r of an interleaved
+// record); partials (r.r, sum wgt r^2, sum wgt b^2).  With an ELL copy's
+// columns (cols.any()) the CSR values are read with those columns instead
+// of the int32 column array.
 template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ ci,
-                                                    const T *__restrict__ val,
+                                                    const T *__restrict__ val, EllCols cols,
                                                     const T *__restrict__ wgt,
                                                     const T *__restrict__ b,
                                                     const T *__restrict__ x, T *__restrict__ r, int rs,
                                                     double *part) {
     __shared__ double lds[3 * kBlock / kWave];
     double acc[3] = {0.0, 0.0, 0.0};
-    csr_rows<T, 1, C>(
-        n, rp, ci, val, [&](int, int c, T v, bool ok, T(&a)[1]) {
-            const T t = v * x[c];
-            a[0] += ok ? t : T(0);
-        },
-        [&](int row, int lane, T(&a)[1]) {
-            if (lane == 0) {
-                const T ri = b[row] - a[0];
-                r[static_cast<long long>(row) * rs] = ri;
-                const double rd = ri, bd = b[row], wd = wgt[row];
-                acc[0] += rd * rd;
-                acc[1] += wd * rd * rd;
-                acc[2] += wd * bd * bd;
-            }
-        });
+    auto gather = [&](int, int c, T v, bool ok, T(&a)[1]) {
+        const T t = v * x[c];
+        a[0] += ok ? t : T(0);
+    };
+    auto finish = [&](int row, int lane, T(&a)[1]) {
+        if (lane == 0) {
+            const T ri = b[row] - a[0];
+            r[static_cast<long long>(row) * rs] = ri;
+            const double rd = ri, bd = b[row], wd = wgt[row];
+            acc[0] += rd * rd;
+            acc[1] += wd * rd * rd;
+            acc[2] += wd * bd * bd;
+        }
+    };
+    if (cols.any())
+        csr_cols_rows<T, 1, 2>(n, rp, val, cols, gather, finish);
+    else
+        csr_rows<T, 1, C>(n, rp, ci, val, gather, finish);
     write_partials<3>(acc, part, lds);
 }
 
@@ -858,8 +863,8 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     // explicit residual into the r of the record that iteration `at` reads
     auto residual = [&](int mode, int at) -> int {
         T *r = sr ? reinterpret_cast<T *>(w.rec[at & 1]) : reinterpret_cast<T *>(w.pair[at & 1]);
-        hipLaunchKernelGGL((k_cg_init<T, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                           b, x, r, sr ? 4 : 2, w.partB);
+        hipLaunchKernelGGL((k_cg_init<T, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val,
+                           ell ? w.cols : EllCols{}, wgt, b, x, r, sr ? 4 : 2, w.partB);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, gi, w.st,
                            rtol * rtol, mode, 0.0);
@@ -1014,8 +1019,8 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     out = SolveOut();
     // FP64 residual of the FP64 accumulator, then its FP32 copy (x_lo = 0)
     auto replace = [&](int mode) -> int {
-        hipLaunchKernelGGL((k_cg_init<double, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                           b, x, rhi, 1, w.partB);
+        hipLaunchKernelGGL((k_cg_init<double, C>), dim3(gi), dim3(kBlock), 0, s, n, rp, ci, val,
+                           ell ? w.cols : EllCols{}, wgt, b, x, rhi, 1, w.partB);
         OASIS_TRY_LAUNCH();
         hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, gi, w.st,
                            rtol * rtol, mode, upd);
@@ -1162,8 +1167,8 @@ int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double
                 const double *wgt, const double *b, const double *x, double *r,
                 CGWork<double> &w, double *wrr, double *wbb) {
     const int g1 = grid_for(n, rows_per_block<Cfg8x2x1>(), partial_cap());
-    hipLaunchKernelGGL((k_cg_init<double, Cfg8x2x1>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val, wgt,
-                       b, x, r, 1, w.partB);
+    hipLaunchKernelGGL((k_cg_init<double, Cfg8x2x1>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
+                       ell_enabled() ? w.cols : EllCols{}, wgt, b, x, r, 1, w.partB);
     OASIS_TRY_LAUNCH();
     hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0, 0.0);
     OASIS_TRY_LAUNCH();

@@ -220,6 +220,50 @@ __device__ __forceinline__ void ell_rows(int n, const EllCols &cols, const TA *_
     }
 }
 
+// The csr_rows contract for CSR values whose columns come from an ELL
+// copy's column storage (the offset dictionary or per-entry offsets): slot
+// k of row i is CSR entry rp[i] + k, so the values are read in CSR order
+// and the int32 column array is not read at all.  L lanes per row, kEll / L
+// slots per lane, loads from clamped addresses; slots past the row's
+// length are passed with ok = false.
+template <typename TA, int NR, int L, int BS = kBlock, class Gather, class Finish>
+__device__ __forceinline__ void csr_cols_rows(int n, const int *__restrict__ rp, const TA *__restrict__ val,
+                                              const EllCols &cols, Gather gather, Finish finish) {
+    constexpr int E = kEll / L;
+    static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 slots per lane");
+    const int lane = threadIdx.x & (L - 1);
+    const RowRange<L, BS> rr(n);
+    for (long long row = rr.first + rr.gid; row < rr.last; row += rr.ngroups) {
+        const int s = rp[row], len = rp[row + 1] - s;
+        const short *off = cols.offsets(row) + lane * E;
+        int c[E];
+        TA w[E];
+        bool ok[E];
+#pragma unroll
+        for (int g = 0; g < E / 4; ++g) {
+            const short4 d = *reinterpret_cast<const short4 *>(off + 4 * g);
+            c[4 * g] = ell_col(row, d.x, n);
+            c[4 * g + 1] = ell_col(row, d.y, n);
+            c[4 * g + 2] = ell_col(row, d.z, n);
+            c[4 * g + 3] = ell_col(row, d.w, n);
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int slot = lane * E + k;
+            ok[k] = slot < len;
+            w[k] = val[s + (ok[k] ? slot : 0)];
+        }
+        TA acc[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = TA(0);
+#pragma unroll
+        for (int k = 0; k < E; ++k) gather(s + lane * E + k, c[k], w[k], ok[k], acc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = group_sum<L>(acc[k]);
+        finish(static_cast<int>(row), lane, acc);
+    }
+}
+
 // A matrix on the shared CSR pattern with an optional ELL copy (columns
 // and eval both set) that products use instead.
 template <typename T>
