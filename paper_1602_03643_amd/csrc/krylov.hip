@@ -381,7 +381,10 @@ template <typename T, int BS>
 static int launch_p1_ell(hipStream_t s, int n, const EllCols &cols, const T *eval, const RP<T> *cur, RP<T> *nxt,
                          T *q, const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
                          const T *vnull, double *partOut, bool grid_only = false) {
-    const int cap = kMaxPartials * kBlock / BS;
+    // The producer grid cap: the update kernel reads every block's partials,
+    // and 1024 blocks measured 59 us per FP64 product against 66 us with
+    // 2048 and 65 / 80 us with 768 / 512 (1.6M rows).
+    const int cap = partial_cap() * kBlock / BS;
     auto go = [&](auto kern, int rows_per_blk) {
         const int g = grid_for(n, rows_per_blk, cap);
         if (!grid_only)
@@ -431,7 +434,7 @@ __device__ __forceinline__ void sr_partials(double (&acc)[kSr], const Q4<T> &o, 
 
 // One iteration (see above).  Convergence tests on the incoming residual
 // as in k_cg_p1; a non-positive p.s is a breakdown.
-template <typename T, int BS, int L, bool PROJ>
+template <typename T, int BS, int L, bool PROJ, bool DICT>
 __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__restrict__ eval,
                                               const Q4<T> *__restrict__ cur, Q4<T> *__restrict__ nxt,
                                               T *__restrict__ x, const T *__restrict__ wgt,
@@ -480,36 +483,69 @@ __global__ __launch_bounds__(BS) void k_cg_sr(int n, EllCols cols, const T *__re
     for (int k = 0; k < kSr; ++k) acc[k] = 0.0;
     const int lane = threadIdx.x & (L - 1);
     const RowRange<L, BS> range(n);
-    // software-pipelined: the next row's offsets and values are fetched
-    // while this row's gathers are in flight
     long long row = range.first + range.gid;
-    int c[E];
-    T w[E];
-    if (row < range.last) ell_fetch<T, E>(row, lane, n, cols, eval, c, w);
-    for (; row < range.last; row += range.ngroups) {
-        Q4<T> g[E];
+    if (row < range.last) {
+        // Software-pipelined, straight-line loop: while this row's gathers
+        // are in flight, every lane fetches the next row's offsets and
+        // values, its own-row state (record, x, null-vector entry, weight)
+        // and the pattern id of the row after it.  Row indices of these
+        // fetches are clamped into the range (the last iteration re-reads
+        // a valid row and drops it), so no load sits behind a branch and
+        // the owning lane's update waits on none of them.  The loop is
+        // unrolled twice over two register sets, so that no loaded value
+        // is copied across the back edge (a copy waits for its load).
+        const long long top = range.last - 1;
+        auto clamp = [top](long long r) { return r < top ? r : top; };
+        const T *wsrc = wgt ? wgt : x;   // read unused when the weights come from vnull
+        struct Stage {
+            int c[E];
+            T w[E];
+            Q4<T> me;
+            T xr, vr, wr;
+        };
+        auto fetch = [&](Stage &S, long long r, int key) {
+            ell_fetch_key<DICT, T, E>(r, key, lane, n, cols, eval, S.c, S.w);
+            S.me = cur[r];
+            S.xr = x[r];
+            S.vr = PROJ ? vnull[r] : T(0);
+            S.wr = wsrc[r];
+        };
+        auto step = [&](const Stage &S, Stage &N, int kin, int &kout) {
+            Q4<T> g[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) g[k] = cur[c[k]];
-        T a = T(0);
+            for (int k = 0; k < E; ++k) g[k] = cur[S.c[k]];
+            fetch(N, clamp(row + range.ngroups), kin);
+            kout = ell_key<DICT>(cols, clamp(row + 2 * range.ngroups));
+            T a = T(0);
 #pragma unroll
-        for (int k = 0; k < E; ++k) a += w[k] * fmsub(g[k].r, al, fmadd(bt, g[k].s, g[k].w));
-        const long long nrow = row + range.ngroups;
-        if (nrow < range.last) ell_fetch<T, E>(nrow, lane, n, cols, eval, c, w);
-        a = group_sum<L>(a);
-        if (lane == 0) {
-            const Q4<T> me = cur[row];
-            const T vr = PROJ ? vnull[row] : T(0);
-            const T wp = PROJ ? fmsub(me.w, cw, vr) : me.w;
-            const T sp = PROJ ? fmsub(me.s, cs, vr) : me.s;
-            Q4<T> o;
-            o.s = fmadd(bt, sp, wp);
-            o.p = fmadd(bt, me.p, me.r);
-            o.r = fmsub(me.r, al, o.s);
-            o.w = a;
-            x[row] = fmadd(al, o.p, x[row]);
-            nxt[row] = o;
-            const double vd = vr;
-            sr_partials<T>(acc, o, wgt ? static_cast<double>(wgt[row]) : vscale * vd * vd, vd);
+            for (int k = 0; k < E; ++k) a += S.w[k] * fmsub(g[k].r, al, fmadd(bt, g[k].s, g[k].w));
+            a = group_sum<L>(a);
+            if (lane == 0) {
+                const Q4<T> &m = S.me;
+                const T wp = PROJ ? fmsub(m.w, cw, S.vr) : m.w;
+                const T sp = PROJ ? fmsub(m.s, cs, S.vr) : m.s;
+                Q4<T> o;
+                o.s = fmadd(bt, sp, wp);
+                o.p = fmadd(bt, m.p, m.r);
+                o.r = fmsub(m.r, al, o.s);
+                o.w = a;
+                x[row] = fmadd(al, o.p, S.xr);
+                nxt[row] = o;
+                const double vd = S.vr;
+                sr_partials<T>(acc, o, wgt ? static_cast<double>(S.wr) : vscale * vd * vd, vd);
+            }
+        };
+        Stage A, B;
+        int ka, kb;
+        fetch(A, row, ell_key<DICT>(cols, row));
+        ka = ell_key<DICT>(cols, clamp(row + range.ngroups));
+        for (;;) {
+            step(A, B, ka, kb);
+            row += range.ngroups;
+            if (row >= range.last) break;
+            step(B, A, kb, ka);
+            row += range.ngroups;
+            if (row >= range.last) break;
         }
     }
     write_partials<kSr>(acc, partOut, lds);
@@ -600,17 +636,18 @@ struct SrLoop {
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     }
-    template <bool PROJ>
+    template <bool PROJ, bool DICT>
     void go(int it, int beta_zero, T *x) {
-        hipLaunchKernelGGL((k_cg_sr<T, BS, L, PROJ>), dim3(grid), dim3(BS), 0, s, n, cols, eval, w->rec[it & 1],
-                           w->rec[(it + 1) & 1], x, wgt, vnull, vscale, part(it), grid, w->st, it, beta_zero,
-                           part(it + 1));
+        hipLaunchKernelGGL((k_cg_sr<T, BS, L, PROJ, DICT>), dim3(grid), dim3(BS), 0, s, n, cols, eval,
+                           w->rec[it & 1], w->rec[(it + 1) & 1], x, wgt, vnull, vscale, part(it), grid, w->st, it,
+                           beta_zero, part(it + 1));
     }
     void iterate(int it, int beta_zero, T *x) {
+        const bool dict = cols.pid != nullptr;
         if (vnull)
-            go<true>(it, beta_zero, x);
+            dict ? go<true, true>(it, beta_zero, x) : go<true, false>(it, beta_zero, x);
         else
-            go<false>(it, beta_zero, x);
+            dict ? go<false, true>(it, beta_zero, x) : go<false, false>(it, beta_zero, x);
     }
 };
 

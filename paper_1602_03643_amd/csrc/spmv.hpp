@@ -175,10 +175,10 @@ bool ell_enabled();
 // Offsets (decoded to columns) and values of one lane's E entries of row
 // `row` of an ELL copy.
 template <typename TA, int E>
-__device__ __forceinline__ void ell_fetch(long long row, int lane, int n, const EllCols &cols,
-                                          const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
+__device__ __forceinline__ void ell_fetch_at(const short *off, long long row, int lane, int n,
+                                             const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
     const long long base = row * kEll + lane * E;
-    const short *off = cols.offsets(row) + lane * E;
+    off += lane * E;
 #pragma unroll
     for (int g = 0; g < E / 4; ++g) {
         const short4 d = *reinterpret_cast<const short4 *>(off + 4 * g);
@@ -191,6 +191,33 @@ __device__ __forceinline__ void ell_fetch(long long row, int lane, int n, const 
 #pragma unroll
         for (int k = 0; k < 4; ++k) w[4 * g + k] = t[k];
     }
+}
+
+template <typename TA, int E>
+__device__ __forceinline__ void ell_fetch(long long row, int lane, int n, const EllCols &cols,
+                                          const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
+    ell_fetch_at<TA, E>(cols.offsets(row), row, lane, n, eval, c, w);
+}
+
+// The same fetch split in two for row loops that run the pattern-id load
+// one row further ahead: ell_key reads a row's key (its pattern id; 0
+// without a dictionary) and ell_fetch_key the row's offsets and values given
+// that key.  DICT fixes the column storage at compile time, so that such a
+// loop is straight-line code whose outstanding loads the compiler counts
+// exactly (a run-time choice merges two paths and makes it wait for all).
+template <bool DICT>
+__device__ __forceinline__ int ell_key(const EllCols &cols, long long row) {
+    if constexpr (DICT)
+        return cols.pid[row];
+    else
+        return 0;
+}
+
+template <bool DICT, typename TA, int E>
+__device__ __forceinline__ void ell_fetch_key(long long row, int key, int lane, int n, const EllCols &cols,
+                                              const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
+    const short *off = DICT ? cols.ptab + key * kEll : cols.ecol + row * kEll;
+    ell_fetch_at<TA, E>(off, row, lane, n, eval, c, w);
 }
 
 // The row loop is software-pipelined: the next row's offsets and values are
