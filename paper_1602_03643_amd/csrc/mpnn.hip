@@ -21,6 +21,7 @@
 // All reductions are fixed-order (block partials, then one ordered sum).
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "mpnn.hpp"
@@ -280,6 +281,55 @@ __device__ __forceinline__ void agg8(int i, int f0, const int *__restrict__ rp, 
     for (int k = 0; k < 8; ++k) out[k] = acc[k];
 }
 
+// Edge weights of the forward aggregation: W_e = Ks_e s_{col(e)} rounded to
+// FP32, the weight agg8 forms per gathered entry; computed once per forward
+// pass for all layers (agg8w then reads 4 bytes per edge instead of the FP64
+// value and a gathered FP64 scale).
+__global__ __launch_bounds__(kBlock) void k_mp_edge_w(long long nnz, const int *__restrict__ ci,
+                                                      const double *__restrict__ Ks, const double *__restrict__ s,
+                                                      float *__restrict__ W) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz;
+         e += (long long)gridDim.x * blockDim.x)
+        W[e] = static_cast<float>(Ks[e] * s[ci[e]]);
+}
+
+// agg8 with scale_by_j on precomputed edge weights (the same sums, bit for
+// bit: the same FP32 weights accumulated in the same order).
+__device__ __forceinline__ void agg8w(int i, int f0, const int *__restrict__ rp, const int *__restrict__ ci,
+                                      const float *__restrict__ W, const unsigned short *__restrict__ V,
+                                      float (&out)[8]) {
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+    constexpr int U = 8;
+    const int e0 = rp[i], len = rp[i + 1] - e0;
+    for (int c0 = 0; c0 < len; c0 += U) {
+        int j[U];
+        float w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + (c0 + u < len ? c0 + u : len - 1);
+            j[u] = ci[e];
+            w[u] = W[e];
+        }
+        uint4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = *reinterpret_cast<const uint4 *>(V + (size_t)j[u] * kHid + f0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c0 + u >= len || j[u] == i) continue;
+            const unsigned qq[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc[2 * k] += w[u] * bf2f(static_cast<unsigned short>(qq[k] & 0xffffu));
+                acc[2 * k + 1] += w[u] * bf2f(static_cast<unsigned short>(qq[k] >> 16));
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = acc[k];
+}
+
 // LDS B operand for z = [h | a] W^T: B[k][o] with k < 32 -> Ws[o][k], k >= 32 -> Wn[o][k-32]
 __device__ __forceinline__ void load_layer_weights(const float *__restrict__ P, int l, unsigned short (*B)[kHid]) {
     for (int q = threadIdx.x; q < 2 * kHid * kHid; q += blockDim.x) {
@@ -292,11 +342,13 @@ __device__ __forceinline__ void load_layer_weights(const float *__restrict__ P, 
 
 // STORE: keep the activations (aggregate, pre-activation, and the last
 // layer's output) for the backward pass; inference needs only the hidden
-// state that the next layer reads.
-template <bool LAST, bool STORE>
+// state that the next layer reads.  EW: the aggregation reads the edge
+// weights W of k_mp_edge_w.
+template <bool LAST, bool STORE, bool EW>
 __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__restrict__ rp,
                                                      const int *__restrict__ ci, const double *__restrict__ Ks,
-                                                     const double *__restrict__ s, const float *__restrict__ P,
+                                                     const double *__restrict__ s, const float *__restrict__ W,
+                                                     const float *__restrict__ P,
                                                      const unsigned short *__restrict__ Hin,
                                                      unsigned short *__restrict__ Aout, unsigned short *__restrict__ Zout,
                                                      unsigned short *__restrict__ Hout, float *__restrict__ delta,
@@ -319,10 +371,14 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__
             const int ln = threadIdx.x >> 2, f0 = (threadIdx.x & 3) * 8;
             const long long i = base + ln;
             if (i < n) {
-                float a[8];
-                agg8(static_cast<int>(i), f0, rp, ci, Ks, s, Hin, true, a);
-                const float inv = static_cast<float>(-1.0 / s[i]);
                 const uint4 hq = *reinterpret_cast<const uint4 *>(Hin + (size_t)i * kHid + f0);
+                const double si = s[i];
+                float a[8];
+                if constexpr (EW)
+                    agg8w(static_cast<int>(i), f0, rp, ci, W, Hin, a);
+                else
+                    agg8(static_cast<int>(i), f0, rp, ci, Ks, s, Hin, true, a);
+                const float inv = static_cast<float>(-1.0 / si);
                 const unsigned hv[4] = {hq.x, hq.y, hq.z, hq.w};
                 unsigned av[4];
 #pragma unroll
@@ -704,17 +760,35 @@ static int mp_forward(void *stream, const oasis_csr *Ks, const double *s, int32_
                        w.Z[0], w.H[0]);
     OASIS_TRY_LAUNCH();
     const int gt = (int)std::min<long long>((n + kTile - 1) / kTile, 1 << 20);
+    // the edge weights live in the gradient buffer (n x kHid floats, unused
+    // until the backward pass) when the matrix has at most kHid entries per
+    // row on average
+    const long long nnz = Ks->nnz;
+    const bool ew = nnz >= 0 && nnz <= static_cast<long long>(n) * kHid;
+    if (ew) {
+        hipLaunchKernelGGL(k_mp_edge_w, dim3((unsigned)std::min<long long>((nnz + kBlock - 1) / kBlock, 16384)),
+                           dim3(kBlock), 0, st, nnz, Ks->col_idx, val, s, w.G);
+        OASIS_TRY_LAUNCH();
+    }
     for (int l = 0; l < kLayers; ++l) {
         const bool last = l == kLayers - 1;
         float *dl = delta ? delta : w.delta;
         auto go = [&](auto kern, float *d, double *g) {
-            hipLaunchKernelGGL(kern, dim3(gt), dim3(kBlock), 0, st, n, l, Ks->row_ptr, Ks->col_idx, val, s, params,
-                               w.H[l], w.Ag[l], w.Z[l + 1], w.H[l + 1], d, g, phi_prev, w.scal);
+            hipLaunchKernelGGL(kern, dim3(gt), dim3(kBlock), 0, st, n, l, Ks->row_ptr, Ks->col_idx, val, s, w.G,
+                               params, w.H[l], w.Ag[l], w.Z[l + 1], w.H[l + 1], d, g, phi_prev, w.scal);
         };
-        if (last)
-            store ? go(k_mp_layer<true, true>, dl, guess) : go(k_mp_layer<true, false>, dl, guess);
+        auto pick = [&](auto ewc) {
+            constexpr bool E = decltype(ewc)::value;
+            if (last)
+                store ? go(k_mp_layer<true, true, E>, dl, guess) : go(k_mp_layer<true, false, E>, dl, guess);
+            else
+                store ? go(k_mp_layer<false, true, E>, nullptr, nullptr)
+                      : go(k_mp_layer<false, false, E>, nullptr, nullptr);
+        };
+        if (ew)
+            pick(std::true_type{});
         else
-            store ? go(k_mp_layer<false, true>, nullptr, nullptr) : go(k_mp_layer<false, false>, nullptr, nullptr);
+            pick(std::false_type{});
         OASIS_TRY_LAUNCH();
     }
     if (delta && store) {
