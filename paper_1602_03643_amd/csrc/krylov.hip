@@ -597,15 +597,13 @@ __global__ __launch_bounds__(BS) void k_cg_sr_start(int n, EllCols cols,
     write_partials<kSr>(acc, partOut, lds);
 }
 
-// Grid cap of the single-reduction kernels (env OASIS_SR_GRID): every block
-// of an iteration reads all partials of the previous one, kSr per block.
+// Grid cap of the single-reduction kernels (env OASIS_SR_GRID, read at the
+// start of every solve): every block of an iteration reads all partials of
+// the previous one, kSr per block.
 int sr_grid_cap() {
-    static int g = [] {
-        const char *e = std::getenv("OASIS_SR_GRID");
-        const int v = e ? std::atoi(e) : kMaxPartials / 2;
-        return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
-    }();
-    return g;
+    const char *e = std::getenv("OASIS_SR_GRID");
+    const int v = e ? std::atoi(e) : kMaxPartials / 2;
+    return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
 }
 
 // Single-reduction CG on the ELL copy in rec / the workspace partials.

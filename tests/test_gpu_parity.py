@@ -295,6 +295,47 @@ def test_pcg_mixed_meets_fp64_tolerance(oa, prob):
     assert abs(out["iters"] - rr.iters) <= 0.15 * rr.iters + 5, (out["iters"], rr.iters)
 
 
+def test_pcg_mixed_several_rows_per_lane_group(oa):
+    """The FP32 CG iteration walks its rows in a two-stage software pipeline,
+    unrolled twice, with the next row's fetch clamped into the lane group's
+    range.  At the default grid the test meshes give each lane group at most
+    one row per launch; a 64-block grid (env OASIS_SR_GRID, read per solve)
+    gives the 33x33x25 channel's groups 3 or 4 rows each, so both halves of
+    the unrolled loop and the clamped fetch past a range's end run.  The
+    solve must meet the FP64 tolerance against the oracle as at the default
+    grid, with the same iteration count up to the partial-sum order."""
+    import os
+    prob = synth.channel_flow((33, 33, 25), seed=1)
+    say("pcg mixed, 64-block grid", prob.name)
+    S, st, A, b = _tent_problem(prob)
+    dm, pat, _ = device_mesh(prob.mesh)
+    Kp = pat.with_values(T(p1.on_pattern(S.K, csr_host(pat))))
+    rng = np.random.default_rng(12)
+    bphi = rng.normal(size=prob.mesh.n_dof)
+    bphi -= bphi.mean()
+    ref = krylov.pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8)
+    outs, xs = [], []
+    for grid in (None, "64"):
+        old = os.environ.pop("OASIS_SR_GRID", None)
+        if grid:
+            os.environ["OASIS_SR_GRID"] = grid
+        try:
+            x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+            outs.append(oa.pcg(Kp, T(bphi), x, rtol=1e-8, precision=oa.F32, nullspace_const=True))
+            xs.append(x.cpu().numpy())
+        finally:
+            os.environ.pop("OASIS_SR_GRID", None)
+            if old is not None:
+                os.environ["OASIS_SR_GRID"] = old
+    xr = ref.x - ref.x.mean()
+    for out, xg in zip(outs, xs):
+        true = np.linalg.norm(bphi - S.K @ xg) / np.linalg.norm(bphi)
+        assert out["rc"] == 0 and true <= 1.0001e-8, (out, true)
+        assert rel(xg - xg.mean(), xr) < 1e-5
+    assert abs(outs[0]["iters"] - outs[1]["iters"]) <= max(3, outs[0]["iters"] // 50), \
+        (outs[0]["iters"], outs[1]["iters"])
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_pcg_poll_schedule_does_not_change_the_solve(oa, precision):
     """The host polls the device-side convergence state between chunks of
