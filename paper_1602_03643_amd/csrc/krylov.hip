@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string_view>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -291,8 +292,12 @@ __global__ __launch_bounds__(BS) void k_cg_p2(int n, RP<T> *__restrict__ nxt,
 // Iteration part 1 on the ELL copy of the matrix: the same computation as
 // k_cg_p1.  L lanes share a row (each holds E = kEll / L entries, fetched
 // with 8-byte offset and 16-byte value loads), so that a lane has E pair
-// gathers in flight.
-template <typename T, int BS, int L>
+// gathers in flight.  The row loop is straight-line code as in k_cg_sr:
+// every lane fetches the next row's offsets, values and own-row state from
+// clamped row indices, the pattern id one row further ahead, over two
+// register sets; DICT fixes the column storage and BZ (beta = 0) the
+// direction update at compile time.
+template <typename T, int BS, int L, bool DICT>
 __global__ __launch_bounds__(BS) void k_cg_p1_ell(int n, EllCols cols,
                                                   const T *__restrict__ eval,
                                                   const RP<T> *__restrict__ cur,
@@ -332,35 +337,62 @@ __global__ __launch_bounds__(BS) void k_cg_p1_ell(int n, EllCols cols,
     double acc[2] = {0.0, 0.0};
     const int lane = threadIdx.x & (L - 1);
     const RowRange<L, BS> range(n);
-    // software-pipelined: the next row's offsets and values are fetched
-    // while this row's gathers are in flight
     long long row = range.first + range.gid;
-    int c[E];
-    T w[E];
-    if (row < range.last) ell_fetch<T, E>(row, lane, n, cols, eval, c, w);
-    for (; row < range.last; row += range.ngroups) {
-        T a = T(0);
-        if (beta_zero) {
+    if (row < range.last) {
+        const long long top = range.last - 1;
+        auto clamp = [top](long long r) { return r < top ? r : top; };
+        const T *vsrc = vnull ? vnull : eval;   // read unused without a null vector
+        struct Stage {
+            int c[E];
+            T w[E];
+            RP<T> me;
+            T vr;
+        };
+        auto fetch = [&](Stage &S, long long r, int key) {
+            ell_fetch_key<DICT, T, E>(r, key, lane, n, cols, eval, S.c, S.w);
+            S.me = cur[r];
+            S.vr = vsrc[r];
+        };
+        auto run = [&](auto bzc) {
+            constexpr bool BZ = decltype(bzc)::value;
+            auto step = [&](const Stage &S, Stage &N, int kin, int &kout) {
+                RP<T> gv[E];
 #pragma unroll
-            for (int k = 0; k < E; ++k) a += w[k] * cur[c[k]].r;
-        } else {
-            RP<T> gv[E];
+                for (int k = 0; k < E; ++k) gv[k] = cur[S.c[k]];
+                T wv[E];
 #pragma unroll
-            for (int k = 0; k < E; ++k) gv[k] = cur[c[k]];
+                for (int k = 0; k < E; ++k) wv[k] = S.w[k];
+                fetch(N, clamp(row + range.ngroups), kin);
+                kout = ell_key<DICT>(cols, clamp(row + 2 * range.ngroups));
+                T a = T(0);
 #pragma unroll
-            for (int k = 0; k < E; ++k) a += w[k] * (gv[k].r + bt * gv[k].p);
-        }
-        const long long nrow = row + range.ngroups;
-        if (nrow < range.last) ell_fetch<T, E>(nrow, lane, n, cols, eval, c, w);
-        a = group_sum<L>(a);
-        if (lane == 0) {
-            const RP<T> me = cur[row];
-            const T pn = beta_zero ? me.r : me.r + bt * me.p;
-            nxt[row] = RP<T>{me.r, pn};
-            q[row] = a;
-            acc[0] += static_cast<double>(pn) * static_cast<double>(a);
-            if (vnull) acc[1] += static_cast<double>(vnull[row]) * static_cast<double>(a);
-        }
+                for (int k = 0; k < E; ++k) a += wv[k] * (BZ ? gv[k].r : gv[k].r + bt * gv[k].p);
+                a = group_sum<L>(a);
+                if (lane == 0) {
+                    const T pn = BZ ? S.me.r : S.me.r + bt * S.me.p;
+                    nxt[row] = RP<T>{S.me.r, pn};
+                    q[row] = a;
+                    acc[0] += static_cast<double>(pn) * static_cast<double>(a);
+                    if (vnull) acc[1] += static_cast<double>(S.vr) * static_cast<double>(a);
+                }
+            };
+            Stage A, B;
+            int ka, kb;
+            fetch(A, row, ell_key<DICT>(cols, row));
+            ka = ell_key<DICT>(cols, clamp(row + range.ngroups));
+            for (;;) {
+                step(A, B, ka, kb);
+                row += range.ngroups;
+                if (row >= range.last) break;
+                step(B, A, kb, ka);
+                row += range.ngroups;
+                if (row >= range.last) break;
+            }
+        };
+        if (beta_zero)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
     }
     write_partials<2>(acc, partOut, lds);
 }
@@ -392,10 +424,11 @@ static int launch_p1_ell(hipStream_t s, int n, const EllCols &cols, const T *eva
                                it, beta_zero, vnull, partOut);
         return g;
     };
+    const bool dict = cols.pid != nullptr;
     switch (ell_shape()) {
-        case 41: return go(k_cg_p1_ell<T, BS, 4>, BS / 4);
-        case 11: return go(k_cg_p1_ell<T, BS, 1>, BS);
-        default: return go(k_cg_p1_ell<T, BS, 2>, BS / 2);
+        case 41: return dict ? go(k_cg_p1_ell<T, BS, 4, true>, BS / 4) : go(k_cg_p1_ell<T, BS, 4, false>, BS / 4);
+        case 11: return dict ? go(k_cg_p1_ell<T, BS, 1, true>, BS) : go(k_cg_p1_ell<T, BS, 1, false>, BS);
+        default: return dict ? go(k_cg_p1_ell<T, BS, 2, true>, BS / 2) : go(k_cg_p1_ell<T, BS, 2, false>, BS / 2);
     }
 }
 
