@@ -1392,36 +1392,66 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, const RW<T> *r
     double acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    mat_rows<T, NR, C>(
-        n, m,
-        [&](int, int c, T vv, bool ok, T(&a)[NR]) {
-            // all right-hand sides, active or not: branch-free, so that the
-            // gathers of one entry are issued together (finish discards the
-            // inactive ones)
+    // all right-hand sides, active or not: branch-free, so that the gathers
+    // of one entry are issued together (finish discards the inactive ones)
+    struct Own {
+        RW<T> me[NR];
+        T hk[NR];
+    };
+    auto fin = [&](int row, int lane, T(&a)[NR], const Own &o) {
+        if (lane != 0) return;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const RW<T> g = ru[(long long)c * NR + k];
-                const T t = vv * fmadd(beta[k], g.w, g.r);
-                a[k] += ok ? t : T(0);
-            }
-        },
-        [&](int row, int lane, T(&a)[NR]) {
-            if (lane != 0) return;
-            RW<T> me[NR];
-            T hk[NR];
+        for (int k = 0; k < NR; ++k) {
+            if (!((active >> k) & 1)) continue;
+            p.p[k][row] = fmadd(beta[k], o.me[k].w, o.me[k].r);
+            rv[(long long)row * NR + k] = RW<T>{o.me[k].r, a[k]};
+            acc[k] += static_cast<double>(o.hk[k]) * static_cast<double>(a[k]);
+        }
+    };
+    auto own = [&](long long row) {
+        Own o;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                me[k] = ru[(long long)row * NR + k];
-                hk[k] = rhat.p[k][row];
-            }
+        for (int k = 0; k < NR; ++k) {
+            o.me[k] = ru[row * NR + k];
+            o.hk[k] = rhat.p[k][row];
+        }
+        return o;
+    };
+    if (m.eval) {
+        // ELL copy: the straight-line row loop with the own-row state prefetched
+        struct G {
+            RW<T> g[NR];
+        };
+        auto load = [&](int c) {
+            G x;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (!((active >> k) & 1)) continue;
-                p.p[k][row] = fmadd(beta[k], me[k].w, me[k].r);
-                rv[(long long)row * NR + k] = RW<T>{me[k].r, a[k]};
-                acc[k] += static_cast<double>(hk[k]) * static_cast<double>(a[k]);
-            }
-        });
+            for (int k = 0; k < NR; ++k) x.g[k] = ru[(long long)c * NR + k];
+            return x;
+        };
+        auto add = [&](const G &g, T vv, T(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) a[k] += vv * fmadd(beta[k], g.g[k].w, g.g[k].r);
+        };
+        if (m.cols.pid)
+            ell_rows_pipe<T, NR, 2, true, G, Own>(n, m.cols, m.eval, load, add, own, fin);
+        else
+            ell_rows_pipe<T, NR, 2, false, G, Own>(n, m.cols, m.eval, load, add, own, fin);
+    } else {
+        csr_rows<T, NR, C>(
+            n, m.rp, m.ci, m.val,
+            [&](int, int c, T vv, bool ok, T(&a)[NR]) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const RW<T> g = ru[(long long)c * NR + k];
+                    const T t = vv * fmadd(beta[k], g.w, g.r);
+                    a[k] += ok ? t : T(0);
+                }
+            },
+            [&](int row, int lane, T(&a)[NR]) {
+                if (lane != 0) return;
+                fin(row, lane, a, own(row));
+            });
+    }
     write_partials<NR>(acc, partOut, lds);
 }
 
@@ -1469,35 +1499,67 @@ __global__ __launch_bounds__(kBlock) void k_bi_2(int n, Mat<T> m, const T *__res
     double acc[3 * NR];
 #pragma unroll
     for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
-    mat_rows<T, NR, C>(
-        n, m,
-        [&](int, int c, T w, bool ok, T(&a)[NR]) {
-            // branch-free over the right-hand sides (see k_bi_1)
+    // branch-free over the right-hand sides (see k_bi_1)
+    struct Own {
+        RW<T> mv[NR];
+        T w;
+    };
+    auto fin = [&](int row, int lane, T(&a)[NR], const Own &o) {
+        if (lane != 0) return;
+        const double wd = o.w;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const RW<T> g = rv[(long long)c * NR + k];
-                const T tk = w * fmsub(g.r, al[k], g.w);
-                a[k] += ok ? tk : T(0);
-            }
-        },
-        [&](int row, int lane, T(&a)[NR]) {
-            if (lane != 0) return;
-            const double wd = wgt[row];
-            RW<T> mv[NR];
+        for (int k = 0; k < NR; ++k) {
+            if (!((active >> k) & 1)) continue;
+            const RW<T> me = o.mv[k];
+            const T sn = fmsub(me.r, al[k], me.w);
+            t.p[k][row] = a[k];
+            const double sd = sn, td = a[k];
+            acc[3 * k + 0] += td * sd;
+            acc[3 * k + 1] += td * td;
+            acc[3 * k + 2] += wd * sd * sd;
+        }
+    };
+    auto own = [&](long long row) {
+        Own o;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) mv[k] = rv[(long long)row * NR + k];
+        for (int k = 0; k < NR; ++k) o.mv[k] = rv[row * NR + k];
+        o.w = wgt[row];
+        return o;
+    };
+    if (m.eval) {
+        struct G {
+            RW<T> g[NR];
+        };
+        auto load = [&](int c) {
+            G x;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (!((active >> k) & 1)) continue;
-                const RW<T> me = mv[k];
-                const T sn = fmsub(me.r, al[k], me.w);
-                t.p[k][row] = a[k];
-                const double sd = sn, td = a[k];
-                acc[3 * k + 0] += td * sd;
-                acc[3 * k + 1] += td * td;
-                acc[3 * k + 2] += wd * sd * sd;
-            }
-        });
+            for (int k = 0; k < NR; ++k) x.g[k] = rv[(long long)c * NR + k];
+            return x;
+        };
+        auto add = [&](const G &g, T w, T(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) a[k] += w * fmsub(g.g[k].r, al[k], g.g[k].w);
+        };
+        if (m.cols.pid)
+            ell_rows_pipe<T, NR, 2, true, G, Own>(n, m.cols, m.eval, load, add, own, fin);
+        else
+            ell_rows_pipe<T, NR, 2, false, G, Own>(n, m.cols, m.eval, load, add, own, fin);
+    } else {
+        csr_rows<T, NR, C>(
+            n, m.rp, m.ci, m.val,
+            [&](int, int c, T w, bool ok, T(&a)[NR]) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const RW<T> g = rv[(long long)c * NR + k];
+                    const T tk = w * fmsub(g.r, al[k], g.w);
+                    a[k] += ok ? tk : T(0);
+                }
+            },
+            [&](int row, int lane, T(&a)[NR]) {
+                if (lane != 0) return;
+                fin(row, lane, a, own(row));
+            });
+    }
     write_partials<3 * NR>(acc, partOut, lds);
 }
 

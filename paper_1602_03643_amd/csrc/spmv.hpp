@@ -247,6 +247,68 @@ __device__ __forceinline__ void ell_rows(int n, const EllCols &cols, const TA *_
     }
 }
 
+// ell_rows as straight-line code (the row loop of the CG iteration
+// kernels): while a row's operand gathers are in flight, every lane fetches
+// the next row's offsets, values and own(row), the inputs of the row's
+// finish step, from row indices clamped into the lane group's range; the
+// pattern id comes one row further ahead, and the loop alternates two
+// register sets so that no loaded value is copied across the back edge.
+// The gather is split in two: load(c) -> G reads the operand(s) of column c
+// and add(g, v, acc) adds one entry's contribution (padding has value 0);
+// finish(row, lane, acc, o) runs on all L lanes with o = own(row).
+template <typename TA, int NR, int L, bool DICT, class G, class O, class Load, class Add, class Own, class Finish>
+__device__ __forceinline__ void ell_rows_pipe(int n, const EllCols &cols, const TA *__restrict__ eval, Load load,
+                                              Add add, Own own, Finish finish) {
+    constexpr int E = kEll / L;
+    static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
+    const int lane = threadIdx.x & (L - 1);
+    const RowRange<L> rr(n);
+    long long row = rr.first + rr.gid;
+    if (row >= rr.last) return;
+    const long long top = rr.last - 1;
+    auto clamp = [top](long long r) { return r < top ? r : top; };
+    struct Stage {
+        int c[E];
+        TA w[E];
+        O o;
+    };
+    auto fetch = [&](Stage &S, long long r, int key) {
+        ell_fetch_key<DICT, TA, E>(r, key, lane, n, cols, eval, S.c, S.w);
+        S.o = own(r);
+    };
+    auto step = [&](const Stage &S, Stage &N, int kin, int &kout) {
+        G g[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) g[k] = load(S.c[k]);
+        TA wv[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) wv[k] = S.w[k];
+        const O o = S.o;
+        fetch(N, clamp(row + rr.ngroups), kin);
+        kout = ell_key<DICT>(cols, clamp(row + 2 * rr.ngroups));
+        TA acc[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = TA(0);
+#pragma unroll
+        for (int k = 0; k < E; ++k) add(g[k], wv[k], acc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = group_sum<L>(acc[k]);
+        finish(static_cast<int>(row), lane, acc, o);
+    };
+    Stage A, B;
+    int ka, kb;
+    fetch(A, row, ell_key<DICT>(cols, row));
+    ka = ell_key<DICT>(cols, clamp(row + rr.ngroups));
+    for (;;) {
+        step(A, B, ka, kb);
+        row += rr.ngroups;
+        if (row >= rr.last) break;
+        step(B, A, kb, ka);
+        row += rr.ngroups;
+        if (row >= rr.last) break;
+    }
+}
+
 // The csr_rows contract for CSR values whose columns come from an ELL
 // copy's column storage (the offset dictionary or per-entry offsets): slot
 // k of row i is CSR entry rp[i] + k, so the values are read in CSR order
