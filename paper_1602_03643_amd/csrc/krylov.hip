@@ -54,13 +54,11 @@ bool ell_enabled() {
 // producer (up to 9 per block in BiCGStab), so fewer, fuller producer
 // blocks pay off: 1024 measured the velocity phase at 6.9 ms per step
 // against 8.3 ms with 2048 and 8.0 ms with 512 blocks (1.6M rows).
+// env OASIS_PARTIALS, read on every call (grids are sized once per solve).
 int partial_cap() {
-    static int cap = [] {
-        const char *e = std::getenv("OASIS_PARTIALS");
-        const int v = e ? std::atoi(e) : kMaxPartials / 2;
-        return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
-    }();
-    return cap;
+    const char *e = std::getenv("OASIS_PARTIALS");
+    const int v = e ? std::atoi(e) : kMaxPartials / 2;
+    return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
 }
 
 // A flag written by an earlier kernel (or by block 0 of this one when it

@@ -336,6 +336,57 @@ def test_pcg_mixed_several_rows_per_lane_group(oa):
         (outs[0]["iters"], outs[1]["iters"])
 
 
+def test_products_several_rows_per_lane_group(oa):
+    """BiCGStab (both precisions) and the FP64 PCG run their ELL products in
+    the same straight-line row loops as the FP32 CG iteration.  With the
+    producer grid cut to 64 blocks (env OASIS_PARTIALS, read per solve) the
+    33x33x25 channel gives each lane group 3 or 4 rows, so both halves of
+    the unrolled loops and the clamped fetches run; the solves must meet
+    their tolerances in the oracle's own residual and agree with the solves
+    at the default grid."""
+    import os
+    prob = synth.channel_flow((33, 33, 25), seed=3)
+    say("products, 64-block grid", prob.name)
+    S, st, A, b = _tent_problem(prob)
+    dm, pat, _ = device_mesh(prob.mesh)
+    Ap = pat.with_values(T(p1.on_pattern(A, csr_host(pat))))
+    Kp = pat.with_values(T(p1.on_pattern(S.K, csr_host(pat))))
+    rng = np.random.default_rng(14)
+    bphi = rng.normal(size=prob.mesh.n_dof)
+    bphi -= bphi.mean()
+
+    def solves():
+        res = []
+        for prec in (oa.F64, oa.F32):
+            x = T(st.U1)
+            out = oa.bicgstab(Ap, T(b), x, rtol=1e-10, precision=prec)
+            res.append((out, x.cpu().numpy()))
+        x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+        out = oa.pcg(Kp, T(bphi), x, rtol=1e-10, nullspace_const=True)
+        res.append((out, x.cpu().numpy()))
+        return res
+
+    old = os.environ.pop("OASIS_PARTIALS", None)
+    try:
+        os.environ["OASIS_PARTIALS"] = "64"
+        cut = solves()
+        os.environ.pop("OASIS_PARTIALS")
+        ref = solves()
+    finally:
+        os.environ.pop("OASIS_PARTIALS", None)
+        if old is not None:
+            os.environ["OASIS_PARTIALS"] = old
+    for (out, x), (rout, rx) in zip(cut[:2], ref[:2]):
+        for k in range(3):
+            true = np.linalg.norm(b[k] - A @ x[k]) / np.linalg.norm(b[k])
+            assert out[k]["status"] == 0 and true <= 1.0001e-10, (k, out[k], true)
+            assert rel(x[k], rx[k]) < 1e-7
+    out, x = cut[2]
+    true = np.linalg.norm(bphi - S.K @ x) / np.linalg.norm(bphi)
+    assert out["rc"] == 0 and true <= 1.0001e-10, (out, true)
+    assert abs(out["iters"] - ref[2][0]["iters"]) <= max(3, out["iters"] // 50)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_pcg_poll_schedule_does_not_change_the_solve(oa, precision):
     """The host polls the device-side convergence state between chunks of
