@@ -1275,43 +1275,81 @@ __global__ __launch_bounds__(kBlock) void k_bi_resid(int n, Mat<T> m,
     double acc[3 * NR];
 #pragma unroll
     for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
-    mat_rows<T, NR, C>(
-        n, m,
-        [&](int, int c, T v, bool ok, T(&a)[NR]) {
-            // every right-hand side is gathered (no branch per k, so that the
-            // loads of all of them are in flight together); finish uses
-            // only those in mask_res
+    // every right-hand side is gathered (no branch per k, so that the loads
+    // of all of them are in flight together); finish uses only those in
+    // mask_res.  The row's own inputs are read for every k as well.
+    struct Own {
+        T w, b[NR], r[NR], h[NR];
+    };
+    auto own = [&](long long row) {
+        Own o;
+        o.w = wgt[row];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const T t = v * xsrc.p[k][c];
-                a[k] += ok ? t : T(0);
-            }
-        },
-        [&](int row, int lane, T(&a)[NR]) {
-            if (lane != 0) return;
-            const double wd = wgt[row];
+        for (int k = 0; k < NR; ++k) {
+            o.b[k] = b.p[k][row];
+            o.r[k] = ru[row * NR + k].r;
+            o.h[k] = rhat.p[k][row];
+        }
+        return o;
+    };
+    auto fin = [&](int row, int lane, T(&a)[NR], const Own &o) {
+        if (lane != 0) return;
+        const double wd = o.w;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                T rk;
-                if ((mask_res >> k) & 1) {
-                    rk = b.p[k][row] - a[k];
-                    ru[(long long)row * NR + k].r = rk;
-                } else {
-                    rk = ru[(long long)row * NR + k].r;
-                }
-                T hk;
-                if ((mask_rhat >> k) & 1) {
-                    rhat.p[k][row] = rk;
-                    hk = rk;
-                } else {
-                    hk = rhat.p[k][row];
-                }
-                const double rd = rk, bd = b.p[k][row];
-                acc[3 * k + 0] += static_cast<double>(hk) * rd;
-                acc[3 * k + 1] += wd * rd * rd;
-                acc[3 * k + 2] += wd * bd * bd;
+        for (int k = 0; k < NR; ++k) {
+            T rk;
+            if ((mask_res >> k) & 1) {
+                rk = o.b[k] - a[k];
+                ru[(long long)row * NR + k].r = rk;
+            } else {
+                rk = o.r[k];
             }
-        });
+            T hk;
+            if ((mask_rhat >> k) & 1) {
+                rhat.p[k][row] = rk;
+                hk = rk;
+            } else {
+                hk = o.h[k];
+            }
+            const double rd = rk, bd = o.b[k];
+            acc[3 * k + 0] += static_cast<double>(hk) * rd;
+            acc[3 * k + 1] += wd * rd * rd;
+            acc[3 * k + 2] += wd * bd * bd;
+        }
+    };
+    if (m.eval) {
+        struct G {
+            T x[NR];
+        };
+        auto load = [&](int c) {
+            G g;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) g.x[k] = xsrc.p[k][c];
+            return g;
+        };
+        auto add = [&](const G &g, T v, T(&a)[NR]) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) a[k] += v * g.x[k];
+        };
+        if (m.cols.pid)
+            ell_rows_pipe<T, NR, 2, true, G, Own>(n, m.cols, m.eval, load, add, own, fin);
+        else
+            ell_rows_pipe<T, NR, 2, false, G, Own>(n, m.cols, m.eval, load, add, own, fin);
+    } else {
+        csr_rows<T, NR, C>(
+            n, m.rp, m.ci, m.val,
+            [&](int, int c, T v, bool ok, T(&a)[NR]) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const T t = v * xsrc.p[k][c];
+                    a[k] += ok ? t : T(0);
+                }
+            },
+            [&](int row, int lane, T(&a)[NR]) {
+                if (lane != 0) return;
+                fin(row, lane, a, own(row));
+            });
+    }
     write_partials<3 * NR>(acc, part, lds);
 }
 
