@@ -336,6 +336,43 @@ def test_pcg_mixed_several_rows_per_lane_group(oa):
         (outs[0]["iters"], outs[1]["iters"])
 
 
+def test_pcg_mixed_without_null_vector(oa):
+    """FP32 CG iterations on an SPD matrix without a null space (K + M): the
+    single-reduction kernel then reads the Jacobi norm weights instead of
+    forming them from a null vector, and projects nothing.  At the default
+    grid and at a 64-block grid (3-4 rows per lane group) the solve must meet
+    the FP64 tolerance in the oracle's residual and match the oracle's FP64
+    solution."""
+    import os
+    prob = synth.channel_flow((33, 33, 25), seed=4)
+    say("pcg mixed, no null vector", prob.name)
+    S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
+    Am = (S.K + S.M).tocsr()
+    dm, pat, _ = device_mesh(prob.mesh)
+    Ap = pat.with_values(T(p1.on_pattern(Am, csr_host(pat))))
+    rng = np.random.default_rng(16)
+    bv = rng.normal(size=prob.mesh.n_dof)
+    ref = krylov.pcg(Am, bv, np.zeros_like(bv), rtol=1e-8)
+    iters = []
+    for grid in (None, "64"):
+        old = os.environ.pop("OASIS_SR_GRID", None)
+        if grid:
+            os.environ["OASIS_SR_GRID"] = grid
+        try:
+            x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+            out = oa.pcg(Ap, T(bv), x, rtol=1e-8, precision=oa.F32)
+        finally:
+            os.environ.pop("OASIS_SR_GRID", None)
+            if old is not None:
+                os.environ["OASIS_SR_GRID"] = old
+        xg = x.cpu().numpy()
+        true = np.linalg.norm(bv - Am @ xg) / np.linalg.norm(bv)
+        assert out["rc"] == 0 and true <= 1.0001e-8, (grid, out, true)
+        assert rel(xg, ref.x) < 1e-6
+        iters.append(out["iters"])
+    assert abs(iters[0] - iters[1]) <= max(3, iters[0] // 50), iters
+
+
 def test_products_several_rows_per_lane_group(oa):
     """BiCGStab (both precisions) and the FP64 PCG run their ELL products in
     the same straight-line row loops as the FP32 CG iteration.  With the
