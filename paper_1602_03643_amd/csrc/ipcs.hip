@@ -347,8 +347,11 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                 for (int c = 0; c < D; ++c) gw += e.g[jl][c] * w[c];
                 const double v = fac * gw;
                 const int target = dd[jl];
+                // a[q] + v where the column matches, as an FMA with a 0/1
+                // factor (one select per slot instead of a 64-bit select of
+                // v and an add; the same sums)
 #pragma unroll
-                for (int q = 0; q < MAXC; ++q) a[q] += (col[q] == target) ? v : 0.0;
+                for (int q = 0; q < MAXC; ++q) a[q] = __fma_rn((col[q] == target) ? 1.0 : 0.0, v, a[q]);
             }
         }
 #pragma unroll
