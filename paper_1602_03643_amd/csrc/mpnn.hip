@@ -320,14 +320,17 @@ __device__ __forceinline__ void agg8w(int i, int f0, const int *__restrict__ rp,
         uint4 q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) q[u] = *reinterpret_cast<const uint4 *>(V + (size_t)j[u] * kHid + f0);
+        // the diagonal and the clamped tail get weight 0 instead of a branch:
+        // adding 0 * (a finite feature) to a sum that started at +0 leaves it
+        // unchanged, so the sums are those of agg8
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (c0 + u >= len || j[u] == i) continue;
+            const float wu = (c0 + u >= len || j[u] == i) ? 0.f : w[u];
             const unsigned qq[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                acc[2 * k] += w[u] * bf2f(static_cast<unsigned short>(qq[k] & 0xffffu));
-                acc[2 * k + 1] += w[u] * bf2f(static_cast<unsigned short>(qq[k] >> 16));
+                acc[2 * k] += wu * bf2f(static_cast<unsigned short>(qq[k] & 0xffffu));
+                acc[2 * k + 1] += wu * bf2f(static_cast<unsigned short>(qq[k] >> 16));
             }
         }
     }
