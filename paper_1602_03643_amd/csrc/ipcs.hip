@@ -311,32 +311,42 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
             col[q] = q < len ? ci[s + q] : -1;
             a[q] = q < len ? B[s + q] : 0.0;
         }
-        for (int t = iptr[i]; t < iptr[i + 1]; ++t) {
-            const int code = inc[t];
-            const int cell = code / NV, la = code - cell * NV;
+        // cells two at a time: both cells' loads (incidence, vertices, dofs,
+        // coordinates, u_bar) are issued before either is added, so that
+        // their dependent chains overlap; the second of an odd tail is a
+        // clamped copy that is not added.  Cells are added in ascending
+        // order, as one at a time.
+        struct Cell {
             double x[NV][D], ub[NV][D];
-            int dd[NV];
+            int dd[NV], la;
+        };
+        auto load = [&](int t, Cell &C) {
+            const int code = inc[t];
+            const int cell = code / NV;
+            C.la = code - cell * NV;
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 const int v = cells[(long long)cell * NV + k];
-                dd[k] = v2d[v];
+                C.dd[k] = v2d[v];
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
-                    x[k][c] = X[(long long)v * D + c];
-                    ub[k][c] = ubar[(long long)dd[k] * UW + c];
+                    C.x[k][c] = X[(long long)v * D + c];
+                    C.ub[k][c] = ubar[(long long)C.dd[k] * UW + c];
                 }
             }
+        };
+        auto add = [&](const Cell &C) {
             Elem<D> e;
-            p1_element<D>(x, e);
+            p1_element<D>(C.x, e);
             double w[D];   // S + u_bar at the row's local vertex
 #pragma unroll
             for (int c = 0; c < D; ++c) {
                 double S = 0.0;
 #pragma unroll
-                for (int k = 0; k < NV; ++k) S += ub[k][c];
-                double ua = ub[0][c];
+                for (int k = 0; k < NV; ++k) S += C.ub[k][c];
+                double ua = C.ub[0][c];
 #pragma unroll
-                for (int k = 1; k < NV; ++k) ua = (la == k) ? ub[k][c] : ua;
+                for (int k = 1; k < NV; ++k) ua = (C.la == k) ? C.ub[k][c] : ua;
                 w[c] = S + ua;
             }
             const double fac = e.vol * mfac;
@@ -346,13 +356,22 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
 #pragma unroll
                 for (int c = 0; c < D; ++c) gw += e.g[jl][c] * w[c];
                 const double v = fac * gw;
-                const int target = dd[jl];
+                const int target = C.dd[jl];
                 // a[q] + v where the column matches, as an FMA with a 0/1
                 // factor (one select per slot instead of a 64-bit select of
                 // v and an add; the same sums)
 #pragma unroll
                 for (int q = 0; q < MAXC; ++q) a[q] = __fma_rn((col[q] == target) ? 1.0 : 0.0, v, a[q]);
             }
+        };
+        const int t0 = iptr[i], t1 = iptr[i + 1];
+        for (int t = t0; t < t1; t += 2) {
+            const bool two = t + 1 < t1;
+            Cell c0, c1;
+            load(t, c0);
+            load(two ? t + 1 : t, c1);
+            add(c0);
+            if (two) add(c1);
         }
 #pragma unroll
         for (int q = 0; q < MAXC; ++q)
