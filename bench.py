@@ -20,7 +20,11 @@ the faster learned+FP32 variant (the configuration the metric names; its
 plain start is a solver option) when one is timed, else the fastest one;
 `speedup_vs_fp64` compares it with plain FP64 from phi_prev.
 
-One JSON line is printed; see the design doc for the fields.
+One JSON line is printed: the headline value and ms per step, the per-variant
+phase timings and iteration counts, `roofline` (the FP32 CG iteration kernel
+timed live over repeated launches against its algorithmic bytes, with the
+HBM traffic of the committed rocprofv3 counter summary when its sources
+match) and `cpu_baseline` (the FP64 oracle on a bounded sample).
 """
 from __future__ import annotations
 
