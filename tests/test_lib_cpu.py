@@ -126,7 +126,6 @@ def test_build_script_loads_without_the_package():
     package refuses to import because liboasis.so is not built yet: it loads
     the build script by path, and that script imports nothing from the
     package."""
-    import importlib.util
     import subprocess
     import sys
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
