@@ -165,3 +165,26 @@ def test_mpnn_training_reduces_loss():
         opt.step(P, mpnn.backward(P, c, d, target, W))
     l1 = mpnn.loss(mpnn.forward(P, X, W)[0], target)
     assert l1 < 0.5 * l0
+
+
+def test_adam_matches_torch_optim_adam():
+    """The oracle's Adam (Kingma & Ba, Algorithm 1: bias-corrected moments,
+    eps added to sqrt of the second moment) against torch.optim.Adam, an
+    implementation written independently of the oracle, over several steps
+    with gradients that change sign and scale."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(11)
+    P = {"a": rng.normal(size=(4, 3)), "b": rng.normal(size=5)}
+    lr, b1, b2, eps = 3e-2, 0.8, 0.95, 1e-3     # non-default values expose swapped roles
+    opt = mpnn.Adam({k: v.copy() for k, v in P.items()}, lr=lr, b1=b1, b2=b2, eps=eps)
+    tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.items()}
+    topt = torch.optim.Adam(list(tp.values()), lr=lr, betas=(b1, b2), eps=eps)
+    for step in range(5):
+        G = {k: rng.normal(size=v.shape) * 10.0 ** (step - 2) for k, v in P.items()}
+        P = opt.step(P, G)
+        topt.zero_grad()
+        for k, t in tp.items():
+            t.grad = torch.tensor(G[k], dtype=torch.float64)
+        topt.step()
+        for k in P:
+            np.testing.assert_allclose(P[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-14)
