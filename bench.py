@@ -274,15 +274,12 @@ def main():
     avg_ms, cnt = time_cg_kernel(oa, torch, handles[head], pat, prec, args.kernel_iters)
     # the ELL kernels run when every row has at most 16 entries (P1 on
     # Kuhn-split hexahedra: at most 15; the 16-bit column offsets fit the
-    # periodic channel numbering) unless OASIS_ELL=0; on the ELL copy the
-    # FP32 iteration is the single-reduction kernel unless OASIS_CG_SR=0
-    # (OASIS_CG_SR=1 selects it for FP64 values too)
-    ell = (os.environ.get("OASIS_ELL", "1") != "0"
-           and int((pat.row_ptr[1:] - pat.row_ptr[:-1]).max()) <= 16)
-    sr_mode = os.environ.get("OASIS_CG_SR", "")
+    # periodic channel numbering); on the ELL copy the FP32 iteration is the
+    # single-reduction kernel (the default tuning)
+    ell = int((pat.row_ptr[1:] - pat.row_ptr[:-1]).max()) <= 16
 
     def kernel_of(vb):
-        sr = ell and (sr_mode == "1" or (sr_mode != "0" and vb == 4))
+        sr = ell and vb == 4
         if sr:
             return "k_cg_sr<%s>" % ("double" if vb == 8 else "float"), True
         return "k_cg_p1%s<%s>" % ("_ell" if ell else "", "double" if vb == 8 else "float"), False

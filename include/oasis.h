@@ -162,6 +162,30 @@ int oasis_spmv(void *stream, const oasis_csr *A, const void *x, void *y, double 
 
 /* ---- Krylov solvers (Sec. 6.2: BiCGStab + Jacobi; CG for pressure) ------ */
 
+/* Storage and kernel-shape choices of the Krylov iterations.  An all-zero
+ * struct selects the measured defaults.  They change timings and, for
+ * `storage` = CSR or the CG form, the summation order; never the stopping
+ * test. */
+typedef struct {
+    int32_t storage;      /* OASIS_STORAGE_AUTO: products on a 16-slot ELL copy of the matrix
+                             with 16-bit column offsets, whose rows share a dictionary of offset
+                             lists when they have few distinct ones (else per-entry offsets);
+                             OASIS_STORAGE_ELL: the ELL copy with per-entry offsets always;
+                             OASIS_STORAGE_CSR: CSR products (no ELL copy is used) */
+    int32_t grid_cap;     /* most blocks of a kernel that writes per-block partial sums
+                             (0 = 1024; otherwise 64..2048) */
+    int32_t cg_form;      /* OASIS_CG_FORM_AUTO: one single-reduction pass per CG iteration with
+                             FP32 values, two kernels with FP64 values; OASIS_CG_FORM_TWO;
+                             OASIS_CG_FORM_SINGLE (both need the ELL copy) */
+} oasis_tuning;
+
+#define OASIS_STORAGE_AUTO 0
+#define OASIS_STORAGE_ELL 1
+#define OASIS_STORAGE_CSR 2
+#define OASIS_CG_FORM_AUTO 0
+#define OASIS_CG_FORM_TWO 1
+#define OASIS_CG_FORM_SINGLE 2
+
 typedef struct {
     double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) */
     int32_t maxit;        /* total (inner) iteration cap */
@@ -174,6 +198,7 @@ typedef struct {
     int32_t max_outer;    /* F32 mode BiCGStab: cap on refinement steps (0 = 50) */
     int32_t check_every;  /* iterations launched between host convergence polls (0 = auto) */
     int32_t flags;        /* OASIS_KRYLOV_TIME, OASIS_KRYLOV_NULLSPACE_CONST */
+    oasis_tuning tuning;
 } oasis_krylov_opts;
 
 /* Kernel timing.  oasis_pcg: when the solve stops at maxit, its last
@@ -245,6 +270,9 @@ typedef struct {
     int32_t pressure_start;   /* plain start of the pressure-correction solve (the paper does
                                  not fix it): OASIS_PSTART_PREV (phi_prev, default) or
                                  OASIS_PSTART_ZERO (phi_0 = 0: solving for p from p*) */
+    double pressure_delta;    /* F32 mode: the pressure CG replaces its FP32 residual by the FP64
+                                 one each time the former fell by this factor (0 = 0.03) */
+    oasis_tuning tuning;      /* Krylov storage and kernel shapes of the step's solves */
 } oasis_ipcs_params;
 
 #define OASIS_ASSEMBLE_ROWS 0

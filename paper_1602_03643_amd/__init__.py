@@ -9,6 +9,7 @@ from . import _lib
 from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUNSUPPORTED, F32, F64,
                    FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, PSTART_PREV,
                    PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS,
+                   STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR, CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE,
                    OasisError)
 
 _lib.load()
@@ -20,4 +21,5 @@ __all__ = ["IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bicgstab",
            "colorize", "p1_pattern", "pcg", "rcm", "relabel", "spmv", "OasisError",
            "OK", "EINVAL", "EHIP", "ENOTCONV", "EBREAKDOWN", "ENAN", "EWORKSPACE", "EUNSUPPORTED", "F32", "F64",
            "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV", "PSTART_PREV",
-           "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS"]
+           "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS",
+           "STORAGE_AUTO", "STORAGE_ELL", "STORAGE_CSR", "CG_FORM_AUTO", "CG_FORM_TWO", "CG_FORM_SINGLE"]

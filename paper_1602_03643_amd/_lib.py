@@ -19,6 +19,8 @@ KRYLOV_NULLSPACE_CONST = 2
 ASSEMBLE_ROWS, ASSEMBLE_COLORS = 0, 1
 PSTART_PREV, PSTART_ZERO = 0, 1
 INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS = 100, 101, 102
+STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR = 0, 1, 2
+CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE = 0, 1, 2
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
 
@@ -41,9 +43,13 @@ class Mesh(C.Structure):
                 ("color_cells", vp)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("storage", i32), ("grid_cap", i32), ("cg_form", i32)]
+
+
 class KrylovOpts(C.Structure):
     _fields_ = [("rtol", f64), ("maxit", i32), ("precision", i32), ("inner_rtol", f64),
-                ("max_outer", i32), ("check_every", i32), ("flags", i32)]
+                ("max_outer", i32), ("check_every", i32), ("flags", i32), ("tuning", Tuning)]
 
 
 class KrylovStats(C.Structure):
@@ -54,7 +60,8 @@ class KrylovStats(C.Structure):
 class IpcsParams(C.Structure):
     _fields_ = [("dt", f64), ("nu", f64), ("f", f64 * 3), ("n_bc", i32), ("bc_dofs", vp),
                 ("rtol_u", f64), ("rtol_p", f64), ("maxit", i32), ("precision", i32),
-                ("inner_rtol", f64), ("assembly", i32), ("pressure_start", i32)]
+                ("inner_rtol", f64), ("assembly", i32), ("pressure_start", i32),
+                ("pressure_delta", f64), ("tuning", Tuning)]
 
 
 class State(C.Structure):

@@ -198,9 +198,14 @@ def spmv(A: DeviceCSR, x: torch.Tensor, y: torch.Tensor, alpha=1.0, beta=0.0, st
     return y
 
 
-def _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel):
+def _tuning(storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO):
+    return L.Tuning(int(storage), int(grid_cap), int(cg_form))
+
+
+def _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel, tuning=None):
     return L.KrylovOpts(float(rtol), int(maxit), int(precision), float(inner_rtol), int(max_outer),
-                        int(check_every), L.KRYLOV_TIME if time_kernel else 0)
+                        int(check_every), L.KRYLOV_TIME if time_kernel else 0,
+                        tuning if tuning is not None else _tuning())
 
 
 def _stats(st):
@@ -210,11 +215,13 @@ def _stats(st):
 
 
 def pcg(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=0.1, max_outer=50,
-        check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True, nullspace_const=False):
+        check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True, nullspace_const=False,
+        storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO):
     """F32 mode: FP32 iterations with reliable updates every `inner_rtol`
-    reduction of the residual."""
+    reduction of the residual.  storage, grid_cap, cg_form: oasis_tuning."""
     lib = _lib()
-    o = _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel)
+    o = _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel,
+              _tuning(storage, grid_cap, cg_form))
     if nullspace_const:
         o.flags |= L.KRYLOV_NULLSPACE_CONST
     nb = C.c_size_t()
@@ -231,11 +238,13 @@ def pcg(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=
 
 
 def bicgstab(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4, max_outer=50,
-             check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True):
+             check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True,
+             storage=L.STORAGE_AUTO, grid_cap=0):
     """b, x: [nrhs, n] (or [n]) float64 tensors; x holds x0 on entry."""
     lib = _lib()
     nrhs = 1 if b.dim() == 1 else b.shape[0]
-    o = _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel)
+    o = _opts(rtol, maxit, precision, inner_rtol, max_outer, check_every, time_kernel,
+              _tuning(storage, grid_cap))
     nb = C.c_size_t()
     L.check(lib.oasis_krylov_workspace_size(A.n, A.nnz, nrhs, C.byref(o), C.byref(nb)),
             "oasis_krylov_workspace_size")
@@ -257,7 +266,8 @@ class IPCS:
 
     def __init__(self, mesh: DeviceMesh, pattern: DeviceCSR, dt, nu, f, bc_dofs: torch.Tensor,
                  rtol_u=1e-8, rtol_p=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4,
-                 assembly=L.ASSEMBLE_ROWS, pressure_start=L.PSTART_PREV, stream=None):
+                 assembly=L.ASSEMBLE_ROWS, pressure_start=L.PSTART_PREV, pressure_delta=0.0,
+                 storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO, stream=None):
         lib = _lib()
         self.mesh, self.pattern = mesh, pattern
         self.dim, self.n = mesh.dim, mesh.n_dof
@@ -266,7 +276,8 @@ class IPCS:
         self.params = L.IpcsParams(float(dt), float(nu), fv, int(self.bc_dofs.numel()),
                                    self.bc_dofs.data_ptr() if self.bc_dofs.numel() else None,
                                    float(rtol_u), float(rtol_p), int(maxit), int(precision), float(inner_rtol),
-                                   int(assembly), int(pressure_start))
+                                   int(assembly), int(pressure_start), float(pressure_delta),
+                                   _tuning(storage, grid_cap, cg_form))
         cm = mesh.c()
         nb = C.c_size_t()
         L.check(lib.oasis_ipcs_workspace_size(C.byref(cm), pattern.nnz, C.byref(self.params), C.byref(nb)),

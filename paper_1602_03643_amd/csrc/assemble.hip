@@ -143,11 +143,8 @@ static int spmv_launch(hipStream_t s, const oasis_csr *A, const T *x, T *y, T al
     const T *val = static_cast<const T *>(A->val);
     return with_cfg([&](auto c) -> int {
         using C = decltype(c);
-        static const int cap = [] {
-            const char *e = std::getenv("OASIS_SPMV_GRIDCAP");
-            return e ? std::max(8, std::atoi(e)) : (1 << 20);
-        }();
-        const int g = grid_for(A->n, rows_per_block<C>(), cap);
+        // one lane group per row group: the grid is not capped (no partials)
+        const int g = grid_for(A->n, rows_per_block<C>(), 1 << 20);
         hipLaunchKernelGGL((k_spmv<T, C>), dim3(g), dim3(kBlock), 0, s, A->n, A->row_ptr, A->col_idx, val, x,
                            y, alpha, beta);
         OASIS_TRY_LAUNCH();

@@ -38,6 +38,33 @@ void set_hip_error(hipError_t e);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Per-call storage and kernel-shape choices (oasis_tuning, validated).
+struct Tuning {
+    int storage = OASIS_STORAGE_AUTO;
+    int grid_cap = kMaxPartials / 2;
+    int cg_form = OASIS_CG_FORM_AUTO;
+    bool ell() const { return storage != OASIS_STORAGE_CSR; }
+    bool dict() const { return storage == OASIS_STORAGE_AUTO; }
+    // single-reduction CG iterations for values of tbytes bytes
+    bool single(int tbytes) const {
+        return cg_form == OASIS_CG_FORM_SINGLE || (cg_form == OASIS_CG_FORM_AUTO && tbytes == 4);
+    }
+    // EINVAL on out-of-range fields; a null pointer gives the defaults
+    static int from(const oasis_tuning *t, Tuning *out) {
+        Tuning v;
+        if (t) {
+            if (t->storage < OASIS_STORAGE_AUTO || t->storage > OASIS_STORAGE_CSR) return OASIS_EINVAL;
+            if (t->cg_form < OASIS_CG_FORM_AUTO || t->cg_form > OASIS_CG_FORM_SINGLE) return OASIS_EINVAL;
+            if (t->grid_cap != 0 && (t->grid_cap < 64 || t->grid_cap > kMaxPartials)) return OASIS_EINVAL;
+            v.storage = t->storage;
+            v.cg_form = t->cg_form;
+            if (t->grid_cap) v.grid_cap = t->grid_cap;
+        }
+        *out = v;
+        return OASIS_OK;
+    }
+};
+
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 // Sequential sub-allocation of a caller workspace.  With base == nullptr it

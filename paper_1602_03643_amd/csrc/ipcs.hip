@@ -610,11 +610,14 @@ static void carve_ir(Carver &c, int n, int nr, IRBufs &ir) {
     ir.sums = c.take<double>(8);
 }
 
+// FP64 residuals of nr systems; the ELL copy's columns (when the tuning
+// allows the ELL storage) replace the int32 CSR columns.
 static int ir_outer_resid(hipStream_t s, int n, int nr, const int *rp, const int *ci,
-                          const double *val, const EllCols &cols, const double *w, P3 b, P3 x, IRBufs &ir,
-                          double *host_sums) {
+                          const double *val, const EllCols &ecols, const Tuning &tun, const double *w, P3 b, P3 x,
+                          IRBufs &ir, double *host_sums) {
     using L = Cfg8x2x1;
-    const int g = grid_for(n, rows_per_block<L>(), partial_cap());
+    const EllCols cols = tun.ell() ? ecols : EllCols{};
+    const int g = grid_for(n, rows_per_block<L>(), tun.grid_cap);
     if (nr == 1) {
         hipLaunchKernelGGL((k_ir_resid<1, L>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, cols, w, b, x,
                            ir.r32[0], ir.r32[1], ir.r32[2], ir.part);
@@ -659,7 +662,7 @@ static int ir_cg(hipStream_t s, int n, const int *rp, const int *ci, const doubl
     double hs[2];
     int total = 0;
     for (int outer = 0;; ++outer) {
-        OASIS_TRY(ir_outer_resid(s, n, 1, rp, ci, val, ell_enabled() ? cw.cols : EllCols{}, w, pb, px, ir, hs));
+        OASIS_TRY(ir_outer_resid(s, n, 1, rp, ci, val, cw.cols, cw.tun, w, pb, px, ir, hs));
         out.rel_res = hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : std::sqrt(hs[0]);
         if (!std::isfinite(hs[0])) {
             out.status = OASIS_ENAN;
@@ -710,7 +713,7 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
     bool done[3] = {false, false, false};
     double hs[6];
     for (int outer = 0;; ++outer) {
-        OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, ell_enabled() ? bw.cols : EllCols{}, w, pb, px, ir, hs));
+        OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, bw.cols, bw.tun, w, pb, px, ir, hs));
         int active[3], na = 0;
         for (int k = 0; k < nr; ++k) {
             if (done[k]) continue;
@@ -768,10 +771,11 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
 
 static double reliable_delta(double inner) { return (inner > 0.0 && inner < 1.0) ? inner : 0.1; }
 
-// Replacement factor of the step's mixed pressure solve.  On the 129x129x97
-// channel (zero start, 1e-8) 0.1 takes 8 replacements per solve, 0.03 takes
-// 6 at the same iteration count (0.6 ms less per step), 0.01 about 4 but 90
-// more iterations, 0.3 16.
+// Default replacement factor of the step's mixed pressure solve
+// (oasis_ipcs_params.pressure_delta = 0).  On the 129x129x97 channel (zero
+// start, 1e-8) 0.1 takes 8 replacements per solve, 0.03 takes 6 at the same
+// iteration count (0.6 ms less per step), 0.01 about 4 but 90 more
+// iterations, 0.3 16.
 constexpr double kPressureDelta = 0.03;
 
 static KOpts kopts(const oasis_krylov_opts *o) {
@@ -798,6 +802,7 @@ struct oasis_ipcs {
     int dim = 0, n = 0, nnz = 0;
     const int *rp = nullptr, *ci = nullptr;
     oasis_ipcs_params par;
+    Tuning tun;
     bool mixed = false;
     double *M = nullptr, *Ks = nullptr, *dP[3] = {nullptr, nullptr, nullptr}, *B = nullptr, *A = nullptr;
     float *A32 = nullptr, *Ks32 = nullptr;
@@ -838,17 +843,18 @@ struct oasis_ipcs {
 // offsets; *cols receives the columns the products use (none when the
 // offsets do not fit, and the products then run on CSR).  Synchronises.
 static int ell_setup(hipStream_t s, int n, const int *rp, const int *ci, const double *val, short *ecol,
-                     unsigned short *pid, short *ptab, double *eval, float *eval32, int *tmp, EllCols *cols,
-                     int *storage = nullptr) {
+                     unsigned short *pid, short *ptab, double *eval, float *eval32, int *tmp, const Tuning &tun,
+                     EllCols *cols, int *storage = nullptr) {
     bool fits = false;
     *cols = EllCols{};
     if (storage) *storage = 0;
+    if (!tun.ell()) return OASIS_OK;
     OASIS_TRY(csr_to_ell(s, n, rp, ci, val, ecol, eval, eval32, tmp, &fits));
     if (!fits) return OASIS_OK;
     int npat = 0;
-    OASIS_TRY(ell_dictionary(s, n, ecol, pid, ptab, &npat));
+    OASIS_TRY(ell_dictionary(s, n, ecol, pid, ptab, &npat, tun.dict()));
     *cols = ell_cols(ecol, pid, ptab, npat);
-    if (storage && ell_enabled()) *storage = npat > 0 ? npat : -1;
+    if (storage) *storage = npat > 0 ? npat : -1;
     return OASIS_OK;
 }
 
@@ -915,7 +921,9 @@ static int check_params(const oasis_ipcs_params *p) {
     if (!(p->rtol_u > 0) || !(p->rtol_p > 0)) return OASIS_EINVAL;
     if (p->precision != OASIS_F64 && p->precision != OASIS_F32) return OASIS_EINVAL;
     if (p->pressure_start != OASIS_PSTART_PREV && p->pressure_start != OASIS_PSTART_ZERO) return OASIS_EINVAL;
-    return OASIS_OK;
+    if (!(p->pressure_delta >= 0.0 && p->pressure_delta < 1.0)) return OASIS_EINVAL;
+    Tuning t;
+    return Tuning::from(&p->tuning, &t);
 }
 
 extern "C" int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz, const oasis_ipcs_params *par,
@@ -951,9 +959,12 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     h->rp = row_ptr;
     h->ci = col_idx;
     h->par = *par;
+    (void)Tuning::from(&par->tuning, &h->tun);
     h->mixed = par->precision == OASIS_F32;
     Carver c(ws, ws_bytes);
     carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, *h);
+    h->cg.tun = h->cg32.tun = h->tun;
+    h->bi.tun = h->bi32.tun = h->tun;
     auto fail = [&](int rc) {
         delete h;
         return rc;
@@ -997,7 +1008,7 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     // column offsets allow it (else the CSR product runs)
     {
         const int rc4 = ell_setup(s, n, row_ptr, col_idx, h->Ks, h->ecol, h->pid, h->ptab, h->eval, h->eval32,
-                                  h->flag + 24, &h->cols);
+                                  h->flag + 24, h->tun, &h->cols);
         if (rc4 != OASIS_OK) return fail(rc4);
         const bool fits = h->cols.any();
         h->ell = fits;
@@ -1201,7 +1212,7 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     // right Jacobi: the solves run on A D^{-1} in y = D x (ELL values for
     // the Krylov products when the pattern fits, else the FP32 CSR copy)
     {
-        const bool e = h->ell && ell_enabled();
+        const bool e = h->ell && h->tun.ell();
         hipLaunchKernelGGL(k_colscale, dim3(grid_for(n, kBlock / kEll, 1 << 20)), dim3(kBlock), 0, s, n, h->rp,
                            h->ci, h->dA, h->A, h->mixed && !e ? h->A32 : nullptr, e ? h->eA : nullptr,
                            e ? h->eA32 : nullptr);
@@ -1272,8 +1283,8 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     if (h->mixed)
         rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->vscale, h->bs,
                               h->xs,
-                              ko.rtol, kPressureDelta, ko.maxit, 0, false, h->cg32, h->xlo,
-                              h->rhi, sp);
+                              ko.rtol, h->par.pressure_delta > 0.0 ? h->par.pressure_delta : kPressureDelta,
+                              ko.maxit, 0, false, h->cg32, h->xlo, h->rhi, sp);
     else
         rc_p = cg_solve<double>(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, 0, false,
                                 h->cg, sp);
@@ -1389,7 +1400,8 @@ static void fill_stats(const SolveOut &o, int ell_storage, oasis_krylov_stats *s
 static int check_opts(const oasis_krylov_opts *o) {
     if (!o || !(o->rtol > 0) || o->maxit < 0) return OASIS_EINVAL;
     if (o->precision != OASIS_F64 && o->precision != OASIS_F32) return OASIS_EINVAL;
-    return OASIS_OK;
+    Tuning t;
+    return Tuning::from(&o->tuning, &t);
 }
 
 extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x, const oasis_krylov_opts *opt,
@@ -1403,6 +1415,10 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     KrylovWs k;
     carve_krylov(c, n, nnz, 1, mixed, k);
     if (!c.ok) return OASIS_EWORKSPACE;
+    Tuning tun;
+    (void)Tuning::from(&opt->tuning, &tun);
+    k.cg.tun = k.cg32.tun = tun;
+    k.bi.tun = k.bi32.tun = tun;
     hipStream_t s = as_stream(stream);
     const double *val = static_cast<const double *>(A->val);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
@@ -1421,7 +1437,7 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     {
         EllCols cols;
         OASIS_TRY(ell_setup(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.pid, k.ptab, k.eval, k.eval32,
-                            k.flag + 8, &cols, &ell_storage));
+                            k.flag + 8, tun, &cols, &ell_storage));
         if (cols.any() && mixed) {
             k.cg32.cols = cols;
             k.cg32.eval = k.eval32;
@@ -1467,6 +1483,10 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
     KrylovWs k;
     carve_krylov(c, n, nnz, nrhs, mixed, k);
     if (!c.ok) return OASIS_EWORKSPACE;
+    Tuning tun;
+    (void)Tuning::from(&opt->tuning, &tun);
+    k.cg.tun = k.cg32.tun = tun;
+    k.bi.tun = k.bi32.tun = tun;
     hipStream_t s = as_stream(stream);
     const double *val = static_cast<const double *>(A->val);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
@@ -1484,7 +1504,7 @@ extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, co
     {
         EllCols cols;
         OASIS_TRY(ell_setup(s, n, A->row_ptr, A->col_idx, k.val, k.ecol, k.pid, k.ptab, k.eval, k.eval32,
-                            k.flag + 8, &cols, &ell_storage));
+                            k.flag + 8, tun, &cols, &ell_storage));
         if (cols.any() && mixed) {
             k.bi32.cols = cols;
             k.bi32.eval = k.eval32;

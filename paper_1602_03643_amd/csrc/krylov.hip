@@ -33,33 +33,11 @@
 
 namespace oasis {
 
-int spmv_cfg() {
-    static int cfg = [] {
-        const char *e = std::getenv("OASIS_SPMV_CFG");
-        const int v = e ? std::atoi(e) : 1;
-        return (v >= 0 && v <= 4) ? v : 1;
-    }();
-    return cfg;
-}
-
-bool ell_enabled() {
-    static bool on = [] {
-        const char *e = std::getenv("OASIS_ELL");
-        return !(e && e[0] == '0');
-    }();
-    return on;
-}
-
-// Default producer grid cap: every consumer block reads all partials of its
-// producer (up to 9 per block in BiCGStab), so fewer, fuller producer
-// blocks pay off: 1024 measured the velocity phase at 6.9 ms per step
-// against 8.3 ms with 2048 and 8.0 ms with 512 blocks (1.6M rows).
-// env OASIS_PARTIALS, read on every call (grids are sized once per solve).
-int partial_cap() {
-    const char *e = std::getenv("OASIS_PARTIALS");
-    const int v = e ? std::atoi(e) : kMaxPartials / 2;
-    return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
-}
+// Producer grid cap (Tuning::grid_cap, default 1024): every consumer block
+// reads all partials of its producer (up to 9 per block in BiCGStab), so
+// fewer, fuller producer blocks pay off: 1024 measured the velocity phase
+// at 6.9 ms per step against 8.3 ms with 2048 and 8.0 ms with 512 blocks
+// (1.6M rows).
 
 // A flag written by an earlier kernel (or by block 0 of this one when it
 // decides to stop, a decision every block reaches identically), read once
@@ -395,39 +373,24 @@ __global__ __launch_bounds__(BS) void k_cg_p1_ell(int n, EllCols cols,
     write_partials<2>(acc, partOut, lds);
 }
 
-// ELL product shape, lanes per row (env OASIS_ELL_SHAPE: 41, 21, 11 for
-// 4, 2, 1 lanes; 2 measures fastest).
-int ell_shape() {
-    static int v = [] {
-        const char *e = std::getenv("OASIS_ELL_SHAPE");
-        const int x = e ? std::atoi(e) : 21;
-        return (x == 41 || x == 21 || x == 11) ? x : 21;
-    }();
-    return v;
-}
-
-// Launch the ELL product kernel in the selected shape; returns its grid.
+// Launch the ELL product kernel (two lanes per row, which measured faster
+// than one or four); returns its grid.  The producer grid cap `cap`: the
+// update kernel reads every block's partials, and 1024 blocks measured 59 us
+// per FP64 product against 66 us with 2048 and 65 / 80 us with 768 / 512
+// (1.6M rows).
 template <typename T, int BS>
-static int launch_p1_ell(hipStream_t s, int n, const EllCols &cols, const T *eval, const RP<T> *cur, RP<T> *nxt,
-                         T *q, const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
-                         const T *vnull, double *partOut, bool grid_only = false) {
-    // The producer grid cap: the update kernel reads every block's partials,
-    // and 1024 blocks measured 59 us per FP64 product against 66 us with
-    // 2048 and 65 / 80 us with 768 / 512 (1.6M rows).
-    const int cap = partial_cap() * kBlock / BS;
+static int launch_p1_ell(hipStream_t s, int cap, int n, const EllCols &cols, const T *eval, const RP<T> *cur,
+                         RP<T> *nxt, T *q, const double *partIn, int nIn, int stride, CGState *st, int it,
+                         int beta_zero, const T *vnull, double *partOut, bool grid_only = false) {
     auto go = [&](auto kern, int rows_per_blk) {
-        const int g = grid_for(n, rows_per_blk, cap);
+        const int g = grid_for(n, rows_per_blk, cap * kBlock / BS);
         if (!grid_only)
             hipLaunchKernelGGL(kern, dim3(g), dim3(BS), 0, s, n, cols, eval, cur, nxt, q, partIn, nIn, stride, st,
                                it, beta_zero, vnull, partOut);
         return g;
     };
     const bool dict = cols.pid != nullptr;
-    switch (ell_shape()) {
-        case 41: return dict ? go(k_cg_p1_ell<T, BS, 4, true>, BS / 4) : go(k_cg_p1_ell<T, BS, 4, false>, BS / 4);
-        case 11: return dict ? go(k_cg_p1_ell<T, BS, 1, true>, BS) : go(k_cg_p1_ell<T, BS, 1, false>, BS);
-        default: return dict ? go(k_cg_p1_ell<T, BS, 2, true>, BS / 2) : go(k_cg_p1_ell<T, BS, 2, false>, BS / 2);
-    }
+    return dict ? go(k_cg_p1_ell<T, BS, 2, true>, BS / 2) : go(k_cg_p1_ell<T, BS, 2, false>, BS / 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -628,15 +591,6 @@ __global__ __launch_bounds__(BS) void k_cg_sr_start(int n, EllCols cols,
     write_partials<kSr>(acc, partOut, lds);
 }
 
-// Grid cap of the single-reduction kernels (env OASIS_SR_GRID, read at the
-// start of every solve): every block of an iteration reads all partials of
-// the previous one, kSr per block.
-int sr_grid_cap() {
-    const char *e = std::getenv("OASIS_SR_GRID");
-    const int v = e ? std::atoi(e) : kMaxPartials / 2;
-    return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
-}
-
 // Single-reduction CG on the ELL copy in rec / the workspace partials.
 // Used by cg_run and cg_mixed_run when the ELL copy is present.
 template <typename T>
@@ -655,7 +609,9 @@ struct SrLoop {
     SrLoop(hipStream_t s_, int n_, CGWork<T> &w_, const T *wgt_, const T *vnull_, double vscale_)
         : s(s_), n(n_), cols(w_.cols), eval(w_.eval), wgt(vnull_ && vscale_ > 0.0 ? nullptr : wgt_),
           vnull(vnull_), vscale(vnull_ && vscale_ > 0.0 ? vscale_ : 0.0), w(&w_) {
-        grid = grid_for(n, BS / L, std::min(kMaxPartials, sr_grid_cap()));
+        // every block of an iteration reads all partials of the previous
+        // one, kSr per block: the grid is capped by the tuning's grid_cap
+        grid = grid_for(n, BS / L, std::min(kMaxPartials, w_.tun.grid_cap));
     }
     double *part(int it) const { return (it & 1) ? w->partA : w->partB; }
     // partials for iteration `at`, written into part(at)
@@ -743,11 +699,11 @@ int csr_to_ell(hipStream_t s, int n, const int *rp, const int *ci, const double 
 
 // Rows sharing an offset list share a dictionary entry; ids in order of
 // first occurrence, so the dictionary is a function of the pattern alone.
-int ell_dictionary(hipStream_t s, int n, const short *ecol, unsigned short *pid, short *ptab, int *npat) {
+int ell_dictionary(hipStream_t s, int n, const short *ecol, unsigned short *pid, short *ptab, int *npat,
+                   bool enable) {
     if (!ecol || !pid || !ptab || !npat || n < 0) return OASIS_EINVAL;
     *npat = 0;
-    const char *e = std::getenv("OASIS_ELL_DICT");
-    if (e && e[0] == '0') return OASIS_OK;
+    if (!enable) return OASIS_OK;
     std::vector<short> off(static_cast<size_t>(n) * kEll);
     OASIS_TRY_HIP(hipMemcpyAsync(off.data(), ecol, off.size() * sizeof(short), hipMemcpyDeviceToHost, s));
     OASIS_TRY_HIP(hipStreamSynchronize(s));
@@ -787,18 +743,10 @@ void carve_cg(Carver &c, int n, CGWork<T> &w) {
     w.st = c.take<CGState>(1);
 }
 
-// Single-reduction iterations on the ELL copy.  Their gathered record is
-// (r, w, s) rather than (r, p): with FP32 values the one pass beats the two
-// (the update pass is gone), with FP64 values the wider gathers cost more
-// than that pass.  Default: FP32 only; env OASIS_CG_SR = 0 (never) or 1
-// (both widths).
-bool sr_enabled(int tbytes) {
-    static int mode = [] {
-        const char *e = std::getenv("OASIS_CG_SR");
-        return e ? std::atoi(e) : -1;
-    }();
-    return mode == 1 || (mode != 0 && tbytes == 4);
-}
+// Single-reduction iterations on the ELL copy (Tuning::single).  Their
+// gathered record is (r, w, s) rather than (r, p): with FP32 values the one
+// pass beats the two (the update pass is gone), with FP64 values the wider
+// gathers cost more than that pass.
 
 // Kernel timing of a solve (time_kernel): when the solve has stopped at
 // maxit, the last iteration's state (a residual just recomputed, the flag
@@ -834,40 +782,19 @@ static int time_product(hipStream_t s, int reps, Launch launch, SolveOut &out) {
     return rc;
 }
 
-// Block size of the iteration kernels (env OASIS_CG_BLOCK = 256 or 1024).
-// 1024-thread blocks keep the occupancy with a quarter of the partial sums
-// but measure slower on the product kernel; 256 is the default.
-int cg_block() {
-    static int bs = [] {
-        const char *e = std::getenv("OASIS_CG_BLOCK");
-        const int v = e ? std::atoi(e) : 256;
-        return v == 1024 ? 1024 : 256;
-    }();
-    return bs;
-}
-
-// Upper bound on the grid of the elementwise update kernel (env
-// OASIS_CG_UPDATE_GRID): a streaming kernel needs fewer resident waves than
-// the gather-bound product, and fewer blocks mean fewer partial sums for
-// the product kernel to read.
-int cg_update_grid() {
-    static int g = [] {
-        const char *e = std::getenv("OASIS_CG_UPDATE_GRID");
-        const int v = e ? std::atoi(e) : kMaxPartials / 2;
-        return (v >= 64 && v <= kMaxPartials) ? v : kMaxPartials / 2;
-    }();
-    return g;
-}
-
-// Grids of the iteration kernels with BS-thread blocks: at most
-// kMaxPartials * kBlock / BS blocks, which keeps the resident waves equal.
+// Grids of the iteration kernels with BS-thread blocks (256: 1024-thread
+// blocks keep the occupancy with a quarter of the partial sums but measured
+// slower on the product kernel).  The elementwise update kernel is capped at
+// the tuning's grid_cap: a streaming kernel needs fewer resident waves than
+// the gather-bound product, and fewer blocks mean fewer partial sums for the
+// product kernel to read.
 template <int BS>
 struct CgGrids {
     int p1, p2;
     template <class C>
-    static CgGrids make(int n) {
+    static CgGrids make(int n, int cap_update) {
         const int cap = kMaxPartials * kBlock / BS;
-        const int cap2 = std::min(cap, cg_update_grid() * kBlock / BS);
+        const int cap2 = std::min(cap, cap_update * kBlock / BS);
         return CgGrids{grid_for(n, rows_per_block<C, BS>(), cap), grid_for(n, BS, cap2)};
     }
 };
@@ -917,12 +844,13 @@ template <typename T, class C, int BS>
 static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
                   CGWork<T> &w, SolveOut &out) {
-    const int gi = grid_for(n, rows_per_block<C>(), partial_cap());     // k_cg_init (kBlock threads)
-    const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
-    const bool ell = w.cols.any() && w.eval && ell_enabled();
-    const bool sr = ell && sr_enabled(sizeof(T));
+    const int cap = w.tun.grid_cap;
+    const int gi = grid_for(n, rows_per_block<C>(), cap);     // k_cg_init (kBlock threads)
+    const CgGrids<BS> g = CgGrids<BS>::template make<C>(n, cap);
+    const bool ell = w.cols.any() && w.eval && w.tun.ell();
+    const bool sr = ell && w.tun.single(sizeof(T));
     SrLoop<T> loop(s, n, w, wgt, nullptr, 0.0);
-    const int g1 = ell ? launch_p1_ell<T, BS>(s, n, w.cols, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
+    const int g1 = ell ? launch_p1_ell<T, BS>(s, cap, n, w.cols, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
                                               nullptr, 0, 0, nullptr, nullptr, true)
                        : g.p1;
     out = SolveOut();
@@ -962,8 +890,8 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             }
             const int nin = fresh ? gi : g.p2, stride = fresh ? 3 : 2;
             if (ell)
-                launch_p1_ell<T, BS>(s, n, w.cols, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, w.partB,
-                                     nin, stride, w.st, itj, fresh ? 1 : 0, static_cast<const T *>(nullptr),
+                launch_p1_ell<T, BS>(s, cap, n, w.cols, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
+                                     w.partB, nin, stride, w.st, itj, fresh ? 1 : 0, static_cast<const T *>(nullptr),
                                      w.partA);
             else
                 hipLaunchKernelGGL((k_cg_p1<T, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val,
@@ -1001,8 +929,8 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                     s, maxit,
                     [&] {
                         if (ell)
-                            launch_p1_ell<T, BS>(s, n, w.cols, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
-                                                 w.partB, gi, 3, w.st, itj, 0, static_cast<const T *>(nullptr),
+                            launch_p1_ell<T, BS>(s, cap, n, w.cols, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1],
+                                                 w.q, w.partB, gi, 3, w.st, itj, 0, static_cast<const T *>(nullptr),
                                                  w.partA);
                         else
                             hipLaunchKernelGGL((k_cg_p1<T, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val,
@@ -1052,11 +980,8 @@ int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, c
              const T *b, T *x, double rtol, int maxit, int check_every, bool time_kernel,
              CGWork<T> &w, SolveOut &out) {
     return with_cfg([&](auto c) {
-        if (cg_block() == 256)
-            return cg_run<T, decltype(c), 256>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
-                                               time_kernel, w, out);
-        return cg_run<T, decltype(c), 1024>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel,
-                                            w, out);
+        return cg_run<T, decltype(c), kBlock>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every,
+                                              time_kernel, w, out);
     });
 }
 
@@ -1072,14 +997,15 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
                         const float *vnull, double vscale, const double *b, double *x, double rtol, double delta,
                         int maxit, int check_every, bool time_kernel, CGWork<float> &w,
                         float *xlo, double *rhi, SolveOut &out) {
-    const int gi = grid_for(n, rows_per_block<C>(), partial_cap());     // k_cg_init (kBlock threads)
-    const int gv = grid_for(n, kBlock, partial_cap());                  // k_cg_cast, k_add_lo
-    const CgGrids<BS> g = CgGrids<BS>::template make<C>(n);
-    const bool ell = w.cols.any() && w.eval && ell_enabled();
-    const bool sr = ell && sr_enabled(4);
+    const int cap = w.tun.grid_cap;
+    const int gi = grid_for(n, rows_per_block<C>(), cap);     // k_cg_init (kBlock threads)
+    const int gv = grid_for(n, kBlock, cap);                  // k_cg_cast, k_add_lo
+    const CgGrids<BS> g = CgGrids<BS>::template make<C>(n, cap);
+    const bool ell = w.cols.any() && w.eval && w.tun.ell();
+    const bool sr = ell && w.tun.single(4);
     SrLoop<float> loop(s, n, w, wgt32, vnull, vscale);
-    const int g1 = ell ? launch_p1_ell<float, BS>(s, n, w.cols, w.eval, nullptr, nullptr, nullptr, nullptr, 0, 2,
-                                                  nullptr, 0, 0, nullptr, nullptr, true)
+    const int g1 = ell ? launch_p1_ell<float, BS>(s, cap, n, w.cols, w.eval, nullptr, nullptr, nullptr, nullptr, 0,
+                                                  2, nullptr, 0, 0, nullptr, nullptr, true)
                        : g.p1;
     const double upd = delta * delta;
     out = SolveOut();
@@ -1138,7 +1064,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
             }
             const int ni = j == 0 ? nin : g.p2;
             if (ell)
-                launch_p1_ell<float, BS>(s, n, w.cols, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
+                launch_p1_ell<float, BS>(s, cap, n, w.cols, w.eval, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q,
                                          w.partB, ni, 2, w.st, itj, itj == restart_at ? 1 : 0, vnull, w.partA);
             else
                 hipLaunchKernelGGL((k_cg_p1<float, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val32,
@@ -1196,8 +1122,9 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
                     s, maxit,
                     [&] {
                         if (ell)
-                            launch_p1_ell<float, BS>(s, n, w.cols, w.eval, w.pair[at & 1], w.pair[(at + 1) & 1],
-                                                     w.q, w.partB, gi, 3, w.st, at, 0, vnull, w.partA);
+                            launch_p1_ell<float, BS>(s, cap, n, w.cols, w.eval, w.pair[at & 1],
+                                                     w.pair[(at + 1) & 1], w.q, w.partB, gi, 3, w.st, at, 0, vnull,
+                                                     w.partA);
                         else
                             hipLaunchKernelGGL((k_cg_p1<float, C, BS>), dim3(g1), dim3(BS), 0, s, n, rp, ci, val32,
                                                w.pair[at & 1], w.pair[(at + 1) & 1], w.q, w.partB, gi, 3, w.st, at,
@@ -1221,20 +1148,17 @@ int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const dou
                    int check_every, bool time_kernel, CGWork<float> &w, float *xlo, double *rhi,
                    SolveOut &out) {
     return with_cfg([&](auto c) {
-        if (cg_block() == 256)
-            return cg_mixed_run<decltype(c), 256>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, vscale, b, x, rtol,
-                                                  delta, maxit, check_every, time_kernel, w, xlo, rhi, out);
-        return cg_mixed_run<decltype(c), 1024>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, vscale, b, x, rtol,
-                                               delta, maxit, check_every, time_kernel, w, xlo, rhi, out);
+        return cg_mixed_run<decltype(c), kBlock>(s, n, rp, ci, val, val32, wgt, wgt32, vnull, vscale, b, x, rtol,
+                                                 delta, maxit, check_every, time_kernel, w, xlo, rhi, out);
     });
 }
 
 int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double *val,
                 const double *wgt, const double *b, const double *x, double *r,
                 CGWork<double> &w, double *wrr, double *wbb) {
-    const int g1 = grid_for(n, rows_per_block<Cfg8x2x1>(), partial_cap());
+    const int g1 = grid_for(n, rows_per_block<Cfg8x2x1>(), w.tun.grid_cap);
     hipLaunchKernelGGL((k_cg_init<double, Cfg8x2x1>), dim3(g1), dim3(kBlock), 0, s, n, rp, ci, val,
-                       ell_enabled() ? w.cols : EllCols{}, wgt, b, x, r, 1, w.partB);
+                       w.tun.ell() ? w.cols : EllCols{}, wgt, b, x, r, 1, w.partB);
     OASIS_TRY_LAUNCH();
     hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0, 0.0);
     OASIS_TRY_LAUNCH();
@@ -1722,10 +1646,10 @@ template <typename T, int NR, class C>
 static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *const *b, T *const *x, double rtol, int maxit, int check_every,
                   bool time_kernel, BiWork<T> &w, SolveOut *out) {
-    const int g1 = grid_for(n, rows_per_block<C>(), partial_cap());
-    const int g2 = grid_for(n, kBlock, partial_cap());
+    const int g1 = grid_for(n, rows_per_block<C>(), w.tun.grid_cap);
+    const int g2 = grid_for(n, kBlock, w.tun.grid_cap);
     const int gv = grid_for(n, kBlock, 4096);
-    const bool ell = w.cols.any() && w.eval && ell_enabled();
+    const bool ell = w.cols.any() && w.eval && w.tun.ell();
     const Mat<T> mat{rp, ci, val, ell ? w.cols : EllCols{}, ell ? w.eval : nullptr};
     C3<T> cb{}, cx{}, crh{}, ct{}, cp{};
     V3<T> vx{}, vrh{}, vt{}, vp{}, vxs{};

@@ -50,9 +50,10 @@ struct CGWork {
     double *partA = nullptr, *partB = nullptr;
     CGState *st = nullptr;
     // optional ELL copy of the iteration matrix (set by the owner); the
-    // product kernel uses it when present
+    // product kernel uses it when present and the tuning allows it
     EllCols cols;
     const T *eval = nullptr;
+    Tuning tun;
 };
 
 struct BiState {
@@ -95,6 +96,7 @@ struct BiWork {
     // optional ELL copy of the iteration matrix (set by the owner)
     EllCols cols;
     const T *eval = nullptr;
+    Tuning tun;
 };
 
 struct SolveOut {
@@ -159,10 +161,10 @@ constexpr int kMaxEllPatterns = 4096;
 // csr_to_ell): pid [n] receives each row's pattern id and ptab
 // [kMaxEllPatterns][kEll] the distinct offset lists, numbered in order of
 // first occurrence.  *npat = their number, or 0 when there are more than
-// min(kMaxEllPatterns, n / 8) (pid and ptab then must not be used) or the
-// dictionary is switched off (env OASIS_ELL_DICT=0).  Host work on a copy
-// of ecol; synchronises.
-int ell_dictionary(hipStream_t s, int n, const short *ecol, unsigned short *pid, short *ptab, int *npat);
+// min(kMaxEllPatterns, n / 8) (pid and ptab then must not be used) or
+// `enable` is false.  Host work on a copy of ecol; synchronises.
+int ell_dictionary(hipStream_t s, int n, const short *ecol, unsigned short *pid, short *ptab, int *npat,
+                   bool enable);
 
 // The columns of an ELL copy: the dictionary when it was built, else the
 // per-entry offsets.

@@ -164,10 +164,6 @@ __device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[
     v[3] = b.y;
 }
 
-// Whether ELL product kernels are used when available (env OASIS_ELL=0
-// selects the CSR kernels, for comparisons).
-bool ell_enabled();
-
 // The csr_rows contract on the ELL copy, L lanes per row: gather(j, c, v,
 // ok, acc) for each of the row's kEll stored entries (padding: c = row,
 // v = 0, ok = true) and finish(row, lane, acc) on all L lanes after the
@@ -372,31 +368,19 @@ __device__ __forceinline__ void mat_rows(int n, const Mat<TA> &m, Gather gather,
         csr_rows<TA, NR, C>(n, m.rp, m.ci, m.val, gather, finish);
 }
 
-// Row-iteration shapes compiled into the library (selected at run time).
+// Row-iteration shapes of the CSR kernels.
 using Cfg4x4x1 = RowCfg<4, 4, 1>;
 using Cfg8x2x1 = RowCfg<8, 2, 1>;
-using Cfg8x2x2 = RowCfg<8, 2, 2>;
-using Cfg16x1x2 = RowCfg<16, 1, 2>;
-using Cfg16x1x4 = RowCfg<16, 1, 4>;
-
-// Selected shape (default 1): 0 = 8x2x1, 1 = 4x4x1, 2 = 8x2x2, 3 = 16x1x2, 4 = 16x1x4
-int spmv_cfg();
-// Upper bound on producer grids (partials read by every consumer block).
-int partial_cap();
 
 template <class C, int BS = kBlock>
 constexpr int rows_per_block() { return (BS / C::L) * C::R; }
 
-// Dispatch a callable templated on the row shape.
+// Call f with the CSR row shape of the general kernels: 4 lanes x 4
+// unrolled entries x 1 row per lane group (the fastest of 8x2x1, 4x4x1,
+// 8x2x2, 16x1x2 and 16x1x4 on the P1 patterns here).
 template <class F>
 auto with_cfg(F &&f) {
-    switch (spmv_cfg()) {
-        case 1: return f(Cfg4x4x1{});
-        case 2: return f(Cfg8x2x2{});
-        case 3: return f(Cfg16x1x2{});
-        case 4: return f(Cfg16x1x4{});
-        default: return f(Cfg8x2x1{});
-    }
+    return f(Cfg4x4x1{});
 }
 
 }  // namespace oasis

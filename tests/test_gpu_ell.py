@@ -5,12 +5,10 @@ offsets (27 at every size: interior rows, the two walls, the periodic
 seams and their intersections), so the products read the offsets through a
 per-row dictionary id instead of per entry.  Both forms name the same
 columns in the same order, so every solve must be bit-for-bit identical
-with the dictionary switched off (OASIS_ELL_DICT=0, read at set-up), and
+with the dictionary switched off (storage OASIS_STORAGE_ELL), and
 the solvers must report which storage they used.  A relabelled mesh whose
 rows have as many offset lists as rows keeps the per-entry offsets.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -28,16 +26,8 @@ def oa():
     return m
 
 
-def _with_dict(on, fn):
-    old = os.environ.get("OASIS_ELL_DICT")
-    os.environ["OASIS_ELL_DICT"] = "1" if on else "0"
-    try:
-        return fn()
-    finally:
-        if old is None:
-            del os.environ["OASIS_ELL_DICT"]
-        else:
-            os.environ["OASIS_ELL_DICT"] = old
+def _storage(oa, on):
+    return oa.STORAGE_AUTO if on else oa.STORAGE_ELL
 
 
 def _problem(mesh_seed=3, permute=None):
@@ -61,8 +51,8 @@ def test_pcg_dictionary_is_bit_identical(oa, precision):
     outs, xs = [], []
     for on in (True, False):
         x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=T(0.0).device)
-        outs.append(_with_dict(on, lambda: oa.pcg(K, T(bphi), x, rtol=1e-10, precision=prec,
-                                                  nullspace_const=True)))
+        outs.append(oa.pcg(K, T(bphi), x, rtol=1e-10, precision=prec, nullspace_const=True,
+                           storage=_storage(oa, on)))
         xs.append(x)
     assert 0 < outs[0]["ell_patterns"] <= 64, outs[0]
     assert outs[1]["ell_patterns"] == -1, outs[1]
@@ -81,7 +71,7 @@ def test_bicgstab_dictionary_is_bit_identical(oa, precision):
     outs, xs = [], []
     for on in (True, False):
         x = T(np.zeros_like(b))
-        outs.append(_with_dict(on, lambda: oa.bicgstab(Ap, T(b), x, rtol=1e-10, precision=prec)))
+        outs.append(oa.bicgstab(Ap, T(b), x, rtol=1e-10, precision=prec, storage=_storage(oa, on)))
         xs.append(x)
     for k in range(b.shape[0]):
         assert 0 < outs[0][k]["ell_patterns"] <= 64 and outs[1][k]["ell_patterns"] == -1
@@ -97,8 +87,8 @@ def test_ipcs_step_dictionary_is_bit_identical(oa):
     res = []
     for on in (True, False):
         for prec in (oa.F64, oa.F32):
-            h = _with_dict(on, lambda: oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32),
-                                               rtol_u=1e-10, rtol_p=1e-10, precision=prec))
+            h = oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32), rtol_u=1e-10,
+                        rtol_p=1e-10, precision=prec, storage=_storage(oa, on))
             U1, U2, p, phi = T(prob.U1), T(prob.U2), T(prob.p), T(prob.phi_prev)
             bc = T(prob.bc_values(prob.t0 + prob.dt))
             for _ in range(2):

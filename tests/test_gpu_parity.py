@@ -299,12 +299,11 @@ def test_pcg_mixed_several_rows_per_lane_group(oa):
     """The FP32 CG iteration walks its rows in a two-stage software pipeline,
     unrolled twice, with the next row's fetch clamped into the lane group's
     range.  At the default grid the test meshes give each lane group at most
-    one row per launch; a 64-block grid (env OASIS_SR_GRID, read per solve)
+    one row per launch; a 64-block grid (the tuning's grid_cap)
     gives the 33x33x25 channel's groups 3 or 4 rows each, so both halves of
     the unrolled loop and the clamped fetch past a range's end run.  The
     solve must meet the FP64 tolerance against the oracle as at the default
     grid, with the same iteration count up to the partial-sum order."""
-    import os
     prob = synth.channel_flow((33, 33, 25), seed=1)
     say("pcg mixed, 64-block grid", prob.name)
     S, st, A, b = _tent_problem(prob)
@@ -315,18 +314,10 @@ def test_pcg_mixed_several_rows_per_lane_group(oa):
     bphi -= bphi.mean()
     ref = krylov.pcg(S.K, bphi, np.zeros_like(bphi), rtol=1e-8)
     outs, xs = [], []
-    for grid in (None, "64"):
-        old = os.environ.pop("OASIS_SR_GRID", None)
-        if grid:
-            os.environ["OASIS_SR_GRID"] = grid
-        try:
-            x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
-            outs.append(oa.pcg(Kp, T(bphi), x, rtol=1e-8, precision=oa.F32, nullspace_const=True))
-            xs.append(x.cpu().numpy())
-        finally:
-            os.environ.pop("OASIS_SR_GRID", None)
-            if old is not None:
-                os.environ["OASIS_SR_GRID"] = old
+    for grid in (0, 64):
+        x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+        outs.append(oa.pcg(Kp, T(bphi), x, rtol=1e-8, precision=oa.F32, nullspace_const=True, grid_cap=grid))
+        xs.append(x.cpu().numpy())
     xr = ref.x - ref.x.mean()
     for out, xg in zip(outs, xs):
         true = np.linalg.norm(bphi - S.K @ xg) / np.linalg.norm(bphi)
@@ -343,7 +334,6 @@ def test_pcg_mixed_without_null_vector(oa):
     grid and at a 64-block grid (3-4 rows per lane group) the solve must meet
     the FP64 tolerance in the oracle's residual and match the oracle's FP64
     solution."""
-    import os
     prob = synth.channel_flow((33, 33, 25), seed=4)
     say("pcg mixed, no null vector", prob.name)
     S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
@@ -354,17 +344,9 @@ def test_pcg_mixed_without_null_vector(oa):
     bv = rng.normal(size=prob.mesh.n_dof)
     ref = krylov.pcg(Am, bv, np.zeros_like(bv), rtol=1e-8)
     iters = []
-    for grid in (None, "64"):
-        old = os.environ.pop("OASIS_SR_GRID", None)
-        if grid:
-            os.environ["OASIS_SR_GRID"] = grid
-        try:
-            x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
-            out = oa.pcg(Ap, T(bv), x, rtol=1e-8, precision=oa.F32)
-        finally:
-            os.environ.pop("OASIS_SR_GRID", None)
-            if old is not None:
-                os.environ["OASIS_SR_GRID"] = old
+    for grid in (0, 64):
+        x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
+        out = oa.pcg(Ap, T(bv), x, rtol=1e-8, precision=oa.F32, grid_cap=grid)
         xg = x.cpu().numpy()
         true = np.linalg.norm(bv - Am @ xg) / np.linalg.norm(bv)
         assert out["rc"] == 0 and true <= 1.0001e-8, (grid, out, true)
@@ -376,12 +358,11 @@ def test_pcg_mixed_without_null_vector(oa):
 def test_products_several_rows_per_lane_group(oa):
     """BiCGStab (both precisions) and the FP64 PCG run their ELL products in
     the same straight-line row loops as the FP32 CG iteration.  With the
-    producer grid cut to 64 blocks (env OASIS_PARTIALS, read per solve) the
+    producer grid cut to 64 blocks (the tuning's grid_cap) the
     33x33x25 channel gives each lane group 3 or 4 rows, so both halves of
     the unrolled loops and the clamped fetches run; the solves must meet
     their tolerances in the oracle's own residual and agree with the solves
     at the default grid."""
-    import os
     prob = synth.channel_flow((33, 33, 25), seed=3)
     say("products, 64-block grid", prob.name)
     S, st, A, b = _tent_problem(prob)
@@ -392,27 +373,19 @@ def test_products_several_rows_per_lane_group(oa):
     bphi = rng.normal(size=prob.mesh.n_dof)
     bphi -= bphi.mean()
 
-    def solves():
+    def solves(grid):
         res = []
         for prec in (oa.F64, oa.F32):
             x = T(st.U1)
-            out = oa.bicgstab(Ap, T(b), x, rtol=1e-10, precision=prec)
+            out = oa.bicgstab(Ap, T(b), x, rtol=1e-10, precision=prec, grid_cap=grid)
             res.append((out, x.cpu().numpy()))
         x = torch.zeros(prob.mesh.n_dof, dtype=torch.float64, device=dev())
-        out = oa.pcg(Kp, T(bphi), x, rtol=1e-10, nullspace_const=True)
+        out = oa.pcg(Kp, T(bphi), x, rtol=1e-10, nullspace_const=True, grid_cap=grid)
         res.append((out, x.cpu().numpy()))
         return res
 
-    old = os.environ.pop("OASIS_PARTIALS", None)
-    try:
-        os.environ["OASIS_PARTIALS"] = "64"
-        cut = solves()
-        os.environ.pop("OASIS_PARTIALS")
-        ref = solves()
-    finally:
-        os.environ.pop("OASIS_PARTIALS", None)
-        if old is not None:
-            os.environ["OASIS_PARTIALS"] = old
+    cut = solves(64)
+    ref = solves(0)
     for (out, x), (rout, rx) in zip(cut[:2], ref[:2]):
         for k in range(3):
             true = np.linalg.norm(b[k] - A @ x[k]) / np.linalg.norm(b[k])

@@ -55,7 +55,7 @@ def test_header_constants_match_binding():
 
 STRUCTS = {"oasis_csr": "Csr", "oasis_mesh": "Mesh", "oasis_krylov_opts": "KrylovOpts",
            "oasis_krylov_stats": "KrylovStats", "oasis_ipcs_params": "IpcsParams", "oasis_state": "State",
-           "oasis_step_stats": "StepStats"}
+           "oasis_step_stats": "StepStats", "oasis_tuning": "Tuning"}
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):
@@ -99,9 +99,15 @@ def test_invalid_ipcs_params_rejected_on_host(lib):
     good = L.IpcsParams(0.01, 1e-3, (C.c_double * 3)(1, 0, 0), 0, None, 1e-8, 1e-8, 100, L.F64, 0.0, 0,
                         L.PSTART_PREV)
     assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(good), C.byref(nb)) == L.OK and nb.value > 0
-    for field, bad in [("pressure_start", 7), ("precision", 5), ("dt", 0.0), ("rtol_p", -1.0)]:
+    for field, bad in [("pressure_start", 7), ("precision", 5), ("dt", 0.0), ("rtol_p", -1.0),
+                       ("pressure_delta", 1.5)]:
         p = L.IpcsParams.from_buffer_copy(good)
         setattr(p, field, bad)
+        assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL, field
+    # storage and kernel shapes are per-call options, range-checked on the host
+    for field, bad in [("storage", 9), ("grid_cap", 10), ("grid_cap", 4096), ("cg_form", -1)]:
+        p = L.IpcsParams.from_buffer_copy(good)
+        setattr(p.tuning, field, bad)
         assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL, field
 
 
