@@ -17,6 +17,7 @@ Modules
   graph       CSR pattern, Cuthill-McKee ordering, greedy cell colouring
   mixed       FP32-inner / FP64-outer iterative refinement
   mpnn        message-passing warm-start network, forward/backward/Adam
+  amg         smoothed-aggregation multigrid hierarchy, V-cycle, AMG-PCG
 
 Readings of the paper where it is silent or inconsistent are listed in the
 docstrings of the functions that take them.
