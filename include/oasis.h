@@ -251,6 +251,89 @@ int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, const double 
                    double *x, const oasis_krylov_opts *opt, void *ws, size_t ws_bytes,
                    oasis_krylov_stats *stats);
 
+/* ---- algebraic multigrid for the pressure correction -------------------- */
+/* The paper's channel runs precondition the pressure-correction solve with
+ * algebraic multigrid (Sec. 6.2, channel performance paragraph: a few
+ * iterations per solve).  The method here is smoothed aggregation (Vanek,
+ * Mandel & Brezina 1996): per level, strong couplings |a_ij| >= theta_l
+ * sqrt(|a_ii a_jj|) with theta_l = theta / 2^l; greedy aggregation in index
+ * order; the near-null vector B restricted to each aggregate as the
+ * tentative prolongator; one damped Jacobi smoothing step on the filtered
+ * matrix, weight (4/3) / (Gershgorin bound); Galerkin coarse matrices
+ * P^T A P; a dense inverse on the coarsest level (regularised along its
+ * near-null vector for a singular matrix).  The preconditioner is one
+ * V(1,1) cycle with damped Jacobi smoothing, weight (4/3) / (Gershgorin
+ * bound of D^-1 A) per level. */
+
+typedef struct oasis_amg oasis_amg;   /* opaque host handle */
+
+typedef struct {
+    double theta;         /* strength threshold of level 0, halved per level (0 = 0.25) */
+    int32_t coarse_size;  /* a level of at most this many rows is the coarsest (0 = 1024;
+                             at most 2048) */
+    int32_t max_levels;   /* 0 = 12; at most 16 */
+    int32_t precision;    /* values and vectors of the cycle: OASIS_F64 or OASIS_F32 (the CG
+                             around it, its dot products and stopping test stay FP64) */
+    int32_t flags;        /* OASIS_KRYLOV_NULLSPACE_CONST: A is singular with null vector B */
+    oasis_tuning tuning;  /* storage of level 0 (an ELL copy when its rows fit, unless CSR)
+                             and the grid cap of the CG kernels */
+} oasis_amg_params;
+
+/* Build the hierarchy of the symmetric positive (semi-)definite F64 CSR
+ * matrix A (device; row_ptr, col_idx and val are kept by reference for the
+ * handle's lifetime and used by the CG residuals).  B: device double [n],
+ * the near-null-space vector (NULL = ones).  The set-up copies A to the host
+ * and runs there, once per matrix.  Synchronises `stream`.  EUNSUPPORTED if
+ * the coarsest level exceeds 2048 rows or its (regularised) matrix is not
+ * positive definite. */
+int oasis_amg_setup(void *stream, const oasis_csr *A, const double *B, const oasis_amg_params *par,
+                    oasis_amg **out);
+
+/* Device workspace that oasis_amg_upload needs for this hierarchy. */
+int oasis_amg_workspace_size(const oasis_amg *h, size_t *bytes);
+
+/* Copy the hierarchy into ws (device, kept by reference) and build level
+ * 0's ELL copy; the handle's cycles and solves then run from ws.
+ * Synchronises `stream`. */
+int oasis_amg_upload(void *stream, oasis_amg *h, void *ws, size_t ws_bytes);
+
+/* Host view of level `level` (0 = the input matrix) for inspection; the
+ * pointers are host memory owned by the handle.  The prolongator and
+ * aggregation fields are empty on the coarsest level, whose dense inverse
+ * (row-major [n][n], as applied) is in coarse_inv. */
+typedef struct {
+    int32_t n, nnz;
+    const int32_t *row_ptr, *col_idx;   /* the level matrix */
+    const double *val;
+    const double *near_null;            /* [n] */
+    double omega;                       /* smoother weight (4/3) / Gershgorin bound */
+    int32_t n_agg;                      /* rows of the next level (0 on the coarsest) */
+    const int32_t *agg;                 /* [n] aggregate of every row */
+    int32_t p_nnz;
+    const int32_t *p_row_ptr, *p_col_idx;   /* prolongator [n][n_agg] */
+    const double *p_val;
+    const double *coarse_inv;           /* coarsest level only */
+} oasis_amg_level_info;
+
+int oasis_amg_levels(const oasis_amg *h, int32_t *n_levels);
+int oasis_amg_level(const oasis_amg *h, int32_t level, oasis_amg_level_info *info);
+
+/* z = M^{-1} r: one V(1,1) cycle from a zero start (r, z: device double
+ * [n]; the cycle runs in the handle's precision).  Asynchronous. */
+int oasis_amg_vcycle(void *stream, oasis_amg *h, const double *r, double *z);
+
+/* CG on the handle's matrix preconditioned by one cycle per iteration:
+ * b (device double [n]), x (device double [n], in: x0, out: solution).
+ * opt: rtol, maxit, check_every and OASIS_KRYLOV_TIME (a solve stopped at
+ * maxit then repeats its last cycle maxit times between two HIP events,
+ * kernel_ms / kernel_count) are used; the CG is FP64 whatever
+ * opt->precision says.  Uses the uploaded workspace: calls on one handle
+ * must not overlap.  Synchronises `stream`. */
+int oasis_amg_pcg(void *stream, oasis_amg *h, const double *b, double *x, const oasis_krylov_opts *opt,
+                  oasis_krylov_stats *stats);
+
+int oasis_amg_destroy(oasis_amg *h);
+
 /* ---- the IPCS time step (Alg. 1 with one inner iteration + Alg. 2) ------ */
 
 typedef struct {
@@ -349,6 +432,16 @@ int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
  * The step's forward pass keeps no activations in ws (it is inference only). */
 int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, const double *coords,
                              void *ws, size_t ws_bytes);
+
+/* Precondition the pressure-correction solve of every later step with an
+ * uploaded multigrid handle (NULL: back to Jacobi).  The handle must have
+ * been built on this step handle's scaled pressure matrix: A = the values
+ * oasis_ipcs_matrix returns for OASIS_FORM_STIFF on the shared pattern, B
+ * = its scaled_diag_sqrt, OASIS_KRYLOV_NULLSPACE_CONST (else EINVAL).  The
+ * step then runs FP64 CG with one cycle per iteration (in the multigrid
+ * handle's precision) to the same true-residual tolerance.  Kept by
+ * reference; the two handles' calls must not overlap. */
+int oasis_ipcs_set_amg(oasis_ipcs *h, oasis_amg *amg);
 
 /* Device pointers to the handle's preassembled matrices (values on the
  * shared pattern) for inspection: which = OASIS_FORM_MASS, _STIFF (the

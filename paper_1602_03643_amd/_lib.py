@@ -57,6 +57,17 @@ class KrylovStats(C.Structure):
                 ("rel_res", f64), ("kernel_ms", f64), ("kernel_count", i32), ("ell_patterns", i32)]
 
 
+class AmgParams(C.Structure):
+    _fields_ = [("theta", f64), ("coarse_size", i32), ("max_levels", i32), ("precision", i32), ("flags", i32),
+                ("tuning", Tuning)]
+
+
+class AmgLevelInfo(C.Structure):
+    _fields_ = [("n", i32), ("nnz", i32), ("row_ptr", P(i32)), ("col_idx", P(i32)), ("val", P(f64)),
+                ("near_null", P(f64)), ("omega", f64), ("n_agg", i32), ("agg", P(i32)), ("p_nnz", i32),
+                ("p_row_ptr", P(i32)), ("p_col_idx", P(i32)), ("p_val", P(f64)), ("coarse_inv", P(f64))]
+
+
 class IpcsParams(C.Structure):
     _fields_ = [("dt", f64), ("nu", f64), ("f", f64 * 3), ("n_bc", i32), ("bc_dofs", vp),
                 ("rtol_u", f64), ("rtol_p", f64), ("maxit", i32), ("precision", i32),
@@ -89,6 +100,15 @@ _SIGS = {
     "oasis_krylov_workspace_size": (i32, [i32, i32, i32, P(KrylovOpts), P(sz)]),
     "oasis_pcg": (i32, [vp, P(Csr), vp, vp, P(KrylovOpts), vp, sz, P(KrylovStats)]),
     "oasis_bicgstab": (i32, [vp, P(Csr), i32, vp, vp, P(KrylovOpts), vp, sz, P(KrylovStats)]),
+    "oasis_amg_setup": (i32, [vp, P(Csr), vp, P(AmgParams), P(vp)]),
+    "oasis_amg_workspace_size": (i32, [vp, P(sz)]),
+    "oasis_amg_upload": (i32, [vp, vp, vp, sz]),
+    "oasis_amg_levels": (i32, [vp, P(i32)]),
+    "oasis_amg_level": (i32, [vp, i32, P(AmgLevelInfo)]),
+    "oasis_amg_vcycle": (i32, [vp, vp, vp, vp]),
+    "oasis_amg_pcg": (i32, [vp, vp, vp, vp, P(KrylovOpts), P(KrylovStats)]),
+    "oasis_amg_destroy": (i32, [vp]),
+    "oasis_ipcs_set_amg": (i32, [vp, vp]),
     "oasis_ipcs_workspace_size": (i32, [P(Mesh), i32, P(IpcsParams), P(sz)]),
     "oasis_ipcs_create": (i32, [vp, P(Mesh), vp, vp, i32, P(IpcsParams), vp, sz, P(vp)]),
     "oasis_ipcs_step": (i32, [vp, vp, P(State), vp, vp, P(StepStats)]),

@@ -259,6 +259,79 @@ def bicgstab(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_
 
 
 # ---------------------------------------------------------------------------
+# algebraic multigrid
+
+class AMG:
+    """Handle for oasis_amg_setup/upload/vcycle/pcg/destroy: the
+    smoothed-aggregation hierarchy of an F64 CSR matrix (set up on the host
+    by the library) and its device image in a torch-allocated workspace."""
+
+    def __init__(self, A: DeviceCSR, B=None, precision=L.F64, singular=False, theta=0.0, coarse_size=0,
+                 max_levels=0, storage=L.STORAGE_AUTO, grid_cap=0, stream=None):
+        lib = _lib()
+        self.A, self.B = A, B
+        self.n = A.n
+        self.params = L.AmgParams(float(theta), int(coarse_size), int(max_levels), int(precision),
+                                  L.KRYLOV_NULLSPACE_CONST if singular else 0, _tuning(storage, grid_cap))
+        self._csr = A.c()
+        h = C.c_void_p()
+        L.check(lib.oasis_amg_setup(_stream(stream), C.byref(self._csr), _p(B), C.byref(self.params), C.byref(h)),
+                "oasis_amg_setup")
+        self.handle = h
+        nb = C.c_size_t()
+        L.check(lib.oasis_amg_workspace_size(h, C.byref(nb)), "oasis_amg_workspace_size")
+        self.ws = _workspace(nb.value, A.row_ptr.device)
+        L.check(lib.oasis_amg_upload(_stream(stream), h, _p(self.ws), self.ws.numel()), "oasis_amg_upload")
+
+    def n_levels(self):
+        v = C.c_int32()
+        L.check(_lib().oasis_amg_levels(self.handle, C.byref(v)), "oasis_amg_levels")
+        return v.value
+
+    def level(self, l):
+        """Host copy of level l: dict of numpy arrays (matrix, near-null vector,
+        omega, aggregation, prolongator; coarse_inv on the coarsest level)."""
+        info = L.AmgLevelInfo()
+        L.check(_lib().oasis_amg_level(self.handle, int(l), C.byref(info)), "oasis_amg_level")
+        n, nnz = info.n, info.nnz
+        arr = lambda ptr, cnt: np.ctypeslib.as_array(ptr, shape=(cnt,)).copy()  # noqa: E731
+        out = dict(n=n, row_ptr=arr(info.row_ptr, n + 1), col_idx=arr(info.col_idx, nnz), val=arr(info.val, nnz),
+                   near_null=arr(info.near_null, n), omega=info.omega, n_agg=info.n_agg)
+        if info.n_agg > 0:
+            out.update(agg=arr(info.agg, n), p_row_ptr=arr(info.p_row_ptr, n + 1),
+                       p_col_idx=arr(info.p_col_idx, info.p_nnz), p_val=arr(info.p_val, info.p_nnz))
+        else:
+            out["coarse_inv"] = arr(info.coarse_inv, n * n).reshape(n, n)
+        return out
+
+    def vcycle(self, r, z=None, stream=None):
+        z = torch.empty_like(r) if z is None else z
+        L.check(_lib().oasis_amg_vcycle(_stream(stream), self.handle, _p(r), _p(z)), "oasis_amg_vcycle")
+        return z
+
+    def pcg(self, b, x, rtol=1e-8, maxit=1000, check_every=0, time_kernel=False, stream=None, raise_on=True):
+        o = _opts(rtol, maxit, L.F64, 0.0, 0, check_every, time_kernel)
+        st = L.KrylovStats()
+        rc = _lib().oasis_amg_pcg(_stream(stream), self.handle, _p(b), _p(x), C.byref(o), C.byref(st))
+        if raise_on:
+            L.check(rc, "oasis_amg_pcg", allow=(L.ENOTCONV, L.EBREAKDOWN, L.ENAN))
+        out = _stats(st)
+        out["rc"] = rc
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib().oasis_amg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
 # the IPCS step
 
 class IPCS:
@@ -315,6 +388,21 @@ class IPCS:
                  ms_total=stats.ms_total, rc=rc)
         return d
 
+    def pressure_amg(self, precision=L.F64, theta=0.0, coarse_size=0, max_levels=0, stream=None):
+        """Build a multigrid hierarchy on the handle's scaled pressure matrix,
+        upload it and attach it to the pressure solve (oasis_ipcs_set_amg)."""
+        Ks, s = self.matrix(L.FORM_STIFF, copy=False)     # the hierarchy keeps these by reference
+        amg = AMG(self.pattern.with_values(Ks), s, precision=precision, singular=True, theta=theta,
+                  coarse_size=coarse_size, max_levels=max_levels, stream=stream)
+        self.set_amg(amg)
+        return amg
+
+    def set_amg(self, amg):
+        """Attach an AMG handle built on this handle's pressure matrix (None
+        detaches it: Jacobi again)."""
+        L.check(_lib().oasis_ipcs_set_amg(self.handle, None if amg is None else amg.handle), "oasis_ipcs_set_amg")
+        self._amg = amg
+
     def set_warmstart(self, params, coords):
         """Attach a learned pressure warm start (params: float32 [MPNN.NPARAM],
         coords: float64 [n, dim], both on the device); None detaches it."""
@@ -332,14 +420,15 @@ class IPCS:
                 "oasis_ipcs_set_warmstart")
         self._warm = (params, coords, ws)   # kept alive while attached
 
-    def matrix(self, which, count=None):
-        """Device tensor view (copy) of a handle matrix: values on the pattern."""
+    def matrix(self, which, count=None, copy=True):
+        """A handle matrix's values on the pattern as a device tensor: a copy,
+        or (copy=False) a view of the handle's own memory."""
         val = C.c_void_p()
         sq = C.c_void_p()
         L.check(_lib().oasis_ipcs_matrix(self.handle, int(which), C.byref(val), C.byref(sq)), "oasis_ipcs_matrix")
         n = self.pattern.nnz if count is None else count
-        out = _from_ptr(val.value, n, self.ws)
-        sqt = _from_ptr(sq.value, self.n, self.ws) if sq.value else None
+        out = _from_ptr(val.value, n, self.ws, copy)
+        sqt = _from_ptr(sq.value, self.n, self.ws, copy) if sq.value else None
         return out, sqt
 
     def close(self):
@@ -354,13 +443,15 @@ class IPCS:
             pass
 
 
-def _from_ptr(ptr, count, ws):
-    """Copy `count` doubles at device address ptr (inside ws) into a new tensor."""
+def _from_ptr(ptr, count, ws, copy=True):
+    """`count` doubles at device address ptr (inside ws): a new tensor, or a
+    view of ws."""
     base = ws.data_ptr()
     off = ptr - base
     if off < 0 or off % 8 or off + 8 * count > ws.numel():
         raise ValueError("pointer outside the workspace")
-    return ws[off: off + 8 * count].view(torch.float64).clone()
+    v = ws[off: off + 8 * count].view(torch.float64)
+    return v.clone() if copy else v
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,472 @@
+// Smoothed-aggregation AMG on the device: the V(1,1) cycle as the
+// preconditioner of CG for the pressure correction.  The paper's channel
+// runs precondition the pressure solve with algebraic multigrid (Sec. 6.2,
+// channel performance paragraph); the hierarchy is built on the host once
+// per matrix (amg_setup.hip) and uploaded into a caller workspace.
+//
+// Cycle on level l (b: right-hand side, w_i = omega_l / a_ii):
+//   pre      t = b - A (w .* b)          (one Jacobi sweep from x = 0, then
+//                                          its residual; x = w .* b is never
+//                                          stored)
+//   restrict b_{l+1} = P^T t
+//   coarse   x_L = A_L^-1 b_L            (dense inverse)
+//   prolong  t = w .* b + P x_{l+1}
+//   post     x = t + w .* (b - A t)
+// Level 0 runs on the ELL copy of the matrix (16-bit offsets, dictionary on
+// structured meshes) when it fits, CSR otherwise; coarser levels on CSR.
+// The cycle is in FP64 or FP32 (values and vectors); CG stays in FP64 and
+// its dot products too, so the FP32 cycle is an inner approximation only.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "amg.hpp"
+
+namespace oasis {
+
+namespace {
+
+__device__ __forceinline__ bool stopped(const int *flag) {
+    if (!flag) return false;
+    __shared__ int v;
+    if (threadIdx.x == 0) v = __atomic_load_n(flag, __ATOMIC_RELAXED);
+    __syncthreads();
+    const int r = v;
+    __syncthreads();
+    return r != 0;
+}
+
+using Cfg = Cfg4x4x1;
+
+// pre-smoothing residual, ELL: t = b - A (w .* b)
+template <typename T, typename TB, bool DICT>
+__global__ __launch_bounds__(kBlock) void k_amg_pre_ell(int n, EllCols cols, const T *__restrict__ e,
+                                                        const T *__restrict__ wd, const TB *__restrict__ b,
+                                                        T *__restrict__ t, const int *flag) {
+    if (stopped(flag)) return;
+    ell_rows<T, 1, 2>(
+        n, cols, e,
+        [&](int, int c, T v, bool, T(&a)[1]) { a[0] += v * (wd[c] * static_cast<T>(b[c])); },
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) t[row] = static_cast<T>(b[row]) - a[0];
+        });
+}
+
+// pre-smoothing residual, CSR
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_amg_pre_csr(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const T *__restrict__ val, const T *__restrict__ wd,
+                                                        const TB *__restrict__ b, T *__restrict__ t,
+                                                        const int *flag) {
+    if (stopped(flag)) return;
+    csr_rows<T, 1, Cfg>(
+        n, rp, ci, val,
+        [&](int, int c, T v, bool ok, T(&a)[1]) {
+            const T g = v * (wd[c] * static_cast<T>(b[c]));
+            a[0] += ok ? g : T(0);
+        },
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) t[row] = static_cast<T>(b[row]) - a[0];
+        });
+}
+
+// restriction y = R x (R = P^T as CSR)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_amg_restrict(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                         const T *__restrict__ val, const T *__restrict__ x,
+                                                         T *__restrict__ y, const int *flag) {
+    if (stopped(flag)) return;
+    csr_rows<T, 1, Cfg>(
+        n, rp, ci, val,
+        [&](int, int c, T v, bool ok, T(&a)[1]) {
+            const T g = v * x[c];
+            a[0] += ok ? g : T(0);
+        },
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) y[row] = a[0];
+        });
+}
+
+// prolongation and correction: t = w .* b + P xc
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_amg_prolong(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const T *__restrict__ val, const T *__restrict__ xc,
+                                                        const T *__restrict__ wd, const TB *__restrict__ b,
+                                                        T *__restrict__ t, const int *flag) {
+    if (stopped(flag)) return;
+    csr_rows<T, 1, Cfg>(
+        n, rp, ci, val,
+        [&](int, int c, T v, bool ok, T(&a)[1]) {
+            const T g = v * xc[c];
+            a[0] += ok ? g : T(0);
+        },
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) t[row] = wd[row] * static_cast<T>(b[row]) + a[0];
+        });
+}
+
+// post-smoothing x = t + w .* (b - A t), written as TO at out[i * os];
+// with part: per-block partials (b.x, sum wgt b^2)
+template <typename T, typename TB, typename TO>
+struct PostFinish {
+    const T *wd;
+    const TB *b;
+    const T *t;
+    TO *out;
+    int os;
+    const double *wgt;
+    double *acc;
+    __device__ __forceinline__ void operator()(int row, int lane, T (&a)[1]) const {
+        if (lane == 0) {
+            const T bi = static_cast<T>(b[row]);
+            const T x = t[row] + wd[row] * (bi - a[0]);
+            out[static_cast<long long>(row) * os] = static_cast<TO>(x);
+            if (wgt) {
+                const double bd = static_cast<double>(b[row]);
+                acc[0] += bd * static_cast<double>(x);
+                acc[1] += wgt[row] * bd * bd;
+            }
+        }
+    }
+};
+
+template <typename T, typename TB, typename TO, bool DICT>
+__global__ __launch_bounds__(kBlock) void k_amg_post_ell(int n, EllCols cols, const T *__restrict__ e,
+                                                         const T *__restrict__ wd, const TB *__restrict__ b,
+                                                         const T *__restrict__ t, TO *__restrict__ out, int os,
+                                                         const double *__restrict__ wgt, double *part,
+                                                         const int *flag) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (stopped(flag)) return;
+    double acc[2] = {0.0, 0.0};
+    const PostFinish<T, TB, TO> fin{wd, b, t, out, os, part ? wgt : nullptr, acc};
+    ell_rows<T, 1, 2>(
+        n, cols, e, [&](int, int c, T v, bool, T(&a)[1]) { a[0] += v * t[c]; }, fin);
+    if (part) write_partials<2>(acc, part, lds);
+}
+
+template <typename T, typename TB, typename TO>
+__global__ __launch_bounds__(kBlock) void k_amg_post_csr(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                         const T *__restrict__ val, const T *__restrict__ wd,
+                                                         const TB *__restrict__ b, const T *__restrict__ t,
+                                                         TO *__restrict__ out, int os, const double *__restrict__ wgt,
+                                                         double *part, const int *flag) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (stopped(flag)) return;
+    double acc[2] = {0.0, 0.0};
+    const PostFinish<T, TB, TO> fin{wd, b, t, out, os, part ? wgt : nullptr, acc};
+    csr_rows<T, 1, Cfg>(
+        n, rp, ci, val,
+        [&](int, int c, T v, bool ok, T(&a)[1]) {
+            const T g = v * t[c];
+            a[0] += ok ? g : T(0);
+        },
+        fin);
+    if (part) write_partials<2>(acc, part, lds);
+}
+
+// coarsest level: x = C b with the dense inverse C (row-major); one wave
+// per row; with part, partials (b.x, sum wgt b^2) as the post kernel
+template <typename T, typename TB, typename TO>
+__global__ __launch_bounds__(kBlock) void k_amg_dense(int nc, const T *__restrict__ cinv, const TB *__restrict__ b,
+                                                      TO *__restrict__ out, int os, const double *__restrict__ wgt,
+                                                      double *part, const int *flag) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (stopped(flag)) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    double acc[2] = {0.0, 0.0};
+    for (int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; row < nc;
+         row += gridDim.x * (kBlock / kWave)) {
+        double s = 0.0;
+        for (int j = lane; j < nc; j += kWave)
+            s += static_cast<double>(cinv[static_cast<long long>(row) * nc + j]) * static_cast<double>(b[j]);
+        s = wave_sum(s);
+        if (lane == 0) {
+            out[static_cast<long long>(row) * os] = static_cast<TO>(static_cast<T>(s));
+            if (part && wgt) {
+                const double bd = static_cast<double>(b[row]);
+                acc[0] += bd * static_cast<double>(static_cast<T>(s));
+                acc[1] += wgt[row] * bd * bd;
+            }
+        }
+    }
+    if (part) write_partials<2>(acc, part, lds);
+}
+
+// CG update: alpha = (r.z) / (p.q), x += alpha p, r -= alpha q (p from the
+// (z, p) pairs written by the product kernel)
+__global__ __launch_bounds__(kBlock) void k_apcg_update(int n, const RP<double> *__restrict__ nxt,
+                                                        const double *__restrict__ q, double *__restrict__ x,
+                                                        double *__restrict__ r, const double *partIn, int nIn,
+                                                        CGState *st, int it) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (stopped(&st->flag)) return;
+    double v[2];
+    read_partials<2>(partIn, nIn, v, lds);
+    const double pq = v[0];
+    if (!(pq > 0.0) || !finite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->flag = finite(pq) ? 2 : 3;
+            st->it_done = it;
+        }
+        return;
+    }
+    const double a = st->rr[it & 1] / pq;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        x[i] += a * nxt[i].p;
+        r[i] -= a * q[i];
+    }
+}
+
+int csr_grid(int n) { return grid_for(n, rows_per_block<Cfg>(), 1 << 20); }
+
+// reps launches of `launch` back to back between two events on s
+template <class Launch>
+int time_repeats(hipStream_t s, int reps, Launch launch, SolveOut &out) {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    int rc = OASIS_OK;
+    for (auto &v : e)
+        if (rc == OASIS_OK && hipEventCreate(&v) != hipSuccess) rc = OASIS_EHIP;
+    if (rc == OASIS_OK && hipEventRecord(e[0], s) != hipSuccess) rc = OASIS_EHIP;
+    for (int k = 0; k < reps && rc == OASIS_OK; ++k) rc = launch();
+    float ms = 0.f;
+    if (rc == OASIS_OK && (hipEventRecord(e[1], s) != hipSuccess || hipEventSynchronize(e[1]) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess))
+        rc = OASIS_EHIP;
+    for (auto &v : e)
+        if (v) (void)hipEventDestroy(v);
+    if (rc == OASIS_OK) {
+        out.kernel_ms = ms;
+        out.kernel_count = reps;
+    }
+    return rc;
+}
+int ell_grid(int n, int cap) { return grid_for(n, kBlock / 2, cap); }
+
+}  // namespace
+
+template <typename T>
+int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, int zs, const double *wgt,
+               double *part, int *gpost, const int *flag, int grid_cap) {
+    const int L = c.nlev;
+    const bool ell0 = c.cols.any() && c.e;
+    const bool dict = c.cols.pid != nullptr;
+    if (L == 1) {
+        const int g = std::min(grid_for(c.nc, kBlock / kWave, 1 << 20), part ? grid_cap : 1 << 20);
+        hipLaunchKernelGGL((k_amg_dense<T, double, double>), dim3(g), dim3(kBlock), 0, s, c.nc, c.cinv, r, z, zs,
+                           wgt, part, flag);
+        OASIS_TRY_LAUNCH();
+        if (gpost) *gpost = g;
+        return OASIS_OK;
+    }
+    // down
+    for (int l = 0; l + 1 < L; ++l) {
+        const AmgDevLevel<T> &v = c.lv[l];
+        if (l == 0 && ell0) {
+            if (dict)
+                hipLaunchKernelGGL((k_amg_pre_ell<T, double, true>), dim3(ell_grid(v.n, 1 << 20)), dim3(kBlock), 0,
+                                   s, v.n, c.cols, c.e, v.wd, r, v.t, flag);
+            else
+                hipLaunchKernelGGL((k_amg_pre_ell<T, double, false>), dim3(ell_grid(v.n, 1 << 20)), dim3(kBlock), 0,
+                                   s, v.n, c.cols, c.e, v.wd, r, v.t, flag);
+        } else if (l == 0) {
+            hipLaunchKernelGGL((k_amg_pre_csr<T, double>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
+                               v.val, v.wd, r, v.t, flag);
+        } else {
+            hipLaunchKernelGGL((k_amg_pre_csr<T, T>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
+                               v.val, v.wd, v.b, v.t, flag);
+        }
+        OASIS_TRY_LAUNCH();
+        const AmgDevLevel<T> &nx = c.lv[l + 1];
+        hipLaunchKernelGGL((k_amg_restrict<T>), dim3(csr_grid(nx.n)), dim3(kBlock), 0, s, nx.n, v.rrp, v.rci, v.rval,
+                           v.t, nx.b, flag);
+        OASIS_TRY_LAUNCH();
+    }
+    // coarsest
+    {
+        const AmgDevLevel<T> &v = c.lv[L - 1];
+        hipLaunchKernelGGL((k_amg_dense<T, T, T>), dim3(grid_for(c.nc, kBlock / kWave, 1 << 20)), dim3(kBlock), 0,
+                           s, c.nc, c.cinv, v.b, v.x, 1, static_cast<const double *>(nullptr),
+                           static_cast<double *>(nullptr), flag);
+        OASIS_TRY_LAUNCH();
+    }
+    // up
+    for (int l = L - 2; l >= 0; --l) {
+        const AmgDevLevel<T> &v = c.lv[l];
+        const AmgDevLevel<T> &nx = c.lv[l + 1];
+        if (l == 0)
+            hipLaunchKernelGGL((k_amg_prolong<T, double>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.prp,
+                               v.pci, v.pval, nx.x, v.wd, r, v.t, flag);
+        else
+            hipLaunchKernelGGL((k_amg_prolong<T, T>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.prp, v.pci,
+                               v.pval, nx.x, v.wd, v.b, v.t, flag);
+        OASIS_TRY_LAUNCH();
+        if (l == 0 && ell0) {
+            const int g = ell_grid(v.n, part ? grid_cap : 1 << 20);
+            if (dict)
+                hipLaunchKernelGGL((k_amg_post_ell<T, double, double, true>), dim3(g), dim3(kBlock), 0, s, v.n,
+                                   c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
+            else
+                hipLaunchKernelGGL((k_amg_post_ell<T, double, double, false>), dim3(g), dim3(kBlock), 0, s, v.n,
+                                   c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
+            if (gpost) *gpost = g;
+        } else if (l == 0) {
+            const int g = std::min(csr_grid(v.n), part ? grid_cap : 1 << 20);
+            hipLaunchKernelGGL((k_amg_post_csr<T, double, double>), dim3(g), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
+                               v.val, v.wd, r, v.t, z, zs, wgt, part, flag);
+            if (gpost) *gpost = g;
+        } else {
+            hipLaunchKernelGGL((k_amg_post_csr<T, T, T>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
+                               v.val, v.wd, v.b, v.t, v.x, 1, static_cast<const double *>(nullptr),
+                               static_cast<double *>(nullptr), flag);
+        }
+        OASIS_TRY_LAUNCH();
+    }
+    return OASIS_OK;
+}
+
+// Iterations to launch before the next poll: from the observed rate of
+// log(wrr) per iteration, aiming just before convergence, within [1, 32]
+// (an AMG iteration costs many kernels, so a late poll wastes more than an
+// early one); 2 before any rate is known.
+struct AmgPlan {
+    int fixed;
+    double rate = 0.0, w0 = 0.0;
+    int it0 = 0, next = 2;
+    explicit AmgPlan(int every) : fixed(every) {
+        if (fixed > 0) next = fixed;
+    }
+    void restart(double wrr, int it) {
+        w0 = wrr;
+        it0 = it;
+        if (fixed <= 0) next = 2;
+    }
+    void observe(double wrr, int it_last, double target) {
+        if (fixed > 0) return;
+        if (it_last > it0 && wrr > 0.0 && w0 > 0.0) {
+            const double r = std::log(wrr / w0) / (it_last - it0);
+            if (r < 0.0) rate = r;
+        }
+        if (rate < 0.0 && wrr > 0.0 && target > 0.0) {
+            const double k = std::log(target / wrr) / rate;
+            next = static_cast<int>(std::min(32.0, std::max(1.0, std::floor(k))));
+        } else {
+            next = 2;
+        }
+    }
+};
+
+template <typename T>
+int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val, const double *e64,
+                  const AmgCycle<T> &c, const double *wgt, const double *b, double *x, double rtol, int maxit,
+                  int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out) {
+    out = SolveOut();
+    const int cap = w.tun.grid_cap;
+    const EllCols cols = (c.cols.any() && e64) ? c.cols : EllCols{};
+    double *pv = w.partB;           // partials of the cycle's last kernel: (r.z, sum wgt r^2)
+    double *pq = w.partA;           // partials of the product kernel: (p.q, 0)
+    int gpost = 0, g1 = 0;
+    auto zslot = [&](int at) { return reinterpret_cast<double *>(w.pair[at & 1]); };   // z in the pair's r
+    auto start = [&](int mode, int at) -> int {
+        OASIS_TRY(cg_residual_state(s, cap, n, rp, ci, val, cols, wgt, b, x, r, 1, pv, w.st, rtol * rtol,
+                                    mode));
+        return OASIS_OK;
+    };
+    auto precondition = [&](int at) -> int {
+        return amg_vcycle<T>(s, c, r, zslot(at), 2, wgt, pv, &gpost, &w.st->flag, cap);
+    };
+    OASIS_TRY(start(0, 0));
+    CGState h;
+    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    const double wbb = h.wbb, tol2 = h.tol2;
+    auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
+    if (!std::isfinite(h.wrr)) {
+        out.status = OASIS_ENAN;
+        out.rel_res = NAN;
+        return out.status;
+    }
+    if (h.wrr <= tol2) {
+        out.rel_res = rel(h.wrr);
+        return OASIS_OK;
+    }
+    OASIS_TRY(precondition(0));
+    AmgPlan plan(check_every);
+    plan.restart(h.wrr, 0);
+    int it = 0, restart_at = 0, rc = OASIS_OK;
+    auto iterate = [&](int itj) -> int {
+        OASIS_TRY(cg_product_launch(s, cap, n, rp, ci, val, cols, e64, w.pair[itj & 1], w.pair[(itj + 1) & 1],
+                                    w.q, pv, gpost, 2, w.st, itj, itj == restart_at ? 1 : 0, pq, &g1));
+        hipLaunchKernelGGL(k_apcg_update, dim3(grid_for(n, kBlock, kMaxPartials)), dim3(kBlock), 0, s, n,
+                           w.pair[(itj + 1) & 1], w.q, x, r, pq, g1, w.st, itj);
+        OASIS_TRY_LAUNCH();
+        return precondition(itj + 1);
+    };
+    while (true) {
+        const int m = std::min(plan.next, maxit - it);
+        for (int j = 0; j < m; ++j) OASIS_TRY(iterate(it + j));
+        it += m;
+        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        if (h.flag == 0 && it < maxit) {
+            plan.observe(h.wrr_it, h.it_last, tol2);
+            continue;
+        }
+        if (h.flag == 2 || h.flag == 3) {
+            out.iters = h.it_done;
+            out.status = rc = h.flag == 2 ? OASIS_EBREAKDOWN : OASIS_ENAN;
+            out.rel_res = NAN;
+            break;
+        }
+        // converged candidate (or maxit): confirm on the true residual
+        const int at = h.flag == 0 ? it : h.it_done;
+        OASIS_TRY(start(1, at));
+        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        out.rel_res = rel(h.wrr);
+        if (!std::isfinite(h.wrr)) {
+            out.iters = at;
+            out.status = rc = OASIS_ENAN;
+            break;
+        }
+        if (h.wrr <= tol2) {
+            out.iters = at;
+            out.status = rc = OASIS_OK;
+            break;
+        }
+        if (at >= maxit) {
+            out.iters = at;
+            out.status = rc = OASIS_ENOTCONV;
+            if (time_kernel) {
+                // repeat the cycle on the final residual maxit times (it
+                // reads r and writes only the z slot, so x is unchanged)
+                OASIS_TRY(time_repeats(s, maxit, [&] {
+                    return amg_vcycle<T>(s, c, r, zslot(at), 2, wgt, pv, &gpost, nullptr, cap);
+                }, out));
+            }
+            break;
+        }
+        // continue from the explicit residual with a fresh direction
+        out.replacements += 1;
+        OASIS_TRY(precondition(at));
+        it = at;
+        restart_at = at;
+        plan.restart(h.wrr, at);
+    }
+    return rc;
+}
+
+template int amg_vcycle<double>(hipStream_t, const AmgCycle<double> &, const double *, double *, int,
+                                const double *, double *, int *, const int *, int);
+template int amg_vcycle<float>(hipStream_t, const AmgCycle<float> &, const double *, double *, int, const double *,
+                               double *, int *, const int *, int);
+template int amg_pcg_solve<double>(hipStream_t, int, const int *, const int *, const double *, const double *,
+                                   const AmgCycle<double> &, const double *, const double *, double *, double, int,
+                                   int, bool, double *, CGWork<double> &, SolveOut &);
+template int amg_pcg_solve<float>(hipStream_t, int, const int *, const int *, const double *, const double *,
+                                  const AmgCycle<float> &, const double *, const double *, double *, double, int, int,
+                                  bool, double *, CGWork<double> &, SolveOut &);
+
+}  // namespace oasis

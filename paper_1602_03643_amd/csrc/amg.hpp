@@ -1,0 +1,104 @@
+// Smoothed-aggregation algebraic multigrid: the host-built hierarchy, its
+// device image and the preconditioned CG that the IPCS step and the
+// stand-alone entry points share.
+#pragma once
+
+#include <vector>
+
+#include "krylov.hpp"
+
+namespace oasis {
+
+constexpr int kAmgMaxLevels = 16;
+constexpr int kAmgMaxCoarse = 2048;
+
+// Host CSR (sorted columns).
+struct HostCsr {
+    int n = 0, m = 0;            // rows, columns
+    std::vector<int> rp, ci;
+    std::vector<double> v;
+    long long nnz() const { return static_cast<long long>(ci.size()); }
+};
+
+// One level of the host hierarchy: its matrix, the smoother weight and,
+// below the coarsest level, the aggregation and the prolongator to the next.
+struct HostLevel {
+    HostCsr A;                   // level 0: a host copy of the input matrix
+    std::vector<double> B;       // near-null-space vector
+    double omega = 0.0;          // smoother weight (4/3) / rho(D^-1 A)
+    std::vector<int> agg;        // aggregate of every row (not on the coarsest level)
+    int n_agg = 0;
+    HostCsr P;                   // n x n_agg
+    HostCsr R;                   // P^T
+};
+
+struct AmgHostParams {
+    double theta = 0.25;
+    int coarse_size = 1024;
+    int max_levels = 12;
+    bool singular = false;
+};
+
+// Builds the hierarchy of A0 with near-null vector B0 (host work).
+// coarse_inv receives the dense inverse (row-major) of the coarsest level,
+// regularised along its near-null vector when `singular`.  EUNSUPPORTED if
+// the coarsest matrix is not positive definite (after regularisation).
+int amg_build(const HostCsr &A0, const std::vector<double> &B0, const AmgHostParams &p,
+              std::vector<HostLevel> &levels, std::vector<double> &coarse_inv);
+
+// Device image of one level below the coarsest: matrix (CSR; level 0 uses
+// the ELL copy instead), smoother weights w_i = omega / a_ii, prolongator P
+// and restriction R = P^T (CSR), and the cycle's vectors.
+template <typename T>
+struct AmgDevLevel {
+    int n = 0;
+    const int *rp = nullptr, *ci = nullptr;
+    const T *val = nullptr;
+    const T *wd = nullptr;
+    const int *prp = nullptr, *pci = nullptr;
+    const T *pval = nullptr;
+    const int *rrp = nullptr, *rci = nullptr;
+    const T *rval = nullptr;
+    T *b = nullptr, *t = nullptr, *x = nullptr;   // right-hand side, scratch, solution
+};
+
+// The cycle in precision T: level 0's matrix is the ELL copy (cols, e),
+// the coarsest level a dense inverse (nc x nc, row-major).
+template <typename T>
+struct AmgCycle {
+    int nlev = 0;
+    AmgDevLevel<T> lv[kAmgMaxLevels];
+    EllCols cols;
+    const T *e = nullptr;
+    int nc = 0;
+    const T *cinv = nullptr;
+};
+
+// One V(1,1) cycle z = M^{-1} r on level 0: r is FP64 (the CG residual), z
+// is written as FP64 at z[i * zs].  With part (nullable), the last kernel
+// writes per-block partials (r.z, sum wgt r^2) and returns its grid in
+// *gpost.  flag (nullable): a device int; while it is nonzero every kernel
+// returns at once.  grid_cap bounds the partial-writing kernel's grid.
+template <typename T>
+int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, int zs, const double *wgt,
+               double *part, int *gpost, const int *flag, int grid_cap);
+
+// CG on level 0's matrix (FP64 ELL values e64 with c's columns) preconditioned
+// by the cycle c; stopping test sum wgt r^2 <= rtol^2 sum wgt b^2 on the
+// true residual.  r: FP64 scratch [n]; w: CG workspace (pairs, q, partials,
+// state).
+template <typename T>
+int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val, const double *e64,
+                  const AmgCycle<T> &c, const double *wgt, const double *b, double *x, double rtol, int maxit,
+                  int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out);
+
+// The pressure solve of an IPCS step through an uploaded handle: CG on the
+// handle's matrix with its cycle, weights wgt for the stopping test.
+int amg_handle_solve(hipStream_t s, oasis_amg *h, const double *wgt, const double *b, double *x, double rtol,
+                     int maxit, SolveOut &out);
+
+// Whether h was built (and uploaded) on this matrix and null vector as a
+// singular pressure matrix.
+bool amg_handle_matches(const oasis_amg *h, int n, const int *rp, const double *val, const double *B);
+
+}  // namespace oasis

@@ -23,6 +23,7 @@
 #include <new>
 #include <vector>
 
+#include "amg.hpp"
 #include "assemble.hpp"
 #include "krylov.hpp"
 #include "mpnn.hpp"
@@ -832,6 +833,8 @@ struct oasis_ipcs {
     BiWork<float> bi32;
     IRBufs ir;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // multigrid preconditioner of the pressure solve (optional)
+    oasis_amg *amg = nullptr;
     // learned warm start (optional)
     const float *ws_params = nullptr;
     const double *ws_coords = nullptr;
@@ -1083,6 +1086,13 @@ extern "C" int oasis_ipcs_set_warmstart(oasis_ipcs *h, const float *params, cons
     return OASIS_OK;
 }
 
+extern "C" int oasis_ipcs_set_amg(oasis_ipcs *h, oasis_amg *amg) {
+    if (!h) return OASIS_EINVAL;
+    if (amg && !amg_handle_matches(amg, h->n, h->rp, h->Ks, h->sK)) return OASIS_EINVAL;
+    h->amg = amg;
+    return OASIS_OK;
+}
+
 extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const double **val,
                                  const double **scaled_diag_sqrt) {
     if (!h || !val) return OASIS_EINVAL;
@@ -1280,7 +1290,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     ko = kopts(&o);
     SolveOut sp;
     int rc_p;
-    if (h->mixed)
+    if (h->amg)
+        rc_p = amg_handle_solve(s, h->amg, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, sp);
+    else if (h->mixed)
         rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->vscale, h->bs,
                               h->xs,
                               ko.rtol, h->par.pressure_delta > 0.0 ? h->par.pressure_delta : kPressureDelta,

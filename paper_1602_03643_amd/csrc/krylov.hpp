@@ -179,6 +179,24 @@ inline EllCols ell_cols(const short *ecol, const unsigned short *pid, const shor
     return c;
 }
 
+// One direction + product launch of the FP64 CG iteration (the ELL kernel
+// when cols and eval are given, else CSR): p_new = g.r + beta p_old from
+// the gathered (r, p_old) pairs of cur, q = A p_new, nxt = (r, p_new),
+// partials (p.q, 0) per block, with beta = partIn[0] / st->rr of the
+// previous iteration and the convergence test on partIn[1] (the same
+// contract as the CG solver's own iterations).  *grid: its grid.
+int cg_product_launch(hipStream_t s, int cap, int n, const int *rp, const int *ci, const double *val,
+                      const EllCols &cols, const double *eval, const RP<double> *cur, RP<double> *nxt, double *q,
+                      const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
+                      double *partOut, int *grid);
+
+// r[i * rs] = b - A x with FP64 values (columns from cols when given), then
+// the CG state's norms: mode 0 starts a solve (tol2 = rtol2 sum wgt b^2),
+// mode 1 refreshes wrr only; the flag is cleared.
+int cg_residual_state(hipStream_t s, int cap, int n, const int *rp, const int *ci, const double *val,
+                      const EllCols &cols, const double *wgt, const double *b, const double *x, double *r, int rs,
+                      double *part, CGState *st, double rtol2, int mode);
+
 // Weighted residual of x for the scaled system: r = b - Ms x, returns
 // (sum wgt r^2, sum wgt b^2) on the host.  Uses w's buffers.
 int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double *val,

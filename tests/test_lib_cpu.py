@@ -55,7 +55,8 @@ def test_header_constants_match_binding():
 
 STRUCTS = {"oasis_csr": "Csr", "oasis_mesh": "Mesh", "oasis_krylov_opts": "KrylovOpts",
            "oasis_krylov_stats": "KrylovStats", "oasis_ipcs_params": "IpcsParams", "oasis_state": "State",
-           "oasis_step_stats": "StepStats", "oasis_tuning": "Tuning"}
+           "oasis_step_stats": "StepStats", "oasis_tuning": "Tuning", "oasis_amg_params": "AmgParams",
+           "oasis_amg_level_info": "AmgLevelInfo"}
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):
