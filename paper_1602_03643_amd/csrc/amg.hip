@@ -37,33 +37,60 @@ __device__ __forceinline__ bool stopped(const int *flag) {
     return r != 0;
 }
 
-using Cfg = Cfg4x4x1;
+// CSR row shapes of the coarse-level kernels: L lanes x 4 unrolled entries
+// per row, L chosen per matrix from its mean row length (upload time), so
+// that short rows (prolongator: ~5) do not issue 16 clamped loads each.
+template <int L>
+using AmgCfg = RowCfg<L, 4, 1>;
 
-// pre-smoothing residual, ELL: t = b - A (w .* b)
+template <class F>
+int with_lanes(int lanes, F &&f) {
+    switch (lanes) {
+        case 2: return f(AmgCfg<2>{});
+        case 8: return f(AmgCfg<8>{});
+        case 16: return f(AmgCfg<16>{});
+        default: return f(AmgCfg<4>{});
+    }
+}
+
+// y = w .* b: the one operand the pre-smoothing residual gathers
+template <typename T, typename TB>
+__global__ __launch_bounds__(kBlock) void k_amg_scale(int n, const T *__restrict__ wd, const TB *__restrict__ b,
+                                                      T *__restrict__ y, const int *flag) {
+    if (stopped(flag)) return;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = wd[i] * static_cast<T>(b[i]);
+}
+
+// pre-smoothing residual on the ELL copy: t = b - A y (straight-line row
+// loop: the next row's offsets, values and b are fetched while this row's
+// gathers are in flight)
 template <typename T, typename TB, bool DICT>
 __global__ __launch_bounds__(kBlock) void k_amg_pre_ell(int n, EllCols cols, const T *__restrict__ e,
-                                                        const T *__restrict__ wd, const TB *__restrict__ b,
+                                                        const T *__restrict__ y, const TB *__restrict__ b,
                                                         T *__restrict__ t, const int *flag) {
     if (stopped(flag)) return;
-    ell_rows<T, 1, 2>(
-        n, cols, e,
-        [&](int, int c, T v, bool, T(&a)[1]) { a[0] += v * (wd[c] * static_cast<T>(b[c])); },
-        [&](int row, int lane, T(&a)[1]) {
-            if (lane == 0) t[row] = static_cast<T>(b[row]) - a[0];
-        });
+    auto load = [&](int c) { return y[c]; };
+    auto add = [&](const T &g, T v, T(&a)[1]) { a[0] += v * g; };
+    auto own = [&](long long r) { return b[r]; };
+    auto fin = [&](int row, int lane, T(&a)[1], const TB &o) {
+        if (lane == 0) t[row] = static_cast<T>(o) - a[0];
+    };
+    ell_rows_pipe<T, 1, 2, DICT, T, TB>(n, cols, e, load, add, own, fin);
 }
 
 // pre-smoothing residual, CSR
-template <typename T, typename TB>
+template <typename T, typename TB, class C>
 __global__ __launch_bounds__(kBlock) void k_amg_pre_csr(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                        const T *__restrict__ val, const T *__restrict__ wd,
+                                                        const T *__restrict__ val, const T *__restrict__ y,
                                                         const TB *__restrict__ b, T *__restrict__ t,
                                                         const int *flag) {
     if (stopped(flag)) return;
-    csr_rows<T, 1, Cfg>(
+    csr_rows<T, 1, C>(
         n, rp, ci, val,
         [&](int, int c, T v, bool ok, T(&a)[1]) {
-            const T g = v * (wd[c] * static_cast<T>(b[c]));
+            const T g = v * y[c];
             a[0] += ok ? g : T(0);
         },
         [&](int row, int lane, T(&a)[1]) {
@@ -71,64 +98,65 @@ __global__ __launch_bounds__(kBlock) void k_amg_pre_csr(int n, const int *__rest
         });
 }
 
-// restriction y = R x (R = P^T as CSR)
-template <typename T>
+// restriction b_c = R t (R = P^T as CSR), and y_c = w_c .* b_c when the
+// next level smooths (wdc non-null)
+template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_amg_restrict(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                                          const T *__restrict__ val, const T *__restrict__ x,
-                                                         T *__restrict__ y, const int *flag) {
+                                                         T *__restrict__ bc, const T *__restrict__ wdc,
+                                                         T *__restrict__ yc, const int *flag) {
     if (stopped(flag)) return;
-    csr_rows<T, 1, Cfg>(
+    csr_rows<T, 1, C>(
         n, rp, ci, val,
         [&](int, int c, T v, bool ok, T(&a)[1]) {
             const T g = v * x[c];
             a[0] += ok ? g : T(0);
         },
         [&](int row, int lane, T(&a)[1]) {
-            if (lane == 0) y[row] = a[0];
+            if (lane == 0) {
+                bc[row] = a[0];
+                if (wdc) yc[row] = wdc[row] * a[0];
+            }
         });
 }
 
-// prolongation and correction: t = w .* b + P xc
-template <typename T, typename TB>
+// prolongation and correction: t = y + P xc (y = w .* b, the pre-smoothed
+// iterate)
+template <typename T, class C>
 __global__ __launch_bounds__(kBlock) void k_amg_prolong(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                                         const T *__restrict__ val, const T *__restrict__ xc,
-                                                        const T *__restrict__ wd, const TB *__restrict__ b,
-                                                        T *__restrict__ t, const int *flag) {
+                                                        const T *__restrict__ y, T *__restrict__ t, const int *flag) {
     if (stopped(flag)) return;
-    csr_rows<T, 1, Cfg>(
+    csr_rows<T, 1, C>(
         n, rp, ci, val,
         [&](int, int c, T v, bool ok, T(&a)[1]) {
             const T g = v * xc[c];
             a[0] += ok ? g : T(0);
         },
         [&](int row, int lane, T(&a)[1]) {
-            if (lane == 0) t[row] = wd[row] * static_cast<T>(b[row]) + a[0];
+            if (lane == 0) t[row] = y[row] + a[0];
         });
 }
 
 // post-smoothing x = t + w .* (b - A t), written as TO at out[i * os];
-// with part: per-block partials (b.x, sum wgt b^2)
+// with acc: per-thread partials (b.x, sum wgt b^2)
 template <typename T, typename TB, typename TO>
-struct PostFinish {
-    const T *wd;
-    const TB *b;
-    const T *t;
-    TO *out;
-    int os;
-    const double *wgt;
-    double *acc;
-    __device__ __forceinline__ void operator()(int row, int lane, T (&a)[1]) const {
-        if (lane == 0) {
-            const T bi = static_cast<T>(b[row]);
-            const T x = t[row] + wd[row] * (bi - a[0]);
-            out[static_cast<long long>(row) * os] = static_cast<TO>(x);
-            if (wgt) {
-                const double bd = static_cast<double>(b[row]);
-                acc[0] += bd * static_cast<double>(x);
-                acc[1] += wgt[row] * bd * bd;
-            }
-        }
+__device__ __forceinline__ void amg_post_finish(int row, T ti, T wi, TB braw, T sum, TO *out, int os,
+                                                const double *wgt, double *acc) {
+    const T bi = static_cast<T>(braw);
+    const T x = ti + wi * (bi - sum);
+    out[static_cast<long long>(row) * os] = static_cast<TO>(x);
+    if (wgt) {
+        const double bd = static_cast<double>(braw);
+        acc[0] += bd * static_cast<double>(x);
+        acc[1] += wgt[row] * bd * bd;
     }
+}
+
+template <typename T, typename TB>
+struct PostOwn {
+    T t, w;
+    TB b;
 };
 
 template <typename T, typename TB, typename TO, bool DICT>
@@ -140,13 +168,19 @@ __global__ __launch_bounds__(kBlock) void k_amg_post_ell(int n, EllCols cols, co
     __shared__ double lds[2 * kBlock / kWave];
     if (stopped(flag)) return;
     double acc[2] = {0.0, 0.0};
-    const PostFinish<T, TB, TO> fin{wd, b, t, out, os, part ? wgt : nullptr, acc};
-    ell_rows<T, 1, 2>(
-        n, cols, e, [&](int, int c, T v, bool, T(&a)[1]) { a[0] += v * t[c]; }, fin);
+    const double *w2 = part ? wgt : nullptr;
+    using O = PostOwn<T, TB>;
+    auto load = [&](int c) { return t[c]; };
+    auto add = [&](const T &g, T v, T(&a)[1]) { a[0] += v * g; };
+    auto own = [&](long long r) { return O{t[r], wd[r], b[r]}; };
+    auto fin = [&](int row, int lane, T(&a)[1], const O &o) {
+        if (lane == 0) amg_post_finish<T, TB, TO>(row, o.t, o.w, o.b, a[0], out, os, w2, acc);
+    };
+    ell_rows_pipe<T, 1, 2, DICT, T, O>(n, cols, e, load, add, own, fin);
     if (part) write_partials<2>(acc, part, lds);
 }
 
-template <typename T, typename TB, typename TO>
+template <typename T, typename TB, typename TO, class C>
 __global__ __launch_bounds__(kBlock) void k_amg_post_csr(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                                                          const T *__restrict__ val, const T *__restrict__ wd,
                                                          const TB *__restrict__ b, const T *__restrict__ t,
@@ -155,14 +189,16 @@ __global__ __launch_bounds__(kBlock) void k_amg_post_csr(int n, const int *__res
     __shared__ double lds[2 * kBlock / kWave];
     if (stopped(flag)) return;
     double acc[2] = {0.0, 0.0};
-    const PostFinish<T, TB, TO> fin{wd, b, t, out, os, part ? wgt : nullptr, acc};
-    csr_rows<T, 1, Cfg>(
+    const double *w2 = part ? wgt : nullptr;
+    csr_rows<T, 1, C>(
         n, rp, ci, val,
         [&](int, int c, T v, bool ok, T(&a)[1]) {
             const T g = v * t[c];
             a[0] += ok ? g : T(0);
         },
-        fin);
+        [&](int row, int lane, T(&a)[1]) {
+            if (lane == 0) amg_post_finish<T, TB, TO>(row, t[row], wd[row], b[row], a[0], out, os, w2, acc);
+        });
     if (part) write_partials<2>(acc, part, lds);
 }
 
@@ -195,10 +231,13 @@ __global__ __launch_bounds__(kBlock) void k_amg_dense(int nc, const T *__restric
 }
 
 // CG update: alpha = (r.z) / (p.q), x += alpha p, r -= alpha q (p from the
-// (z, p) pairs written by the product kernel)
+// (z, p) pairs written by the product kernel), and the cycle's first
+// operand y0 = w0 .* r in the cycle's precision
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_apcg_update(int n, const RP<double> *__restrict__ nxt,
                                                         const double *__restrict__ q, double *__restrict__ x,
-                                                        double *__restrict__ r, const double *partIn, int nIn,
+                                                        double *__restrict__ r, const T *__restrict__ wd0,
+                                                        T *__restrict__ y0, const double *partIn, int nIn,
                                                         CGState *st, int it) {
     __shared__ double lds[2 * kBlock / kWave];
     if (stopped(&st->flag)) return;
@@ -216,11 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_apcg_update(int n, const RP<double> 
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         x[i] += a * nxt[i].p;
-        r[i] -= a * q[i];
+        const double ri = r[i] - a * q[i];
+        r[i] = ri;
+        if (y0) y0[i] = wd0[i] * static_cast<T>(ri);
     }
 }
 
-int csr_grid(int n) { return grid_for(n, rows_per_block<Cfg>(), 1 << 20); }
+template <class C>
+int csr_grid(int n) { return grid_for(n, rows_per_block<C>(), 1 << 20); }
 
 // reps launches of `launch` back to back between two events on s
 template <class Launch>
@@ -248,8 +290,8 @@ int ell_grid(int n, int cap) { return grid_for(n, kBlock / 2, cap); }
 }  // namespace
 
 template <typename T>
-int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, int zs, const double *wgt,
-               double *part, int *gpost, const int *flag, int grid_cap) {
+int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_ready, double *z, int zs,
+               const double *wgt, double *part, int *gpost, const int *flag, int grid_cap) {
     const int L = c.nlev;
     const bool ell0 = c.cols.any() && c.e;
     const bool dict = c.cols.pid != nullptr;
@@ -261,28 +303,47 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, 
         if (gpost) *gpost = g;
         return OASIS_OK;
     }
+    if (!y0_ready) {
+        const AmgDevLevel<T> &v = c.lv[0];
+        hipLaunchKernelGGL((k_amg_scale<T, double>), dim3(grid_for(v.n, kBlock, 8192)), dim3(kBlock), 0, s, v.n,
+                           v.wd, r, v.y, flag);
+        OASIS_TRY_LAUNCH();
+    }
     // down
     for (int l = 0; l + 1 < L; ++l) {
         const AmgDevLevel<T> &v = c.lv[l];
         if (l == 0 && ell0) {
+            const int g = ell_grid(v.n, 1 << 20);
             if (dict)
-                hipLaunchKernelGGL((k_amg_pre_ell<T, double, true>), dim3(ell_grid(v.n, 1 << 20)), dim3(kBlock), 0,
-                                   s, v.n, c.cols, c.e, v.wd, r, v.t, flag);
+                hipLaunchKernelGGL((k_amg_pre_ell<T, double, true>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols, c.e,
+                                   v.y, r, v.t, flag);
             else
-                hipLaunchKernelGGL((k_amg_pre_ell<T, double, false>), dim3(ell_grid(v.n, 1 << 20)), dim3(kBlock), 0,
-                                   s, v.n, c.cols, c.e, v.wd, r, v.t, flag);
-        } else if (l == 0) {
-            hipLaunchKernelGGL((k_amg_pre_csr<T, double>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
-                               v.val, v.wd, r, v.t, flag);
+                hipLaunchKernelGGL((k_amg_pre_ell<T, double, false>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols,
+                                   c.e, v.y, r, v.t, flag);
+            OASIS_TRY_LAUNCH();
         } else {
-            hipLaunchKernelGGL((k_amg_pre_csr<T, T>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
-                               v.val, v.wd, v.b, v.t, flag);
+            OASIS_TRY(with_lanes(v.alanes, [&](auto cfg) -> int {
+                using C = decltype(cfg);
+                if (l == 0)
+                    hipLaunchKernelGGL((k_amg_pre_csr<T, double, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s,
+                                       v.n, v.rp, v.ci, v.val, v.y, r, v.t, flag);
+                else
+                    hipLaunchKernelGGL((k_amg_pre_csr<T, T, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s, v.n,
+                                       v.rp, v.ci, v.val, v.y, v.b, v.t, flag);
+                OASIS_TRY_LAUNCH();
+                return OASIS_OK;
+            }));
         }
-        OASIS_TRY_LAUNCH();
         const AmgDevLevel<T> &nx = c.lv[l + 1];
-        hipLaunchKernelGGL((k_amg_restrict<T>), dim3(csr_grid(nx.n)), dim3(kBlock), 0, s, nx.n, v.rrp, v.rci, v.rval,
-                           v.t, nx.b, flag);
-        OASIS_TRY_LAUNCH();
+        const bool smooth_next = l + 2 < L;
+        OASIS_TRY(with_lanes(v.rlanes, [&](auto cfg) -> int {
+            using C = decltype(cfg);
+            hipLaunchKernelGGL((k_amg_restrict<T, C>), dim3(csr_grid<C>(nx.n)), dim3(kBlock), 0, s, nx.n, v.rrp,
+                               v.rci, v.rval, v.t, nx.b, smooth_next ? nx.wd : nullptr,
+                               smooth_next ? nx.y : nullptr, flag);
+            OASIS_TRY_LAUNCH();
+            return OASIS_OK;
+        }));
     }
     // coarsest
     {
@@ -296,13 +357,13 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, 
     for (int l = L - 2; l >= 0; --l) {
         const AmgDevLevel<T> &v = c.lv[l];
         const AmgDevLevel<T> &nx = c.lv[l + 1];
-        if (l == 0)
-            hipLaunchKernelGGL((k_amg_prolong<T, double>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.prp,
-                               v.pci, v.pval, nx.x, v.wd, r, v.t, flag);
-        else
-            hipLaunchKernelGGL((k_amg_prolong<T, T>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.prp, v.pci,
-                               v.pval, nx.x, v.wd, v.b, v.t, flag);
-        OASIS_TRY_LAUNCH();
+        OASIS_TRY(with_lanes(v.planes, [&](auto cfg) -> int {
+            using C = decltype(cfg);
+            hipLaunchKernelGGL((k_amg_prolong<T, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s, v.n, v.prp, v.pci,
+                               v.pval, nx.x, v.y, v.t, flag);
+            OASIS_TRY_LAUNCH();
+            return OASIS_OK;
+        }));
         if (l == 0 && ell0) {
             const int g = ell_grid(v.n, part ? grid_cap : 1 << 20);
             if (dict)
@@ -311,18 +372,25 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, 
             else
                 hipLaunchKernelGGL((k_amg_post_ell<T, double, double, false>), dim3(g), dim3(kBlock), 0, s, v.n,
                                    c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
-            if (gpost) *gpost = g;
-        } else if (l == 0) {
-            const int g = std::min(csr_grid(v.n), part ? grid_cap : 1 << 20);
-            hipLaunchKernelGGL((k_amg_post_csr<T, double, double>), dim3(g), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
-                               v.val, v.wd, r, v.t, z, zs, wgt, part, flag);
+            OASIS_TRY_LAUNCH();
             if (gpost) *gpost = g;
         } else {
-            hipLaunchKernelGGL((k_amg_post_csr<T, T, T>), dim3(csr_grid(v.n)), dim3(kBlock), 0, s, v.n, v.rp, v.ci,
-                               v.val, v.wd, v.b, v.t, v.x, 1, static_cast<const double *>(nullptr),
-                               static_cast<double *>(nullptr), flag);
+            OASIS_TRY(with_lanes(v.alanes, [&](auto cfg) -> int {
+                using C = decltype(cfg);
+                if (l == 0) {
+                    const int g = std::min(csr_grid<C>(v.n), part ? grid_cap : 1 << 20);
+                    hipLaunchKernelGGL((k_amg_post_csr<T, double, double, C>), dim3(g), dim3(kBlock), 0, s, v.n,
+                                       v.rp, v.ci, v.val, v.wd, r, v.t, z, zs, wgt, part, flag);
+                    if (gpost) *gpost = g;
+                } else {
+                    hipLaunchKernelGGL((k_amg_post_csr<T, T, T, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s, v.n,
+                                       v.rp, v.ci, v.val, v.wd, v.b, v.t, v.x, 1,
+                                       static_cast<const double *>(nullptr), static_cast<double *>(nullptr), flag);
+                }
+                OASIS_TRY_LAUNCH();
+                return OASIS_OK;
+            }));
         }
-        OASIS_TRY_LAUNCH();
     }
     return OASIS_OK;
 }
@@ -374,8 +442,11 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
                                     mode));
         return OASIS_OK;
     };
-    auto precondition = [&](int at) -> int {
-        return amg_vcycle<T>(s, c, r, zslot(at), 2, wgt, pv, &gpost, &w.st->flag, cap);
+    const bool smooth0 = c.nlev > 1;
+    // y0 = w0 .* r comes from the update kernel inside the loop, from the
+    // cycle's own scaling kernel after an explicit residual
+    auto precondition = [&](int at, bool y0_ready) -> int {
+        return amg_vcycle<T>(s, c, r, y0_ready, zslot(at), 2, wgt, pv, &gpost, &w.st->flag, cap);
     };
     OASIS_TRY(start(0, 0));
     CGState h;
@@ -392,17 +463,18 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
         out.rel_res = rel(h.wrr);
         return OASIS_OK;
     }
-    OASIS_TRY(precondition(0));
+    OASIS_TRY(precondition(0, false));
     AmgPlan plan(check_every);
     plan.restart(h.wrr, 0);
     int it = 0, restart_at = 0, rc = OASIS_OK;
     auto iterate = [&](int itj) -> int {
         OASIS_TRY(cg_product_launch(s, cap, n, rp, ci, val, cols, e64, w.pair[itj & 1], w.pair[(itj + 1) & 1],
                                     w.q, pv, gpost, 2, w.st, itj, itj == restart_at ? 1 : 0, pq, &g1));
-        hipLaunchKernelGGL(k_apcg_update, dim3(grid_for(n, kBlock, kMaxPartials)), dim3(kBlock), 0, s, n,
-                           w.pair[(itj + 1) & 1], w.q, x, r, pq, g1, w.st, itj);
+        hipLaunchKernelGGL((k_apcg_update<T>), dim3(grid_for(n, kBlock, kMaxPartials)), dim3(kBlock), 0, s, n,
+                           w.pair[(itj + 1) & 1], w.q, x, r, smooth0 ? c.lv[0].wd : nullptr,
+                           smooth0 ? c.lv[0].y : nullptr, pq, g1, w.st, itj);
         OASIS_TRY_LAUNCH();
-        return precondition(itj + 1);
+        return precondition(itj + 1, smooth0);
     };
     while (true) {
         const int m = std::min(plan.next, maxit - it);
@@ -443,14 +515,14 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
                 // repeat the cycle on the final residual maxit times (it
                 // reads r and writes only the z slot, so x is unchanged)
                 OASIS_TRY(time_repeats(s, maxit, [&] {
-                    return amg_vcycle<T>(s, c, r, zslot(at), 2, wgt, pv, &gpost, nullptr, cap);
+                    return amg_vcycle<T>(s, c, r, false, zslot(at), 2, wgt, pv, &gpost, nullptr, cap);
                 }, out));
             }
             break;
         }
         // continue from the explicit residual with a fresh direction
         out.replacements += 1;
-        OASIS_TRY(precondition(at));
+        OASIS_TRY(precondition(at, false));
         it = at;
         restart_at = at;
         plan.restart(h.wrr, at);
@@ -458,10 +530,10 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
     return rc;
 }
 
-template int amg_vcycle<double>(hipStream_t, const AmgCycle<double> &, const double *, double *, int,
+template int amg_vcycle<double>(hipStream_t, const AmgCycle<double> &, const double *, bool, double *, int,
                                 const double *, double *, int *, const int *, int);
-template int amg_vcycle<float>(hipStream_t, const AmgCycle<float> &, const double *, double *, int, const double *,
-                               double *, int *, const int *, int);
+template int amg_vcycle<float>(hipStream_t, const AmgCycle<float> &, const double *, bool, double *, int,
+                               const double *, double *, int *, const int *, int);
 template int amg_pcg_solve<double>(hipStream_t, int, const int *, const int *, const double *, const double *,
                                    const AmgCycle<double> &, const double *, const double *, double *, double, int,
                                    int, bool, double *, CGWork<double> &, SolveOut &);

@@ -60,6 +60,8 @@ struct AmgDevLevel {
     const int *rrp = nullptr, *rci = nullptr;
     const T *rval = nullptr;
     T *b = nullptr, *t = nullptr, *x = nullptr;   // right-hand side, scratch, solution
+    T *y = nullptr;                               // w .* b, the pre-smoothed iterate
+    int alanes = 4, planes = 4, rlanes = 4;       // CSR lanes per row of A, P and R
 };
 
 // The cycle in precision T: level 0's matrix is the ELL copy (cols, e),
@@ -75,13 +77,14 @@ struct AmgCycle {
 };
 
 // One V(1,1) cycle z = M^{-1} r on level 0: r is FP64 (the CG residual), z
-// is written as FP64 at z[i * zs].  With part (nullable), the last kernel
+// is written as FP64 at z[i * zs].  y0_ready: level 0's y = w .* r is
+// already in c.lv[0].y (else the cycle forms it first).  With part (nullable), the last kernel
 // writes per-block partials (r.z, sum wgt r^2) and returns its grid in
 // *gpost.  flag (nullable): a device int; while it is nonzero every kernel
 // returns at once.  grid_cap bounds the partial-writing kernel's grid.
 template <typename T>
-int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, double *z, int zs, const double *wgt,
-               double *part, int *gpost, const int *flag, int grid_cap);
+int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_ready, double *z, int zs,
+               const double *wgt, double *part, int *gpost, const int *flag, int grid_cap);
 
 // CG on level 0's matrix (FP64 ELL values e64 with c's columns) preconditioned
 // by the cycle c; stopping test sum wgt r^2 <= rtol^2 sum wgt b^2 on the

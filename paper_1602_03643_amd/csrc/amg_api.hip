@@ -79,6 +79,7 @@ void carve_levels(Carver &c, const oasis_amg &h, AmgCycle<T> &cy) {
         }
         if (l + 1 < L) {
             d.wd = c.take<T>(hl.A.n);
+            d.y = c.take<T>(hl.A.n);
             d.prp = c.take<int>(hl.A.n + 1);
             d.pci = c.take<int>(hl.P.nnz());
             d.pval = c.take<T>(hl.P.nnz());
@@ -95,6 +96,19 @@ void carve_levels(Carver &c, const oasis_amg &h, AmgCycle<T> &cy) {
     }
     cy.nc = h.levels.back().A.n;
     cy.cinv = c.take<T>(static_cast<size_t>(cy.nc) * cy.nc);
+    // CSR lanes per row from the mean row length
+    auto lanes = [](const HostCsr &M) {
+        const double avg = M.n ? static_cast<double>(M.nnz()) / M.n : 0.0;
+        return avg <= 6.0 ? 2 : avg <= 12.0 ? 4 : avg <= 28.0 ? 8 : 16;
+    };
+    for (int l = 0; l < L; ++l) {
+        const HostLevel &hl = h.levels[l];
+        cy.lv[l].alanes = lanes(hl.A);
+        if (l + 1 < L) {
+            cy.lv[l].planes = lanes(hl.P);
+            cy.lv[l].rlanes = lanes(hl.R);
+        }
+    }
 }
 
 void carve_amg(Carver &c, const oasis_amg &h, AmgImage &d) {
@@ -329,8 +343,8 @@ extern "C" int oasis_amg_vcycle(void *stream, oasis_amg *h, const double *r, dou
     if (!h || !h->uploaded || !r || !z) return OASIS_EINVAL;
     hipStream_t s = as_stream(stream);
     if (h->f32)
-        return amg_vcycle<float>(s, h->d.c32, r, z, 1, nullptr, nullptr, nullptr, nullptr, h->tun.grid_cap);
-    return amg_vcycle<double>(s, h->d.c64, r, z, 1, nullptr, nullptr, nullptr, nullptr, h->tun.grid_cap);
+        return amg_vcycle<float>(s, h->d.c32, r, false, z, 1, nullptr, nullptr, nullptr, nullptr, h->tun.grid_cap);
+    return amg_vcycle<double>(s, h->d.c64, r, false, z, 1, nullptr, nullptr, nullptr, nullptr, h->tun.grid_cap);
 }
 
 extern "C" int oasis_amg_pcg(void *stream, oasis_amg *h, const double *b, double *x, const oasis_krylov_opts *opt,
