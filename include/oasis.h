@@ -241,6 +241,21 @@ int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x,
               const oasis_krylov_opts *opt, void *ws, size_t ws_bytes,
               oasis_krylov_stats *stats);
 
+/* oasis_pcg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, with its workspace in a file-scope device array of the
+ * library of OASIS_PCG_NOALLOC_BYTES bytes (one per device, held until the
+ * process ends) instead of a caller workspace.  It calls no hipMalloc,
+ * hipFree or other allocating routine; the offset dictionary (built on the
+ * host) is not used, and OASIS_KRYLOV_TIME is refused (EINVAL).
+ * EUNSUPPORTED when oasis_krylov_workspace_size(n, nnz, 1, opt) exceeds
+ * OASIS_PCG_NOALLOC_BYTES.  All calls on one device share the array: calls
+ * that overlap on one device (other streams, other threads) race.
+ * Synchronises `stream`. */
+#define OASIS_PCG_NOALLOC_BYTES (64u << 20)
+int oasis_pcg_noalloc(void *stream, const oasis_csr *A, const double *b, double *x,
+                      const oasis_krylov_opts *opt, oasis_krylov_stats *stats);
+
 /* BiCGStab (van der Vorst) with right Jacobi preconditioning (the iteration
  * runs on A D^{-1} y = b, x = D^{-1} y, so its residual is the true one) on
  * an F64 CSR matrix, for nrhs in {1,2,3} right-hand sides sharing A (one

@@ -15,10 +15,10 @@ from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUN
 _lib.load()
 
 from .api import (AMG, IPCS, MPNN, DeviceCSR, DeviceMesh, assemble_p1, bicgstab, color_cells,  # noqa: E402
-                  color_classes, colorize, p1_pattern, pcg, rcm, relabel, spmv)
+                  color_classes, colorize, p1_pattern, pcg, pcg_noalloc, rcm, relabel, spmv)
 
 __all__ = ["AMG", "IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bicgstab", "color_cells", "color_classes",
-           "colorize", "p1_pattern", "pcg", "rcm", "relabel", "spmv", "OasisError",
+           "colorize", "p1_pattern", "pcg", "pcg_noalloc", "rcm", "relabel", "spmv", "OasisError",
            "OK", "EINVAL", "EHIP", "ENOTCONV", "EBREAKDOWN", "ENAN", "EWORKSPACE", "EUNSUPPORTED", "F32", "F64",
            "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV", "PSTART_PREV",
            "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS",

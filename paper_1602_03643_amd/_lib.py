@@ -20,6 +20,7 @@ ASSEMBLE_ROWS, ASSEMBLE_COLORS = 0, 1
 PSTART_PREV, PSTART_ZERO = 0, 1
 INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS = 100, 101, 102
 STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR = 0, 1, 2
+PCG_NOALLOC_BYTES = 64 << 20
 CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE = 0, 1, 2
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
@@ -99,6 +100,7 @@ _SIGS = {
     "oasis_spmv": (i32, [vp, P(Csr), vp, vp, f64, f64]),
     "oasis_krylov_workspace_size": (i32, [i32, i32, i32, P(KrylovOpts), P(sz)]),
     "oasis_pcg": (i32, [vp, P(Csr), vp, vp, P(KrylovOpts), vp, sz, P(KrylovStats)]),
+    "oasis_pcg_noalloc": (i32, [vp, P(Csr), vp, vp, P(KrylovOpts), P(KrylovStats)]),
     "oasis_bicgstab": (i32, [vp, P(Csr), i32, vp, vp, P(KrylovOpts), vp, sz, P(KrylovStats)]),
     "oasis_amg_setup": (i32, [vp, P(Csr), vp, P(AmgParams), P(vp)]),
     "oasis_amg_workspace_size": (i32, [vp, P(sz)]),

@@ -237,6 +237,23 @@ def pcg(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=
     return out
 
 
+def pcg_noalloc(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=0.1, check_every=0,
+                stream=None, raise_on=True, nullspace_const=False, storage=L.STORAGE_ELL, grid_cap=0,
+                cg_form=L.CG_FORM_AUTO):
+    """oasis_pcg with the library's own scratch array as workspace (no
+    device allocation here or in the library)."""
+    o = _opts(rtol, maxit, precision, inner_rtol, 0, check_every, False, _tuning(storage, grid_cap, cg_form))
+    if nullspace_const:
+        o.flags |= L.KRYLOV_NULLSPACE_CONST
+    st = L.KrylovStats()
+    rc = _lib().oasis_pcg_noalloc(_stream(stream), C.byref(A.c()), _p(b), _p(x), C.byref(o), C.byref(st))
+    if raise_on:
+        L.check(rc, "oasis_pcg_noalloc", allow=(L.ENOTCONV, L.EBREAKDOWN, L.ENAN))
+    out = _stats(st)
+    out["rc"] = rc
+    return out
+
+
 def bicgstab(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4, max_outer=50,
              check_every=0, time_kernel=False, ws=None, stream=None, raise_on=True,
              storage=L.STORAGE_AUTO, grid_cap=0):

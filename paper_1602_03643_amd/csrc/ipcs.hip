@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1416,8 +1417,11 @@ static int check_opts(const oasis_krylov_opts *o) {
     return Tuning::from(&o->tuning, &t);
 }
 
-extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x, const oasis_krylov_opts *opt,
-                         void *ws, size_t ws_bytes, oasis_krylov_stats *stats) {
+// The stand-alone PCG on a workspace ws (the caller's, or the library's
+// no-allocation scratch array with `dict` false: the offset dictionary is
+// built on the host, which the no-allocation entry point must not do).
+static int pcg_run(void *stream, const oasis_csr *A, const double *b, double *x, const oasis_krylov_opts *opt,
+                   void *ws, size_t ws_bytes, oasis_krylov_stats *stats, bool dict) {
     OASIS_TRY(check_csr(A));
     OASIS_TRY(check_opts(opt));
     if (A->dtype != OASIS_F64 || !b || !x || !ws || !stats || !aligned(ws, 256)) return OASIS_EINVAL;
@@ -1429,6 +1433,7 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     if (!c.ok) return OASIS_EWORKSPACE;
     Tuning tun;
     (void)Tuning::from(&opt->tuning, &tun);
+    if (!dict && tun.storage == OASIS_STORAGE_AUTO) tun.storage = OASIS_STORAGE_ELL;
     k.cg.tun = k.cg32.tun = tun;
     k.bi.tun = k.bi32.tun = tun;
     hipStream_t s = as_stream(stream);
@@ -1481,6 +1486,57 @@ extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, doub
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     fill_stats(so, ell_storage, stats);
     return rc;
+}
+
+extern "C" int oasis_pcg(void *stream, const oasis_csr *A, const double *b, double *x, const oasis_krylov_opts *opt,
+                         void *ws, size_t ws_bytes, oasis_krylov_stats *stats) {
+    return pcg_run(stream, A, b, x, opt, ws, ws_bytes, stats, true);
+}
+
+// ---------------------------------------------------------------------------
+// PCG without any allocation: the workspace is a file-scope device array.
+// Host code never passes the array's name to a kernel or a copy: each
+// device's copy of the array has its own address, obtained once per device
+// with hipGetSymbolAddress and kept in scratch_addr.
+
+constexpr size_t kScratchBytes = OASIS_PCG_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex scratch_mu;
+static void *scratch_addr[kMaxDevices] = {};
+
+// The address of the current device's scratch array (looked up on the first
+// call on that device).
+static int scratch_ptr(void **out) {
+    int dev = 0;
+    OASIS_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return OASIS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return OASIS_EHIP;
+        }
+        scratch_addr[dev] = p;
+    }
+    *out = scratch_addr[dev];
+    return OASIS_OK;
+}
+
+extern "C" int oasis_pcg_noalloc(void *stream, const oasis_csr *A, const double *b, double *x,
+                                 const oasis_krylov_opts *opt, oasis_krylov_stats *stats) {
+    OASIS_TRY(check_csr(A));
+    OASIS_TRY(check_opts(opt));
+    if (opt->flags & OASIS_KRYLOV_TIME) return OASIS_EINVAL;     // the timing mode creates events
+    size_t need = 0;
+    OASIS_TRY(oasis_krylov_workspace_size(A->n, A->nnz, 1, opt, &need));
+    if (need > kScratchBytes) return OASIS_EUNSUPPORTED;
+    void *ws = nullptr;
+    OASIS_TRY(scratch_ptr(&ws));
+    return pcg_run(stream, A, b, x, opt, ws, kScratchBytes, stats, false);
 }
 
 extern "C" int oasis_bicgstab(void *stream, const oasis_csr *A, int32_t nrhs, const double *b, double *x,
