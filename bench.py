@@ -35,7 +35,8 @@ Also printed in the one JSON line:
                 committed rocprofv3 counter summary when its sources match
   cpu_baseline  the FP64 oracle as it stands: one whole step (step 2, after
                 an untimed step 1) on the same 129 x 129 x 97 mesh, in a
-                single-threaded process
+                single-threaded child process that runs on one host core
+                while the GPU variants are timed
 """
 from __future__ import annotations
 
@@ -275,19 +276,24 @@ def cpu_model():
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(size, threads):
-    """The oracle as it stands on the benchmark mesh, in a child process
+def cpu_baseline_start(size, threads):
+    """Start the oracle as it stands on the benchmark mesh in a child process
     whose BLAS/OpenMP pools are held to `threads` threads (scipy's CSR
     product is single-threaded whatever the setting): set-up untimed, step 1
-    untimed, step 2 timed."""
+    untimed, step 2 timed.  It uses no GPU and one host core, so it runs
+    while the GPU variants are timed."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[k] = str(threads)
     code = CPU_SNIPPET % {"root": ROOT, "size": size}
-    r = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, env=env, timeout=900)
-    if r.returncode != 0:
-        raise RuntimeError("oracle baseline failed (%d)" % r.returncode)
-    return json.loads(r.stdout.strip().split("\n")[-1])
+    return subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, env=env)
+
+
+def cpu_baseline_wait(proc):
+    out, _ = proc.communicate(timeout=1200)
+    if proc.returncode != 0:
+        raise RuntimeError("oracle baseline failed (%d)" % proc.returncode)
+    return json.loads(out.strip().split("\n")[-1])
 
 
 def main():
@@ -316,6 +322,10 @@ def main():
     import synth
 
     dev = torch.device("cuda", 0)
+    cpu_proc = None
+    if not args.no_cpu:
+        log("starting the CPU oracle on %s (set-up and step 1 untimed, step 2 timed) ..." % args.size)
+        cpu_proc = cpu_baseline_start(args.size, 1)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -378,21 +388,24 @@ def main():
                                    "guess_used": results[k]["guess_used"]}
 
     # per-field error of the FP32-inner runs against the FP64 runs
+    # (and, for scale, the spread between two FP64 runs with different
+    # pressure solvers at the same tolerance)
     mixed_error = None
     if args.error_steps > 0:
         mixed_error = {"steps": args.error_steps}
-        for ref, v in (("fp64_amg", "mixed_amg"), ("fp64", "mixed")):
-            if ref not in results and v not in results:
-                continue
-            finals = {}
-            for tag in (ref, v):
+        finals = {}
+        for tag in ("fp64_amg", "mixed_amg", "fp64", "mixed"):
+            if tag in results:
                 _, prec, pstart, amg = parse(tag)
-                hh, _, fin = run_variant(oa, torch, pr, dm, pat, bcd, prec, 0, args.error_steps, tag + "/error",
-                                         None, pstart, amg)
-                finals[tag] = fin
+                hh, _, finals[tag] = run_variant(oa, torch, pr, dm, pat, bcd, prec, 0, args.error_steps,
+                                                 tag + "/error", None, pstart, amg)
                 hh.close()
-            mixed_error[v] = dict(field_errors(finals[v], finals[ref]), against=ref)
-            log("[%s] per-field error vs %s after %d steps: %s" % (v, ref, args.error_steps, mixed_error[v]))
+        for v, ref in (("mixed_amg", "fp64_amg"), ("mixed", "fp64"), ("fp64_amg", "fp64")):
+            if v in finals and ref in finals:
+                key = v if v.startswith("mixed") else "%s_vs_%s" % (v, ref)
+                mixed_error[key] = dict(field_errors(finals[v], finals[ref]), against=ref)
+                log("[%s] per-field relative L2 vs %s after %d steps: %s" % (v, ref, args.error_steps,
+                                                                             mixed_error[key]))
 
     # config 4: displaced mesh, random numbering, on-device RCM
     config4 = None
@@ -431,9 +444,9 @@ def main():
                                           achieved=round(kb32 / (a32 * 1e-3) / 1e9, 1))
 
     cpu = None
-    if not args.no_cpu:
-        log("timing the CPU oracle on %s (set-up and step 1 untimed, step 2 timed) ..." % m.name)
-        d1 = cpu_baseline(args.size, 1)
+    if cpu_proc is not None:
+        log("waiting for the CPU oracle ...")
+        d1 = cpu_baseline_wait(cpu_proc)
         cpu = dict(value=1.0 / d1["step2_s"], unit="steps/s", cores=1, kind="oracle",
                    sample=("one whole FP64 oracle step (step 2, after an untimed step 1) of the %s channel "
                            "(%d dofs/field; %d Jacobi-PCG, %s BiCGStab iterations) in a single-threaded "
@@ -444,7 +457,7 @@ def main():
                    cpu_model=cpu_model(), host_threads=os.cpu_count())
         if args.cpu_all_cores:
             nt = os.cpu_count() or 1
-            d2 = cpu_baseline(args.size, nt)
+            d2 = cpu_baseline_wait(cpu_baseline_start(args.size, nt))
             cpu["all_cores"] = dict(value=1.0 / d2["step2_s"], cores=nt, step2_s=d2["step2_s"])
     line = {
         "metric": METRIC,
