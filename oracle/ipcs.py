@@ -16,7 +16,7 @@ Readings (where the paper is silent or inconsistent):
   eq:pressure and eq:pressureVF print the opposite sign.
 * The velocity update subtracts dt * M_L^{-1} dP^k phi (the correction phi,
   as in eq:correction), not the full pressure.
-* One inner iteration (plain IPCS), lumped-mass update.
+* By default one inner iteration (plain IPCS) and the lumped-mass update.
 * Dirichlet rows of A become identity rows (columns kept); b_i = g_i there.
   All velocity components share the Dirichlet dof set, so one A serves all.
 * No pressure boundary condition: b_phi is projected onto 1-perp before the
@@ -27,6 +27,30 @@ Readings (where the paper is silent or inconsistent):
   phi_0 = 0, i.e. solving for p from p*, as the pressure-solve routine of
   the naive solver (Sec. 4) would with an iterative solver.  A caller
   guess (phi_guess) replaces either.
+
+Options beyond the channel runs' configuration (Alg. 1 in general, Sec. 5's
+other update types, eq:scalar_disc):
+* inner_iters > 1: Alg. 1's inner velocity-pressure loop.  The coefficient
+  matrix and b_tmp are built on the first inner iteration only (Sec. 5:
+  the convecting velocity holds only known velocities); every inner
+  iteration subtracts the gradient of the current p* (eq:dp_matrix),
+  solves the tentative velocity (from U^{n-1} on the first iteration, from
+  the previous U^I after), the pressure correction (from the plain start
+  on the first iteration, from 0 after: it corrects the p* just updated),
+  and sets p* = p* + phi.  The velocity update uses the last correction,
+  which also becomes phi_prev.
+* update="consistent": eq:velocity_update, M U^n = M U^I - dt dP^k phi,
+  solved by Jacobi-PCG from U^I to rtol_u.  Dirichlet values are imposed by
+  symmetric elimination (rows and columns of the Dirichlet dofs removed,
+  their known values moved to the right-hand side), which has the same
+  solution as identity rows and keeps the matrix SPD for CG.
+* scalars: eq:scalar_disc with the convection term of the paper's scalar
+  discretisation, u_bar . grad(c~) with the same Adams-Bashforth u_bar and
+  Crank-Nicolson c~, i.e. the tentative-velocity system with nu replaced
+  by D_alpha and no pressure gradient, assembled in Alg. 2's order:
+  (M/dt + C/2 + D K/2) c^n = (M/dt - C/2 - D K/2) c^{n-1} + f_alpha M_L,
+  solved after the velocity update (Alg. 1) by BiCGStab + Jacobi from
+  c^{n-1}.  Dirichlet values on the velocity's Dirichlet dofs.
 """
 from __future__ import annotations
 
@@ -59,6 +83,16 @@ class State:
     p: np.ndarray           # [N]     p* (pressure from the last step)
     phi_prev: np.ndarray    # [N]
     t: float
+    C1: np.ndarray | None = None   # [n_scalars, N] c^{n-1}
+
+
+@dataclasses.dataclass
+class Scalar:
+    """A passive scalar of eq:scalar: diffusivity D, constant source f and
+    its Dirichlet values bc(t) -> [n_bc] on the velocity's Dirichlet dofs."""
+    D: float
+    f: float = 0.0
+    bc: object = None
 
 
 @dataclasses.dataclass
@@ -74,6 +108,9 @@ class StepOut:
     res_u: list
     res_p: float
     status: int
+    phis: list = dataclasses.field(default_factory=list)    # phi of every inner iteration
+    iters_m: list = dataclasses.field(default_factory=list)  # consistent-update CG iterations
+    iters_c: list = dataclasses.field(default_factory=list)  # scalar BiCGStab iterations
 
 
 def setup(mesh, nu, dt, f):
@@ -99,8 +136,9 @@ def apply_dirichlet_rows(A, rows):
     return A
 
 
-def tentative_system(S: Setup, st: State, t_new: float, bc_vals):
-    """Alg. 2 literal: returns (A after BC rows, b [d, N] after BC values)."""
+def tentative_system(S: Setup, st: State, t_new: float, bc_vals, with_tmp=False):
+    """Alg. 2 literal: returns (A after BC rows, b [d, N] after BC values),
+    and b_tmp with with_tmp."""
     mesh = S.mesh
     d = mesh.dim
     ubar = 1.5 * st.U1 - 0.5 * st.U2
@@ -112,10 +150,64 @@ def tentative_system(S: Setup, st: State, t_new: float, bc_vals):
     A = -1.0 * A                                         # A._scale(-1)
     A = A + (2.0 / S.dt) * S.M                           # A.axpy(2/dt, M)
     A = apply_dirichlet_rows(A, mesh.bc_dofs)
-    b = np.stack([b_tmp[k] - S.dP[k] @ st.p for k in range(d)])
-    if mesh.bc_dofs.size:
-        b[:, mesh.bc_dofs] = bc_vals
+    b = tentative_rhs(S, b_tmp, st.p, bc_vals)
+    if with_tmp:
+        return A.tocsr(), b, b_tmp
     return A.tocsr(), b
+
+
+def tentative_rhs(S: Setup, b_tmp, p_star, bc_vals):
+    """b^k = b_tmp^k - dP^k p* with the Dirichlet values."""
+    b = np.stack([b_tmp[k] - S.dP[k] @ p_star for k in range(S.mesh.dim)])
+    if S.mesh.bc_dofs.size:
+        b[:, S.mesh.bc_dofs] = bc_vals
+    return b
+
+
+def scalar_system(S: Setup, st: State, c1, sc: Scalar, bc_vals):
+    """eq:scalar_disc assembled in Alg. 2's order with D in place of nu and
+    the scalar's source: returns (A_c after Dirichlet rows, b_c)."""
+    ubar = 1.5 * st.U1 - 0.5 * st.U2
+    A = p1.convection_matrix(S.mesh, ubar, S.geo)        # A <- C(u_bar)
+    A = -0.5 * A
+    A = A + (1.0 / S.dt) * S.M
+    A = A + (-0.5 * sc.D) * S.K
+    b = sc.f * S.ML + A @ c1
+    A = -1.0 * A
+    A = A + (2.0 / S.dt) * S.M
+    A = apply_dirichlet_rows(A, S.mesh.bc_dofs)
+    if S.mesh.bc_dofs.size:
+        b[S.mesh.bc_dofs] = bc_vals
+    return A.tocsr(), b
+
+
+def consistent_update(S: Setup, UI, phi, g, rtol, maxit):
+    """eq:velocity_update by Jacobi-PCG with the Dirichlet dofs eliminated
+    symmetrically; returns (U^n [d, N], iterations per component)."""
+    mesh = S.mesh
+    n = mesh.n_dof
+    bc = mesh.bc_dofs
+    keep = np.ones(n)
+    keep[bc] = 0.0
+    Kp = sp.diags(keep)
+    Mbc = (Kp @ S.M @ Kp + sp.diags(1.0 - keep)).tocsr()
+    Un = np.empty_like(UI)
+    its = []
+    for k in range(mesh.dim):
+        rhs = S.M @ UI[k] - S.dt * (S.dP[k] @ phi)
+        if bc.size:
+            gk = np.zeros(n)
+            gk[bc] = g[k]
+            rhs = keep * (rhs - S.M @ gk) + gk
+        x0 = UI[k].copy()
+        if bc.size:
+            x0[bc] = g[k]
+        r = krylov.pcg(Mbc, rhs, x0, rtol=rtol, maxit=maxit)
+        Un[k] = r.x
+        its.append(r.iters)
+    if bc.size:
+        Un[:, bc] = g
+    return Un, its
 
 
 def pressure_rhs(S: Setup, UI):
@@ -124,34 +216,63 @@ def pressure_rhs(S: Setup, UI):
 
 
 def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
-         phi_guess=None, pressure_start="prev") -> StepOut:
-    """Advance one time step.  bc_values: callable t -> [d, n_bc]."""
+         phi_guess=None, pressure_start="prev", inner_iters=1, update="lumped", scalars=()) -> StepOut:
+    """Advance one time step (Alg. 1).  bc_values: callable t -> [d, n_bc]."""
     mesh = S.mesh
     d = mesh.dim
     t_new = st.t + S.dt
     g = bc_values(t_new) if mesh.bc_dofs.size else np.zeros((d, 0))
-    A, b = tentative_system(S, st, t_new, g)
-    UI = np.empty_like(st.U1)
-    iters_u, res_u = [], []
-    status = 0
-    for k in range(d):
-        r = krylov.bicgstab(A, b[k], st.U1[k], rtol=rtol_u, maxit=maxit)
-        UI[k] = r.x
-        iters_u.append(r.iters)
-        res_u.append(r.rel_res)
-        status = max(status, r.status)
-    b_phi = pressure_rhs(S, UI)
-    x0 = plain_pressure_start(st, b_phi, pressure_start) if phi_guess is None else phi_guess
-    rp = krylov.pcg(S.K, b_phi, x0, rtol=rtol_p, maxit=maxit)
-    status = max(status, rp.status)
-    phi = rp.x - rp.x.mean()
-    p_new = st.p + phi
-    p_new = p_new - p_new.mean()
-    Un = np.stack([UI[k] - S.dt * (S.dP[k] @ phi) / S.ML for k in range(d)])
-    if mesh.bc_dofs.size:
-        Un[:, mesh.bc_dofs] = g
-    new = State(Un, st.U1.copy(), p_new, phi, t_new)
-    return StepOut(new, A, b, UI, b_phi, phi, iters_u, rp.iters, res_u, rp.rel_res, status)
+    A, b, b_tmp = tentative_system(S, st, t_new, g, with_tmp=True)
+    UI = st.U1.copy()
+    iters_u, res_u = [0] * d, [0.0] * d
+    iters_p, res_p, status = 0, 0.0, 0
+    p_star = st.p
+    phis = []
+    for i in range(inner_iters):
+        if i > 0:
+            b = tentative_rhs(S, b_tmp, p_star, g)
+        for k in range(d):
+            r = krylov.bicgstab(A, b[k], UI[k], rtol=rtol_u, maxit=maxit)
+            UI[k] = r.x
+            iters_u[k] += r.iters
+            res_u[k] = r.rel_res
+            status = max(status, r.status)
+        b_phi = pressure_rhs(S, UI)
+        if i == 0:
+            x0 = plain_pressure_start(st, b_phi, pressure_start) if phi_guess is None else phi_guess
+        else:
+            x0 = np.zeros_like(b_phi)
+        rp = krylov.pcg(S.K, b_phi, x0, rtol=rtol_p, maxit=maxit)
+        status = max(status, rp.status)
+        iters_p += rp.iters
+        res_p = rp.rel_res
+        phi = rp.x - rp.x.mean()
+        p_star = p_star + phi
+        p_star = p_star - p_star.mean()
+        phis.append(phi)
+    p_new = p_star
+    iters_m = []
+    if update == "lumped":
+        Un = np.stack([UI[k] - S.dt * (S.dP[k] @ phi) / S.ML for k in range(d)])
+        if mesh.bc_dofs.size:
+            Un[:, mesh.bc_dofs] = g
+    elif update == "consistent":
+        Un, iters_m = consistent_update(S, UI, phi, g, rtol_u, maxit)
+    else:
+        raise ValueError(update)
+    C1 = st.C1
+    Cn, iters_c = None, []
+    if scalars:
+        Cn = np.empty_like(C1)
+        for a, sc in enumerate(scalars):
+            gc = sc.bc(t_new) if mesh.bc_dofs.size else np.zeros(0)
+            Ac, bc_ = scalar_system(S, st, C1[a], sc, gc)
+            r = krylov.bicgstab(Ac, bc_, C1[a], rtol=rtol_u, maxit=maxit)
+            Cn[a] = r.x
+            iters_c.append(r.iters)
+            status = max(status, r.status)
+    new = State(Un, st.U1.copy(), p_new, phi, t_new, Cn)
+    return StepOut(new, A, b, UI, b_phi, phi, iters_u, iters_p, res_u, res_p, status, phis, iters_m, iters_c)
 
 
 def plain_pressure_start(st: State, b_phi, pressure_start="prev"):
@@ -162,9 +283,9 @@ def plain_pressure_start(st: State, b_phi, pressure_start="prev"):
     raise ValueError(pressure_start)
 
 
-def initial_state(problem) -> State:
+def initial_state(problem, C1=None) -> State:
     return State(problem.U1.copy(), problem.U2.copy(), problem.p.copy(),
-                 problem.phi_prev.copy(), problem.t0)
+                 problem.phi_prev.copy(), problem.t0, None if C1 is None else np.array(C1, dtype=float))
 
 
 def run(problem, steps, rtol_u=None, rtol_p=None, callback=None):
