@@ -30,6 +30,8 @@ Also printed in the one JSON line:
   config4       the displaced mesh with randomly permuted numbering,
                 reordered by the on-device RCM, timed with the headline
                 solver configuration
+  extensions    the headline configuration with Alg. 1's inner iterations
+                (2), the consistent-mass update, or one passive scalar
   roofline      the dominant kernel timed live over repeated launches
                 against its algorithmic bytes, with the HBM traffic of the
                 committed rocprofv3 counter summary when its sources match
@@ -137,15 +139,18 @@ def device_problem(oa, torch, synth, pr, dev, rcm=False):
 
 
 def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm=None, pstart=0, amg=None,
-                perm=None, dof_coords=None):
+                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0):
     """Time `steps` steps after `warmup` untimed ones; returns the handle, the
-    results and the final (U, p, phi)."""
+    results and the final (U, p, phi).  scalars: that many passive scalars
+    with Prandtl number 0.71 (D = nu / 0.71), Dirichlet values y on the
+    walls and the start y plus seeded U(-0.05, 0.05) noise."""
     import numpy as np
     dev = dm.coords.device
     m = pr.mesh
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, bcd, rtol_u=pr.rtol_u, rtol_p=pr.rtol_p, precision=precision,
-                inner_rtol=1e-4, pressure_start=pstart)
+                inner_rtol=1e-4, pressure_start=pstart, inner_iters=inner_iters, velocity_update=velocity_update,
+                diffusivity=[pr.nu / 0.71] * scalars)
 
     def T(a):
         """Host field [..., n] onto the device, in the reordered numbering."""
@@ -174,10 +179,22 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
     bc = torch.zeros(3 * bcd.numel(), dtype=torch.float64, device=dev)      # no-slip walls
     bufs = [torch.empty_like(U[0]) for _ in range(3)]
     stats = []
+    Cs = None
+    if scalars:
+        y = m.dof_coords[:, 1]
+        rng = np.random.default_rng(17)
+        c1 = np.stack([y + rng.uniform(-0.05, 0.05, y.size) for _ in range(scalars)])
+        c1[:, m.bc_dofs] = y[m.bc_dofs]
+        Cs = [T(c1), torch.empty_like(T(c1))]
+        cbc = torch.as_tensor(np.stack([y[m.bc_dofs]] * scalars), dtype=torch.float64, device=dev)
 
     def one(i):
         Un = bufs[i % 3] if bufs[i % 3].data_ptr() not in (U[0].data_ptr(), U[1].data_ptr()) else bufs[(i + 1) % 3]
-        st = h.step(U[1], U[0], Un, p, phi, bc_values=bc)
+        if Cs is not None:
+            st = h.step(U[1], U[0], Un, p, phi, bc_values=bc, C1=Cs[0], Cn=Cs[1], C_bc=cbc)
+            Cs.reverse()
+        else:
+            st = h.step(U[1], U[0], Un, p, phi, bc_values=bc)
         U[0], U[1] = U[1], Un
         return st
 
@@ -209,6 +226,11 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
                    guess_used=mean("guess_used"),
                    max_res_p=float(max(s["res_p"] for s in stats)),
                    max_res_u=float(max(max(s["res_u"]) for s in stats)))
+        if velocity_update:
+            res["iters_m"] = [float(np.mean([s["iters_m"][k] for s in stats])) for k in range(3)]
+        if scalars:
+            res.update(iters_c=[float(np.mean([s["iters_c"][a] for s in stats])) for a in range(scalars)],
+                       ms_scalars=mean("ms_scalars"))
         log("[%s] %.2f steps/s (%.2f ms/step), iters_p %.1f, iters_u %s" %
             (tag, res["steps_per_s"], res["ms_per_step"], res["iters_p"], res["iters_u"]))
     return h, res, (U[1], p, phi)
@@ -310,6 +332,9 @@ def main():
     ap.add_argument("--cpu-all-cores", action="store_true", help="also time the oracle with every host thread")
     ap.add_argument("--error-steps", type=int, default=50, help="0 skips the per-field mixed-precision error")
     ap.add_argument("--no-config4", action="store_true")
+    ap.add_argument("--ext-steps", type=int, default=10,
+                    help="timed steps of the headline configuration with each option beyond the channel runs' "
+                         "(inner iterations, consistent update, a passive scalar); 0 skips them")
     ap.add_argument("--kernel-iters", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -422,6 +447,18 @@ def main():
                                 "dofs randomly permuted (seed 2000), reordered by the on-device RCM")
         h4.close()
 
+    # options beyond the channel runs' configuration, on the headline solvers
+    extensions = None
+    if args.ext_steps > 0:
+        extensions = {}
+        for name, kw in (("inner_iters_2", dict(inner_iters=2)),
+                         ("consistent_update", dict(velocity_update=oa.UPDATE_CONSISTENT)),
+                         ("one_scalar", dict(scalars=1))):
+            hh, res, _ = run_variant(oa, torch, pr, dm, pat, bcd, hprec, args.ext_steps, 3, head + "+" + name,
+                                     None, hstart, hamg, **kw)
+            extensions[name] = dict(res, base=head)
+            hh.close()
+
     # dominant kernel of the headline path and its live timing
     sr = hprec == oa.F32 and hamg is None    # the FP32 Jacobi-CG iteration is one single-reduction kernel
     vbytes = 4 if sr else 8
@@ -484,6 +521,7 @@ def main():
         "learned_gain": learned_gain,
         "mixed_error": mixed_error,
         "config4": config4,
+        "extensions": extensions,
         "roofline": roof,
         "cpu_baseline": cpu,
         "setup_s": {"graph": gtimes["graph_s"]},

@@ -371,12 +371,34 @@ typedef struct {
     double pressure_delta;    /* F32 mode: the pressure CG replaces its FP32 residual by the FP64
                                  one each time the former fell by this factor (0 = 0.03) */
     oasis_tuning tuning;      /* Krylov storage and kernel shapes of the step's solves */
+    int32_t inner_iters;      /* Alg. 1's inner velocity-pressure iterations (0 = 1, at most 16):
+                                 the coefficient matrix and the right-hand side's explicit part
+                                 are built once; each iteration subtracts the gradient of the
+                                 current p* (eq:dp_matrix), solves the tentative velocity (from
+                                 U^{n-1}, then from the previous U^I) and the pressure correction
+                                 (from the plain start, then from 0) and sets p* += phi; the
+                                 velocity update uses the last correction */
+    int32_t velocity_update;  /* OASIS_UPDATE_LUMPED: U^n = U^I - dt M_L^-1 dP^k phi (the channel
+                                 runs of Sec. 6.2); OASIS_UPDATE_CONSISTENT: M U^n = M U^I -
+                                 dt dP^k phi (eq:velocity_update) by Jacobi-PCG in FP64 to rtol_u,
+                                 the Dirichlet dofs eliminated symmetrically */
+    int32_t n_scalars;        /* passive scalars solved after the velocity update (Alg. 1),
+                                 0..OASIS_MAX_SCALARS: eq:scalar_disc with the velocity's u_bar
+                                 and Crank-Nicolson, i.e. (M/dt + C/2 + D K/2) c^n =
+                                 (M/dt - C/2 - D K/2) c^{n-1} + f M_L, Dirichlet values on the
+                                 velocity's Dirichlet dofs, BiCGStab + Jacobi to rtol_u in the
+                                 step's precision */
+    double diffusivity[4];    /* D_alpha of each scalar */
+    double scalar_source[4];  /* constant f_alpha of each scalar */
 } oasis_ipcs_params;
 
+#define OASIS_MAX_SCALARS 4
 #define OASIS_ASSEMBLE_ROWS 0
 #define OASIS_ASSEMBLE_COLORS 1
 #define OASIS_PSTART_PREV 0
 #define OASIS_PSTART_ZERO 1
+#define OASIS_UPDATE_LUMPED 0
+#define OASIS_UPDATE_CONSISTENT 1
 
 typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
 
@@ -388,7 +410,9 @@ typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
  *         OASIS_PSTART_PREV, and an input of an attached warm start), the
  *         new correction on return
  *  UI[k], b_phi: optional (NULL) outputs of the tentative velocity and the
- *  projected pressure right-hand side. */
+ *  projected pressure right-hand side (of the last inner iteration).
+ *  C1[a]  c_a^{n-1} (read), Cn[a] c_a^n (written), C_bc[a] its Dirichlet
+ *  values at t^n (device double [n_bc]), for a < n_scalars. */
 typedef struct {
     const double *U1[3];
     const double *U2[3];
@@ -397,15 +421,24 @@ typedef struct {
     double *phi;
     double *UI[3];
     double *b_phi;
+    const double *C1[4];
+    double *Cn[4];
+    const double *C_bc[4];
 } oasis_state;
 
 typedef struct {
-    int32_t iters_u[3], iters_p;
+    int32_t iters_u[3], iters_p;  /* summed over inner iterations */
     int32_t outer_u, outer_p;
     int32_t status;           /* worst Krylov status of the step */
     int32_t guess_used;       /* 1 if the guess had a smaller residual than the plain start */
-    double res_u[3], res_p;   /* final true relative residuals */
-    double ms_assemble, ms_velocity, ms_pressure, ms_update, ms_total;  /* HIP-event phase times */
+    double res_u[3], res_p;   /* final true relative residuals (last inner iteration) */
+    double ms_assemble, ms_velocity, ms_pressure, ms_update, ms_total;  /* HIP-event phase times;
+                                 with inner iterations, ms_velocity is the first velocity solve
+                                 and ms_pressure runs to the end of the last pressure solve */
+    int32_t iters_m[3];       /* consistent update: CG iterations per component */
+    int32_t iters_c[4];       /* BiCGStab iterations per scalar */
+    double res_c[4];
+    double ms_scalars;        /* scalar phase (included in ms_total) */
 } oasis_step_stats;
 
 /* Workspace for a handle on this mesh/pattern/params. */

@@ -10,7 +10,7 @@ from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUN
                    FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, PSTART_PREV,
                    PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS,
                    STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR, CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE,
-                   OasisError)
+                   UPDATE_LUMPED, UPDATE_CONSISTENT, MAX_SCALARS, OasisError)
 
 _lib.load()
 
@@ -22,4 +22,5 @@ __all__ = ["AMG", "IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bic
            "OK", "EINVAL", "EHIP", "ENOTCONV", "EBREAKDOWN", "ENAN", "EWORKSPACE", "EUNSUPPORTED", "F32", "F64",
            "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV", "PSTART_PREV",
            "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS",
-           "STORAGE_AUTO", "STORAGE_ELL", "STORAGE_CSR", "CG_FORM_AUTO", "CG_FORM_TWO", "CG_FORM_SINGLE"]
+           "STORAGE_AUTO", "STORAGE_ELL", "STORAGE_CSR", "CG_FORM_AUTO", "CG_FORM_TWO", "CG_FORM_SINGLE",
+           "UPDATE_LUMPED", "UPDATE_CONSISTENT", "MAX_SCALARS"]

@@ -18,6 +18,8 @@ KRYLOV_TIME = 1
 KRYLOV_NULLSPACE_CONST = 2
 ASSEMBLE_ROWS, ASSEMBLE_COLORS = 0, 1
 PSTART_PREV, PSTART_ZERO = 0, 1
+UPDATE_LUMPED, UPDATE_CONSISTENT = 0, 1
+MAX_SCALARS = 4
 INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS = 100, 101, 102
 STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR = 0, 1, 2
 PCG_NOALLOC_BYTES = 64 << 20
@@ -73,19 +75,21 @@ class IpcsParams(C.Structure):
     _fields_ = [("dt", f64), ("nu", f64), ("f", f64 * 3), ("n_bc", i32), ("bc_dofs", vp),
                 ("rtol_u", f64), ("rtol_p", f64), ("maxit", i32), ("precision", i32),
                 ("inner_rtol", f64), ("assembly", i32), ("pressure_start", i32),
-                ("pressure_delta", f64), ("tuning", Tuning)]
+                ("pressure_delta", f64), ("tuning", Tuning), ("inner_iters", i32), ("velocity_update", i32),
+                ("n_scalars", i32), ("diffusivity", f64 * 4), ("scalar_source", f64 * 4)]
 
 
 class State(C.Structure):
     _fields_ = [("U1", vp * 3), ("U2", vp * 3), ("Un", vp * 3), ("p", vp), ("phi", vp),
-                ("UI", vp * 3), ("b_phi", vp)]
+                ("UI", vp * 3), ("b_phi", vp), ("C1", vp * 4), ("Cn", vp * 4), ("C_bc", vp * 4)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("iters_u", i32 * 3), ("iters_p", i32), ("outer_u", i32), ("outer_p", i32),
                 ("status", i32), ("guess_used", i32), ("res_u", f64 * 3), ("res_p", f64),
                 ("ms_assemble", f64), ("ms_velocity", f64), ("ms_pressure", f64),
-                ("ms_update", f64), ("ms_total", f64)]
+                ("ms_update", f64), ("ms_total", f64), ("iters_m", i32 * 3), ("iters_c", i32 * 4),
+                ("res_c", f64 * 4), ("ms_scalars", f64)]
 
 
 _SIGS = {

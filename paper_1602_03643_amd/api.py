@@ -357,17 +357,26 @@ class IPCS:
     def __init__(self, mesh: DeviceMesh, pattern: DeviceCSR, dt, nu, f, bc_dofs: torch.Tensor,
                  rtol_u=1e-8, rtol_p=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4,
                  assembly=L.ASSEMBLE_ROWS, pressure_start=L.PSTART_PREV, pressure_delta=0.0,
-                 storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO, stream=None):
+                 storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO, inner_iters=1,
+                 velocity_update=L.UPDATE_LUMPED, diffusivity=(), scalar_source=None, stream=None):
         lib = _lib()
         self.mesh, self.pattern = mesh, pattern
         self.dim, self.n = mesh.dim, mesh.n_dof
         self.bc_dofs = bc_dofs.to(torch.int32).contiguous()
         fv = (C.c_double * 3)(*([float(v) for v in f] + [0.0] * (3 - len(f))))
+        nsc = len(diffusivity)
+        if nsc > L.MAX_SCALARS:
+            raise ValueError("at most %d scalars" % L.MAX_SCALARS)
+        src = list(scalar_source) if scalar_source is not None else [0.0] * nsc
+        dv = (C.c_double * 4)(*([float(v) for v in diffusivity] + [0.0] * (4 - nsc)))
+        sv = (C.c_double * 4)(*([float(v) for v in src] + [0.0] * (4 - len(src))))
+        self.n_scalars = nsc
         self.params = L.IpcsParams(float(dt), float(nu), fv, int(self.bc_dofs.numel()),
                                    self.bc_dofs.data_ptr() if self.bc_dofs.numel() else None,
                                    float(rtol_u), float(rtol_p), int(maxit), int(precision), float(inner_rtol),
                                    int(assembly), int(pressure_start), float(pressure_delta),
-                                   _tuning(storage, grid_cap, cg_form))
+                                   _tuning(storage, grid_cap, cg_form), int(inner_iters), int(velocity_update),
+                                   nsc, dv, sv)
         cm = mesh.c()
         nb = C.c_size_t()
         L.check(lib.oasis_ipcs_workspace_size(C.byref(cm), pattern.nnz, C.byref(self.params), C.byref(nb)),
@@ -381,9 +390,15 @@ class IPCS:
         self._mesh_c = cm
 
     def step(self, U1, U2, Un, p, phi, bc_values=None, phi_guess=None, UI=None, b_phi=None, stream=None,
-             raise_on=True):
-        """U1, U2, Un: [dim, n] float64; p, phi: [n] (updated in place)."""
+             raise_on=True, C1=None, Cn=None, C_bc=None):
+        """U1, U2, Un: [dim, n] float64; p, phi: [n] (updated in place).
+        Scalars: C1, Cn [n_scalars, n], C_bc [n_scalars, n_bc]."""
         st = L.State()
+        for a in range(self.n_scalars):
+            st.C1[a] = C1[a].data_ptr()
+            st.Cn[a] = Cn[a].data_ptr()
+            if C_bc is not None:
+                st.C_bc[a] = C_bc[a].data_ptr()
         for k in range(self.dim):
             st.U1[k] = U1[k].data_ptr()
             st.U2[k] = U2[k].data_ptr()
@@ -402,7 +417,9 @@ class IPCS:
                  outer_p=stats.outer_p, status=stats.status, guess_used=stats.guess_used,
                  res_u=list(stats.res_u)[: self.dim], res_p=stats.res_p, ms_assemble=stats.ms_assemble,
                  ms_velocity=stats.ms_velocity, ms_pressure=stats.ms_pressure, ms_update=stats.ms_update,
-                 ms_total=stats.ms_total, rc=rc)
+                 ms_total=stats.ms_total, iters_m=list(stats.iters_m)[: self.dim],
+                 iters_c=list(stats.iters_c)[: self.n_scalars], res_c=list(stats.res_c)[: self.n_scalars],
+                 ms_scalars=stats.ms_scalars, rc=rc)
         return d
 
     def pressure_amg(self, precision=L.F64, theta=0.0, coarse_size=0, max_levels=0, stream=None):

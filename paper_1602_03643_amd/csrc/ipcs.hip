@@ -240,11 +240,12 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
             const int c = ci[j];
             const double a = A[j];
             const double rhs_coef = two_over_dt * M[j] - a;
-            const double pc = p[c];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                acc[k] += rhs_coef * U1.p[k][c];
-                accp[k] += dP.p[k][j] * pc;
+            for (int k = 0; k < D; ++k) acc[k] += rhs_coef * U1.p[k][c];
+            if (p) {                                  // no pressure gradient for a scalar
+                const double pc = p[c];
+#pragma unroll
+                for (int k = 0; k < D; ++k) accp[k] += dP.p[k][j] * pc;
             }
             if (c == i) diag = a;
         }
@@ -521,6 +522,97 @@ __global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__rest
             const double inv = dt / ML[row];
 #pragma unroll
             for (int k = 0; k < D; ++k) uo[k][row] = q >= 0 ? g[k * nbc + q] : UI.p[k][row] - inv * acc[k];
+        }
+    }
+}
+
+// Inner iterations (Alg. 1): the tentative right-hand sides b^k -= dP^k phi
+// on the non-Dirichlet rows (p* grew by phi; the explicit part stays).
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void k_rhs_dp(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                   P3 dP, const double *__restrict__ phi,
+                                                   const int *__restrict__ bc_index, double *__restrict__ b0,
+                                                   double *__restrict__ b1, double *__restrict__ b2) {
+    double *bo[3] = {b0, b1, b2};
+    const int lane = threadIdx.x & (L - 1);
+    const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
+    const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
+    for (long long row = gid; row < n; row += ngroups) {
+        double acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = 0.0;
+        for (int j = rp[row] + lane; j < rp[row + 1]; j += L) {
+            const double f = phi[ci[j]];
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] += dP.p[k][j] * f;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = group_sum<L>(acc[k]);
+        if (lane == 0 && bc_index[row] < 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) bo[k][row] -= acc[k];
+        }
+    }
+}
+
+// Consistent update (eq:velocity_update): M with the rows and columns of
+// the Dirichlet dofs removed and a unit diagonal there (symmetric
+// elimination keeps the matrix SPD for CG).
+__global__ __launch_bounds__(kBlock) void k_mass_bc(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                    const double *__restrict__ M, const int *__restrict__ bc_index,
+                                                    double *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const bool bi = bc_index[i] >= 0;
+        for (int j = rp[i]; j < rp[i + 1]; ++j) {
+            const int c = ci[j];
+            out[j] = (bi || bc_index[c] >= 0) ? (bi && c == i ? 1.0 : 0.0) : M[j];
+        }
+    }
+}
+
+// Its right-hand sides M U^I - dt dP^k phi - M_{I,B} g (g on the Dirichlet
+// rows), scaled for the symmetrically scaled system: b_s = rhs / s, and the
+// scaled start x_s = s U^I (s g on the Dirichlet rows).
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void k_mass_rhs(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                     const double *__restrict__ M, P3 dP, P3 UI,
+                                                     const double *__restrict__ phi,
+                                                     const int *__restrict__ bc_index, const double *__restrict__ g,
+                                                     int nbc, double dt, const double *__restrict__ sM,
+                                                     double *__restrict__ b0, double *__restrict__ b1,
+                                                     double *__restrict__ b2, double *__restrict__ x0,
+                                                     double *__restrict__ x1, double *__restrict__ x2) {
+    double *bo[3] = {b0, b1, b2};
+    double *xo[3] = {x0, x1, x2};
+    const int lane = threadIdx.x & (L - 1);
+    const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
+    const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
+    for (long long row = gid; row < n; row += ngroups) {
+        double acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = 0.0;
+        for (int j = rp[row] + lane; j < rp[row + 1]; j += L) {
+            const int c = ci[j];
+            const double m = M[j], f = phi[c];
+            const int qc = bc_index[c];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                acc[k] += m * UI.p[k][c] - dt * dP.p[k][j] * f;
+                if (qc >= 0) acc[k] -= m * g[k * nbc + qc];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = group_sum<L>(acc[k]);
+        if (lane == 0) {
+            const int q = bc_index[row];
+            const double si = sM[row];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double gk = q >= 0 ? g[k * nbc + q] : 0.0;
+                bo[k][row] = (q >= 0 ? gk : acc[k]) / si;
+                xo[k][row] = si * (q >= 0 ? gk : UI.p[k][row]);
+            }
         }
     }
 }
@@ -833,9 +925,16 @@ struct oasis_ipcs {
     BiWork<double> bi;
     BiWork<float> bi32;
     IRBufs ir;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // multigrid preconditioner of the pressure solve (optional)
     oasis_amg *amg = nullptr;
+    // options of Alg. 1 / Sec. 5 / eq:scalar_disc
+    int inner = 1;            // inner velocity-pressure iterations
+    bool consistent = false;  // consistent-mass velocity update
+    double *Ms = nullptr, *eM = nullptr, *sM = nullptr, *wM = nullptr;   // its scaled matrix
+    CGWork<double> cgM;
+    int nsc = 0;              // passive scalars
+    double *Bs[OASIS_MAX_SCALARS] = {nullptr, nullptr, nullptr, nullptr};   // M/dt + D K/2 each
     // learned warm start (optional)
     const float *ws_params = nullptr;
     const double *ws_coords = nullptr;
@@ -862,7 +961,8 @@ static int ell_setup(hipStream_t s, int n, const int *rp, const int *ci, const d
     return OASIS_OK;
 }
 
-static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, oasis_ipcs &h) {
+static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, bool consistent, int nsc,
+                       oasis_ipcs &h) {
     h.ecol = c.take<short>((size_t)n * kEll);
     h.pid = c.take<unsigned short>(n);
     h.ptab = c.take<short>((size_t)kMaxEllPatterns * kEll);
@@ -918,6 +1018,14 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
         carve_bi<float>(c, n, dim, h.bi32);
         carve_ir(c, n, dim, h.ir);
     }
+    if (consistent) {
+        h.Ms = c.take<double>(nnz);
+        h.eM = c.take<double>((size_t)n * kEll);
+        h.sM = c.take<double>(n);
+        h.wM = c.take<double>(n);
+        carve_cg<double>(c, n, h.cgM);
+    }
+    for (int a = 0; a < nsc; ++a) h.Bs[a] = c.take<double>(nnz);
 }
 
 static int check_params(const oasis_ipcs_params *p) {
@@ -926,6 +1034,13 @@ static int check_params(const oasis_ipcs_params *p) {
     if (p->precision != OASIS_F64 && p->precision != OASIS_F32) return OASIS_EINVAL;
     if (p->pressure_start != OASIS_PSTART_PREV && p->pressure_start != OASIS_PSTART_ZERO) return OASIS_EINVAL;
     if (!(p->pressure_delta >= 0.0 && p->pressure_delta < 1.0)) return OASIS_EINVAL;
+    if (p->inner_iters < 0 || p->inner_iters > 16) return OASIS_EINVAL;
+    if (p->velocity_update != OASIS_UPDATE_LUMPED && p->velocity_update != OASIS_UPDATE_CONSISTENT)
+        return OASIS_EINVAL;
+    if (p->n_scalars < 0 || p->n_scalars > OASIS_MAX_SCALARS) return OASIS_EINVAL;
+    for (int a = 0; a < p->n_scalars; ++a)
+        if (!(p->diffusivity[a] >= 0.0) || !std::isfinite(p->diffusivity[a]) || !std::isfinite(p->scalar_source[a]))
+            return OASIS_EINVAL;
     Tuning t;
     return Tuning::from(&p->tuning, &t);
 }
@@ -936,7 +1051,8 @@ extern "C" int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz, co
     OASIS_TRY(check_params(par));
     Carver c(nullptr, 0);
     oasis_ipcs h;
-    carve_ipcs(c, mesh->dim, mesh->n_dof, mesh->n_cell, nnz, par->precision == OASIS_F32, h);
+    carve_ipcs(c, mesh->dim, mesh->n_dof, mesh->n_cell, nnz, par->precision == OASIS_F32,
+               par->velocity_update == OASIS_UPDATE_CONSISTENT, par->n_scalars, h);
     *bytes = c.bytes();
     return OASIS_OK;
 }
@@ -965,16 +1081,19 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     h->par = *par;
     (void)Tuning::from(&par->tuning, &h->tun);
     h->mixed = par->precision == OASIS_F32;
+    h->inner = par->inner_iters > 0 ? par->inner_iters : 1;
+    h->consistent = par->velocity_update == OASIS_UPDATE_CONSISTENT;
+    h->nsc = par->n_scalars;
     Carver c(ws, ws_bytes);
-    carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, *h);
-    h->cg.tun = h->cg32.tun = h->tun;
+    carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, h->consistent, h->nsc, *h);
+    h->cg.tun = h->cg32.tun = h->cgM.tun = h->tun;
     h->bi.tun = h->bi32.tun = h->tun;
     auto fail = [&](int rc) {
         delete h;
         return rc;
     };
     if (!c.ok) return fail(OASIS_EWORKSPACE);
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 6; ++k)
         if (hipEventCreate(&h->ev[k]) != hipSuccess) return fail(OASIS_EHIP);
     const int n = h->n, D = h->dim;
     int rc = OASIS_OK;
@@ -1004,8 +1123,23 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
                        h->flag + 1);
     hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->B, h->sK, kScaleSym,
                        h->Ks, h->Ks32);
+    // scalars: M/dt + D K/2 each (before B takes its own combination)
+    for (int a = 0; a < h->nsc; ++a)
+        hipLaunchKernelGGL(k_lincomb, dim3(gvec(nnz)), dim3(kBlock), 0, s, (long long)nnz, h->Bs[a], h->M,
+                           1.0 / par->dt, h->B, 0.5 * par->diffusivity[a]);
     hipLaunchKernelGGL(k_lincomb, dim3(gvec(nnz)), dim3(kBlock), 0, s, (long long)nnz, h->B, h->M,
                        1.0 / par->dt, h->B, 0.5 * par->nu);
+    // consistent update: M with the Dirichlet dofs eliminated, symmetrically scaled
+    if (h->consistent) {
+        hipLaunchKernelGGL(k_mass_bc, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->M, h->bc_index,
+                           h->Ms);
+        hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->Ms,
+                           h->dtmp);
+        hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dtmp, 0, h->sM, h->wM,
+                           static_cast<float *>(nullptr), h->flag + 1);
+        hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, col_idx, h->Ms, h->sM,
+                           kScaleSym, h->Ms, static_cast<float *>(nullptr));
+    }
     hipLaunchKernelGGL(k_row_sums, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->M, h->ML);
     if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
     // ELL copy of the pressure matrix for the CG product when its rows and
@@ -1016,6 +1150,16 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
         if (rc4 != OASIS_OK) return fail(rc4);
         const bool fits = h->cols.any();
         h->ell = fits;
+        if (fits && h->consistent) {
+            // the mass matrix's ELL values on the same columns
+            bool f2 = false;
+            const int rc5 = csr_to_ell(s, n, row_ptr, col_idx, h->Ms, h->ecol, h->eM, nullptr, h->flag + 24, &f2);
+            if (rc5 != OASIS_OK) return fail(rc5);
+            if (f2) {
+                h->cgM.cols = h->cols;
+                h->cgM.eval = h->eM;
+            }
+        }
         if (fits && h->mixed) {
             h->cg32.cols = h->bi32.cols = h->cols;
             h->cg32.eval = h->eval32;
@@ -1177,6 +1321,74 @@ static void launch_update(hipStream_t s, oasis_ipcs *h, double *const *x, const 
                        h->ML, h->bc_index, g, h->par.n_bc, h->par.dt, un[0], un[1], D > 2 ? un[2] : nullptr);
 }
 
+// One passive scalar: A_c = M/dt + D K/2 + C(u_bar)/2 by the step's
+// assembly (into h->A: the velocity's matrix is no longer needed), the
+// right-hand side (2M/dt - A_c) c^{n-1} + f M_L with the Dirichlet rows
+// (k_tent_rows for one field without pressure gradient), column scaling,
+// BiCGStab in the step's precision, unscaling into Cn.
+static int scalar_solve(hipStream_t s, oasis_ipcs *h, oasis_state *st, int a, int D, const oasis_krylov_opts &o0,
+                        oasis_step_stats &S, int *status) {
+    const int n = h->n;
+    if (!st->C1[a] || !st->Cn[a] || (h->par.n_bc > 0 && !st->C_bc[a])) return OASIS_EINVAL;
+    if (h->assembly == OASIS_ASSEMBLE_ROWS) {
+        const int grid = grid_for(n, kBlock, 1 << 20);
+        if (D == 3 && h->maxc == 16)
+            hipLaunchKernelGGL((k_asm_rows<3, 16>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
+                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+        else if (D == 3)
+            hipLaunchKernelGGL((k_asm_rows<3, 32>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
+                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+        else if (h->maxc == 16)
+            hipLaunchKernelGGL((k_asm_rows<2, 16>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
+                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+        else
+            hipLaunchKernelGGL((k_asm_rows<2, 32>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
+                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+        OASIS_TRY_LAUNCH();
+    } else {
+        P3 U1{}, U2{};
+        for (int k = 0; k < D; ++k) {
+            U1.p[k] = st->U1[k];
+            U2.p[k] = st->U2[k];
+        }
+        OASIS_TRY(scale_copy(s, h->nnz, h->A, h->Bs[a], 1.0));
+        OASIS_TRY(assemble_colored(s, &h->mesh, h->rp, h->ci, h->A, OASIS_FORM_CONV, 0.5, U1, U2, 1.5, -0.5,
+                                   nullptr));
+    }
+    P3 none{}, C1{};
+    C1.p[0] = st->C1[a];
+    const int grid = grid_for(n, kBlock / 8, 1 << 20);
+    hipLaunchKernelGGL((k_tent_rows<1, 8>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A, none, C1,
+                       static_cast<const double *>(nullptr), h->ML, h->bc_index, st->C_bc[a], h->par.n_bc,
+                       h->par.scalar_source[a], 0.0, 0.0, 2.0 / h->par.dt, h->bt[0], static_cast<double *>(nullptr),
+                       static_cast<double *>(nullptr), st->Cn[a], static_cast<double *>(nullptr),
+                       static_cast<double *>(nullptr), h->dA, h->wA, h->wA32);
+    OASIS_TRY_LAUNCH();
+    const bool e = h->ell && h->tun.ell();
+    hipLaunchKernelGGL(k_colscale, dim3(grid_for(n, kBlock / kEll, 1 << 20)), dim3(kBlock), 0, s, n, h->rp, h->ci,
+                       h->dA, h->A, h->mixed && !e ? h->A32 : nullptr, e ? h->eA : nullptr, e ? h->eA32 : nullptr);
+    OASIS_TRY_LAUNCH();
+    oasis_krylov_opts o = o0;
+    o.rtol = h->par.rtol_u;
+    const KOpts ko = kopts(&o);
+    double *b[3] = {h->bt[0], nullptr, nullptr};
+    double *x[3] = {st->Cn[a], nullptr, nullptr};
+    SolveOut sc[3];
+    int rc;
+    if (h->mixed)
+        rc = ir_bicgstab(s, n, 1, h->rp, h->ci, h->A, h->A32, h->wA, h->wA32, b, x, ko, h->bi32, h->ir, sc);
+    else
+        rc = bicgstab_solve<double>(s, n, 1, h->rp, h->ci, h->A, h->wA, b, x, ko.rtol, ko.maxit, 0, false, h->bi, sc);
+    if (rc == OASIS_EHIP) return rc;
+    hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dA, 2, st->Cn[a],
+                       static_cast<double *>(nullptr), static_cast<double *>(nullptr));
+    OASIS_TRY_LAUNCH();
+    S.iters_c[a] = sc[0].iters;
+    S.res_c[a] = sc[0].rel_res;
+    *status = sc[0].status;
+    return OASIS_OK;
+}
+
 extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, const double *bc_values,
                                const double *phi_guess, oasis_step_stats *stats) {
     if (!h || !st || !st->p || !st->phi) return OASIS_EINVAL;
@@ -1185,6 +1397,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         if (!st->U1[k] || !st->U2[k] || !st->Un[k] || st->Un[k] == st->U1[k] || st->Un[k] == st->U2[k])
             return OASIS_EINVAL;
     if (h->par.n_bc > 0 && !bc_values) return OASIS_EINVAL;
+    for (int a = 0; a < h->nsc; ++a)
+        if (!st->C1[a] || !st->Cn[a] || st->Cn[a] == st->C1[a] || (h->par.n_bc > 0 && !st->C_bc[a]))
+            return OASIS_EINVAL;
     hipStream_t s = as_stream(stream);
     oasis_step_stats loc{};
     oasis_step_stats &S = stats ? *stats : loc;
@@ -1230,111 +1445,182 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         OASIS_TRY_LAUNCH();
     }
     OASIS_TRY_HIP(hipEventRecord(h->ev[1], s));
-    // 3. tentative velocity
     oasis_krylov_opts o{};
-    o.rtol = h->par.rtol_u;
     o.maxit = h->par.maxit > 0 ? h->par.maxit : 10000;
     o.inner_rtol = h->par.inner_rtol;
-    KOpts ko = kopts(&o);
-    SolveOut su[3];
-    int rc_u;
-    if (h->mixed)
-        rc_u = ir_bicgstab(s, n, D, h->rp, h->ci, h->A, h->A32, h->wA, h->wA32, h->bt, x, ko, h->bi32, h->ir, su);
-    else
-        rc_u = bicgstab_solve<double>(s, n, D, h->rp, h->ci, h->A, h->wA, h->bt, x, ko.rtol, ko.maxit, 0, false,
-                                      h->bi, su);
-    if (rc_u == OASIS_EHIP) return rc_u;
-    hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dA, 2, x[0], x[1], D > 2 ? x[2] : nullptr);
-    OASIS_TRY_LAUNCH();
-    OASIS_TRY_HIP(hipEventRecord(h->ev[2], s));
-    // 4. pressure correction
-    int gd = 0;
-    if (D == 3)
-        launch_div<3, 8>(s, h, x, &gd);
-    else
-        launch_div<2, 8>(s, h, x, &gd);
-    OASIS_TRY_LAUNCH();
+    int worst = OASIS_OK;
+    auto note = [&](int status) {
+        if (status != OASIS_OK && (worst == OASIS_OK || status < worst)) worst = status;
+    };
     const int zero_start = h->par.pressure_start == OASIS_PSTART_ZERO ? 1 : 0;
-    hipLaunchKernelGGL(k_bphi_finish, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->red, gd, h->bphi, h->sK,
-                       st->phi, zero_start, h->bs, h->xs);
-    OASIS_TRY_LAUNCH();
-    if (st->b_phi) {
-        hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, st->b_phi, h->bphi);
-        OASIS_TRY_LAUNCH();
-    }
     S.guess_used = 0;
-    if (!phi_guess && h->ws_params) {
-        // learned warm start from the projected right-hand side and phi_prev
-        oasis_csr Kc{n, h->nnz, h->rp, h->ci, h->Ks, OASIS_F64};
-        OASIS_TRY(mpnn_infer(stream, &Kc, h->sK, D, h->ws_coords, h->bphi, st->phi, h->ws_params, h->dtmp,
-                             h->ws_mem, h->ws_bytes));
-        phi_guess = h->dtmp;
-    }
-    if (phi_guess) {
-        // compare with the plain start (its residual is b itself for phi_0 = 0)
-        double wr_plain = 0, wr_guess = 0, wbb = 0;
-        hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, phi_guess, h->sK, 1, h->xg);
-        OASIS_TRY_LAUNCH();
-        OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->rtmp, h->cg, &wr_guess, &wbb));
-        if (zero_start)
-            wr_plain = wbb;
-        else
-            OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->rtmp, h->cg, &wr_plain,
-                                  &wbb));
-        if (std::isfinite(wr_guess) && wr_guess < wr_plain) {
-            hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, h->xs, h->xg);
+    SolveOut su[3], sp;
+    for (int it = 0; it < h->inner; ++it) {
+        if (it > 0) {
+            // 3'. p* grew by phi: b^k -= dP^k phi; start from the last U^I
+            P3 dP{};
+            for (int k = 0; k < D; ++k) dP.p[k] = h->dP[k];
+            const int g8 = grid_for(n, kBlock / 8, 1 << 20);
+            if (D == 3)
+                hipLaunchKernelGGL((k_rhs_dp<3, 8>), dim3(g8), dim3(kBlock), 0, s, n, h->rp, h->ci, dP, st->phi,
+                                   h->bc_index, h->bt[0], h->bt[1], h->bt[2]);
+            else
+                hipLaunchKernelGGL((k_rhs_dp<2, 8>), dim3(g8), dim3(kBlock), 0, s, n, h->rp, h->ci, dP, st->phi,
+                                   h->bc_index, h->bt[0], h->bt[1], static_cast<double *>(nullptr));
+            hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dA, 1, x[0], x[1],
+                               D > 2 ? x[2] : nullptr);
             OASIS_TRY_LAUNCH();
-            S.guess_used = 1;
         }
+        // 3. tentative velocity
+        o.rtol = h->par.rtol_u;
+        KOpts ko = kopts(&o);
+        SolveOut sui[3];
+        int rc_u;
+        if (h->mixed)
+            rc_u = ir_bicgstab(s, n, D, h->rp, h->ci, h->A, h->A32, h->wA, h->wA32, h->bt, x, ko, h->bi32, h->ir,
+                               sui);
+        else
+            rc_u = bicgstab_solve<double>(s, n, D, h->rp, h->ci, h->A, h->wA, h->bt, x, ko.rtol, ko.maxit, 0, false,
+                                          h->bi, sui);
+        if (rc_u == OASIS_EHIP) return rc_u;
+        for (int k = 0; k < D; ++k) {
+            su[k].iters += sui[k].iters;
+            su[k].outer = std::max(su[k].outer, sui[k].outer);
+            su[k].rel_res = sui[k].rel_res;
+            note(sui[k].status);
+        }
+        hipLaunchKernelGGL(k_scale3, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->dA, 2, x[0], x[1],
+                           D > 2 ? x[2] : nullptr);
+        OASIS_TRY_LAUNCH();
+        if (it == 0) OASIS_TRY_HIP(hipEventRecord(h->ev[2], s));
+        // 4. pressure correction
+        int gd = 0;
+        if (D == 3)
+            launch_div<3, 8>(s, h, x, &gd);
+        else
+            launch_div<2, 8>(s, h, x, &gd);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL(k_bphi_finish, dim3(gvec(n)), dim3(kBlock), 0, s, n, h->red, gd, h->bphi, h->sK,
+                           st->phi, it > 0 ? 1 : zero_start, h->bs, h->xs);
+        OASIS_TRY_LAUNCH();
+        if (st->b_phi) {
+            hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, st->b_phi, h->bphi);
+            OASIS_TRY_LAUNCH();
+        }
+        const double *guess = it == 0 ? phi_guess : nullptr;
+        if (it == 0 && !guess && h->ws_params) {
+            // learned warm start from the projected right-hand side and phi_prev
+            oasis_csr Kc{n, h->nnz, h->rp, h->ci, h->Ks, OASIS_F64};
+            OASIS_TRY(mpnn_infer(stream, &Kc, h->sK, D, h->ws_coords, h->bphi, st->phi, h->ws_params, h->dtmp,
+                                 h->ws_mem, h->ws_bytes));
+            guess = h->dtmp;
+        }
+        if (guess) {
+            // compare with the plain start (its residual is b itself for phi_0 = 0)
+            double wr_plain = 0, wr_guess = 0, wbb = 0;
+            hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, guess, h->sK, 1, h->xg);
+            OASIS_TRY_LAUNCH();
+            OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xg, h->rtmp, h->cg, &wr_guess, &wbb));
+            if (zero_start)
+                wr_plain = wbb;
+            else
+                OASIS_TRY(cg_residual(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, h->rtmp, h->cg, &wr_plain,
+                                      &wbb));
+            if (std::isfinite(wr_guess) && wr_guess < wr_plain) {
+                hipLaunchKernelGGL(k_copy_d, dim3(gvec(n)), dim3(kBlock), 0, s, (long long)n, h->xs, h->xg);
+                OASIS_TRY_LAUNCH();
+                S.guess_used = 1;
+            }
+        }
+        o.rtol = h->par.rtol_p;
+        ko = kopts(&o);
+        SolveOut spi;
+        int rc_p;
+        if (h->amg)
+            rc_p = amg_handle_solve(s, h->amg, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, spi);
+        else if (h->mixed)
+            rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->vscale, h->bs,
+                                  h->xs, ko.rtol,
+                                  h->par.pressure_delta > 0.0 ? h->par.pressure_delta : kPressureDelta, ko.maxit, 0,
+                                  false, h->cg32, h->xlo, h->rhi, spi);
+        else
+            rc_p = cg_solve<double>(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, 0, false,
+                                    h->cg, spi);
+        if (rc_p == OASIS_EHIP) return rc_p;
+        sp.iters += spi.iters;
+        sp.outer += spi.outer;
+        sp.rel_res = spi.rel_res;
+        note(spi.status);
+        // 5. phi, p* += phi, normalisation
+        const int gp = grid_for(n, kBlock);
+        hipLaunchKernelGGL(k_phi_a, dim3(gp), dim3(kBlock), 0, s, n, h->xs, h->sK, st->phi, h->red);
+        hipLaunchKernelGGL(k_phi_b, dim3(gp), dim3(kBlock), 0, s, n, h->red, gp, st->phi, st->p,
+                           h->red + kMaxPartials);
+        hipLaunchKernelGGL(k_phi_c, dim3(gp), dim3(kBlock), 0, s, n, h->red + kMaxPartials, gp, st->p);
+        OASIS_TRY_LAUNCH();
     }
-    o.rtol = h->par.rtol_p;
-    ko = kopts(&o);
-    SolveOut sp;
-    int rc_p;
-    if (h->amg)
-        rc_p = amg_handle_solve(s, h->amg, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, sp);
-    else if (h->mixed)
-        rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->vscale, h->bs,
-                              h->xs,
-                              ko.rtol, h->par.pressure_delta > 0.0 ? h->par.pressure_delta : kPressureDelta,
-                              ko.maxit, 0, false, h->cg32, h->xlo, h->rhi, sp);
-    else
-        rc_p = cg_solve<double>(s, n, h->rp, h->ci, h->Ks, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, 0, false,
-                                h->cg, sp);
-    if (rc_p == OASIS_EHIP) return rc_p;
     OASIS_TRY_HIP(hipEventRecord(h->ev[3], s));
-    // 5. phi, p normalisation
-    const int gp = grid_for(n, kBlock);
-    hipLaunchKernelGGL(k_phi_a, dim3(gp), dim3(kBlock), 0, s, n, h->xs, h->sK, st->phi, h->red);
-    hipLaunchKernelGGL(k_phi_b, dim3(gp), dim3(kBlock), 0, s, n, h->red, gp, st->phi, st->p, h->red + kMaxPartials);
-    hipLaunchKernelGGL(k_phi_c, dim3(gp), dim3(kBlock), 0, s, n, h->red + kMaxPartials, gp, st->p);
-    OASIS_TRY_LAUNCH();
     // 6. velocity correction
-    if (D == 3)
-        launch_update<3, 8>(s, h, x, st->phi, bc_values, st->Un);
-    else
-        launch_update<2, 8>(s, h, x, st->phi, bc_values, st->Un);
-    OASIS_TRY_LAUNCH();
+    if (h->consistent) {
+        P3 dP{}, UI{};
+        for (int k = 0; k < D; ++k) {
+            dP.p[k] = h->dP[k];
+            UI.p[k] = x[k];
+        }
+        const int g8 = grid_for(n, kBlock / 8, 1 << 20);
+        double *un[3] = {st->Un[0], st->Un[1], D > 2 ? st->Un[2] : nullptr};
+        if (D == 3)
+            hipLaunchKernelGGL((k_mass_rhs<3, 8>), dim3(g8), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, dP, UI,
+                               st->phi, h->bc_index, bc_values, h->par.n_bc, h->par.dt, h->sM, h->bt[0], h->bt[1],
+                               h->bt[2], un[0], un[1], un[2]);
+        else
+            hipLaunchKernelGGL((k_mass_rhs<2, 8>), dim3(g8), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, dP, UI,
+                               st->phi, h->bc_index, bc_values, h->par.n_bc, h->par.dt, h->sM, h->bt[0], h->bt[1],
+                               static_cast<double *>(nullptr), un[0], un[1], static_cast<double *>(nullptr));
+        OASIS_TRY_LAUNCH();
+        for (int k = 0; k < D; ++k) {
+            SolveOut sm;
+            const int rc = cg_solve<double>(s, n, h->rp, h->ci, h->Ms, h->wM, h->bt[k], un[k], h->par.rtol_u,
+                                            o.maxit, 0, false, h->cgM, sm);
+            if (rc == OASIS_EHIP) return rc;
+            S.iters_m[k] = sm.iters;
+            note(sm.status);
+            hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, un[k], h->sM, 2, un[k]);
+            OASIS_TRY_LAUNCH();
+        }
+    } else {
+        if (D == 3)
+            launch_update<3, 8>(s, h, x, st->phi, bc_values, st->Un);
+        else
+            launch_update<2, 8>(s, h, x, st->phi, bc_values, st->Un);
+        OASIS_TRY_LAUNCH();
+    }
     OASIS_TRY_HIP(hipEventRecord(h->ev[4], s));
-    OASIS_TRY_HIP(hipEventSynchronize(h->ev[4]));
-    float t[4];
-    for (int k = 0; k < 4; ++k) OASIS_TRY_HIP(hipEventElapsedTime(&t[k], h->ev[k], h->ev[k + 1]));
+    // 7. passive scalars (eq:scalar_disc): the velocity's u_bar (still in
+    // h->ubar), M/dt + D K/2 in place of B, no pressure gradient
+    for (int a = 0; a < h->nsc; ++a) {
+        int status = OASIS_OK;
+        OASIS_TRY(scalar_solve(s, h, st, a, D, o, S, &status));
+        note(status);
+    }
+    OASIS_TRY_HIP(hipEventRecord(h->ev[5], s));
+    OASIS_TRY_HIP(hipEventSynchronize(h->ev[5]));
+    float t[5];
+    for (int k = 0; k < 5; ++k) OASIS_TRY_HIP(hipEventElapsedTime(&t[k], h->ev[k], h->ev[k + 1]));
     S.ms_assemble = t[0];
     S.ms_velocity = t[1];
     S.ms_pressure = t[2];
     S.ms_update = t[3];
-    S.ms_total = t[0] + t[1] + t[2] + t[3];
-    int worst = OASIS_OK;
+    S.ms_scalars = t[4];
+    S.ms_total = t[0] + t[1] + t[2] + t[3] + t[4];
     for (int k = 0; k < D; ++k) {
         S.iters_u[k] = su[k].iters;
         S.res_u[k] = su[k].rel_res;
         S.outer_u = std::max(S.outer_u, su[k].outer);
-        if (su[k].status != OASIS_OK && (worst == OASIS_OK || su[k].status < worst)) worst = su[k].status;
     }
     S.iters_p = sp.iters;
     S.res_p = sp.rel_res;
     S.outer_p = sp.outer;
-    if (sp.status != OASIS_OK && (worst == OASIS_OK || sp.status < worst)) worst = sp.status;
     S.status = worst;
     return worst;
 }

@@ -105,6 +105,14 @@ def test_invalid_ipcs_params_rejected_on_host(lib):
         p = L.IpcsParams.from_buffer_copy(good)
         setattr(p, field, bad)
         assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL, field
+    for field, bad in [("inner_iters", 17), ("velocity_update", 2), ("n_scalars", 5)]:
+        p = L.IpcsParams.from_buffer_copy(good)
+        setattr(p, field, bad)
+        assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL, field
+    p = L.IpcsParams.from_buffer_copy(good)
+    p.n_scalars = 1
+    p.diffusivity[0] = -1.0
+    assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL
     # storage and kernel shapes are per-call options, range-checked on the host
     for field, bad in [("storage", 9), ("grid_cap", 10), ("grid_cap", 4096), ("cg_form", -1)]:
         p = L.IpcsParams.from_buffer_copy(good)
