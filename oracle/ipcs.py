@@ -44,6 +44,20 @@ other update types, eq:scalar_disc):
   symmetric elimination (rows and columns of the Dirichlet dofs removed,
   their known values moved to the right-hand side), which has the same
   solution as identity rows and keeps the matrix SPD for CG.
+* convection="abe": eq:convection_ABE in place of eq:convection_ABCN.  The
+  convection is fully explicit, so the coefficient matrix is the constant
+  M/dt + nu K/2 (Dirichlet rows as above) and the right-hand side carries
+  it: b_tmp = f M_L + (M/dt - nu K/2) U^{n-1} - 1.5 C(u^{n-1}) U^{n-1}
+  + 0.5 C(u^{n-2}) U^{n-2}, with C(w) the convection matrix of the
+  convecting field w.  Scalars keep the u_bar form (the paper's scalar
+  discretisation is that form for either velocity convection).
+* update="gradient": the direct update with the weighted gradient matrix
+  G^k of Sec. 5 (last paragraphs).  The paper does not define its weights;
+  it is read as the nodal average of the cellwise constant gradient,
+  weighted by cell volume: (G^k q)_i = sum_{T ni i} |T| d_k q|_T /
+  sum_{T ni i} |T|.  For P1 elements int_T phi_i = |T|/(d+1) for every
+  vertex of T, so G^k = M_L^{-1} dP^k (the rows of dP^k over the lumped
+  mass), and U^n = U^I - dt G^k phi with the Dirichlet values.
 * scalars: eq:scalar_disc with the convection term of the paper's scalar
   discretisation, u_bar . grad(c~) with the same Adams-Bashforth u_bar and
   Crank-Nicolson c~, i.e. the tentative-velocity system with nu replaced
@@ -136,9 +150,14 @@ def apply_dirichlet_rows(A, rows):
     return A
 
 
-def tentative_system(S: Setup, st: State, t_new: float, bc_vals, with_tmp=False):
+def tentative_system(S: Setup, st: State, t_new: float, bc_vals, with_tmp=False, convection="abcn"):
     """Alg. 2 literal: returns (A after BC rows, b [d, N] after BC values),
-    and b_tmp with with_tmp."""
+    and b_tmp with with_tmp.  convection="abe" builds the explicit form
+    instead (tentative_system_abe)."""
+    if convection == "abe":
+        return tentative_system_abe(S, st, bc_vals, with_tmp)
+    if convection != "abcn":
+        raise ValueError(convection)
     mesh = S.mesh
     d = mesh.dim
     ubar = 1.5 * st.U1 - 0.5 * st.U2
@@ -154,6 +173,32 @@ def tentative_system(S: Setup, st: State, t_new: float, bc_vals, with_tmp=False)
     if with_tmp:
         return A.tocsr(), b, b_tmp
     return A.tocsr(), b
+
+
+def tentative_system_abe(S: Setup, st: State, bc_vals, with_tmp=False):
+    """eq:NStentative with eq:convection_ABE in matrix form:
+    (M/dt + nu K/2) U^I = f M_L + (M/dt - nu K/2) U^{n-1}
+                          - 1.5 C(u^{n-1}) U^{n-1} + 0.5 C(u^{n-2}) U^{n-2} - dP^k p*."""
+    mesh = S.mesh
+    d = mesh.dim
+    C1 = p1.convection_matrix(mesh, st.U1, S.geo)        # C(u^{n-1})
+    C2 = p1.convection_matrix(mesh, st.U2, S.geo)        # C(u^{n-2})
+    R = (1.0 / S.dt) * S.M - (0.5 * S.nu) * S.K
+    b_tmp = np.stack([S.b0[k] + R @ st.U1[k] - 1.5 * (C1 @ st.U1[k]) + 0.5 * (C2 @ st.U2[k])
+                      for k in range(d)])
+    A = (1.0 / S.dt) * S.M + (0.5 * S.nu) * S.K
+    A = apply_dirichlet_rows(A, mesh.bc_dofs)
+    b = tentative_rhs(S, b_tmp, st.p, bc_vals)
+    if with_tmp:
+        return A.tocsr(), b, b_tmp
+    return A.tocsr(), b
+
+
+def gradient_update_matrices(S: Setup):
+    """G^k = M_L^{-1} dP^k (the volume-weighted nodal gradient, see the
+    module notes)."""
+    Li = sp.diags(1.0 / S.ML)
+    return [(Li @ S.dP[k]).tocsr() for k in range(S.mesh.dim)]
 
 
 def tentative_rhs(S: Setup, b_tmp, p_star, bc_vals):
@@ -216,13 +261,14 @@ def pressure_rhs(S: Setup, UI):
 
 
 def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
-         phi_guess=None, pressure_start="prev", inner_iters=1, update="lumped", scalars=()) -> StepOut:
+         phi_guess=None, pressure_start="prev", inner_iters=1, update="lumped", scalars=(),
+         convection="abcn") -> StepOut:
     """Advance one time step (Alg. 1).  bc_values: callable t -> [d, n_bc]."""
     mesh = S.mesh
     d = mesh.dim
     t_new = st.t + S.dt
     g = bc_values(t_new) if mesh.bc_dofs.size else np.zeros((d, 0))
-    A, b, b_tmp = tentative_system(S, st, t_new, g, with_tmp=True)
+    A, b, b_tmp = tentative_system(S, st, t_new, g, with_tmp=True, convection=convection)
     UI = st.U1.copy()
     iters_u, res_u = [0] * d, [0.0] * d
     iters_p, res_p, status = 0, 0.0, 0
@@ -258,6 +304,11 @@ def step(S: Setup, st: State, bc_values, rtol_u=1e-8, rtol_p=1e-8, maxit=10000,
             Un[:, mesh.bc_dofs] = g
     elif update == "consistent":
         Un, iters_m = consistent_update(S, UI, phi, g, rtol_u, maxit)
+    elif update == "gradient":
+        G = gradient_update_matrices(S)
+        Un = np.stack([UI[k] - S.dt * (G[k] @ phi) for k in range(d)])
+        if mesh.bc_dofs.size:
+            Un[:, mesh.bc_dofs] = g
     else:
         raise ValueError(update)
     C1 = st.C1
