@@ -31,7 +31,9 @@ Also printed in the one JSON line:
                 reordered by the on-device RCM, timed with the headline
                 solver configuration
   extensions    the headline configuration with Alg. 1's inner iterations
-                (2), the consistent-mass update, or one passive scalar
+                (2), the consistent-mass update, the gradient-matrix update,
+                the explicit Adams-Bashforth convection, or one passive
+                scalar
   roofline      the dominant kernel timed live over repeated launches
                 against its algorithmic bytes, with the HBM traffic of the
                 committed rocprofv3 counter summary when its sources match
@@ -139,7 +141,7 @@ def device_problem(oa, torch, synth, pr, dev, rcm=False):
 
 
 def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm=None, pstart=0, amg=None,
-                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0):
+                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0):
     """Time `steps` steps after `warmup` untimed ones; returns the handle, the
     results and the final (U, p, phi).  scalars: that many passive scalars
     with Prandtl number 0.71 (D = nu / 0.71), Dirichlet values y on the
@@ -150,7 +152,7 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, bcd, rtol_u=pr.rtol_u, rtol_p=pr.rtol_p, precision=precision,
                 inner_rtol=1e-4, pressure_start=pstart, inner_iters=inner_iters, velocity_update=velocity_update,
-                diffusivity=[pr.nu / 0.71] * scalars)
+                diffusivity=[pr.nu / 0.71] * scalars, convection=convection)
 
     def T(a):
         """Host field [..., n] onto the device, in the reordered numbering."""
@@ -453,6 +455,8 @@ def main():
         extensions = {}
         for name, kw in (("inner_iters_2", dict(inner_iters=2)),
                          ("consistent_update", dict(velocity_update=oa.UPDATE_CONSISTENT)),
+                         ("gradient_update", dict(velocity_update=oa.UPDATE_GRADIENT)),
+                         ("abe_convection", dict(convection=oa.CONV_ABE)),
                          ("one_scalar", dict(scalars=1))):
             hh, res, _ = run_variant(oa, torch, pr, dm, pat, bcd, hprec, args.ext_steps, 3, head + "+" + name,
                                      None, hstart, hamg, **kw)

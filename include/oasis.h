@@ -381,7 +381,12 @@ typedef struct {
     int32_t velocity_update;  /* OASIS_UPDATE_LUMPED: U^n = U^I - dt M_L^-1 dP^k phi (the channel
                                  runs of Sec. 6.2); OASIS_UPDATE_CONSISTENT: M U^n = M U^I -
                                  dt dP^k phi (eq:velocity_update) by Jacobi-PCG in FP64 to rtol_u,
-                                 the Dirichlet dofs eliminated symmetrically */
+                                 the Dirichlet dofs eliminated symmetrically;
+                                 OASIS_UPDATE_GRADIENT: U^n = U^I - dt G^k phi with the weighted
+                                 gradient matrix of Sec. 5 (last paragraphs), which the paper
+                                 leaves undefined and is taken as the cell-volume-weighted nodal
+                                 average of the cellwise gradient, G^k = M_L^-1 dP^k for P1,
+                                 precomputed at create (dim more FP64 matrices on the pattern) */
     int32_t n_scalars;        /* passive scalars solved after the velocity update (Alg. 1),
                                  0..OASIS_MAX_SCALARS: eq:scalar_disc with the velocity's u_bar
                                  and Crank-Nicolson, i.e. (M/dt + C/2 + D K/2) c^n =
@@ -390,6 +395,12 @@ typedef struct {
                                  step's precision */
     double diffusivity[4];    /* D_alpha of each scalar */
     double scalar_source[4];  /* constant f_alpha of each scalar */
+    int32_t convection;       /* OASIS_CONV_ABCN: eq:convection_ABCN, A = M/dt + C(u_bar)/2 +
+                                 nu K/2 assembled every step (Alg. 2); OASIS_CONV_ABE:
+                                 eq:convection_ABE, fully explicit: A = M/dt + nu K/2 is constant
+                                 and the right-hand side carries -1.5 C(u^{n-1}) U^{n-1} +
+                                 0.5 C(u^{n-2}) U^{n-2}, gathered row by row from the cells.
+                                 Scalars keep the u_bar form in either case. */
 } oasis_ipcs_params;
 
 #define OASIS_MAX_SCALARS 4
@@ -399,6 +410,9 @@ typedef struct {
 #define OASIS_PSTART_ZERO 1
 #define OASIS_UPDATE_LUMPED 0
 #define OASIS_UPDATE_CONSISTENT 1
+#define OASIS_UPDATE_GRADIENT 2
+#define OASIS_CONV_ABCN 0
+#define OASIS_CONV_ABE 1
 
 typedef struct oasis_ipcs oasis_ipcs;   /* opaque host handle */
 
@@ -457,10 +471,12 @@ int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_p
 
 /* One time step t^{n-1} -> t^n: u_bar, convection assembly with
  * A = M/dt + C/2 + nu K/2 and the right-hand side of eq:tent_intermediate1
- * (Alg. 2), pressure gradient (eq:dp_matrix), Dirichlet rows, BiCGStab for
- * all velocity components, pressure right-hand side -(1/dt) sum_k dP^k U^I
- * projected on 1-perp, Jacobi-PCG for phi, p update and normalisation,
- * lumped velocity update.  bc_values: device double [dim][n_bc] at t^n.
+ * (Alg. 2; with OASIS_CONV_ABE the constant A and the explicit convection
+ * vector instead), pressure gradient (eq:dp_matrix), Dirichlet rows,
+ * BiCGStab for all velocity components, pressure right-hand side
+ * -(1/dt) sum_k dP^k U^I projected on 1-perp, Jacobi-PCG (or AMG-PCG) for
+ * phi, p update and normalisation, velocity update (lumped, consistent or
+ * gradient matrix), scalars.  bc_values: device double [dim][n_bc] at t^n.
  * phi_guess (device, nullable): a candidate initial guess for the
  * pressure solve; it is used only if its initial residual is below that of
  * the plain start (par->pressure_start).  stats: host (nullable).

@@ -10,7 +10,8 @@ from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUN
                    FORM_CONV, FORM_GRAD_X, FORM_GRAD_Y, FORM_GRAD_Z, FORM_MASS, FORM_STIFF, PSTART_PREV,
                    PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS,
                    STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR, CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE,
-                   UPDATE_LUMPED, UPDATE_CONSISTENT, MAX_SCALARS, OasisError)
+                   UPDATE_LUMPED, UPDATE_CONSISTENT, UPDATE_GRADIENT, CONV_ABCN, CONV_ABE, MAX_SCALARS,
+                   OasisError)
 
 _lib.load()
 
@@ -23,4 +24,4 @@ __all__ = ["AMG", "IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bic
            "FORM_MASS", "FORM_STIFF", "FORM_GRAD_X", "FORM_GRAD_Y", "FORM_GRAD_Z", "FORM_CONV", "PSTART_PREV",
            "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS",
            "STORAGE_AUTO", "STORAGE_ELL", "STORAGE_CSR", "CG_FORM_AUTO", "CG_FORM_TWO", "CG_FORM_SINGLE",
-           "UPDATE_LUMPED", "UPDATE_CONSISTENT", "MAX_SCALARS"]
+           "UPDATE_LUMPED", "UPDATE_CONSISTENT", "UPDATE_GRADIENT", "CONV_ABCN", "CONV_ABE", "MAX_SCALARS"]

@@ -18,7 +18,8 @@ KRYLOV_TIME = 1
 KRYLOV_NULLSPACE_CONST = 2
 ASSEMBLE_ROWS, ASSEMBLE_COLORS = 0, 1
 PSTART_PREV, PSTART_ZERO = 0, 1
-UPDATE_LUMPED, UPDATE_CONSISTENT = 0, 1
+UPDATE_LUMPED, UPDATE_CONSISTENT, UPDATE_GRADIENT = 0, 1, 2
+CONV_ABCN, CONV_ABE = 0, 1
 MAX_SCALARS = 4
 INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS = 100, 101, 102
 STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR = 0, 1, 2
@@ -76,7 +77,7 @@ class IpcsParams(C.Structure):
                 ("rtol_u", f64), ("rtol_p", f64), ("maxit", i32), ("precision", i32),
                 ("inner_rtol", f64), ("assembly", i32), ("pressure_start", i32),
                 ("pressure_delta", f64), ("tuning", Tuning), ("inner_iters", i32), ("velocity_update", i32),
-                ("n_scalars", i32), ("diffusivity", f64 * 4), ("scalar_source", f64 * 4)]
+                ("n_scalars", i32), ("diffusivity", f64 * 4), ("scalar_source", f64 * 4), ("convection", i32)]
 
 
 class State(C.Structure):

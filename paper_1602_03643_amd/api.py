@@ -358,7 +358,8 @@ class IPCS:
                  rtol_u=1e-8, rtol_p=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4,
                  assembly=L.ASSEMBLE_ROWS, pressure_start=L.PSTART_PREV, pressure_delta=0.0,
                  storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO, inner_iters=1,
-                 velocity_update=L.UPDATE_LUMPED, diffusivity=(), scalar_source=None, stream=None):
+                 velocity_update=L.UPDATE_LUMPED, diffusivity=(), scalar_source=None, convection=L.CONV_ABCN,
+                 stream=None):
         lib = _lib()
         self.mesh, self.pattern = mesh, pattern
         self.dim, self.n = mesh.dim, mesh.n_dof
@@ -376,7 +377,7 @@ class IPCS:
                                    float(rtol_u), float(rtol_p), int(maxit), int(precision), float(inner_rtol),
                                    int(assembly), int(pressure_start), float(pressure_delta),
                                    _tuning(storage, grid_cap, cg_form), int(inner_iters), int(velocity_update),
-                                   nsc, dv, sv)
+                                   nsc, dv, sv, int(convection))
         cm = mesh.c()
         nb = C.c_size_t()
         L.check(lib.oasis_ipcs_workspace_size(C.byref(cm), pattern.nnz, C.byref(self.params), C.byref(nb)),

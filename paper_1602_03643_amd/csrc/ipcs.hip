@@ -215,10 +215,12 @@ static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, 
 
 // Right-hand side, Dirichlet rows and the diagonal of A, one row per
 // lane group.  x0 of the velocity solve (U^{n-1}) is copied on the way.
+// cv (nullable per component): an explicit convection vector subtracted
+// from the right-hand side (eq:convection_ABE).
 template <int D, int L>
 __global__ __launch_bounds__(kBlock) void k_tent_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ M,
-    double *__restrict__ A, P3 dP, P3 U1, const double *__restrict__ p,
+    double *__restrict__ A, P3 dP, P3 U1, P3 cv, const double *__restrict__ p,
     const double *__restrict__ ML, const int *__restrict__ bc_index, const double *__restrict__ g,
     int nbc, double f0, double f1, double f2, double two_over_dt, double *__restrict__ b0,
     double *__restrict__ b1, double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1,
@@ -262,7 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                bo[k][i] = q >= 0 ? g[k * nbc + q] : f[k] * ML[i] + acc[k] - accp[k];
+                bo[k][i] = q >= 0 ? g[k * nbc + q]
+                                  : f[k] * ML[i] + acc[k] - accp[k] - (cv.p[k] ? cv.p[k][i] : 0.0);
                 xo[k][i] = dd * U1.p[k][i];      // y0 = D x0 for the column-scaled system
             }
             dA[i] = dd;
@@ -379,6 +382,115 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
 #pragma unroll
         for (int q = 0; q < MAXC; ++q)
             if (q < len) A[s + q] = a[q];
+    }
+}
+
+// Dofs of every cell's vertices (the periodic identification applied once)
+__global__ __launch_bounds__(kBlock) void k_cell_dofs(long long nent, const int *__restrict__ cells,
+                                                      const int *__restrict__ v2d, int *__restrict__ cdof) {
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < nent;
+         j += (long long)gridDim.x * blockDim.x)
+        cdof[j] = v2d[cells[j]];
+}
+
+// Explicit Adams-Bashforth convection (eq:convection_ABE) as vectors:
+// cv_k = 1.5 C(u^{n-1}) U_k^{n-1} - 0.5 C(u^{n-2}) U_k^{n-2}, with C(w)
+// the convection matrix of the P1 field w.  On a cell the gradient of a
+// P1 field is constant and int_T phi_i w = vol/((D+1)(D+2)) (S + w_i),
+// S = sum of w over the cell's vertices, so the cell adds
+// vol/((D+1)(D+2)) (S + w_i) . grad U_k.  Row i gathers its incident cells
+// in ascending order (deterministic, no atomics), two cells' loads in
+// flight at a time as in k_asm_rows.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_conv_rows(int n, const int *__restrict__ iptr,
+                                                      const int *__restrict__ inc, const int *__restrict__ cells,
+                                                      const int *__restrict__ cdof, const double *__restrict__ X,
+                                                      P3 U1, P3 U2, double *__restrict__ cv0,
+                                                      double *__restrict__ cv1, double *__restrict__ cv2) {
+    constexpr int NV = D + 1;
+    constexpr double mfac = 1.0 / ((D + 1) * (D + 2));
+    double *co[3] = {cv0, cv1, cv2};
+    struct Cell {
+        double x[NV][D], u1[NV][D], u2[NV][D];
+        int la;
+    };
+    const RowRange<1, kBlock> rr(n);   // XCD-aware rows, as in k_asm_rows
+    for (long long row = rr.first + rr.gid; row < rr.last; row += rr.ngroups) {
+        const int i = static_cast<int>(row);
+        double acc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = 0.0;
+        auto load = [&](int t, Cell &C) {
+            const int code = inc[t];
+            const int cell = code / NV;
+            C.la = code - cell * NV;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                const int v = cells[(long long)cell * NV + m];
+                const int dd = cdof[(long long)cell * NV + m];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    C.x[m][c] = X[(long long)v * D + c];
+                    C.u1[m][c] = U1.p[c][dd];
+                    C.u2[m][c] = U2.p[c][dd];
+                }
+            }
+        };
+        // coef * vol/((D+1)(D+2)) (S + w_la) . grad(w_k) for every component k
+        auto field = [&](const Elem<D> &e, const double (&w)[NV][D], int la, double coef) {
+            double a[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double S = 0.0;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) S += w[m][c];
+                double wl = w[0][c];
+#pragma unroll
+                for (int m = 1; m < NV; ++m) wl = (la == m) ? w[m][c] : wl;
+                a[c] = S + wl;
+            }
+            const double fac = coef * e.vol * mfac;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    double gr = 0.0;
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) gr += e.g[m][c] * w[m][k];
+                    s += a[c] * gr;
+                }
+                acc[k] += fac * s;
+            }
+        };
+        auto add = [&](const Cell &C, double keep) {
+            Elem<D> e;
+            p1_element<D>(C.x, e);
+            field(e, C.u1, C.la, 1.5 * keep);
+            field(e, C.u2, C.la, -0.5 * keep);
+        };
+        const int t0 = iptr[i], t1 = iptr[i + 1];
+        for (int t = t0; t < t1; t += 2) {
+            const bool two = t + 1 < t1;
+            Cell c0, c1;
+            load(t, c0);
+            load(two ? t + 1 : t, c1);
+            add(c0, 1.0);
+            add(c1, two ? 1.0 : 0.0);   // weight 0 on an odd tail's clamped copy
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) co[k][i] = acc[k];
+    }
+}
+
+// G^k = M_L^{-1} dP^k: the rows of dP^k over the lumped mass (the weighted
+// gradient matrix of the direct velocity update)
+__global__ __launch_bounds__(kBlock) void k_row_div(int n, const int *__restrict__ rp, const double *__restrict__ a,
+                                                    const double *__restrict__ d, double *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double r = d[i];
+        for (int j = rp[i]; j < rp[i + 1]; ++j) out[j] = a[j] / r;
     }
 }
 
@@ -519,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__rest
         for (int k = 0; k < D; ++k) acc[k] = group_sum<L>(acc[k]);
         if (lane == 0) {
             const int q = bc_index[row];
-            const double inv = dt / ML[row];
+            const double inv = ML ? dt / ML[row] : dt;   // no M_L: the gradient matrix
 #pragma unroll
             for (int k = 0; k < D; ++k) uo[k][row] = q >= 0 ? g[k * nbc + q] : UI.p[k][row] - inv * acc[k];
         }
@@ -916,6 +1028,7 @@ struct oasis_ipcs {
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
     int *iptr = nullptr, *inc = nullptr, *icnt = nullptr, *itmp = nullptr;
+    int *cdof = nullptr;          // dofs of each cell's vertices
     int assembly = OASIS_ASSEMBLE_ROWS, maxc = 16;
     double *ubar = nullptr;   // per step u_bar, interleaved ([n][D == 3 ? 4 : 2])
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
@@ -933,6 +1046,10 @@ struct oasis_ipcs {
     bool consistent = false;  // consistent-mass velocity update
     double *Ms = nullptr, *eM = nullptr, *sM = nullptr, *wM = nullptr;   // its scaled matrix
     CGWork<double> cgM;
+    bool abe = false;         // explicit Adams-Bashforth convection
+    double *cv[3] = {nullptr, nullptr, nullptr};   // its right-hand-side vectors
+    bool gradient = false;    // weighted-gradient-matrix velocity update
+    double *G[3] = {nullptr, nullptr, nullptr};    // G^k = M_L^{-1} dP^k
     int nsc = 0;              // passive scalars
     double *Bs[OASIS_MAX_SCALARS] = {nullptr, nullptr, nullptr, nullptr};   // M/dt + D K/2 each
     // learned warm start (optional)
@@ -962,7 +1079,7 @@ static int ell_setup(hipStream_t s, int n, const int *rp, const int *ci, const d
 }
 
 static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, bool consistent, int nsc,
-                       oasis_ipcs &h) {
+                       bool abe, bool gradient, oasis_ipcs &h) {
     h.ecol = c.take<short>((size_t)n * kEll);
     h.pid = c.take<unsigned short>(n);
     h.ptab = c.take<short>((size_t)kMaxEllPatterns * kEll);
@@ -1009,6 +1126,7 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
     h.ubar = c.take<double>((size_t)n * (dim == 3 ? 4 : 2));
     h.iptr = c.take<int>((size_t)n + 1);
     h.inc = c.take<int>((size_t)ncell * (dim + 1));
+    h.cdof = c.take<int>((size_t)ncell * (dim + 1));
     h.icnt = c.take<int>((size_t)nmax + 1);
     h.itmp = c.take<int>(incidence_tmp_ints(nmax));
     carve_cg<double>(c, n, h.cg);
@@ -1026,6 +1144,10 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
         carve_cg<double>(c, n, h.cgM);
     }
     for (int a = 0; a < nsc; ++a) h.Bs[a] = c.take<double>(nnz);
+    if (abe)
+        for (int k = 0; k < dim; ++k) h.cv[k] = c.take<double>(n);
+    if (gradient)
+        for (int k = 0; k < dim; ++k) h.G[k] = c.take<double>(nnz);
 }
 
 static int check_params(const oasis_ipcs_params *p) {
@@ -1035,8 +1157,10 @@ static int check_params(const oasis_ipcs_params *p) {
     if (p->pressure_start != OASIS_PSTART_PREV && p->pressure_start != OASIS_PSTART_ZERO) return OASIS_EINVAL;
     if (!(p->pressure_delta >= 0.0 && p->pressure_delta < 1.0)) return OASIS_EINVAL;
     if (p->inner_iters < 0 || p->inner_iters > 16) return OASIS_EINVAL;
-    if (p->velocity_update != OASIS_UPDATE_LUMPED && p->velocity_update != OASIS_UPDATE_CONSISTENT)
+    if (p->velocity_update != OASIS_UPDATE_LUMPED && p->velocity_update != OASIS_UPDATE_CONSISTENT &&
+        p->velocity_update != OASIS_UPDATE_GRADIENT)
         return OASIS_EINVAL;
+    if (p->convection != OASIS_CONV_ABCN && p->convection != OASIS_CONV_ABE) return OASIS_EINVAL;
     if (p->n_scalars < 0 || p->n_scalars > OASIS_MAX_SCALARS) return OASIS_EINVAL;
     for (int a = 0; a < p->n_scalars; ++a)
         if (!(p->diffusivity[a] >= 0.0) || !std::isfinite(p->diffusivity[a]) || !std::isfinite(p->scalar_source[a]))
@@ -1052,7 +1176,8 @@ extern "C" int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz, co
     Carver c(nullptr, 0);
     oasis_ipcs h;
     carve_ipcs(c, mesh->dim, mesh->n_dof, mesh->n_cell, nnz, par->precision == OASIS_F32,
-               par->velocity_update == OASIS_UPDATE_CONSISTENT, par->n_scalars, h);
+               par->velocity_update == OASIS_UPDATE_CONSISTENT, par->n_scalars, par->convection == OASIS_CONV_ABE,
+               par->velocity_update == OASIS_UPDATE_GRADIENT, h);
     *bytes = c.bytes();
     return OASIS_OK;
 }
@@ -1084,8 +1209,10 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     h->inner = par->inner_iters > 0 ? par->inner_iters : 1;
     h->consistent = par->velocity_update == OASIS_UPDATE_CONSISTENT;
     h->nsc = par->n_scalars;
+    h->abe = par->convection == OASIS_CONV_ABE;
+    h->gradient = par->velocity_update == OASIS_UPDATE_GRADIENT;
     Carver c(ws, ws_bytes);
-    carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, h->consistent, h->nsc, *h);
+    carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, h->consistent, h->nsc, h->abe, h->gradient, *h);
     h->cg.tun = h->cg32.tun = h->cgM.tun = h->tun;
     h->bi.tun = h->bi32.tun = h->tun;
     auto fail = [&](int rc) {
@@ -1141,6 +1268,9 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
                            kScaleSym, h->Ms, static_cast<float *>(nullptr));
     }
     hipLaunchKernelGGL(k_row_sums, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->M, h->ML);
+    if (h->gradient)
+        for (int k = 0; k < D; ++k)
+            hipLaunchKernelGGL(k_row_div, dim3(gvec(n)), dim3(kBlock), 0, s, n, row_ptr, h->dP[k], h->ML, h->G[k]);
     if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
     // ELL copy of the pressure matrix for the CG product when its rows and
     // column offsets allow it (else the CSR product runs)
@@ -1185,10 +1315,16 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
             h->maxc = 32;
         else
             h->assembly = OASIS_ASSEMBLE_COLORS;
-        if (h->assembly == OASIS_ASSEMBLE_ROWS) {
-            const int rc2 = incidence_codes(s, &h->mesh, h->iptr, h->inc, h->icnt, h->itmp, h->flag + 3);
-            if (rc2 != OASIS_OK) return fail(rc2);
-        }
+    }
+    // dof -> incident cells and the cells' dofs: the row-gather assembly and
+    // the explicit convection
+    if (h->assembly == OASIS_ASSEMBLE_ROWS || h->abe) {
+        const int rc2 = incidence_codes(s, &h->mesh, h->iptr, h->inc, h->icnt, h->itmp, h->flag + 3);
+        if (rc2 != OASIS_OK) return fail(rc2);
+        const long long nent = (long long)mesh->n_cell * (D + 1);
+        hipLaunchKernelGGL(k_cell_dofs, dim3(grid_for(nent, kBlock, 1 << 20)), dim3(kBlock), 0, s, nent,
+                           mesh->cells, mesh->vert2dof, h->cdof);
+        if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
     }
     // the scaled pressure matrix has null vector s = sqrt(diag K) (K 1 = 0)
     // with it, the norm weights d = s^2 of the FP32 iterations are ||s||^2 v^2
@@ -1267,19 +1403,39 @@ template <int D, int L>
 static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g,
                                      double *const *x) {
     const int n = h->n;
-    P3 dP{}, U1{};
+    P3 dP{}, U1{}, cv{};
     for (int k = 0; k < D; ++k) {
         dP.p[k] = h->dP[k];
         U1.p[k] = st->U1[k];
+        cv.p[k] = h->abe ? h->cv[k] : nullptr;
     }
     const int grid = grid_for(n, kBlock / L, 1 << 20);
     hipLaunchKernelGGL((k_tent_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A,
-                       dP, U1, st->p, h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1],
+                       dP, U1, cv, st->p, h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1],
                        h->par.f[2], 2.0 / h->par.dt, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0],
                        x[1], D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
 }
 
+// A = Bsrc + C(u_bar)/2 by the row-gather kernel (u_bar already in h->ubar)
 template <int D, int MAXC>
+static void launch_asm_kernel(hipStream_t s, oasis_ipcs *h, const double *Bsrc) {
+    hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid_for(h->n, kBlock, 1 << 20)), dim3(kBlock), 0, s, h->n,
+                       h->rp, h->ci, Bsrc, h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar,
+                       h->A);
+}
+
+static void launch_asm(hipStream_t s, oasis_ipcs *h, const double *Bsrc) {
+    if (h->dim == 3 && h->maxc == 16)
+        launch_asm_kernel<3, 16>(s, h, Bsrc);
+    else if (h->dim == 3)
+        launch_asm_kernel<3, 32>(s, h, Bsrc);
+    else if (h->maxc == 16)
+        launch_asm_kernel<2, 16>(s, h, Bsrc);
+    else
+        launch_asm_kernel<2, 32>(s, h, Bsrc);
+}
+
+template <int D>
 static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g, double *const *x) {
     const int n = h->n;
     P3 U1{}, U2{};
@@ -1288,9 +1444,7 @@ static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st,
         U2.p[k] = st->U2[k];
     }
     hipLaunchKernelGGL((k_ubar<D>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
-    const int grid = grid_for(n, kBlock, 1 << 20);
-    hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->B, h->iptr,
-                       h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+    launch_asm(s, h, h->B);
     // right-hand sides, Dirichlet rows, diagonal and y0 (8 lanes per row)
     launch_step_kernels_tent<D, 8>(s, h, st, g, x);
 }
@@ -1313,12 +1467,12 @@ static void launch_update(hipStream_t s, oasis_ipcs *h, double *const *x, const 
                           double *const *un) {
     P3 dP{}, UI{};
     for (int k = 0; k < D; ++k) {
-        dP.p[k] = h->dP[k];
+        dP.p[k] = h->gradient ? h->G[k] : h->dP[k];
         UI.p[k] = x[k];
     }
     const int grid = grid_for(h->n, kBlock / L, 1 << 20);
     hipLaunchKernelGGL((k_update_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, h->n, h->rp, h->ci, dP, UI, phi,
-                       h->ML, h->bc_index, g, h->par.n_bc, h->par.dt, un[0], un[1], D > 2 ? un[2] : nullptr);
+                       h->gradient ? static_cast<const double *>(nullptr) : h->ML, h->bc_index, g, h->par.n_bc, h->par.dt, un[0], un[1], D > 2 ? un[2] : nullptr);
 }
 
 // One passive scalar: A_c = M/dt + D K/2 + C(u_bar)/2 by the step's
@@ -1331,19 +1485,7 @@ static int scalar_solve(hipStream_t s, oasis_ipcs *h, oasis_state *st, int a, in
     const int n = h->n;
     if (!st->C1[a] || !st->Cn[a] || (h->par.n_bc > 0 && !st->C_bc[a])) return OASIS_EINVAL;
     if (h->assembly == OASIS_ASSEMBLE_ROWS) {
-        const int grid = grid_for(n, kBlock, 1 << 20);
-        if (D == 3 && h->maxc == 16)
-            hipLaunchKernelGGL((k_asm_rows<3, 16>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
-                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
-        else if (D == 3)
-            hipLaunchKernelGGL((k_asm_rows<3, 32>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
-                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
-        else if (h->maxc == 16)
-            hipLaunchKernelGGL((k_asm_rows<2, 16>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
-                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
-        else
-            hipLaunchKernelGGL((k_asm_rows<2, 32>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->Bs[a],
-                               h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar, h->A);
+        launch_asm(s, h, h->Bs[a]);
         OASIS_TRY_LAUNCH();
     } else {
         P3 U1{}, U2{};
@@ -1359,7 +1501,7 @@ static int scalar_solve(hipStream_t s, oasis_ipcs *h, oasis_state *st, int a, in
     C1.p[0] = st->C1[a];
     const int grid = grid_for(n, kBlock / 8, 1 << 20);
     hipLaunchKernelGGL((k_tent_rows<1, 8>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A, none, C1,
-                       static_cast<const double *>(nullptr), h->ML, h->bc_index, st->C_bc[a], h->par.n_bc,
+                       none, static_cast<const double *>(nullptr), h->ML, h->bc_index, st->C_bc[a], h->par.n_bc,
                        h->par.scalar_source[a], 0.0, 0.0, 2.0 / h->par.dt, h->bt[0], static_cast<double *>(nullptr),
                        static_cast<double *>(nullptr), st->Cn[a], static_cast<double *>(nullptr),
                        static_cast<double *>(nullptr), h->dA, h->wA, h->wA32);
@@ -1412,16 +1554,28 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     }
     double *x[3];
     for (int k = 0; k < D; ++k) x[k] = st->UI[k] ? st->UI[k] : h->ui[k];
-    if (h->assembly == OASIS_ASSEMBLE_ROWS) {
+    if (h->abe) {
+        // 1+2 (eq:convection_ABE): A = M/dt + nu K/2, the explicit convection
+        // vectors, right-hand sides, Dirichlet rows, diagonal; y0 = D U^{n-1}
+        OASIS_TRY(scale_copy(s, h->nnz, h->A, h->B, 1.0));
+        const int grid = grid_for(n, kBlock, 1 << 20);
+        if (D == 3) {
+            hipLaunchKernelGGL(k_conv_rows<3>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->mesh.cells,
+                               h->cdof, h->mesh.coords, U1, U2, h->cv[0], h->cv[1], h->cv[2]);
+            launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
+        } else {
+            hipLaunchKernelGGL(k_conv_rows<2>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->mesh.cells,
+                               h->cdof, h->mesh.coords, U1, U2, h->cv[0], h->cv[1],
+                               static_cast<double *>(nullptr));
+            launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
+        }
+        OASIS_TRY_LAUNCH();
+    } else if (h->assembly == OASIS_ASSEMBLE_ROWS) {
         // 1+2. rows gather A = B + C(u_bar)/2, right-hand sides, Dirichlet rows, scaling
-        if (D == 3 && h->maxc == 16)
-            launch_asm_rows<3, 16>(s, h, st, bc_values, x);
-        else if (D == 3)
-            launch_asm_rows<3, 32>(s, h, st, bc_values, x);
-        else if (h->maxc == 16)
-            launch_asm_rows<2, 16>(s, h, st, bc_values, x);
+        if (D == 3)
+            launch_asm_rows<3>(s, h, st, bc_values, x);
         else
-            launch_asm_rows<2, 32>(s, h, st, bc_values, x);
+            launch_asm_rows<2>(s, h, st, bc_values, x);
         OASIS_TRY_LAUNCH();
     } else {
         // 1. A = B + C(u_bar)/2, colour by colour
@@ -1597,7 +1751,15 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     }
     OASIS_TRY_HIP(hipEventRecord(h->ev[4], s));
     // 7. passive scalars (eq:scalar_disc): the velocity's u_bar (still in
-    // h->ubar), M/dt + D K/2 in place of B, no pressure gradient
+    // h->ubar, or formed here after an explicit-convection step), M/dt + D K/2
+    // in place of B, no pressure gradient
+    if (h->nsc > 0 && h->abe && h->assembly == OASIS_ASSEMBLE_ROWS) {
+        if (D == 3)
+            hipLaunchKernelGGL((k_ubar<3>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
+        else
+            hipLaunchKernelGGL((k_ubar<2>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
+        OASIS_TRY_LAUNCH();
+    }
     for (int a = 0; a < h->nsc; ++a) {
         int status = OASIS_OK;
         OASIS_TRY(scalar_solve(s, h, st, a, D, o, S, &status));

@@ -6,6 +6,9 @@ against the oracle's (oracle/ipcs.py), field by field:
   Dirichlet values (Taylor-Green) and on the channel;
 * passive scalars (eq:scalar_disc) with their own diffusivity, source and
   Dirichlet values;
+* the explicit Adams-Bashforth convection (eq:convection_ABE), also with
+  inner iterations and a scalar;
+* the weighted-gradient-matrix velocity update;
 * all of them together with the multigrid pressure solve.
 
 FP64 runs at rtol 1e-13 on both sides must agree to 1e-10 per field; the
@@ -52,13 +55,13 @@ def _scalars(prob, k):
     return sc, np.stack(C1) if k else None
 
 
-def _run(oa, prob, steps, rtol, precision=0, inner=1, update=0, nsc=0, amg=None):
+def _run(oa, prob, steps, rtol, precision=0, inner=1, update=0, nsc=0, amg=None, convection=0):
     m = prob.mesh
     dm, pat, _ = device_mesh(m)
     sc, C1 = _scalars(prob, nsc)
     h = oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32), rtol_u=rtol, rtol_p=rtol,
                 precision=precision, inner_iters=inner, velocity_update=update,
-                diffusivity=[s.D for s in sc], scalar_source=[s.f for s in sc])
+                diffusivity=[s.D for s in sc], scalar_source=[s.f for s in sc], convection=convection)
     hamg = h.pressure_amg(precision=amg) if amg is not None else None
     U = [T(prob.U2), T(prob.U1)]
     p, phi = T(prob.p), T(prob.phi_prev)
@@ -80,13 +83,13 @@ def _run(oa, prob, steps, rtol, precision=0, inner=1, update=0, nsc=0, amg=None)
     return out, stats, (h, hamg)
 
 
-def _oracle(prob, steps, rtol, inner=1, update="lumped", nsc=0):
+def _oracle(prob, steps, rtol, inner=1, update="lumped", nsc=0, convection="abcn"):
     S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
     sc, C1 = _scalars(prob, nsc)
     st = ipcs.initial_state(prob, C1)
     for _ in range(steps):
         o = ipcs.step(S, st, prob.bc_values, rtol_u=rtol, rtol_p=rtol, inner_iters=inner, update=update,
-                      scalars=sc)
+                      scalars=sc, convection=convection)
         st = o.state
     return dict(U=st.U1, p=st.p, phi=o.phi, C=st.C1), o
 
@@ -161,3 +164,55 @@ def test_all_options_with_multigrid_fp64_and_mixed(oa):
     # is set by the 1e-8 solver tolerance (a few 1e-6 here): bounded at 1e-5
     for k, v in em.items():
         assert v <= (1e-5 if k == "p" else 1e-6), (k, v)
+
+
+@pytest.mark.parametrize("prob", CASES, ids=lambda p: p.name)
+def test_abe_convection_matches_oracle(oa, prob):
+    say("explicit convection", prob.name)
+    g, stats, keep = _run(oa, prob, 3, 1e-13, convection=oa.CONV_ABE)
+    r, o = _oracle(prob, 3, 1e-13, convection="abe")
+    e = _errors(g, r)
+    say("abe per-field relative L2:", e, "iters_u", [s["iters_u"] for s in stats])
+    assert all(s["status"] == 0 for s in stats)
+    for k, v in e.items():
+        assert v <= 1e-10, (k, v)
+    # and it is not the ABCN step
+    a, _, _ = _run(oa, prob, 3, 1e-13)
+    assert rel(a["U"], g["U"]) > 1e-8
+
+
+def test_abe_with_inner_iterations_and_a_scalar_matches_oracle(oa):
+    prob = synth.channel_flow("small", seed=6)
+    say("explicit convection + inner 2 + scalar", prob.name)
+    g, stats, keep = _run(oa, prob, 2, 1e-13, convection=oa.CONV_ABE, inner=2, nsc=1)
+    r, o = _oracle(prob, 2, 1e-13, convection="abe", inner=2, nsc=1)
+    e = _errors(g, r)
+    say("abe+inner+scalar per-field relative L2:", e)
+    assert all(s["status"] == 0 for s in stats)
+    for k, v in e.items():
+        assert v <= 1e-10, (k, v)
+
+
+@pytest.mark.parametrize("prob", CASES, ids=lambda p: p.name)
+def test_gradient_update_matches_oracle(oa, prob):
+    say("gradient-matrix update", prob.name)
+    g, stats, keep = _run(oa, prob, 2, 1e-13, update=oa.UPDATE_GRADIENT)
+    r, o = _oracle(prob, 2, 1e-13, update="gradient")
+    e = _errors(g, r)
+    say("gradient per-field relative L2:", e)
+    assert all(s["status"] == 0 for s in stats)
+    for k, v in e.items():
+        assert v <= 1e-10, (k, v)
+
+
+def test_abe_gradient_mixed_multigrid_against_fp64_oracle(oa):
+    prob = synth.channel_flow((33, 33, 25), seed=8)
+    say("abe + gradient + mixed amg", prob.name)
+    r, o = _oracle(prob, 2, 1e-13, update="gradient", convection="abe")
+    g, stats, keep = _run(oa, prob, 2, 1e-8, precision=oa.F32, update=oa.UPDATE_GRADIENT, amg=oa.F32,
+                          convection=oa.CONV_ABE)
+    e = _errors(g, r)
+    say("abe + gradient + mixed amg per-field:", e)
+    assert all(s["status"] == 0 for s in stats)
+    for k, v in e.items():
+        assert v <= (1e-5 if k in ("p", "phi") else 1e-6), (k, v)

@@ -105,7 +105,8 @@ def test_invalid_ipcs_params_rejected_on_host(lib):
         p = L.IpcsParams.from_buffer_copy(good)
         setattr(p, field, bad)
         assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL, field
-    for field, bad in [("inner_iters", 17), ("velocity_update", 2), ("n_scalars", 5)]:
+    for field, bad in [("inner_iters", 17), ("velocity_update", 3), ("n_scalars", 5), ("convection", 2),
+                       ("convection", -1)]:
         p = L.IpcsParams.from_buffer_copy(good)
         setattr(p, field, bad)
         assert lib.oasis_ipcs_workspace_size(C.byref(m), 40, C.byref(p), C.byref(nb)) == L.EINVAL, field
