@@ -288,6 +288,21 @@ __global__ __launch_bounds__(kBlock) void k_ubar(int n, P3 U1, P3 U2, double *__
     }
 }
 
+// U^{n-1} and U^{n-2} interleaved per dof for k_conv_rows' gathers
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_uu(int n, P3 U1, P3 U2, double *__restrict__ uu) {
+    constexpr int UW = D == 3 ? 4 : 2;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            uu[i * 2 * UW + c] = U1.p[c][i];
+            uu[i * 2 * UW + UW + c] = U2.p[c][i];
+        }
+        if (D == 3) uu[i * 2 * UW + 3] = uu[i * 2 * UW + 7] = 0.0;
+    }
+}
+
 // Row-gather form of step 1: every row assembles its own entries of
 // A = B + C(u_bar)/2 from the cells around its dof (the convection part of
 // Alg. 2's coefficient matrix); k_tent_rows then forms the right-hand side,
@@ -296,8 +311,13 @@ __global__ __launch_bounds__(kBlock) void k_ubar(int n, P3 U1, P3 U2, double *__
 // (column dof c, value v) is added to the slot whose column equals c (a
 // compile-time unrolled match).  The incident cells are visited in
 // ascending order, so the sums are deterministic; no other thread writes
-// the row, so no atomics and no colouring are needed.
-template <int D, int MAXC>
+// the row, so no atomics and no colouring are needed.  The kernel is bound
+// by how many dependent gathers are in flight (incidence -> vertices ->
+// dofs -> coordinates and u_bar): NC cells are loaded before any is added
+// (an odd tail's clamped copy is added with weight 0, so the compiler
+// cannot sink its loads behind the first cell's arithmetic), and the rows
+// are split XCD-aware so that neighbouring rows' cells share one L2.
+template <int D, int MAXC, int NC = (MAXC <= 16 ? 3 : 2)>
 __global__ __launch_bounds__(kBlock) void k_asm_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ B,
     const int *__restrict__ iptr, const int *__restrict__ inc, const int *__restrict__ cells,
@@ -306,8 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
     constexpr int NV = D + 1;
     constexpr int UW = D == 3 ? 4 : 2;                  // u_bar row width
     constexpr double mfac = 0.5 / ((D + 1) * (D + 2));   // C/2 and the mass-moment factor
-    for (long long row = blockIdx.x * (long long)blockDim.x + threadIdx.x; row < n;
-         row += (long long)gridDim.x * blockDim.x) {
+    const RowRange<1> rr(n);
+    for (long long row = rr.first + rr.gid; row < rr.last; row += rr.ngroups) {
         const int i = static_cast<int>(row);
         const int s = rp[i], len = rp[i + 1] - s;
         int col[MAXC];
@@ -317,11 +337,6 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
             col[q] = q < len ? ci[s + q] : -1;
             a[q] = q < len ? B[s + q] : 0.0;
         }
-        // cells two at a time: both cells' loads (incidence, vertices, dofs,
-        // coordinates, u_bar) are issued before either is added, so that
-        // their dependent chains overlap; the second of an odd tail is a
-        // clamped copy that is not added.  Cells are added in ascending
-        // order, as one at a time.
         struct Cell {
             double x[NV][D], ub[NV][D];
             int dd[NV], la;
@@ -341,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                 }
             }
         };
-        auto add = [&](const Cell &C) {
+        auto add = [&](const Cell &C, double keep) {
             Elem<D> e;
             p1_element<D>(C.x, e);
             double w[D];   // S + u_bar at the row's local vertex
@@ -355,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                 for (int k = 1; k < NV; ++k) ua = (C.la == k) ? C.ub[k][c] : ua;
                 w[c] = S + ua;
             }
-            const double fac = e.vol * mfac;
+            const double fac = keep * e.vol * mfac;
 #pragma unroll
             for (int jl = 0; jl < NV; ++jl) {
                 double gw = 0.0;
@@ -370,27 +385,20 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                 for (int q = 0; q < MAXC; ++q) a[q] = __fma_rn((col[q] == target) ? 1.0 : 0.0, v, a[q]);
             }
         };
+        // NC cells' loads in flight, then their contributions in ascending
+        // order (as one at a time)
         const int t0 = iptr[i], t1 = iptr[i + 1];
-        for (int t = t0; t < t1; t += 2) {
-            const bool two = t + 1 < t1;
-            Cell c0, c1;
-            load(t, c0);
-            load(two ? t + 1 : t, c1);
-            add(c0);
-            if (two) add(c1);
+        for (int t = t0; t < t1; t += NC) {
+            Cell cc[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) load(t + k < t1 ? t + k : t, cc[k]);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) add(cc[k], t + k < t1 ? 1.0 : 0.0);
         }
 #pragma unroll
         for (int q = 0; q < MAXC; ++q)
             if (q < len) A[s + q] = a[q];
     }
-}
-
-// Dofs of every cell's vertices (the periodic identification applied once)
-__global__ __launch_bounds__(kBlock) void k_cell_dofs(long long nent, const int *__restrict__ cells,
-                                                      const int *__restrict__ v2d, int *__restrict__ cdof) {
-    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < nent;
-         j += (long long)gridDim.x * blockDim.x)
-        cdof[j] = v2d[cells[j]];
 }
 
 // Explicit Adams-Bashforth convection (eq:convection_ABE) as vectors:
@@ -399,14 +407,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_dofs(long long nent, const int 
 // P1 field is constant and int_T phi_i w = vol/((D+1)(D+2)) (S + w_i),
 // S = sum of w over the cell's vertices, so the cell adds
 // vol/((D+1)(D+2)) (S + w_i) . grad U_k.  Row i gathers its incident cells
-// in ascending order (deterministic, no atomics), two cells' loads in
-// flight at a time as in k_asm_rows.
+// in ascending order (deterministic, no atomics), with two cells' loads in
+// flight and XCD-aware rows, as k_asm_rows.  uu: U^{n-1} and U^{n-2}
+// interleaved per dof (k_uu), one 64-byte record in 3D.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_conv_rows(int n, const int *__restrict__ iptr,
                                                       const int *__restrict__ inc, const int *__restrict__ cells,
-                                                      const int *__restrict__ cdof, const double *__restrict__ X,
-                                                      P3 U1, P3 U2, double *__restrict__ cv0,
+                                                      const int *__restrict__ v2d, const double *__restrict__ X,
+                                                      const double *__restrict__ uu, double *__restrict__ cv0,
                                                       double *__restrict__ cv1, double *__restrict__ cv2) {
+    constexpr int UW = D == 3 ? 4 : 2;
     constexpr int NV = D + 1;
     constexpr double mfac = 1.0 / ((D + 1) * (D + 2));
     double *co[3] = {cv0, cv1, cv2};
@@ -414,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_rows(int n, const int *__restri
         double x[NV][D], u1[NV][D], u2[NV][D];
         int la;
     };
-    const RowRange<1, kBlock> rr(n);   // XCD-aware rows, as in k_asm_rows
+    const RowRange<1, kBlock> rr(n);
     for (long long row = rr.first + rr.gid; row < rr.last; row += rr.ngroups) {
         const int i = static_cast<int>(row);
         double acc[D];
@@ -427,12 +437,12 @@ __global__ __launch_bounds__(kBlock) void k_conv_rows(int n, const int *__restri
 #pragma unroll
             for (int m = 0; m < NV; ++m) {
                 const int v = cells[(long long)cell * NV + m];
-                const int dd = cdof[(long long)cell * NV + m];
+                const long long dd = v2d[v];
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     C.x[m][c] = X[(long long)v * D + c];
-                    C.u1[m][c] = U1.p[c][dd];
-                    C.u2[m][c] = U2.p[c][dd];
+                    C.u1[m][c] = uu[dd * 2 * UW + c];
+                    C.u2[m][c] = uu[dd * 2 * UW + UW + c];
                 }
             }
         };
@@ -1028,7 +1038,6 @@ struct oasis_ipcs {
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
     int *iptr = nullptr, *inc = nullptr, *icnt = nullptr, *itmp = nullptr;
-    int *cdof = nullptr;          // dofs of each cell's vertices
     int assembly = OASIS_ASSEMBLE_ROWS, maxc = 16;
     double *ubar = nullptr;   // per step u_bar, interleaved ([n][D == 3 ? 4 : 2])
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
@@ -1048,6 +1057,7 @@ struct oasis_ipcs {
     CGWork<double> cgM;
     bool abe = false;         // explicit Adams-Bashforth convection
     double *cv[3] = {nullptr, nullptr, nullptr};   // its right-hand-side vectors
+    double *uu = nullptr;     // U^{n-1}, U^{n-2} interleaved per dof
     bool gradient = false;    // weighted-gradient-matrix velocity update
     double *G[3] = {nullptr, nullptr, nullptr};    // G^k = M_L^{-1} dP^k
     int nsc = 0;              // passive scalars
@@ -1126,7 +1136,6 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
     h.ubar = c.take<double>((size_t)n * (dim == 3 ? 4 : 2));
     h.iptr = c.take<int>((size_t)n + 1);
     h.inc = c.take<int>((size_t)ncell * (dim + 1));
-    h.cdof = c.take<int>((size_t)ncell * (dim + 1));
     h.icnt = c.take<int>((size_t)nmax + 1);
     h.itmp = c.take<int>(incidence_tmp_ints(nmax));
     carve_cg<double>(c, n, h.cg);
@@ -1144,8 +1153,10 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
         carve_cg<double>(c, n, h.cgM);
     }
     for (int a = 0; a < nsc; ++a) h.Bs[a] = c.take<double>(nnz);
-    if (abe)
+    if (abe) {
         for (int k = 0; k < dim; ++k) h.cv[k] = c.take<double>(n);
+        h.uu = c.take<double>((size_t)n * (dim == 3 ? 8 : 4));
+    }
     if (gradient)
         for (int k = 0; k < dim; ++k) h.G[k] = c.take<double>(nnz);
 }
@@ -1316,15 +1327,10 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
         else
             h->assembly = OASIS_ASSEMBLE_COLORS;
     }
-    // dof -> incident cells and the cells' dofs: the row-gather assembly and
-    // the explicit convection
+    // dof -> incident cells: the row-gather assembly and the explicit convection
     if (h->assembly == OASIS_ASSEMBLE_ROWS || h->abe) {
         const int rc2 = incidence_codes(s, &h->mesh, h->iptr, h->inc, h->icnt, h->itmp, h->flag + 3);
         if (rc2 != OASIS_OK) return fail(rc2);
-        const long long nent = (long long)mesh->n_cell * (D + 1);
-        hipLaunchKernelGGL(k_cell_dofs, dim3(grid_for(nent, kBlock, 1 << 20)), dim3(kBlock), 0, s, nent,
-                           mesh->cells, mesh->vert2dof, h->cdof);
-        if (hipGetLastError() != hipSuccess) return fail(OASIS_EHIP);
     }
     // the scaled pressure matrix has null vector s = sqrt(diag K) (K 1 = 0)
     // with it, the norm weights d = s^2 of the FP32 iterations are ||s||^2 v^2
@@ -1560,12 +1566,14 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         OASIS_TRY(scale_copy(s, h->nnz, h->A, h->B, 1.0));
         const int grid = grid_for(n, kBlock, 1 << 20);
         if (D == 3) {
+            hipLaunchKernelGGL(k_uu<3>, dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->uu);
             hipLaunchKernelGGL(k_conv_rows<3>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->mesh.cells,
-                               h->cdof, h->mesh.coords, U1, U2, h->cv[0], h->cv[1], h->cv[2]);
+                               h->mesh.vert2dof, h->mesh.coords, h->uu, h->cv[0], h->cv[1], h->cv[2]);
             launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
         } else {
+            hipLaunchKernelGGL(k_uu<2>, dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->uu);
             hipLaunchKernelGGL(k_conv_rows<2>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->mesh.cells,
-                               h->cdof, h->mesh.coords, U1, U2, h->cv[0], h->cv[1],
+                               h->mesh.vert2dof, h->mesh.coords, h->uu, h->cv[0], h->cv[1],
                                static_cast<double *>(nullptr));
             launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
         }
