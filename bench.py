@@ -141,7 +141,7 @@ def device_problem(oa, torch, synth, pr, dev, rcm=False):
 
 
 def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm=None, pstart=0, amg=None,
-                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0):
+                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0, amg_theta=0.0):
     """Time `steps` steps after `warmup` untimed ones; returns the handle, the
     results and the final (U, p, phi).  scalars: that many passive scalars
     with Prandtl number 0.71 (D = nu / 0.71), Dirichlet values y on the
@@ -171,7 +171,7 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
     t_amg, levels = 0.0, 0
     if amg is not None:
         t0 = time.perf_counter()
-        hamg = h.pressure_amg(precision=amg)
+        hamg = h.pressure_amg(precision=amg, theta=amg_theta)
         torch.cuda.synchronize()
         t_amg = time.perf_counter() - t0
         levels = hamg.n_levels()

@@ -21,6 +21,7 @@ PSTART_PREV, PSTART_ZERO = 0, 1
 UPDATE_LUMPED, UPDATE_CONSISTENT, UPDATE_GRADIENT = 0, 1, 2
 CONV_ABCN, CONV_ABE = 0, 1
 MAX_SCALARS = 4
+AMG_THETA = 0.125
 INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS = 100, 101, 102
 STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR = 0, 1, 2
 PCG_NOALLOC_BYTES = 64 << 20

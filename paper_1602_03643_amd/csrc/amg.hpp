@@ -33,7 +33,7 @@ struct HostLevel {
 };
 
 struct AmgHostParams {
-    double theta = 0.25;
+    double theta = OASIS_AMG_THETA;
     int coarse_size = 1024;
     int max_levels = 12;
     bool singular = false;

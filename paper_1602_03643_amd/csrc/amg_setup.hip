@@ -4,7 +4,8 @@
 // once), so the hierarchy is built once on the host and every cycle then
 // runs on the device (amg.hip).
 //
-// Per level l, with theta_l = theta / 2^l:
+// Per level l, with theta_l = theta / 2^l (theta = OASIS_AMG_THETA unless
+// the caller sets it):
 //   strong couplings  |a_ij| >= theta_l sqrt(|a_ii a_jj|), i != j;
 //   aggregation       three greedy passes in index order: (a) a node whose
 //                     strong neighbours are all free starts an aggregate

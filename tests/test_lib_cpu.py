@@ -40,12 +40,12 @@ def test_binding_covers_header():
 def test_header_constants_match_binding():
     from paper_1602_03643_amd import _lib as L
     text = open(HEADER).read()
-    consts = dict(re.findall(r"#define (OASIS_[A-Z0-9_]+)\s+(-?\d+)\b", text))
+    consts = dict(re.findall(r"#define (OASIS_[A-Z0-9_]+)\s+(-?\d+(?:\.\d+)?)(?![\w.])", text))
     checked = 0
     for name, v in consts.items():
         short = name[len("OASIS_"):]
         if hasattr(L, short):
-            assert getattr(L, short) == int(v), name
+            assert getattr(L, short) == (float(v) if "." in v else int(v)), name
             checked += 1
     for short in ["OK", "EINVAL", "ENOTCONV", "ENAN", "F32", "FORM_CONV", "PSTART_ZERO", "ASSEMBLE_COLORS",
                   "KRYLOV_NULLSPACE_CONST", "MPNN_HID"]:
