@@ -141,7 +141,8 @@ def device_problem(oa, torch, synth, pr, dev, rcm=False):
 
 
 def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm=None, pstart=0, amg=None,
-                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0, amg_theta=0.0):
+                perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0, amg_theta=0.0,
+                inner_rtol=0.0):
     """Time `steps` steps after `warmup` untimed ones; returns the handle, the
     results and the final (U, p, phi).  scalars: that many passive scalars
     with Prandtl number 0.71 (D = nu / 0.71), Dirichlet values y on the
@@ -151,7 +152,7 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
     m = pr.mesh
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, bcd, rtol_u=pr.rtol_u, rtol_p=pr.rtol_p, precision=precision,
-                inner_rtol=1e-4, pressure_start=pstart, inner_iters=inner_iters, velocity_update=velocity_update,
+                inner_rtol=inner_rtol, pressure_start=pstart, inner_iters=inner_iters, velocity_update=velocity_update,
                 diffusivity=[pr.nu / 0.71] * scalars, convection=convection)
 
     def T(a):

@@ -364,7 +364,7 @@ typedef struct {
     double rtol_u, rtol_p;    /* Krylov relative tolerances (true residual) */
     int32_t maxit;
     int32_t precision;        /* OASIS_F64 or OASIS_F32 (FP32 inner Krylov + FP64 refinement) */
-    double inner_rtol;        /* F32 mode inner tolerance of the BiCGStab refinement (0 = 1e-4) */
+    double inner_rtol;        /* F32 mode inner tolerance of the BiCGStab refinement (0 = 3e-5) */
     int32_t assembly;         /* per-step convection assembly: OASIS_ASSEMBLE_ROWS (each row
                                  gathers its cells' contributions; fused with the right-hand
                                  side and scaling) or OASIS_ASSEMBLE_COLORS (colour-by-colour
@@ -449,7 +449,7 @@ typedef struct {
     int32_t iters_u[3], iters_p;  /* summed over inner iterations */
     int32_t outer_u, outer_p;
     int32_t status;           /* worst Krylov status of the step */
-    int32_t guess_used;       /* 1 if the guess had a smaller residual than the plain start */
+    int32_t guess_used;       /* 1 if the guess had a lower CG energy than the plain start */
     double res_u[3], res_p;   /* final true relative residuals (last inner iteration) */
     double ms_assemble, ms_velocity, ms_pressure, ms_update, ms_total;  /* HIP-event phase times;
                                  with inner iterations, ms_velocity is the first velocity solve
@@ -483,8 +483,8 @@ int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_p
  * phi, p update and normalisation, velocity update (lumped, consistent or
  * gradient matrix), scalars.  bc_values: device double [dim][n_bc] at t^n.
  * phi_guess (device, nullable): a candidate initial guess for the
- * pressure solve; it is used only if its initial residual is below that of
- * the plain start (par->pressure_start).  stats: host (nullable).
+ * pressure solve; it is used only if its CG energy 1/2 x^T K x - b^T x is
+ * below that of the plain start (par->pressure_start).  stats: host (nullable).
  * Synchronises `stream`. */
 int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
                     const double *bc_values, const double *phi_guess,
@@ -494,7 +494,7 @@ int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *state,
  * pressure-correction solve: every later oasis_ipcs_step without an explicit
  * phi_guess runs the network (oasis_mpnn_forward) on the step's projected
  * right-hand side, phi_prev and the dof coordinates, and starts CG from the
- * prediction only if its initial residual is below that of the plain start
+ * prediction only if its CG energy is below that of the plain start
  * (par->pressure_start); the solve still stops at the same rtol.  params: device float
  * [OASIS_MPNN_NPARAM]; coords: device double [n_dof][dim]; ws: at least
  * oasis_mpnn_workspace_size(n_dof) bytes.  All three are kept by reference.

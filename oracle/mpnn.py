@@ -19,9 +19,9 @@ Network (hidden width 32, 3 message-passing layers):
   delta = h_3 wd + cd
 Guess: phi_prev + sigma * delta.  Training target: (phi - phi_prev) / sigma,
 loss = mean over nodes of (delta - target)^2, averaged over samples.
-The solve starts from the guess only if its residual is below that of the
-plain start (phi_prev, or 0; guarded_start); PCG then runs to the same
-tolerance.
+The solve starts from the guess only if its CG energy 1/2 x^T K x - b^T x
+is below that of the plain start (phi_prev, or 0; guarded_start); PCG then
+runs to the same tolerance.
 Adam (beta1 0.9, beta2 0.999, eps 1e-8), bias-corrected.
 """
 from __future__ import annotations
@@ -157,12 +157,17 @@ def predict_guess(P, K, b_phi, phi_prev, coords):
     return phi_prev + sigma * delta
 
 
+def energy(K, b, x):
+    """The functional CG minimises: J(x) = 1/2 x^T K x - b^T x."""
+    return 0.5 * (x @ (K @ x)) - b @ x
+
+
 def guarded_start(K, b_phi, plain, guess):
-    """The guess is used only if its initial residual is smaller than that of
-    the plain start `plain` (phi_prev, or zeros); otherwise PCG starts from
-    `plain`."""
-    r_g = np.linalg.norm(b_phi - K @ guess)
-    r_p = np.linalg.norm(b_phi - K @ plain)
-    if np.isfinite(r_g) and r_g < r_p:
+    """The guess is used only if its CG energy is lower than that of the
+    plain start `plain` (phi_prev, or zeros); otherwise PCG starts from
+    `plain`.  J(x) - J(x*) = 1/2 ||x - x*||_K^2, the error norm CG reduces."""
+    j_g = energy(K, b_phi, guess)
+    j_p = energy(K, b_phi, plain)
+    if np.isfinite(j_g) and j_g < j_p:
         return guess, True
     return plain, False

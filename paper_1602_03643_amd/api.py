@@ -355,7 +355,7 @@ class IPCS:
     """Handle for oasis_ipcs_create/step/destroy on one mesh."""
 
     def __init__(self, mesh: DeviceMesh, pattern: DeviceCSR, dt, nu, f, bc_dofs: torch.Tensor,
-                 rtol_u=1e-8, rtol_p=1e-8, maxit=10000, precision=L.F64, inner_rtol=1e-4,
+                 rtol_u=1e-8, rtol_p=1e-8, maxit=10000, precision=L.F64, inner_rtol=0.0,
                  assembly=L.ASSEMBLE_ROWS, pressure_start=L.PSTART_PREV, pressure_delta=0.0,
                  storage=L.STORAGE_AUTO, grid_cap=0, cg_form=L.CG_FORM_AUTO, inner_iters=1,
                  velocity_update=L.UPDATE_LUMPED, diffusivity=(), scalar_source=None, convection=L.CONV_ABCN,

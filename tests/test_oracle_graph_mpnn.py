@@ -147,9 +147,35 @@ def test_mpnn_zero_decoder_is_fallback_and_guard():
     zero = np.zeros_like(phi_prev)
     x0, used = mpnn.guarded_start(S.K, out.b_phi, zero, bad)
     assert not used and x0 is zero
-    # the converged correction itself has a tiny residual: it is taken
+    # the converged correction itself has the lowest energy: it is taken
     x0, used = mpnn.guarded_start(S.K, out.b_phi, phi_prev, out.phi)
     assert used and x0 is out.phi
+
+
+def test_guard_energy_orders_starts_by_their_k_norm_error():
+    """J(x) - J(x*) = 1/2 ||x - x*||_K^2: of two starts the guard keeps the
+    one closer to the solution in the K-norm (the solution from a dense
+    pseudo-inverse, the error norm from K), whatever their residual norms
+    say, and is blind to shifts along the null vector 1."""
+    S, out, phi_prev = _mpnn_problem()
+    K = S.K.toarray()
+    b = out.b_phi
+    xs = np.linalg.pinv(K) @ b
+    rng = np.random.default_rng(11)
+    smooth = np.sin(np.pi * S.mesh.dof_coords[:, 1])          # low-frequency error
+    rough = rng.standard_normal(b.size)                       # high-frequency error
+    knorm = lambda e: e @ (K @ e)  # noqa: E731
+    res = lambda x: np.linalg.norm(b - K @ x)  # noqa: E731
+    a = xs + 0.3 * smooth / np.sqrt(knorm(smooth))
+    c = xs + 0.2 * rough / np.sqrt(knorm(rough))
+    assert knorm(c - xs) < knorm(a - xs)
+    assert res(c) > res(a)               # the residual norm ranks them the other way
+    x0, used = mpnn.guarded_start(S.K, b, a, c)
+    assert used and x0 is c
+    x0, used = mpnn.guarded_start(S.K, b, c, a)
+    assert not used and x0 is c
+    x0, used = mpnn.guarded_start(S.K, b, c + 5.0, a)   # a constant shift changes nothing
+    assert not used
 
 
 def test_mpnn_training_reduces_loss():
