@@ -26,7 +26,7 @@ elliptic problems", Computing 56 (1996) 179-196, written out step by step:
    near-null vector B_c = the norms;
 4. prolongator smoothing with one damped Jacobi step on the filtered
    matrix A^F:  P = (I - omega D_F^{-1} A^F) P_tent,  omega = (4/3) / rho,
-   with rho an upper bound of the spectral radius of D_F^{-1} A^F;
+   with rho an estimate of the spectral radius of D_F^{-1} A^F from above;
 5. Galerkin coarse operator A_c = P^T A P; recurse until a level has at
    most `coarse_size` rows, which is solved exactly (a dense inverse,
    regularised along B_c when the matrix is singular);
@@ -45,9 +45,16 @@ Readings taken where the published method leaves a choice:
   A row whose lumped diagonal would fall to half of a_ii or below (a node
   with few or no strong couplings, whose weak entries nearly cancel its
   diagonal) keeps a_ii instead.
-* rho is the Gershgorin bound max_i sum_j |a_ij| / |a_ii| (an upper bound,
-  so the damping never over-relaxes); the smoother uses the same bound for
-  A itself: x <- x + omega_s D^{-1} (b - A x), omega_s = (4/3) / rho(D^{-1}A).
+* rho is estimated by 15 power iterations on D^{-1/2} A D^{-1/2} (the same
+  spectrum as D^{-1} A) from the alternating vector (+1, -1, +1, ...): 1.1
+  times the last Rayleigh quotient, capped by the Gershgorin bound
+  max_i sum_j |a_ij| / |a_ii|.  The Gershgorin bound alone is safe but loose
+  where the off-diagonals have both signs (P1 tetrahedra): 2.23 against a
+  spectral radius of 2.00 on the structured channel, 2.87 against 2.08 on
+  the displaced one, which under-damps both the prolongator and the
+  smoother (18 and 40 AMG-PCG iterations on 49x49x37, against 16 and 32
+  with the estimate).  The smoother uses the same estimate for A itself:
+  x <- x + omega_s D^{-1} (b - A x), omega_s = (4/3) / rho(D^{-1} A).
 * The level-0 threshold defaults to theta = 0.125.  The method leaves it
   to the user; 0.125 was chosen by a sweep of the pressure solve on the
   129x129x97 channel (0.09-0.25), where it keeps the structured mesh at
@@ -164,10 +171,26 @@ def gershgorin(A):
     return float(np.max(rs / np.abs(A.diagonal())))
 
 
+def rho_estimate(A, iters=15, safety=1.1):
+    """Estimate of rho(D^{-1} A) from above (see the module notes): power
+    iterations on D^{-1/2} A D^{-1/2} from (+1, -1, ...), safety times the
+    last Rayleigh quotient, capped by the Gershgorin bound."""
+    A = sp.csr_matrix(A)
+    s = 1.0 / np.sqrt(np.abs(A.diagonal()))
+    v = np.where(np.arange(A.shape[0]) % 2 == 0, 1.0, -1.0)
+    v = v / np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(iters):
+        w = s * (A @ (s * v))
+        lam = float(v @ w)
+        v = w / np.linalg.norm(w)
+    return min(gershgorin(A), safety * lam)
+
+
 def smoothed_prolongator(A, S, B, agg, na):
     Pt, Bc = tentative(agg, na, B)
     AF = filtered(A, S, B)
-    omega = (4.0 / 3.0) / gershgorin(AF)
+    omega = (4.0 / 3.0) / rho_estimate(AF)
     P = Pt - omega * (sp.diags(1.0 / AF.diagonal()) @ (AF @ Pt))
     return sp.csr_matrix(P), Bc, Pt
 
@@ -200,7 +223,7 @@ def hierarchy(A, B=None, theta=0.125, coarse_size=1024, max_levels=12, singular=
     B = np.ones(A.shape[0]) if B is None else np.asarray(B, dtype=np.float64)
     levels = []
     while True:
-        lv = Level(A=A, B=B, omega=(4.0 / 3.0) / gershgorin(A))
+        lv = Level(A=A, B=B, omega=(4.0 / 3.0) / rho_estimate(A))
         levels.append(lv)
         if A.shape[0] <= coarse_size or len(levels) == max_levels:
             break

@@ -18,7 +18,8 @@
 //   smoothing         P = (I - w D_F^-1 A_F) P_t on the filtered matrix
 //                     A_F (strong entries; weak ones added to the diagonal
 //                     weighted by B unless that would halve it),
-//                     w = (4/3) / (Gershgorin bound of D_F^-1 A_F);
+//                     w = (4/3) / rho(D_F^-1 A_F), rho estimated from above
+//                     (rho_estimate; the smoother's weight likewise);
 //   coarse matrix     A_c = P^T A P.
 // The coarsest level (at most coarse_size rows) gets a dense inverse,
 // regularised along its near-null vector when the matrix is singular.
@@ -167,6 +168,37 @@ double gershgorin(const HostCsr &A, const std::vector<double> &d) {
     return g;
 }
 
+// Estimate of rho(D^-1 A) from above: 15 power iterations on
+// D^-1/2 A D^-1/2 (the same spectrum) from (+1, -1, +1, ...), 1.1 times the
+// last Rayleigh quotient, capped by the Gershgorin bound.  The Gershgorin
+// bound alone is loose where rows hold off-diagonals of both signs (P1
+// tetrahedra, more so on distorted meshes) and then under-damps the
+// prolongator and the smoother.
+double rho_estimate(const HostCsr &A, const std::vector<double> &d) {
+    const int n = A.n;
+    std::vector<double> s(n), v(n), w(n);
+    for (int i = 0; i < n; ++i) s[i] = 1.0 / std::sqrt(std::fabs(d[i]));
+    const double v0 = 1.0 / std::sqrt(static_cast<double>(n));
+    for (int i = 0; i < n; ++i) v[i] = (i % 2 == 0) ? v0 : -v0;
+    double lam = 0.0;
+    for (int it = 0; it < 15; ++it) {
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) acc += A.v[k] * (s[A.ci[k]] * v[A.ci[k]]);
+            w[i] = s[i] * acc;
+        }
+        double vw = 0.0, ww = 0.0;
+        for (int i = 0; i < n; ++i) {
+            vw += v[i] * w[i];
+            ww += w[i] * w[i];
+        }
+        lam = vw;
+        const double inv = 1.0 / std::sqrt(ww);
+        for (int i = 0; i < n; ++i) v[i] = w[i] * inv;
+    }
+    return std::min(gershgorin(A, d), 1.1 * lam);
+}
+
 // Filtered matrix: the diagonal and the strong entries; the dropped ones
 // are added to the diagonal weighted by B, unless the diagonal would fall
 // to half its value or below.
@@ -250,7 +282,7 @@ int amg_build(const HostCsr &A0, const std::vector<double> &B0, const AmgHostPar
         const std::vector<double> d = diagonal(lv.A);
         for (int i = 0; i < lv.A.n; ++i)
             if (!(d[i] != 0.0) || !std::isfinite(d[i])) return OASIS_EINVAL;
-        lv.omega = (4.0 / 3.0) / gershgorin(lv.A, d);
+        lv.omega = (4.0 / 3.0) / rho_estimate(lv.A, d);
         if (lv.A.n <= p.coarse_size || l + 1 == p.max_levels || l + 1 == kAmgMaxLevels) break;
         const double theta = p.theta * std::pow(0.5, l);
         const std::vector<char> S = strength(lv.A, d, theta);
@@ -276,7 +308,7 @@ int amg_build(const HostCsr &A0, const std::vector<double> &B0, const AmgHostPar
         // smoothed prolongator
         const HostCsr F = filtered(lv.A, S, lv.B, d);
         const std::vector<double> dF = diagonal(F);
-        const double w = (4.0 / 3.0) / gershgorin(F, dF);
+        const double w = (4.0 / 3.0) / rho_estimate(F, dF);
         HostCsr FP = matmul(F, Pt);
         HostCsr P;
         P.n = lv.A.n;

@@ -116,6 +116,28 @@ def test_coarse_operators_symmetric_semidefinite_with_null_vector():
         assert np.linalg.norm(Ac @ lv.B) <= 1e-12 * np.abs(Ac).max() * np.linalg.norm(lv.B)
 
 
+@pytest.mark.parametrize("case", ["poisson2d", "channel", "displaced"])
+def test_rho_estimate_lies_between_the_spectral_radius_and_gershgorin(case):
+    """The damping estimate never under-estimates rho(D^{-1} A) (so omega rho
+    stays <= 4/3 < 2), is never above the Gershgorin bound, and is a real
+    improvement on it where the off-diagonals have both signs."""
+    if case == "poisson2d":
+        A = lap2d(20)
+    else:
+        pr = synth.channel_flow("small", seed=0, displace_seed=5 if case == "displaced" else None)
+        A = ipcs.setup(pr.mesh, pr.nu, pr.dt, pr.f).K
+    A = sp.csr_matrix(A)
+    d = A.diagonal()
+    M = (sp.diags(1 / np.sqrt(d)) @ A @ sp.diags(1 / np.sqrt(d))).toarray()
+    rho = np.linalg.eigvalsh(M)[-1]
+    est, g = amg.rho_estimate(A), amg.gershgorin(A)
+    assert rho <= est <= g + 1e-15, (rho, est, g)
+    if case == "displaced":
+        assert est < 0.9 * g, (rho, est, g)           # mixed-sign rows: a looser bound
+    # 1.1 times a Rayleigh quotient of an iterate: at most 10% above rho
+    assert est <= 1.1 * rho * (1 + 1e-12)
+
+
 def _vcycle_matrix(H, n):
     return np.column_stack([amg.vcycle(H, e) for e in np.eye(n)])
 
