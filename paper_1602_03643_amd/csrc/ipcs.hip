@@ -1051,6 +1051,12 @@ struct oasis_ipcs {
     double *rhi = nullptr;
     int *bc_index = nullptr, *flag = nullptr;
     int *iptr = nullptr, *inc = nullptr, *icnt = nullptr, *itmp = nullptr;
+    // the row kernels' copy of the mesh: vertices in dof order, cells in
+    // order of their lowest dof (locality of the per-row cell walks whatever
+    // order the caller's arrays have); same geometry and dofs
+    oasis_mesh rmesh{};
+    int *rcells = nullptr, *rv2d = nullptr;
+    double *rcoords = nullptr;
     int assembly = OASIS_ASSEMBLE_ROWS, maxc = 16;
     double *ubar = nullptr;   // per step u_bar, interleaved ([n][D == 3 ? 4 : 2])
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
@@ -1101,8 +1107,8 @@ static int ell_setup(hipStream_t s, int n, const int *rp, const int *ci, const d
     return OASIS_OK;
 }
 
-static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed, bool consistent, int nsc,
-                       bool abe, bool gradient, oasis_ipcs &h) {
+static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nvert, int nnz, bool mixed, bool consistent,
+                       int nsc, bool abe, bool gradient, bool rows, oasis_ipcs &h) {
     h.ecol = c.take<short>((size_t)n * kEll);
     h.pid = c.take<unsigned short>(n);
     h.ptab = c.take<short>((size_t)kMaxEllPatterns * kEll);
@@ -1148,6 +1154,11 @@ static void carve_ipcs(Carver &c, int dim, int n, int ncell, int nnz, bool mixed
     const int nmax = std::max(n, ncell);
     h.ubar = c.take<double>((size_t)n * (dim == 3 ? 4 : 2));
     h.iptr = c.take<int>((size_t)n + 1);
+    if (rows || abe) {
+        h.rcells = c.take<int>((size_t)ncell * (dim + 1));
+        h.rv2d = c.take<int>((size_t)nvert);
+        h.rcoords = c.take<double>((size_t)nvert * dim);
+    }
     h.inc = c.take<int>((size_t)ncell * (dim + 1));
     h.icnt = c.take<int>((size_t)nmax + 1);
     h.itmp = c.take<int>(incidence_tmp_ints(nmax));
@@ -1199,14 +1210,75 @@ extern "C" int oasis_ipcs_workspace_size(const oasis_mesh *mesh, int32_t nnz, co
     OASIS_TRY(check_params(par));
     Carver c(nullptr, 0);
     oasis_ipcs h;
-    carve_ipcs(c, mesh->dim, mesh->n_dof, mesh->n_cell, nnz, par->precision == OASIS_F32,
+    carve_ipcs(c, mesh->dim, mesh->n_dof, mesh->n_cell, mesh->n_vert, nnz, par->precision == OASIS_F32,
                par->velocity_update == OASIS_UPDATE_CONSISTENT, par->n_scalars, par->convection == OASIS_CONV_ABE,
-               par->velocity_update == OASIS_UPDATE_GRADIENT, h);
+               par->velocity_update == OASIS_UPDATE_GRADIENT, par->assembly != OASIS_ASSEMBLE_COLORS, h);
     *bytes = c.bytes();
     return OASIS_OK;
 }
 
 static inline int gvec(int n) { return grid_for(n, kBlock, 8192); }
+
+// The row kernels' mesh copy: vertices renumbered in dof order and cells
+// sorted by their lowest dof (both stable counting sorts on the host, once),
+// so that the cells a row walks, and their vertices, sit near each other in
+// memory whatever order the caller's arrays have.  Synchronises.
+static int locality_mesh(hipStream_t s, const oasis_mesh *m, int *rcells, int *rv2d, double *rcoords,
+                         oasis_mesh *out) {
+    const int nv = m->n_vert, nc = m->n_cell, D = m->dim, NV = D + 1, n = m->n_dof;
+    std::vector<int> cells((size_t)nc * NV), v2d(nv);
+    std::vector<double> X((size_t)nv * D);
+    OASIS_TRY_HIP(hipMemcpyAsync(cells.data(), m->cells, cells.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipMemcpyAsync(v2d.data(), m->vert2dof, v2d.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipMemcpyAsync(X.data(), m->coords, X.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    // vertices by dof (stable)
+    std::vector<int> cnt(n + 1, 0), vnew(nv);
+    for (int v = 0; v < nv; ++v) {
+        if (v2d[v] < 0 || v2d[v] >= n) return OASIS_EINVAL;
+        ++cnt[v2d[v] + 1];
+    }
+    for (int d = 0; d < n; ++d) cnt[d + 1] += cnt[d];
+    std::vector<int> v2dr(nv);
+    std::vector<double> Xr((size_t)nv * D);
+    for (int v = 0; v < nv; ++v) {
+        const int q = cnt[v2d[v]]++;
+        vnew[v] = q;
+        v2dr[q] = v2d[v];
+        for (int c = 0; c < D; ++c) Xr[(size_t)q * D + c] = X[(size_t)v * D + c];
+    }
+    // cells by their lowest dof (stable), vertex ids renumbered
+    std::fill(cnt.begin(), cnt.end(), 0);
+    std::vector<int> key(nc);
+    for (int e = 0; e < nc; ++e) {
+        int k = n;
+        for (int a = 0; a < NV; ++a) {
+            const int v = cells[(size_t)e * NV + a];
+            if (v < 0 || v >= nv) return OASIS_EINVAL;
+            k = std::min(k, v2d[v]);
+        }
+        key[e] = k;
+        ++cnt[k + 1];
+    }
+    for (int d = 0; d < n; ++d) cnt[d + 1] += cnt[d];
+    std::vector<int> cr((size_t)nc * NV);
+    for (int e = 0; e < nc; ++e) {
+        const int q = cnt[key[e]]++;
+        for (int a = 0; a < NV; ++a) cr[(size_t)q * NV + a] = vnew[cells[(size_t)e * NV + a]];
+    }
+    OASIS_TRY_HIP(hipMemcpyAsync(rcells, cr.data(), cr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    OASIS_TRY_HIP(hipMemcpyAsync(rv2d, v2dr.data(), v2dr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    OASIS_TRY_HIP(hipMemcpyAsync(rcoords, Xr.data(), Xr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    *out = *m;
+    out->cells = rcells;
+    out->vert2dof = rv2d;
+    out->coords = rcoords;
+    out->n_colors = 0;
+    out->color_ptr = nullptr;
+    out->color_cells = nullptr;
+    return OASIS_OK;
+}
 
 extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int32_t *row_ptr,
                                  const int32_t *col_idx, int32_t nnz, const oasis_ipcs_params *par,
@@ -1236,7 +1308,8 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     h->abe = par->convection == OASIS_CONV_ABE;
     h->gradient = par->velocity_update == OASIS_UPDATE_GRADIENT;
     Carver c(ws, ws_bytes);
-    carve_ipcs(c, h->dim, h->n, mesh->n_cell, nnz, h->mixed, h->consistent, h->nsc, h->abe, h->gradient, *h);
+    carve_ipcs(c, h->dim, h->n, mesh->n_cell, mesh->n_vert, nnz, h->mixed, h->consistent, h->nsc, h->abe,
+               h->gradient, par->assembly != OASIS_ASSEMBLE_COLORS, *h);
     h->cg.tun = h->cg32.tun = h->cgM.tun = h->tun;
     h->bi.tun = h->bi32.tun = h->tun;
     auto fail = [&](int rc) {
@@ -1342,7 +1415,9 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
     }
     // dof -> incident cells: the row-gather assembly and the explicit convection
     if (h->assembly == OASIS_ASSEMBLE_ROWS || h->abe) {
-        const int rc2 = incidence_codes(s, &h->mesh, h->iptr, h->inc, h->icnt, h->itmp, h->flag + 3);
+        const int rc1 = locality_mesh(s, mesh, h->rcells, h->rv2d, h->rcoords, &h->rmesh);
+        if (rc1 != OASIS_OK) return fail(rc1);
+        const int rc2 = incidence_codes(s, &h->rmesh, h->iptr, h->inc, h->icnt, h->itmp, h->flag + 3);
         if (rc2 != OASIS_OK) return fail(rc2);
     }
     // the scaled pressure matrix has null vector s = sqrt(diag K) (K 1 = 0)
@@ -1439,7 +1514,7 @@ static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_s
 template <int D, int MAXC>
 static void launch_asm_kernel(hipStream_t s, oasis_ipcs *h, const double *Bsrc) {
     hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid_for(h->n, kBlock, 1 << 20)), dim3(kBlock), 0, s, h->n,
-                       h->rp, h->ci, Bsrc, h->iptr, h->inc, h->mesh.cells, h->mesh.vert2dof, h->mesh.coords, h->ubar,
+                       h->rp, h->ci, Bsrc, h->iptr, h->inc, h->rmesh.cells, h->rmesh.vert2dof, h->rmesh.coords, h->ubar,
                        h->A);
 }
 
@@ -1596,13 +1671,13 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         const int grid = grid_for(n, kBlock, 1 << 20);
         if (D == 3) {
             hipLaunchKernelGGL(k_uu<3>, dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->uu);
-            hipLaunchKernelGGL(k_conv_rows<3>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->mesh.cells,
-                               h->mesh.vert2dof, h->mesh.coords, h->uu, h->cv[0], h->cv[1], h->cv[2]);
+            hipLaunchKernelGGL(k_conv_rows<3>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->rmesh.cells,
+                               h->rmesh.vert2dof, h->rmesh.coords, h->uu, h->cv[0], h->cv[1], h->cv[2]);
             launch_step_kernels_tent<3, 8>(s, h, st, bc_values, x);
         } else {
             hipLaunchKernelGGL(k_uu<2>, dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->uu);
-            hipLaunchKernelGGL(k_conv_rows<2>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->mesh.cells,
-                               h->mesh.vert2dof, h->mesh.coords, h->uu, h->cv[0], h->cv[1],
+            hipLaunchKernelGGL(k_conv_rows<2>, dim3(grid), dim3(kBlock), 0, s, n, h->iptr, h->inc, h->rmesh.cells,
+                               h->rmesh.vert2dof, h->rmesh.coords, h->uu, h->cv[0], h->cv[1],
                                static_cast<double *>(nullptr));
             launch_step_kernels_tent<2, 8>(s, h, st, bc_values, x);
         }
