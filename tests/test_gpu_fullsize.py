@@ -24,7 +24,9 @@ is checked on sampled rows and through properties that hold at any size:
   a bijection whose bandwidth is at most 2 x-y layers and at most 1.5x the
   structured numbering's, a valid colouring of the relabelled mesh, and
   one FP64 step (rtol 1e-12) giving the same fields as the same mesh in
-  structured numbering; a mixed step on it converges.
+  structured numbering, and matching the oracle on sampled rows (tentative
+  equations, pressure right-hand side, velocity update); a mixed step on
+  it converges.
 """
 import dataclasses
 
@@ -253,13 +255,19 @@ def test_fullsize_config4_rcm_relabelled_step(oa):
     to_new = perm.long()[T(dof_perm, torch.int64)]
     dm0, pat0c = _device(oa, m0)
 
-    def run(dm, pat, bcd, fields, precision, rtol):
+    extra = {}
+
+    def run(dm, pat, bcd, fields, precision, rtol, keep=False):
         h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, bcd, rtol_u=rtol, rtol_p=rtol, precision=precision)
         U1, U2, p, phi = [f.clone() for f in fields]
         Un = torch.empty_like(U1)
+        UI, bphi = torch.empty_like(U1), torch.empty_like(p)
         nbc = bcd.numel()
-        st = h.step(U1, U2, Un, p, phi, bc_values=torch.zeros(3 * nbc, dtype=torch.float64, device=dev()))
+        st = h.step(U1, U2, Un, p, phi, bc_values=torch.zeros(3 * nbc, dtype=torch.float64, device=dev()),
+                    UI=UI, b_phi=bphi)
         torch.cuda.synchronize()
+        if keep:
+            extra.update(UI=UI.cpu().numpy(), bphi=bphi.cpu().numpy(), phi=phi.cpu().numpy(), Un=Un.cpu().numpy())
         h.close()
         return st, Un, p
 
@@ -275,8 +283,32 @@ def test_fullsize_config4_rcm_relabelled_step(oa):
 
     fr = [to_rcm(x) for x in f0]
     st0, Un0, p0 = run(dm0, pat0c, T(m0.bc_dofs, torch.int32), f0, oa.F64, 1e-12)
-    str_, Unr, pr_ = run(dmr, patr, bc, fr, oa.F64, 1e-12)
+    str_, Unr, pr_ = run(dmr, patr, bc, fr, oa.F64, 1e-12, keep=True)
     assert st0["status"] == 0 and str_["status"] == 0
+    # the oracle on sampled rows of the RCM-numbered displaced mesh: the
+    # tentative equations (assembled from the cells around each row) hold
+    # for U^I, b_phi is -(1/dt) sum_k dP^k U^I up to the projection constant,
+    # and the lumped update follows from U^I and phi
+    permh = perm.long().cpu().numpy()
+    mr = dataclasses.replace(pm, vert2dof=permh[pm.vert2dof].astype(np.int32),
+                             bc_dofs=np.sort(permh[pm.bc_dofs]).astype(np.int32))
+    prr = dataclasses.replace(pr, mesh=mr)
+    rows = np.unique(np.random.default_rng(17).choice(n, 240, replace=False)).astype(np.int64)
+    S = _local_setup(prr, rows)
+    frh = [x.cpu().numpy() for x in fr]
+    st_in = ipcs.State(frh[0], frh[1], frh[2], frh[3], 0.0)
+    A, b = ipcs.tentative_system(S, st_in, pr.dt, np.zeros((3, mr.bc_dofs.size)))
+    UI, bphi, phi, Un = extra["UI"], extra["bphi"], extra["phi"], extra["Un"]
+    for k in range(3):
+        res = A[rows] @ UI[k] - b[k][rows]
+        scale = abs(A[rows]) @ np.abs(UI[k]) + np.abs(b[k][rows])
+        assert np.abs(res).max() <= 1e-9 * scale.max(), k     # the solve's rtol is 1e-12
+    raw = -(1.0 / pr.dt) * sum(S.dP[k][rows] @ UI[k] for k in range(3))
+    diff = bphi[rows] - raw
+    assert np.abs(diff - diff.mean()).max() <= 1e-12 * np.abs(raw).max()
+    upd = np.stack([UI[k][rows] - pr.dt * (S.dP[k][rows] @ phi) / S.ML[rows] for k in range(3)])
+    upd[:, np.isin(rows, mr.bc_dofs)] = 0.0
+    assert _vec_err(Un[:, rows], upd) < 1e-12
     say("iterations structured %s / %d, rcm %s / %d" % (st0["iters_u"], st0["iters_p"], str_["iters_u"],
                                                          str_["iters_p"]))
     assert rel(Unr[:, to_new].cpu().numpy(), Un0.cpu().numpy()) < 1e-9
