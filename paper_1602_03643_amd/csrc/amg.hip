@@ -49,6 +49,8 @@ int with_lanes(int lanes, F &&f) {
         case 2: return f(AmgCfg<2>{});
         case 8: return f(AmgCfg<8>{});
         case 16: return f(AmgCfg<16>{});
+        case 32: return f(AmgCfg<32>{});
+        case 64: return f(AmgCfg<64>{});
         default: return f(AmgCfg<4>{});
     }
 }

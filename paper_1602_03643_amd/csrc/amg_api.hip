@@ -96,10 +96,11 @@ void carve_levels(Carver &c, const oasis_amg &h, AmgCycle<T> &cy) {
     }
     cy.nc = h.levels.back().A.n;
     cy.cinv = c.take<T>(static_cast<size_t>(cy.nc) * cy.nc);
-    // CSR lanes per row from the mean row length
+    // CSR lanes per row from the mean row length (the coarse levels' rows
+    // grow long, 70-140 entries, and are few: wider groups there)
     auto lanes = [](const HostCsr &M) {
         const double avg = M.n ? static_cast<double>(M.nnz()) / M.n : 0.0;
-        return avg <= 6.0 ? 2 : avg <= 12.0 ? 4 : avg <= 28.0 ? 8 : 16;
+        return avg <= 6.0 ? 2 : avg <= 12.0 ? 4 : avg <= 28.0 ? 8 : avg <= 56.0 ? 16 : avg <= 100.0 ? 32 : 64;
     };
     for (int l = 0; l < L; ++l) {
         const HostLevel &hl = h.levels[l];
