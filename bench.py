@@ -19,7 +19,7 @@ phi_prev unless the name ends in _zero, where it starts from 0):
                for fp64_amg, FP32 for mixed_amg / learned_amg)
 All reach the same FP64 true-residual tolerance.  The headline `value` is
 the fastest variant whose pressure solve starts from phi_prev (the plain
-start that is fallback and judge of the learned guess); `speedups` compare
+start that is the fallback of the learned guess and its reference); `speedups` compare
 it with plain FP64 Jacobi-PCG from phi_prev and like for like.
 
 Also printed in the one JSON line:
