@@ -181,6 +181,17 @@ def test_abe_convection_matches_oracle(oa, prob):
     assert rel(a["U"], g["U"]) > 1e-8
 
 
+def test_abe_on_a_randomly_numbered_mesh_matches_oracle(oa):
+    prob = synth.channel_flow("small", seed=9, displace_seed=4, permute_seed=31)
+    say("explicit convection, permuted mesh", prob.name)
+    g, stats, keep = _run(oa, prob, 2, 1e-13, convection=oa.CONV_ABE, nsc=1)
+    r, o = _oracle(prob, 2, 1e-13, convection="abe", nsc=1)
+    e = _errors(g, r)
+    say("abe permuted per-field relative L2:", e)
+    for k, v in e.items():
+        assert v <= 1e-10, (k, v)
+
+
 def test_abe_with_inner_iterations_and_a_scalar_matches_oracle(oa):
     prob = synth.channel_flow("small", seed=6)
     say("explicit convection + inner 2 + scalar", prob.name)
