@@ -1668,8 +1668,9 @@ void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
     w.part1 = c.take<double>(9 * kMaxPartials);
     w.part2 = c.take<double>(9 * kMaxPartials);
     w.part3 = c.take<double>(9 * kMaxPartials);
-    w.st = c.take<BiState>(3);
-    w.glob = c.take<BiGlobal>(1);
+    BiBlock *blk = c.take<BiBlock>(1);
+    w.st = blk ? blk->st : nullptr;
+    w.glob = blk ? &blk->glob : nullptr;
 }
 
 template <typename T, int NR, class C>
@@ -1692,8 +1693,9 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         cp.p[k] = vp.p[k] = w.p[k];
         vxs.p[k] = w.xs[k];
     }
-    BiState hs[3];
-    BiGlobal hg{};
+    BiBlock hb{};
+    BiState(&hs)[3] = hb.st;
+    BiGlobal &hg = hb.glob;
     for (int k = 0; k < 3; ++k) {
         hs[k] = BiState{};
         for (int q = 0; q < 2; ++q) hs[k].rho[q] = hs[k].alpha[q] = hs[k].omega[q] = 1.0;
@@ -1701,14 +1703,14 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         hs[k].no_sexit_it = -1;
         out[k < NR ? k : 0] = SolveOut();
     }
+    // one copy each way: the states and the pause record share a block
+    BiBlock *dblk = reinterpret_cast<BiBlock *>(w.st);
     auto push_state = [&]() -> int {
-        OASIS_TRY_HIP(hipMemcpyAsync(w.st, hs, sizeof(hs), hipMemcpyHostToDevice, s));
-        OASIS_TRY_HIP(hipMemcpyAsync(w.glob, &hg, sizeof(hg), hipMemcpyHostToDevice, s));
+        OASIS_TRY_HIP(hipMemcpyAsync(dblk, &hb, sizeof(hb), hipMemcpyHostToDevice, s));
         return OASIS_OK;
     };
     auto pull_state = [&]() -> int {
-        OASIS_TRY_HIP(hipMemcpyAsync(hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipMemcpyAsync(&hg, w.glob, sizeof(hg), hipMemcpyDeviceToHost, s));
+        OASIS_TRY_HIP(hipMemcpyAsync(&hb, dblk, sizeof(hb), hipMemcpyDeviceToHost, s));
         OASIS_TRY_HIP(hipStreamSynchronize(s));
         return OASIS_OK;
     };

@@ -72,6 +72,13 @@ struct BiGlobal {
     int pad;
 };
 
+// The per-right-hand-side states and the pause record in one block, so
+// that the host moves them with one copy each way.
+struct BiBlock {
+    BiState st[3];
+    BiGlobal glob;
+};
+
 // A residual interleaved with a companion vector (BiCGStab's u or v).
 template <typename T>
 struct alignas(2 * sizeof(T)) RW {
@@ -91,8 +98,8 @@ struct BiWork {
     RW<T> *ru, *rv;
     T *p[3], *rhat[3], *t[3], *xs[3];
     double *part1, *part2, *part3;
-    BiState *st;       // [3]
-    BiGlobal *glob;
+    BiState *st;       // [3], the start of a BiBlock
+    BiGlobal *glob;    // in the same block
     // optional ELL copy of the iteration matrix (set by the owner)
     EllCols cols;
     const T *eval = nullptr;
