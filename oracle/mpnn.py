@@ -18,7 +18,16 @@ Network (hidden width 32, 3 message-passing layers):
   z_l = h_{l-1} Ws_l^T + a_l Wn_l^T + c_l,  h_l = h_{l-1} + relu(z_l)
   delta = h_3 wd + cd
 Guess: phi_prev + sigma * delta.  Training target: (phi - phi_prev) / sigma,
-loss = mean over nodes of (delta - target)^2, averaged over samples.
+and one of two losses, averaged over samples:
+  mse    mean over nodes of (delta - target)^2;
+  knorm  (delta - target)^T K (delta - target) / target^T K target, the
+         K-norm (energy norm) of the guess error relative to that of
+         phi_prev.  sigma cancels.  With phi the solution of K phi = b_phi,
+         J(x) - J(phi) = 1/2 ||x - phi||_K^2 for J the CG energy below, so
+         this loss is (J(guess) - J(phi)) / (J(phi_prev) - J(phi)): the
+         quantity the guard compares and the error norm CG reduces.  A
+         sample whose target has zero K-norm (phi_prev already exact up to
+         a constant) has loss 0 and no gradient.
 The solve starts from the guess only if its CG energy 1/2 x^T K x - b^T x
 is below that of the plain start (phi_prev, or 0; guarded_start); PCG then
 runs to the same tolerance.
@@ -105,16 +114,32 @@ def forward(P, X, W):
     return delta, cache
 
 
-def loss(delta, target):
+def loss(delta, target, kind="mse", K=None):
     e = delta - target
-    return float(np.mean(e * e))
+    if kind == "mse":
+        return float(np.mean(e * e))
+    if kind != "knorm":
+        raise ValueError(kind)
+    den = float(target @ (K @ target))
+    return float(e @ (K @ e)) / den if den > 0 else 0.0
 
 
-def backward(P, cache, delta, target, W):
-    """Gradients of loss(delta, target) with respect to every parameter."""
-    N = delta.size
+def loss_seed(delta, target, kind="mse", K=None):
+    """d loss / d delta."""
+    e = delta - target
+    if kind == "mse":
+        return 2.0 * e / delta.size
+    if kind != "knorm":
+        raise ValueError(kind)
+    den = float(target @ (K @ target))
+    return 2.0 * (K @ e) / den if den > 0 else np.zeros_like(e)
+
+
+def backward(P, cache, delta, target, W, kind="mse", K=None):
+    """Gradients of loss(delta, target, kind, K) with respect to every
+    parameter (K: the pressure matrix, for the K-norm loss)."""
     G = {k: np.zeros(s) for k, s in PARAM_SHAPES}
-    gd = 2.0 * (delta - target) / N
+    gd = loss_seed(delta, target, kind, K)
     h3 = cache["h"][LAYERS]
     G["wd"] = h3.T @ gd
     G["cd"] = np.array([gd.sum()])

@@ -108,7 +108,8 @@ def _mpnn_problem():
     return S, out, phi_prev
 
 
-def test_mpnn_backward_matches_finite_differences():
+@pytest.mark.parametrize("kind", ["mse", "knorm"])
+def test_mpnn_backward_matches_finite_differences(kind):
     S, out, phi_prev = _mpnn_problem()
     X, sigma = mpnn.features(S.K, out.b_phi, phi_prev, S.mesh.dof_coords)
     W = mpnn.edge_weights(S.K)
@@ -118,7 +119,7 @@ def test_mpnn_backward_matches_finite_differences():
     P["c"] = rng.normal(size=P["c"].shape) * 0.1
     target = (out.phi - phi_prev) / sigma
     delta, cache = mpnn.forward(P, X, W)
-    G = mpnn.backward(P, cache, delta, target, W)
+    G = mpnn.backward(P, cache, delta, target, W, kind, S.K)
     h = 1e-6
     for name in ["We", "ce", "Ws", "Wn", "c", "wd", "cd"]:
         flat = P[name].reshape(-1)
@@ -126,9 +127,9 @@ def test_mpnn_backward_matches_finite_differences():
         for i in idx:
             old = flat[i]
             flat[i] = old + h
-            lp = mpnn.loss(mpnn.forward(P, X, W)[0], target)
+            lp = mpnn.loss(mpnn.forward(P, X, W)[0], target, kind, S.K)
             flat[i] = old - h
-            lm = mpnn.loss(mpnn.forward(P, X, W)[0], target)
+            lm = mpnn.loss(mpnn.forward(P, X, W)[0], target, kind, S.K)
             flat[i] = old
             fd = (lp - lm) / (2 * h)
             an = G[name].reshape(-1)[i]
@@ -176,6 +177,41 @@ def test_guard_energy_orders_starts_by_their_k_norm_error():
     assert not used and x0 is c
     x0, used = mpnn.guarded_start(S.K, b, c + 5.0, a)   # a constant shift changes nothing
     assert not used
+
+
+def test_knorm_loss_is_the_relative_energy_gap():
+    """With x* the exact solution (dense pseudo-inverse) and J the CG
+    energy, the K-norm loss of a network output delta equals
+    (J(phi_prev + sigma delta) - J(x*)) / (J(phi_prev) - J(x*)): 1 for
+    delta = 0 (the guess is phi_prev), 0 for the exact correction and for
+    it shifted by a constant, and below 1 exactly when the guard would take
+    the guess over phi_prev."""
+    S, out, phi_prev = _mpnn_problem()
+    K = S.K.toarray()
+    b = out.b_phi
+    xs = np.linalg.pinv(K) @ b
+    X, sigma = mpnn.features(S.K, b, phi_prev, S.mesh.dof_coords)
+    t = (xs - phi_prev) / sigma
+    assert mpnn.loss(np.zeros_like(t), t, "knorm", S.K) == 1.0
+    assert abs(mpnn.loss(t, t, "knorm", S.K)) < 1e-20
+    assert abs(mpnn.loss(t + 3.7, t, "knorm", S.K)) < 1e-10
+    rng = np.random.default_rng(12)
+    gap = lambda x: mpnn.energy(S.K, b, x) - mpnn.energy(S.K, b, xs)  # noqa: E731
+    for scale in [0.05, 0.5, 2.0]:
+        d = t + scale * rng.standard_normal(t.size)
+        lk = mpnn.loss(d, t, "knorm", S.K)
+        ratio = gap(phi_prev + sigma * d) / gap(phi_prev)
+        assert abs(lk - ratio) <= 1e-8 * max(1.0, ratio), (scale, lk, ratio)
+        _, used = mpnn.guarded_start(S.K, b, phi_prev, phi_prev + sigma * d)
+        assert used == (lk < 1.0)
+    # the MSE loss does not rank guesses this way: a rough error of small
+    # MSE can cost more energy than a smooth one of larger MSE
+    smooth = np.sin(np.pi * S.mesh.dof_coords[:, 1])
+    rough = rng.standard_normal(t.size)
+    a = t + 0.3 * smooth / np.sqrt(np.mean(smooth ** 2))
+    c = t + 0.2 * rough / np.sqrt(np.mean(rough ** 2))
+    assert mpnn.loss(c, t) < mpnn.loss(a, t)
+    assert mpnn.loss(c, t, "knorm", S.K) > mpnn.loss(a, t, "knorm", S.K)
 
 
 def test_mpnn_training_reduces_loss():
