@@ -556,13 +556,23 @@ int oasis_mpnn_forward(void *stream, const oasis_csr *Ks, const double *s, int32
                        const float *params, double *guess, float *delta,
                        void *ws, size_t ws_bytes);
 
-/* Loss mean((delta - target)^2) with target = (phi - phi_prev)/sigma, and the
- * parameter gradient (device float [OASIS_MPNN_NPARAM], overwritten) of the
- * forward pass whose activations ws holds.  *loss_out: host, nullable
- * (synchronises when given). */
+/* Training losses of oasis_mpnn_backward, with target t = (phi -
+ * phi_prev)/sigma and e = delta - t:
+ *   MSE    mean over nodes of e^2;
+ *   KNORM  e^T K e / t^T K t, the energy norm of the guess error relative
+ *          to that of phi_prev (the error norm CG reduces; 0 with a zero
+ *          gradient when t^T K t = 0). */
+#define OASIS_MPNN_LOSS_MSE 0
+#define OASIS_MPNN_LOSS_KNORM 1
+
+/* The loss chosen by loss_kind (EINVAL otherwise) and the parameter
+ * gradient (device float [OASIS_MPNN_NPARAM], overwritten) of the forward
+ * pass whose activations ws holds; phi: the converged correction, device
+ * double [n].  *loss_out: host, nullable (synchronises when given). */
 int oasis_mpnn_backward(void *stream, const oasis_csr *Ks, const double *s,
                         const double *phi, const double *phi_prev, const float *params,
-                        float *grad, double *loss_out, void *ws, size_t ws_bytes);
+                        float *grad, int32_t loss_kind, double *loss_out,
+                        void *ws, size_t ws_bytes);
 
 /* Adam step on device float32 params with moments m, v (device float
  * [OASIS_MPNN_NPARAM], zero-initialised by the caller); t = 1, 2, ... */

@@ -28,6 +28,7 @@ PCG_NOALLOC_BYTES = 64 << 20
 CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE = 0, 1, 2
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
+MPNN_LOSS_MSE, MPNN_LOSS_KNORM = 0, 1
 
 i32 = C.c_int32
 i64 = C.c_int64
@@ -125,7 +126,7 @@ _SIGS = {
     "oasis_ipcs_set_warmstart": (i32, [vp, vp, vp, vp, sz]),
     "oasis_mpnn_workspace_size": (i32, [i32, P(sz)]),
     "oasis_mpnn_forward": (i32, [vp, P(Csr), vp, i32, vp, vp, vp, vp, vp, vp, vp, sz]),
-    "oasis_mpnn_backward": (i32, [vp, P(Csr), vp, vp, vp, vp, vp, P(f64), vp, sz]),
+    "oasis_mpnn_backward": (i32, [vp, P(Csr), vp, vp, vp, vp, vp, i32, P(f64), vp, sz]),
     "oasis_mpnn_adam": (i32, [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32]),
     "oasis_strerror": (C.c_char_p, [i32]),
     "oasis_last_hip_error": (i32, []),

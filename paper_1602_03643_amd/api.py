@@ -515,11 +515,13 @@ class MPNN:
                                           _p(delta), _p(self.ws), self.ws.numel()), "oasis_mpnn_forward")
         return guess, delta
 
-    def backward(self, params, phi, phi_prev, grad, stream=None):
+    def backward(self, params, phi, phi_prev, grad, loss_kind=L.MPNN_LOSS_MSE, stream=None):
+        """Loss of the last forward pass (MPNN_LOSS_MSE or MPNN_LOSS_KNORM)
+        and its parameter gradient into grad."""
         loss = C.c_double()
         L.check(_lib().oasis_mpnn_backward(_stream(stream), C.byref(self.Ks.c()), _p(self.s), _p(phi),
-                                           _p(phi_prev), _p(params), _p(grad), C.byref(loss), _p(self.ws),
-                                           self.ws.numel()), "oasis_mpnn_backward")
+                                           _p(phi_prev), _p(params), _p(grad), int(loss_kind), C.byref(loss),
+                                           _p(self.ws), self.ws.numel()), "oasis_mpnn_backward")
         return loss.value
 
     @staticmethod

@@ -58,14 +58,18 @@ struct MpWs {
     unsigned short *Ag[kLayers];       // [N][32]
     unsigned short *Z[kLayers + 1];    // [N][32] pre-activations (z0 = encoder)
     float *delta;                      // [N]
-    double *scal;                      // [16]: sigma, sig_u, sig_phi, lo[3], hi[3]
+    double *scal;                      // [16]: sigma, sig_u, sig_phi, lo[3], hi[3], eKe, tKt
     double *part;                      // [kMaxPartials][4]
     double *mm;                        // [kMaxPartials][6] min / max partials
     float *G;                          // [N][32]
     unsigned short *GZ, *Y;            // [N][32]
     float *gpart;                      // [kGradBlocks][kNParam]
     double *lpart;                     // [kGradBlocks]
+    double *et;                        // [N][2] K-norm loss: (s e, s t)
+    double *ke;                        // [N] K e
 };
+
+constexpr int kScalEKE = 9, kScalTKT = 10;
 
 static void carve_mp(Carver &c, int n, MpWs &w) {
     w.X = c.take<float>((size_t)n * 8);
@@ -83,6 +87,8 @@ static void carve_mp(Carver &c, int n, MpWs &w) {
     w.Y = c.take<unsigned short>((size_t)n * kHid);
     w.gpart = c.take<float>((size_t)kGradBlocks * kNParam);
     w.lpart = c.take<double>(kGradBlocks);
+    w.et = c.take<double>((size_t)n * 2);
+    w.ke = c.take<double>(n);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,11 +476,13 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__
 // ---------------------------------------------------------------------------
 // backward
 
-// decoder: g_delta = 2 (delta - t) / N, G = g_delta wd; partials of the loss,
-// g_wd, g_cd
+// decoder: g_delta = 2 (delta - t) / N (mean squared error) or, with ke
+// given, 2 (K e)_i / t^T K t (K-norm loss; 0 when t^T K t = 0), G =
+// g_delta wd; partials of the loss (mean squared error only), g_wd, g_cd
 __global__ __launch_bounds__(kBlock) void k_mp_bwd_dec(int n, const unsigned short *__restrict__ H3,
                                                        const float *__restrict__ delta, const double *__restrict__ phi,
                                                        const double *__restrict__ phi_prev, const double *scal,
+                                                       const double *__restrict__ ke,
                                                        const float *__restrict__ P, float *__restrict__ G,
                                                        float *gpart, double *lpart) {
     __shared__ float red[kBlock];
@@ -484,11 +492,17 @@ __global__ __launch_bounds__(kBlock) void k_mp_bwd_dec(int n, const unsigned sho
     float gcd = 0.f;
     double loss = 0.0;
     const double sig = scal[0];
+    const double tkt = ke ? scal[kScalTKT] : 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const double t = (phi[i] - phi_prev[i]) / sig;
-        const double e = static_cast<double>(delta[i]) - t;
-        loss += e * e;
-        const float gd = static_cast<float>(2.0 * e / n);
+        float gd;
+        if (ke) {
+            gd = tkt > 0.0 ? static_cast<float>(2.0 * ke[i] / tkt) : 0.f;
+        } else {
+            const double t = (phi[i] - phi_prev[i]) / sig;
+            const double e = static_cast<double>(delta[i]) - t;
+            loss += e * e;
+            gd = static_cast<float>(2.0 * e / n);
+        }
         gcd += gd;
         for (int o = 0; o < kHid; ++o) {
             G[i * kHid + o] = gd * P[kOffWd + o];
@@ -702,16 +716,75 @@ __global__ __launch_bounds__(kBlock) void k_mp_bwd_enc(int n, const float *__res
 
 // grad[p] = sum over blocks of gpart[b][p] (fixed order); loss
 __global__ __launch_bounds__(kBlock) void k_mp_grad_reduce(const float *gpart, int nb, float *grad,
-                                                           const double *lpart, double *loss_out, int n) {
+                                                           const double *lpart, double *loss_out, int n,
+                                                           const double *scal, int knorm) {
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < kNParam; p += gridDim.x * blockDim.x) {
         float v = 0.f;
         for (int b = 0; b < nb; ++b) v += gpart[(size_t)b * kNParam + p];
         grad[p] = v;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double l = 0.0;
-        for (int b = 0; b < nb; ++b) l += lpart[b];
-        *loss_out = l / n;
+        if (knorm) {
+            const double tkt = scal[kScalTKT];
+            *loss_out = tkt > 0.0 ? scal[kScalEKE] / tkt : 0.0;
+        } else {
+            double l = 0.0;
+            for (int b = 0; b < nb; ++b) l += lpart[b];
+            *loss_out = l / n;
+        }
+    }
+}
+
+// K-norm loss, step 1: the pair (s_i e_i, s_i t_i) per node, e = delta - t,
+// t = (phi - phi_prev) / sigma, s = sqrt(diag K), so that K = S Ks S gives
+// e^T K e = (S e)^T Ks (S e)
+__global__ __launch_bounds__(kBlock) void k_mp_kl_pair(int n, const float *__restrict__ delta,
+                                                       const double *__restrict__ phi,
+                                                       const double *__restrict__ phi_prev,
+                                                       const double *__restrict__ s, const double *scal,
+                                                       double *__restrict__ et) {
+    const double sig = scal[0];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double t = (phi[i] - phi_prev[i]) / sig;
+        const double e = static_cast<double>(delta[i]) - t;
+        et[2 * i] = s[i] * e;
+        et[2 * i + 1] = s[i] * t;
+    }
+}
+
+// step 2: Ks times both halves of the pair; ke_i = s_i (Ks S e)_i = (K e)_i;
+// partials of e^T K e and t^T K t
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_mp_kl_prod(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                       const double *__restrict__ Ks, const double *__restrict__ s,
+                                                       const double *__restrict__ et, double *__restrict__ ke,
+                                                       double *part) {
+    __shared__ double lds[2 * kBlock / kWave];
+    double acc[2] = {0.0, 0.0};
+    csr_rows<double, 2, C>(
+        n, rp, ci, Ks,
+        [&](int, int c, double v, bool ok, double(&a)[2]) {
+            const double2 p = *reinterpret_cast<const double2 *>(et + 2 * (size_t)c);
+            a[0] += ok ? v * p.x : 0.0;
+            a[1] += ok ? v * p.y : 0.0;
+        },
+        [&](int row, int lane, double(&a)[2]) {
+            if (lane != 0) return;
+            ke[row] = s[row] * a[0];
+            acc[0] += et[2 * (size_t)row] * a[0];
+            acc[1] += et[2 * (size_t)row + 1] * a[1];
+        });
+    write_partials<2>(acc, part, lds);
+}
+
+// step 3 (one block): scal[kScalEKE] = e^T K e, scal[kScalTKT] = t^T K t
+__global__ __launch_bounds__(kBlock) void k_mp_kl_sum(int np, const double *part, double *scal) {
+    __shared__ double lds[2 * kBlock / kWave];
+    double v[2];
+    read_partials<2>(part, np, v, lds);
+    if (threadIdx.x == 0) {
+        scal[kScalEKE] = v[0];
+        scal[kScalTKT] = v[1];
     }
 }
 
@@ -828,10 +901,12 @@ int mpnn_infer(void *stream, const oasis_csr *Ks, const double *s, int32_t dim, 
 }  // namespace oasis
 
 extern "C" int oasis_mpnn_backward(void *stream, const oasis_csr *Ks, const double *s, const double *phi,
-                                   const double *phi_prev, const float *params, float *grad, double *loss_out,
-                                   void *ws, size_t ws_bytes) {
+                                   const double *phi_prev, const float *params, float *grad, int32_t loss_kind,
+                                   double *loss_out, void *ws, size_t ws_bytes) {
     OASIS_TRY(mp_check(Ks, s, ws));
     if (!phi || !phi_prev || !params || !grad) return OASIS_EINVAL;
+    if (loss_kind != OASIS_MPNN_LOSS_MSE && loss_kind != OASIS_MPNN_LOSS_KNORM) return OASIS_EINVAL;
+    const bool knorm = loss_kind == OASIS_MPNN_LOSS_KNORM;
     const int n = Ks->n;
     Carver c(ws, ws_bytes);
     MpWs w;
@@ -841,8 +916,19 @@ extern "C" int oasis_mpnn_backward(void *stream, const oasis_csr *Ks, const doub
     hipStream_t st = as_stream(stream);
     const double *val = static_cast<const double *>(Ks->val);
     const int nb = kGradBlocks;
+    if (knorm) {
+        hipLaunchKernelGGL(k_mp_kl_pair, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, n, w.delta, phi,
+                           phi_prev, s, w.scal, w.et);
+        OASIS_TRY_LAUNCH();
+        const int g1 = grid_for(n, rows_per_block<Cfg4x4x1>(), kMaxPartials);
+        hipLaunchKernelGGL((k_mp_kl_prod<Cfg4x4x1>), dim3(g1), dim3(kBlock), 0, st, n, Ks->row_ptr, Ks->col_idx,
+                           val, s, w.et, w.ke, w.part);
+        OASIS_TRY_LAUNCH();
+        hipLaunchKernelGGL(k_mp_kl_sum, dim3(1), dim3(kBlock), 0, st, g1, w.part, w.scal);
+        OASIS_TRY_LAUNCH();
+    }
     hipLaunchKernelGGL(k_mp_bwd_dec, dim3(nb), dim3(kBlock), 0, st, n, w.H[kLayers], w.delta, phi, phi_prev, w.scal,
-                       params, w.G, w.gpart, w.lpart);
+                       knorm ? w.ke : static_cast<const double *>(nullptr), params, w.G, w.gpart, w.lpart);
     OASIS_TRY_LAUNCH();
     // at most 1024 blocks, each walking tiles and loading the layer weights
     // once: 183 us per layer on the 1.6M-node mesh against 248 us with one
@@ -859,7 +945,7 @@ extern "C" int oasis_mpnn_backward(void *stream, const oasis_csr *Ks, const doub
     hipLaunchKernelGGL(k_mp_bwd_enc, dim3(nb), dim3(kBlock), 0, st, n, w.G, w.Z[0], w.X, w.gpart);
     OASIS_TRY_LAUNCH();
     hipLaunchKernelGGL(k_mp_grad_reduce, dim3((kNParam + kBlock - 1) / kBlock), dim3(kBlock), 0, st, w.gpart, nb, grad,
-                       w.lpart, dloss, n);
+                       w.lpart, dloss, n, w.scal, knorm ? 1 : 0);
     OASIS_TRY_LAUNCH();
     if (loss_out) {
         OASIS_TRY_HIP(hipMemcpyAsync(loss_out, dloss, sizeof(double), hipMemcpyDeviceToHost, st));

@@ -6,12 +6,15 @@ channel-flow runs; the network is trained on the GPU with
 oasis_mpnn_forward / oasis_mpnn_backward / oasis_mpnn_adam.  Nothing here
 computes the method: it only drives the C ABI.
 
-    python -m paper_1602_03643_amd.warmstart --sizes c65:40,c129:8 --steps 50
+    python -m paper_1602_03643_amd.warmstart --sizes c65:40,c129:8 --steps 50 --amg
 
-trains on the listed mesh sizes (size:seeds, `--steps` steps per seed),
-validates on held-out seeds, measures the PCG iterations the attached guess
-saves against phi_prev on held-out runs, and writes
-weights/mpnn_channel.npz next to this file.
+trains on the listed mesh sizes (size:seeds, `--steps` steps per seed) on
+the K-norm loss (or `--loss mse`), validates on held-out seeds, measures the
+PCG iterations the attached guess saves against phi_prev on held-out runs
+(with Jacobi and, with `--amg`, multigrid preconditioning), and writes
+weights/mpnn_channel.npz next to this file (the packaged weights;
+weights/mpnn_channel_mse.npz holds a network trained on the mean squared
+error).
 """
 from __future__ import annotations
 
@@ -29,6 +32,12 @@ from .api import IPCS, MPNN, DeviceCSR, DeviceMesh, colorize, p1_pattern
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "mpnn_channel.npz")
+MSE_WEIGHTS = os.path.join(HERE, "weights", "mpnn_channel_mse.npz")
+
+
+def loss_kind(meta):
+    """The training loss recorded in a weights file's metadata."""
+    return L.MPNN_LOSS_KNORM if meta.get("loss", "mse") == "knorm" else L.MPNN_LOSS_MSE
 # flat parameter layout of oasis_mpnn_* (offsets in include/oasis.h)
 SHAPES = [("We", (32, 6)), ("ce", (32,)), ("Ws", (3, 32, 32)), ("Wn", (3, 32, 32)), ("c", (3, 32)),
           ("wd", (32,)), ("cd", (1,))]
@@ -116,9 +125,10 @@ def collect(h: IPCS, st, steps):
     return out
 
 
-def train(samples, epochs=3, lr=1e-3, seed=0, params=None, log=None):
+def train(samples, epochs=3, lr=1e-3, seed=0, params=None, log=None, loss_kind=L.MPNN_LOSS_MSE):
     """samples: [(net, b_phi, phi_prev, phi)]; one Adam step per sample,
-    shuffled each epoch.  Returns (params, mean loss per epoch)."""
+    shuffled each epoch, on the loss loss_kind.  Returns (params, mean loss
+    per epoch)."""
     dev = samples[0][1].device
     P = torch.as_tensor(init_params(seed) if params is None else params, device=dev).contiguous()
     m = torch.zeros_like(P)
@@ -133,7 +143,7 @@ def train(samples, epochs=3, lr=1e-3, seed=0, params=None, log=None):
         for i in rng.permutation(len(samples)):
             net, b, fp, f = samples[i]
             net.forward(P, b, fp)
-            tot += net.backward(P, f, fp, g)
+            tot += net.backward(P, f, fp, g, loss_kind)
             t += 1
             MPNN.adam(P, g, m, v, t, lr=lr)
         hist.append(tot / len(samples))
@@ -142,22 +152,24 @@ def train(samples, epochs=3, lr=1e-3, seed=0, params=None, log=None):
     return P, hist
 
 
-def eval_loss(samples, P):
+def eval_loss(samples, P, loss_kind=L.MPNN_LOSS_MSE):
     g = torch.zeros_like(P)
     tot = 0.0
     for net, b, fp, f in samples:
         net.forward(P, b, fp)
-        tot += net.backward(P, f, fp, g)
+        tot += net.backward(P, f, fp, g, loss_kind)
     return tot / len(samples)
 
 
-def compare(case: Case, P, seed, steps, precision=L.F32):
+def compare(case: Case, P, seed, steps, precision=L.F32, amg=False):
     """Run the same seeded trajectory with a plain handle and one with the
     warm start attached, in lockstep; per-step PCG iterations, whether the
     guess was taken, pressure-solve milliseconds and the final difference of
-    the two phi fields (both solves stop at the same tolerance)."""
+    the two phi fields (both solves stop at the same tolerance).  amg: both
+    handles precondition the pressure solve with the multigrid cycle."""
     plain = case.handle(precision)
     warm = case.handle(precision)
+    keep = [plain.pressure_amg(precision=precision), warm.pressure_amg(precision=precision)] if amg else []
     warm.set_warmstart(P, case.coords)
     sa, sb = case.initial(seed), case.initial(seed)
     rows = []
@@ -169,7 +181,8 @@ def compare(case: Case, P, seed, steps, precision=L.F32):
     dphi = float(torch.linalg.vector_norm(sa["phi"] - sb["phi"]) / torch.linalg.vector_norm(sa["phi"]))
     plain.close()
     warm.close()
-    return dict(size=case.size, seed=seed, steps=steps, iters_plain=float(a[:, 0].mean()),
+    del keep
+    return dict(size=case.size, seed=seed, steps=steps, amg=amg, iters_plain=float(a[:, 0].mean()),
                 iters_warm=float(a[:, 1].mean()), guess_used=float(a[:, 2].mean()),
                 ms_pressure_plain=float(a[:, 3].mean()), ms_pressure_warm=float(a[:, 4].mean()),
                 rel_diff_phi=dphi)
@@ -193,6 +206,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--compare-steps", type=int, default=20)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--loss", choices=["mse", "knorm"], default="knorm",
+                    help="training loss: mean squared error of the scaled correction, or the K-norm of the error")
+    ap.add_argument("--amg", action="store_true", help="compare with the multigrid-preconditioned pressure solve too")
     ap.add_argument("--eval", metavar="WEIGHTS", default=None,
                     help="skip training: compare plain and warm-started runs with these weights")
     args = ap.parse_args(argv)
@@ -201,14 +217,17 @@ def main(argv=None):
         print(*a, file=sys.stderr, flush=True)
 
     dev = torch.device("cuda", 0)
+    kind = L.MPNN_LOSS_KNORM if args.loss == "knorm" else L.MPNN_LOSS_MSE
     sizes = [(s.split(":")[0], int(s.split(":")[1])) for s in args.sizes.split(",") if s]
     if args.eval:
         P = torch.as_tensor(load(args.eval)[0], device=dev)
         cmp = []
         for size, nseed in sizes:
-            c = compare(Case(size, dev), P, seed=nseed + args.val_seeds + 1, steps=args.compare_steps)
-            log("compare %s" % c)
-            cmp.append(c)
+            case = Case(size, dev)
+            for amg in ([False, True] if args.amg else [False]):
+                c = compare(case, P, seed=nseed + args.val_seeds + 1, steps=args.compare_steps, amg=amg)
+                log("compare %s" % c)
+                cmp.append(c)
         print(json.dumps(dict(weights=args.eval, compare=cmp)), flush=True)
         return
     t0 = time.perf_counter()
@@ -222,20 +241,27 @@ def main(argv=None):
             (train_s if sd <= nseed else val_s).extend((case.net,) + s for s in ss)
             log("%s seed %d: %d pairs (%.1f s)" % (size, sd, len(ss), time.perf_counter() - t0))
     t1 = time.perf_counter()
-    P, hist = train(train_s, epochs=args.epochs, lr=args.lr, log=log)
+    P, hist = train(train_s, epochs=args.epochs, lr=args.lr, log=log, loss_kind=kind)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    v0 = eval_loss(val_s, torch.as_tensor(init_params(0), device=dev))
-    v1 = eval_loss(val_s, P)
-    log("validation loss %.4g (guess = phi_prev: %.4g)" % (v1, v0))
+    v0 = eval_loss(val_s, torch.as_tensor(init_params(0), device=dev), kind)
+    v1 = eval_loss(val_s, P, kind)
+    log("validation %s loss %.4g (guess = phi_prev: %.4g)" % (args.loss, v1, v0))
+    # the other loss of the same network, for comparison between the two
+    other = L.MPNN_LOSS_MSE if kind == L.MPNN_LOSS_KNORM else L.MPNN_LOSS_KNORM
+    v1o = eval_loss(val_s, P, other)
+    v0o = eval_loss(val_s, torch.as_tensor(init_params(0), device=dev), other)
+    log("validation %s loss %.4g (guess = phi_prev: %.4g)" % ("mse" if kind else "knorm", v1o, v0o))
     del train_s, val_s
     cmp = []
     for size, nseed in sizes:
-        c = compare(cases[size], P, seed=nseed + args.val_seeds + 1, steps=args.compare_steps)
-        log("compare %s" % c)
-        cmp.append(c)
+        for amg in ([False, True] if args.amg else [False]):
+            c = compare(cases[size], P, seed=nseed + args.val_seeds + 1, steps=args.compare_steps, amg=amg)
+            log("compare %s" % c)
+            cmp.append(c)
     meta = dict(sizes=args.sizes, steps_per_seed=args.steps, val_seeds=args.val_seeds, epochs=args.epochs,
-                lr=args.lr, train_loss=hist, val_loss=v1, val_loss_prev_phi=v0, data_s=t1 - t0,
+                lr=args.lr, loss=args.loss, train_loss=hist, val_loss=v1, val_loss_prev_phi=v0,
+                val_other_loss=v1o, val_other_loss_prev_phi=v0o, data_s=t1 - t0,
                 train_s=t2 - t1, compare=cmp)
     save(args.out, P.cpu().numpy(), meta)
     log("saved %s" % args.out)

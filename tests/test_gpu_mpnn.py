@@ -89,9 +89,10 @@ def test_mpnn_forward_matches_oracle(oa):
     assert torch.equal(guess, T(phi_prev))
 
 
-def test_mpnn_backward_matches_oracle(oa):
+@pytest.mark.parametrize("kind", ["mse", "knorm"])
+def test_mpnn_backward_matches_oracle(oa, kind):
     pr, S, out, phi_prev = _setup()
-    say("mpnn backward", pr.name)
+    say("mpnn backward", kind, pr.name)
     Ks, s = _gpu_graph(oa, pr, S)
     P = _params(2)
     net = oa.MPNN(Ks, s, T(pr.mesh.dof_coords))
@@ -99,16 +100,48 @@ def test_mpnn_backward_matches_oracle(oa):
     pt = T(_flat(P), torch.float32)
     net.forward(pt, T(out.b_phi), T(phi_prev))
     grad = torch.zeros(oa.MPNN.NPARAM, dtype=torch.float32, device=dev())
-    loss = net.backward(pt, T(out.phi), T(phi_prev), grad)
+    code = oa.MPNN_LOSS_KNORM if kind == "knorm" else oa.MPNN_LOSS_MSE
+    loss = net.backward(pt, T(out.phi), T(phi_prev), grad, code)
     X, sigma = mpnn.features(S.K, out.b_phi, phi_prev, pr.mesh.dof_coords)
     W = mpnn.edge_weights(S.K)
     d_ref, cache = mpnn.forward(P, X, W)
     target = (out.phi - phi_prev) / sigma
-    G = mpnn.backward(P, cache, d_ref, target, W)
-    assert abs(loss / mpnn.loss(d_ref, target) - 1.0) < 3e-2
+    G = mpnn.backward(P, cache, d_ref, target, W, kind, S.K)
+    ref = mpnn.loss(d_ref, target, kind, S.K)
+    say("loss", loss, "oracle", ref)
+    assert abs(loss / ref - 1.0) < 3e-2
     g = _unflat(grad.cpu().numpy())
     for k, _ in mpnn.PARAM_SHAPES:
+        if kind == "knorm" and k == "cd":
+            # K 1 = 0: a constant added to delta leaves the K-norm loss
+            # unchanged, so the output bias has zero gradient (rounding
+            # only on both sides)
+            scale = np.linalg.norm(G["wd"])
+            assert abs(G["cd"][0]) < 1e-12 * scale and abs(g["cd"][0]) < 1e-5 * scale, (g["cd"], G["cd"])
+            continue
         assert rel(g[k], G[k]) < 5e-2, (k, rel(g[k], G[k]))
+
+
+def test_mpnn_knorm_loss_of_the_zero_decoder_is_one(oa):
+    """With a zero decoder the guess is phi_prev (delta = 0), so the K-norm
+    loss is exactly t^T K t / t^T K t = 1 and, for phi = phi_prev, the
+    degenerate sample gives loss 0 and a zero gradient."""
+    pr, S, out, phi_prev = _setup(seed=3)
+    Ks, s = _gpu_graph(oa, pr, S)
+    Z = _params(4)
+    Z["wd"][:] = 0.0
+    Z["cd"][:] = 0.0
+    net = oa.MPNN(Ks, s, T(pr.mesh.dof_coords))
+    pt = T(_flat(Z), torch.float32)
+    net.forward(pt, T(out.b_phi), T(phi_prev))
+    grad = torch.zeros(oa.MPNN.NPARAM, dtype=torch.float32, device=dev())
+    loss = net.backward(pt, T(out.phi), T(phi_prev), grad, oa.MPNN_LOSS_KNORM)
+    assert abs(loss - 1.0) < 1e-12
+    net.forward(pt, T(out.b_phi), T(out.phi))
+    loss = net.backward(pt, T(out.phi), T(out.phi), grad, oa.MPNN_LOSS_KNORM)
+    assert loss == 0.0 and not torch.any(grad)
+    with pytest.raises(oa.OasisError):
+        net.backward(pt, T(out.phi), T(phi_prev), grad, 2)
 
 
 def test_mpnn_adam_matches_oracle(oa):

@@ -1,17 +1,19 @@
 """The learned warm start inside the IPCS step.
 
-* The guard: a caller guess is taken only when its residual is below that
+* The guard: a caller guess is taken only when its CG energy is below that
   of the plain start (phi_prev, or phi_0 = 0); the converged correction of
   the oracle is taken and leaves almost nothing to iterate, a useless one
   is refused and the step is then identical to the plain step.
 * The phi_0 = 0 start matches the oracle's zero start.
-* The trained network (packaged weights): on a held-out seeded channel run
-  it must lower the error it is trained on (the mean squared error of the
-  scaled correction) well below that of phi_prev, every warm-started step
-  must reach the same tolerance as the plain one, and where the guard
-  refuses the guess the iteration count must equal the plain one.  The
-  measured change in PCG iterations and pressure-solve time is printed:
-  with Jacobi-PCG to 1e-8 it is small.
+* The trained networks (packaged weights, one trained on the K-norm of the
+  error, one on the mean squared error of the scaled correction): on a
+  held-out seeded channel run each must lower the loss it was trained on
+  well below that of phi_prev, every warm-started step must reach the same
+  tolerance as the plain one, and where the guard refuses the guess the
+  iteration count must equal the plain one.  The K-norm network's guess
+  must pass the energy guard on most steps and, with the multigrid
+  preconditioner, not need more iterations than phi_prev.  The measured
+  change in PCG iterations and pressure-solve time is printed.
 """
 import numpy as np
 import pytest
@@ -109,23 +111,32 @@ def test_random_network_never_breaks_the_step(oa):
     assert rb["guess_used"] == 0
 
 
-def test_trained_network_gain_on_held_out_run(oa):
+@pytest.mark.parametrize("which", ["knorm", "mse"])
+def test_trained_network_gain_on_held_out_run(oa, which):
     from paper_1602_03643_amd import warmstart
-    P, meta = warmstart.load()
+    P, meta = warmstart.load(warmstart.DEFAULT_WEIGHTS if which == "knorm" else warmstart.MSE_WEIGHTS)
+    kind = warmstart.loss_kind(meta)
+    assert kind == (oa.MPNN_LOSS_KNORM if which == "knorm" else oa.MPNN_LOSS_MSE)
     size, steps, seed = "c65", 8, 97           # seed far outside the training seeds
-    say("trained warm start", size, "seed", seed, "weights trained on", meta["sizes"])
+    say("trained warm start", which, size, "seed", seed, "weights trained on", meta["sizes"])
     case = warmstart.Case(size, dev())
     Pt = torch.as_tensor(P, device=dev())
     st = case.initial(seed)
     data = warmstart.collect(case.h, st, steps)
     samples = [(case.net,) + d for d in data]
-    l_prev = warmstart.eval_loss(samples, torch.as_tensor(warmstart.init_params(0), device=dev()))
-    l_net = warmstart.eval_loss(samples, Pt)
-    say("held-out loss: guess = phi_prev %.3f, trained network %.3f" % (l_prev, l_net))
-    assert l_net < 0.6 * l_prev
-    c = warmstart.compare(case, Pt, seed=seed, steps=steps)
-    say("PCG iterations plain %.1f, warm %.1f (guess used in %.0f%% of steps); pressure ms %.2f vs %.2f"
-        % (c["iters_plain"], c["iters_warm"], 100 * c["guess_used"], c["ms_pressure_plain"], c["ms_pressure_warm"]))
-    assert c["rel_diff_phi"] < 1e-5
-    if c["guess_used"] == 0.0:
-        assert c["iters_warm"] == c["iters_plain"]
+    l_prev = warmstart.eval_loss(samples, torch.as_tensor(warmstart.init_params(0), device=dev()), kind)
+    l_net = warmstart.eval_loss(samples, Pt, kind)
+    say("held-out %s loss: guess = phi_prev %.3f, trained network %.3f" % (which, l_prev, l_net))
+    assert l_net < (0.3 if which == "knorm" else 0.6) * l_prev
+    for amg in [False, True]:
+        c = warmstart.compare(case, Pt, seed=seed, steps=steps, amg=amg)
+        say("%s: PCG iterations plain %.1f, warm %.1f (guess used in %.0f%% of steps); pressure ms %.2f vs %.2f"
+            % ("multigrid" if amg else "Jacobi", c["iters_plain"], c["iters_warm"], 100 * c["guess_used"],
+               c["ms_pressure_plain"], c["ms_pressure_warm"]))
+        assert c["rel_diff_phi"] < 1e-5
+        if c["guess_used"] == 0.0:
+            assert c["iters_warm"] == c["iters_plain"]
+        if which == "knorm":
+            assert c["guess_used"] >= 0.5
+            if amg:
+                assert c["iters_warm"] <= c["iters_plain"]
