@@ -452,8 +452,7 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
     };
     OASIS_TRY(start(0, 0));
     CGState h;
-    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
     const double wbb = h.wbb, tol2 = h.tol2;
     auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
     if (!std::isfinite(h.wrr)) {
@@ -482,8 +481,7 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
         const int m = std::min(plan.next, maxit - it);
         for (int j = 0; j < m; ++j) OASIS_TRY(iterate(it + j));
         it += m;
-        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
         if (h.flag == 0 && it < maxit) {
             plan.observe(h.wrr_it, h.it_last, tol2);
             continue;
@@ -497,8 +495,7 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
         // converged candidate (or maxit): confirm on the true residual
         const int at = h.flag == 0 ? it : h.it_done;
         OASIS_TRY(start(1, at));
-        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
         out.rel_res = rel(h.wrr);
         if (!std::isfinite(h.wrr)) {
             out.iters = at;

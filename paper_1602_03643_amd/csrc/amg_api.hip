@@ -27,6 +27,11 @@ struct AmgImage {
 };
 
 struct oasis_amg {
+    oasis_amg() = default;
+    oasis_amg(const oasis_amg &) = delete;
+    oasis_amg &operator=(const oasis_amg &) = delete;
+    ~oasis_amg() { stage_free(stage); }
+    HostStage stage;   // pinned read-back block of the solve loop
     oasis_amg_params par{};
     Tuning tun;
     bool f32 = false, singular = false;
@@ -290,6 +295,8 @@ extern "C" int oasis_amg_upload(void *stream, oasis_amg *h, void *ws, size_t ws_
     if (!c.ok) return OASIS_EWORKSPACE;
     AmgImage &d = h->d;
     d.cg.tun = h->tun;
+    if (!h->stage.h) stage_alloc(h->stage);
+    d.cg.stage = h->stage;
     hipLaunchKernelGGL(k_amg_fill, dim3(grid_for(h->n, kBlock, 8192)), dim3(kBlock), 0, s, h->n, d.ones, 1.0);
     OASIS_TRY_LAUNCH();
     if (h->ell_fits) {

@@ -178,4 +178,22 @@ __device__ __forceinline__ void read_partials(const double *part, int nparts, do
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
+// A small pinned, host-mapped block through which a solver's host loop
+// reads its state back.  A one-block kernel copies the state into it and
+// the host synchronises the stream: one kernel round trip, where a copy to
+// pageable memory also stages through the runtime.  A handle owns one
+// (stage_alloc at create, stage_free at destroy); without it (h null) reads
+// are copies to the caller's host memory.  This is host memory: the
+// library still allocates no device memory.
+struct HostStage {
+    void *h = nullptr;   // host address
+    void *d = nullptr;   // the same memory as the device sees it
+};
+constexpr size_t kStageBytes = 1024;
+void stage_alloc(HostStage &st);   // best effort: stays null on failure
+void stage_free(HostStage &st);
+// bytes (a multiple of 4) of device memory at dev into host memory at out;
+// synchronises the stream
+int read_state(hipStream_t s, const HostStage &st, const void *dev, void *out, size_t bytes);
+
 }  // namespace oasis

@@ -828,6 +828,7 @@ struct IRBufs {
     float *e32[3] = {nullptr, nullptr, nullptr};
     double *part = nullptr;
     double *sums = nullptr;   // device [8]
+    HostStage stage;          // the owner's read-back block (may be null)
 };
 
 static void carve_ir(Carver &c, int n, int nr, IRBufs &ir) {
@@ -864,9 +865,7 @@ static int ir_outer_resid(hipStream_t s, int n, int nr, const int *rp, const int
         hipLaunchKernelGGL((k_sum_to<6>), dim3(1), dim3(kBlock), 0, s, ir.part, g, ir.sums);
     }
     OASIS_TRY_LAUNCH();
-    OASIS_TRY_HIP(hipMemcpyAsync(host_sums, ir.sums, 2 * nr * sizeof(double), hipMemcpyDeviceToHost, s));
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
-    return OASIS_OK;
+    return read_state(s, ir.stage, ir.sums, host_sums, 2 * nr * sizeof(double));
 }
 
 struct KOpts {
@@ -1026,6 +1025,11 @@ using namespace oasis;
 // the IPCS handle
 
 struct oasis_ipcs {
+    oasis_ipcs() = default;
+    oasis_ipcs(const oasis_ipcs &) = delete;
+    oasis_ipcs &operator=(const oasis_ipcs &) = delete;
+    ~oasis_ipcs() { stage_free(stage); }
+    HostStage stage;   // pinned read-back block of the solver loops
     oasis_mesh mesh;
     std::vector<int> color_ptr;
     int dim = 0, n = 0, nnz = 0;
@@ -1312,6 +1316,9 @@ extern "C" int oasis_ipcs_create(void *stream, const oasis_mesh *mesh, const int
                h->gradient, par->assembly != OASIS_ASSEMBLE_COLORS, *h);
     h->cg.tun = h->cg32.tun = h->cgM.tun = h->tun;
     h->bi.tun = h->bi32.tun = h->tun;
+    stage_alloc(h->stage);
+    h->cg.stage = h->cg32.stage = h->cgM.stage = h->stage;
+    h->bi.stage = h->bi32.stage = h->ir.stage = h->stage;
     auto fail = [&](int rc) {
         delete h;
         return rc;
@@ -1635,8 +1642,7 @@ static int step_energy(hipStream_t s, oasis_ipcs *h, const double *x, double *J)
     hipLaunchKernelGGL((k_sum_to<1>), dim3(1), dim3(kBlock), 0, s, h->red, g, h->red + kMaxPartials);
     OASIS_TRY_LAUNCH();
     double v = 0;
-    OASIS_TRY_HIP(hipMemcpyAsync(&v, h->red + kMaxPartials, sizeof(double), hipMemcpyDeviceToHost, s));
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    OASIS_TRY(read_state(s, h->stage, h->red + kMaxPartials, &v, sizeof(v)));
     *J = -0.5 * v;
     return OASIS_OK;
 }

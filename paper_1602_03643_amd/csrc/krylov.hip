@@ -868,8 +868,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     OASIS_TRY(residual(0, 0));
     if (sr) OASIS_TRY(loop.start(0, false));
     CGState h;
-    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
     ChunkPlan plan(check_every);
     plan.restart(h.wrr, 0, h.tol2);
     int it = 0, restart_at = 0;
@@ -903,8 +902,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             OASIS_TRY_LAUNCH();
         }
         it += m;
-        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
         if (h.flag == 0) {
             if (it < maxit) {
                 plan.observe(h.wrr_it, h.it_last, h.tol2);
@@ -912,8 +910,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             }
             const double wbb = h.wbb, tol2 = h.tol2;
             OASIS_TRY(residual(1, it));
-            OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-            OASIS_TRY_HIP(hipStreamSynchronize(s));
+            OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
             out.iters = it;
             finish(h.wrr, wbb);
             out.status = rc = (h.wrr <= tol2) ? OASIS_OK : OASIS_ENOTCONV;
@@ -945,8 +942,7 @@ static int cg_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             const int itd = h.it_done;
             const double wbb = h.wbb, tol2 = h.tol2;
             OASIS_TRY(residual(1, itd));
-            OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-            OASIS_TRY_HIP(hipStreamSynchronize(s));
+            OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
             if (h.wrr <= tol2) {
                 out.iters = itd;
                 finish(h.wrr, wbb);
@@ -1035,8 +1031,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
     };
     OASIS_TRY(replace(0));
     CGState h;
-    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
     const double wbb = h.wbb, tol2 = h.tol2;
     auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
     if (!std::isfinite(h.wrr)) {
@@ -1077,8 +1072,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         }
         it += m;
         nin = g.p2;
-        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
         if (h.flag == 2 || h.flag == 3) {
             OASIS_TRY(fold());
             out.iters = h.it_done;
@@ -1094,8 +1088,7 @@ static int cg_mixed_run(hipStream_t s, int n, const int *rp, const int *ci, cons
         const int at = h.flag == 0 ? it : h.it_done;
         OASIS_TRY(fold());
         OASIS_TRY(replace(1));
-        OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipStreamSynchronize(s));
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
         out.outer += 1;
         out.rel_res = rel(h.wrr);
         if (!std::isfinite(h.wrr)) {
@@ -1193,8 +1186,7 @@ int cg_residual(hipStream_t s, int n, const int *rp, const int *ci, const double
     hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, w.partB, g1, w.st, 1.0, 0, 0.0);
     OASIS_TRY_LAUNCH();
     CGState h;
-    OASIS_TRY_HIP(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s));
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
     *wrr = h.wrr;
     *wbb = h.wbb;
     return OASIS_OK;
@@ -1709,11 +1701,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         OASIS_TRY_HIP(hipMemcpyAsync(dblk, &hb, sizeof(hb), hipMemcpyHostToDevice, s));
         return OASIS_OK;
     };
-    auto pull_state = [&]() -> int {
-        OASIS_TRY_HIP(hipMemcpyAsync(&hb, dblk, sizeof(hb), hipMemcpyDeviceToHost, s));
-        OASIS_TRY_HIP(hipStreamSynchronize(s));
-        return OASIS_OK;
-    };
+    auto pull_state = [&]() -> int { return read_state(s, w.stage, dblk, &hb, sizeof(hb)); };
     auto zero_dirs = [&](int k) -> int {
         hipLaunchKernelGGL((k_zero_u<T>), dim3(gv), dim3(kBlock), 0, s, n, w.ru, NR, k);
         OASIS_TRY_LAUNCH();

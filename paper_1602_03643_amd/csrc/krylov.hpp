@@ -54,6 +54,7 @@ struct CGWork {
     EllCols cols;
     const T *eval = nullptr;
     Tuning tun;
+    HostStage stage;   // the owner's read-back block (may be null)
 };
 
 struct BiState {
@@ -103,6 +104,7 @@ struct BiWork {
     // optional ELL copy of the iteration matrix (set by the owner)
     EllCols cols;
     const T *eval = nullptr;
+    HostStage stage;   // the owner's read-back block (may be null)
     Tuning tun;
 };
 
