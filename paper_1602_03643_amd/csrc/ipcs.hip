@@ -974,12 +974,11 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
             const int k = active[q];
             bb[q] = ir.r32[k];
             xx[q] = ir.e32[k];
-            hipLaunchKernelGGL(k_zero_f, dim3(gv), dim3(kBlock), 0, s, (long long)n, ir.e32[k]);
-            OASIS_TRY_LAUNCH();
         }
+        // the correction starts from zero, which the solve writes itself
         SolveOut in[3];
         const int rc = bicgstab_solve<float>(s, n, na, rp, ci, val32, w32, bb, xx, inner,
-                                             o.maxit, o.check_every, o.time, bw, in);
+                                             o.maxit, o.check_every, o.time, bw, in, true);
         if (rc == OASIS_EHIP) return rc;
         for (int q = 0; q < na; ++q) {
             const int k = active[q];

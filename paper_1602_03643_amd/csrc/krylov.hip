@@ -1369,7 +1369,11 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, const RW<T> *r
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int k = 0; k < NR; ++k)
-            if ((active >> k) & 1) st[k].rho[it & 1] = v[3 * k];
+            if ((active >> k) & 1) {
+                st[k].rho[it & 1] = v[3 * k];
+                st[k].wrr_rec = v[3 * k + 1];
+                st[k].it_rec = it;
+            }
     }
     double acc[NR];
 #pragma unroll
@@ -1646,6 +1650,33 @@ __global__ __launch_bounds__(kBlock) void k_zero_u(int n, RW<T> *ru, int nr, int
         ru[i * nr + k].w = T(0);
 }
 
+// The start from x = 0: x = 0, r = r_hat = b, u = 0, and the partials
+// (r_hat.r, sum wgt r^2, sum wgt b^2) that k_bi_resid would give.
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void k_bi_start0(int n, const T *__restrict__ wgt, C3<T> b, V3<T> x,
+                                                      RW<T> *ru, V3<T> rhat, double *part) {
+    __shared__ double lds[9 * kBlock / kWave];
+    double acc[3 * NR];
+#pragma unroll
+    for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double wd = wgt[i];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const T bk = b.p[k][i];
+            x.p[k][i] = T(0);
+            ru[i * NR + k] = RW<T>{bk, T(0)};
+            rhat.p[k][i] = bk;
+            const double bd = bk;
+            acc[3 * k + 0] += bd * bd;
+            acc[3 * k + 1] += wd * bd * bd;
+            acc[3 * k + 2] += wd * bd * bd;
+        }
+    }
+    write_partials<3 * NR>(acc, part, lds);
+}
+
 template <typename T>
 void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
     std::memset(&w, 0, sizeof(w));
@@ -1668,7 +1699,7 @@ void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
 template <typename T, int NR, class C>
 static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *const *b, T *const *x, double rtol, int maxit, int check_every,
-                  bool time_kernel, BiWork<T> &w, SolveOut *out) {
+                  bool time_kernel, BiWork<T> &w, SolveOut *out, bool x_zero) {
     const int g1 = grid_for(n, rows_per_block<C>(), w.tun.grid_cap);
     const int g2 = grid_for(n, kBlock, w.tun.grid_cap);
     const int gv = grid_for(n, kBlock, 4096);
@@ -1721,8 +1752,14 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     };
     const int all = (1 << NR) - 1;
     OASIS_TRY(push_state());
-    for (int k = 0; k < NR; ++k) OASIS_TRY(zero_dirs(k));
-    OASIS_TRY(resid(all, all, cx));
+    if (x_zero) {
+        // the grid of the product kernels, whose partial count finalize reads
+        hipLaunchKernelGGL((k_bi_start0<T, NR>), dim3(g1), dim3(kBlock), 0, s, n, wgt, cb, vx, w.ru, vrh, w.part3);
+        OASIS_TRY_LAUNCH();
+    } else {
+        for (int k = 0; k < NR; ++k) OASIS_TRY(zero_dirs(k));
+        OASIS_TRY(resid(all, all, cx));
+    }
     OASIS_TRY(finalize(0));
     OASIS_TRY(pull_state());
     double wbb[3], tol2[3];
@@ -1731,6 +1768,28 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         tol2[k] = hs[k].tol2;
     }
     auto rel = [&](int k, double wrr) { return wbb[k] > 0 ? std::sqrt(wrr / wbb[k]) : std::sqrt(wrr); };
+    // Iterations to launch before the next poll.  Each right-hand side's
+    // convergence rate (log of the weighted residual per iteration, from
+    // its last restart to the latest recursive residual k_bi_1 recorded)
+    // predicts the iteration at which the slowest active one meets its
+    // tolerance; the launch reaches one past it, within [1, chunk].  A
+    // launch past the pause costs kernels that return at once, a short one
+    // another poll.  Before any rate is known: `chunk`.
+    double lref[3] = {0, 0, 0}, lrate[3] = {0, 0, 0};
+    int itref[3] = {0, 0, 0};
+    auto set_ref = [&](int k, double wrr, int at) {
+        lref[k] = wrr > 0.0 ? std::log(wrr) : 0.0;
+        itref[k] = at;
+    };
+    for (int k = 0; k < NR; ++k) set_ref(k, hs[k].wrr, 0);
+    auto observe = [&]() {
+        for (int k = 0; k < NR; ++k) {
+            if (!hs[k].active || hs[k].it_rec <= itref[k] || !(hs[k].wrr_rec > 0.0) || !std::isfinite(hs[k].wrr_rec))
+                continue;
+            const double r = (std::log(hs[k].wrr_rec) - lref[k]) / (hs[k].it_rec - itref[k]);
+            if (r < 0.0) lrate[k] = r;
+        }
+    };
     int restarted[3] = {0, 0, 0};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (time_kernel) {
@@ -1738,7 +1797,28 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         OASIS_TRY_HIP(hipEventCreate(&e1));
     }
     const int chunk = check_every > 0 ? check_every : 8;
+    auto plan = [&](int at) -> int {
+        if (check_every > 0) return chunk;
+        int last = at;   // the iteration whose k_bi_1 should see convergence
+        for (int k = 0; k < NR; ++k) {
+            if (!hs[k].active) continue;
+            if (!(lrate[k] < 0.0) || !(tol2[k] > 0.0)) return chunk;
+            // the latest known point: the recorded recursive residual, or
+            // the reference set at the last (re)start
+            double lw = lref[k];
+            int itw = itref[k];
+            if (hs[k].it_rec > itref[k] && hs[k].wrr_rec > 0.0 && std::isfinite(hs[k].wrr_rec)) {
+                lw = std::log(hs[k].wrr_rec);
+                itw = hs[k].it_rec;
+            }
+            const double need = (std::log(tol2[k]) - lw) / lrate[k];
+            const int j = itw + static_cast<int>(std::ceil(std::max(0.0, need)));
+            last = std::max(last, j);
+        }
+        return std::min(chunk, std::max(1, last - at + 2));
+    };
     int it = 0, phase = 1;
+    int next = chunk;
     int part3_count = g1;
     auto n_active = [&]() {
         int a = 0;
@@ -1758,12 +1838,13 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         const int prev = (pit + 1) & 1;
         hs[k].rho[prev] = hs[k].alpha[prev] = hs[k].omega[prev] = 1.0;
         mask_rhat |= 1 << k;
+        set_ref(k, hs[k].wrr, pit);
         return OASIS_OK;
     };
     while (n_active() > 0) {
         // enqueue up to `chunk` iterations
         int launched = 0;
-        while (launched < chunk && it < maxit) {
+        while (launched < next && it < maxit) {
             if (phase == 1) {
                 if (time_kernel) OASIS_TRY_HIP(hipEventRecord(e0, s));
                 hipLaunchKernelGGL((k_bi_1<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat,
@@ -1791,8 +1872,12 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             ++launched;
         }
         OASIS_TRY(pull_state());
+        observe();
         if (!hg.pause) {
-            if (it < maxit) continue;
+            if (it < maxit) {
+                next = plan(it);
+                continue;
+            }
             // iteration cap: confirm with the explicit residual
             int mask = 0;
             for (int k = 0; k < NR; ++k)
@@ -1828,6 +1913,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
                         out[k].rel_res = rel(k, hs[k].wrr);
                     } else {
                         out[k].replacements += 1;
+                        set_ref(k, hs[k].wrr, pit);   // the explicit residual replaced the recursive one
                     }
                 }
             }
@@ -1844,11 +1930,13 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             }
             for (int k = 0; k < NR; ++k) hs[k].event = 0;
             hg = BiGlobal{};
+            if (n_active() == 0) break;
             OASIS_TRY(push_state());
             OASIS_TRY(resid(0, mask_rhat, cx));
             part3_count = g1;
             it = pit;
             phase = 1;
+            next = plan(it);
         } else {
             int cands = 0;
             for (int k = 0; k < NR; ++k)
@@ -1878,9 +1966,11 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             }
             for (int k = 0; k < NR; ++k) hs[k].event = 0;
             hg = BiGlobal{};
+            if (n_active() == 0) break;
             OASIS_TRY(push_state());
             it = pit;
             phase = 3;
+            next = plan(it);
         }
     }
     OASIS_TRY_HIP(hipStreamSynchronize(s));
@@ -1895,14 +1985,17 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
 template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
-                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out) {
+                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out, bool x_zero) {
     return with_cfg([&](auto c) {
         using C = decltype(c);
         if (nrhs == 1)
-            return bi_run<T, 1, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out);
+            return bi_run<T, 1, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out,
+                                   x_zero);
         if (nrhs == 2)
-            return bi_run<T, 2, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out);
-        return bi_run<T, 3, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out);
+            return bi_run<T, 2, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out,
+                                   x_zero);
+        return bi_run<T, 3, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out,
+                               x_zero);
     });
 }
 
@@ -1919,9 +2012,9 @@ template int cg_solve<float>(hipStream_t, int, const int *, const int *, const f
 template int bicgstab_solve<double>(hipStream_t, int, int, const int *, const int *,
                                     const double *, const double *, const double *const *,
                                     double *const *, double, int, int, bool, BiWork<double> &,
-                                    SolveOut *);
+                                    SolveOut *, bool);
 template int bicgstab_solve<float>(hipStream_t, int, int, const int *, const int *, const float *,
                                    const float *, const float *const *, float *const *, double,
-                                   int, int, bool, BiWork<float> &, SolveOut *);
+                                   int, int, bool, BiWork<float> &, SolveOut *, bool);
 
 }  // namespace oasis

@@ -63,7 +63,8 @@ struct BiState {
     int active;        // 1 while iterating
     int event;         // see krylov.hip
     int no_sexit_it;   // iteration whose s-exit test is disabled
-    int pad;
+    int it_rec;        // iteration whose incoming recursive residual is wrr_rec
+    double wrr_rec;    // weighted ||r||^2 entering iteration it_rec (for the host's plan)
 };
 
 struct BiGlobal {
@@ -132,10 +133,11 @@ int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, c
              CGWork<T> &w, SolveOut &out);
 
 // BiCGStab for nrhs systems with the column-scaled matrix As (right Jacobi).
+// x_zero: start from x = 0, which the solve writes itself (r = b, no product).
 template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
-                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out);
+                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out, bool x_zero = false);
 
 // Mixed-precision CG with reliable updates on the scaled system: FP32
 // matrix/vectors inside the iteration, FP64 solution accumulator, and an
