@@ -17,7 +17,11 @@
  *    by the caller; "host" pointers are ordinary host memory.  The library
  *    never allocates or frees device memory: every scratch buffer is a
  *    caller-provided workspace whose size is returned by a *_workspace_size
- *    query.  Workspaces must be 256-byte aligned.
+ *    query.  Workspaces must be 256-byte aligned.  The time-step and
+ *    multigrid handles each hold one 1 KiB pinned, host-mapped block
+ *    (hipHostMalloc at create or upload, freed by destroy) through which
+ *    their solver loops read small state back; without it they fall back
+ *    to ordinary copies.
  *  - Indices are int32; dense vectors are contiguous; multi-component
  *    fields are stored component-major ([dim][n]).
  *  - Every function returns an int status: 0 = OASIS_OK or a negative

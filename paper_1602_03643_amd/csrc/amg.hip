@@ -450,23 +450,16 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
     auto precondition = [&](int at, bool y0_ready) -> int {
         return amg_vcycle<T>(s, c, r, y0_ready, zslot(at), 2, wgt, pv, &gpost, &w.st->flag, cap);
     };
+    // The start residual is not read back: the first product kernel tests
+    // it (converged, non-finite) like any other, and the first poll brings
+    // its norms with the state.
     OASIS_TRY(start(0, 0));
-    CGState h;
-    OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
-    const double wbb = h.wbb, tol2 = h.tol2;
-    auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
-    if (!std::isfinite(h.wrr)) {
-        out.status = OASIS_ENAN;
-        out.rel_res = NAN;
-        return out.status;
-    }
-    if (h.wrr <= tol2) {
-        out.rel_res = rel(h.wrr);
-        return OASIS_OK;
-    }
     OASIS_TRY(precondition(0, false));
+    CGState h;
+    double wbb = 0.0, tol2 = 0.0;
+    bool first = true;
+    auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
     AmgPlan plan(check_every);
-    plan.restart(h.wrr, 0);
     int it = 0, restart_at = 0, rc = OASIS_OK;
     auto iterate = [&](int itj) -> int {
         OASIS_TRY(cg_product_launch(s, cap, n, rp, ci, val, cols, e64, w.pair[itj & 1], w.pair[(itj + 1) & 1],
@@ -482,6 +475,12 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
         for (int j = 0; j < m; ++j) OASIS_TRY(iterate(it + j));
         it += m;
         OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
+        if (first) {
+            first = false;
+            wbb = h.wbb;
+            tol2 = h.tol2;
+            if (h.flag == 0) plan.restart(h.wrr, 0);   // wrr: still the start residual's
+        }
         if (h.flag == 0 && it < maxit) {
             plan.observe(h.wrr_it, h.it_last, tol2);
             continue;

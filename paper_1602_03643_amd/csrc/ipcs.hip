@@ -172,6 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_add_f32(long long n, double *__restr
         x[i] += static_cast<double>(e[i]);
 }
 
+// x_q += e_q for the first nq of up to three (x, e) pairs, one launch
+struct AddSet {
+    double *x[3];
+    const float *e[3];
+};
+__global__ __launch_bounds__(kBlock) void k_add3_f32(long long n, AddSet a, int nq) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        for (int q = 0; q < nq; ++q) a.x[q][i] += static_cast<double>(a.e[q][i]);
+}
+
 // partial sums of x^2
 __global__ __launch_bounds__(kBlock) void k_sumsq(int n, const double *__restrict__ x, double *part) {
     __shared__ double lds[kBlock / kWave];
@@ -980,15 +991,18 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
         const int rc = bicgstab_solve<float>(s, n, na, rp, ci, val32, w32, bb, xx, inner,
                                              o.maxit, o.check_every, o.time, bw, in, true);
         if (rc == OASIS_EHIP) return rc;
+        AddSet as{};
         for (int q = 0; q < na; ++q) {
             const int k = active[q];
             out[k].iters += in[q].iters;
             out[k].outer += 1;
             out[k].kernel_ms += in[q].kernel_ms;
             out[k].kernel_count += in[q].kernel_count;
-            hipLaunchKernelGGL(k_add_f32, dim3(gv), dim3(kBlock), 0, s, (long long)n, x[k], ir.e32[k]);
-            OASIS_TRY_LAUNCH();
+            as.x[q] = x[k];
+            as.e[q] = ir.e32[k];
         }
+        hipLaunchKernelGGL(k_add3_f32, dim3(gv), dim3(kBlock), 0, s, (long long)n, as, na);
+        OASIS_TRY_LAUNCH();
     }
     int worst = OASIS_OK;
     for (int k = 0; k < nr; ++k)

@@ -1677,6 +1677,38 @@ __global__ __launch_bounds__(kBlock) void k_bi_start0(int n, const T *__restrict
     write_partials<3 * NR>(acc, part, lds);
 }
 
+// k_bi_resid with no residual to recompute (mask_res = 0): r_hat_k = r_k
+// for k in mask_rhat and the partials (r_hat.r, sum wgt r^2, sum wgt b^2)
+// from the vectors as they are, without the product.
+template <typename T, int NR>
+__global__ __launch_bounds__(kBlock) void k_bi_parts(int n, const T *__restrict__ wgt, C3<T> b, const RW<T> *ru,
+                                                     V3<T> rhat, int mask_rhat, double *part) {
+    __shared__ double lds[9 * kBlock / kWave];
+    double acc[3 * NR];
+#pragma unroll
+    for (int k = 0; k < 3 * NR; ++k) acc[k] = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double wd = wgt[i];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const T rk = ru[i * NR + k].r;
+            T hk;
+            if ((mask_rhat >> k) & 1) {
+                rhat.p[k][i] = rk;
+                hk = rk;
+            } else {
+                hk = rhat.p[k][i];
+            }
+            const double rd = rk, bd = b.p[k][i];
+            acc[3 * k + 0] += static_cast<double>(hk) * rd;
+            acc[3 * k + 1] += wd * rd * rd;
+            acc[3 * k + 2] += wd * bd * bd;
+        }
+    }
+    write_partials<3 * NR>(acc, part, lds);
+}
+
 template <typename T>
 void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
     std::memset(&w, 0, sizeof(w));
@@ -1739,8 +1771,12 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         return OASIS_OK;
     };
     auto resid = [&](int mask_res, int mask_rhat, C3<T> src) -> int {
-        hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat, wgt,
-                           cb, src, w.ru, vrh, mask_res, mask_rhat, w.part3);
+        if (mask_res == 0)   // partials only (same grid, so finalize and k_bi_1 read g1 of them)
+            hipLaunchKernelGGL((k_bi_parts<T, NR>), dim3(g1), dim3(kBlock), 0, s, n, wgt, cb, w.ru, vrh, mask_rhat,
+                               w.part3);
+        else
+            hipLaunchKernelGGL((k_bi_resid<T, NR, C>), dim3(g1), dim3(kBlock), 0, s, n, mat, wgt,
+                               cb, src, w.ru, vrh, mask_res, mask_rhat, w.part3);
         OASIS_TRY_LAUNCH();
         return OASIS_OK;
     };
@@ -1761,12 +1797,10 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         OASIS_TRY(resid(all, all, cx));
     }
     OASIS_TRY(finalize(0));
-    OASIS_TRY(pull_state());
-    double wbb[3], tol2[3];
-    for (int k = 0; k < NR; ++k) {
-        wbb[k] = hs[k].wbb;
-        tol2[k] = hs[k].tol2;
-    }
+    // The start residuals are not read back here: k_bi_1 tests them like
+    // any other, and the first poll brings the norms with the states.
+    double wbb[3] = {0, 0, 0}, tol2[3] = {0, 0, 0};
+    bool known = false;
     auto rel = [&](int k, double wrr) { return wbb[k] > 0 ? std::sqrt(wrr / wbb[k]) : std::sqrt(wrr); };
     // Iterations to launch before the next poll.  Each right-hand side's
     // convergence rate (log of the weighted residual per iteration, from
@@ -1781,7 +1815,15 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
         lref[k] = wrr > 0.0 ? std::log(wrr) : 0.0;
         itref[k] = at;
     };
-    for (int k = 0; k < NR; ++k) set_ref(k, hs[k].wrr, 0);
+    auto learn = [&]() {
+        if (known) return;
+        known = true;
+        for (int k = 0; k < NR; ++k) {
+            wbb[k] = hs[k].wbb;
+            tol2[k] = hs[k].tol2;
+            set_ref(k, hs[k].wrr, 0);   // wrr: the start residual's until a finalize(1)
+        }
+    };
     auto observe = [&]() {
         for (int k = 0; k < NR; ++k) {
             if (!hs[k].active || hs[k].it_rec <= itref[k] || !(hs[k].wrr_rec > 0.0) || !std::isfinite(hs[k].wrr_rec))
@@ -1872,6 +1914,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             ++launched;
         }
         OASIS_TRY(pull_state());
+        learn();
         observe();
         if (!hg.pause) {
             if (it < maxit) {
