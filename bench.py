@@ -142,7 +142,7 @@ def device_problem(oa, torch, synth, pr, dev, rcm=False):
 
 def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm=None, pstart=0, amg=None,
                 perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0, amg_theta=0.0,
-                inner_rtol=0.0):
+                inner_rtol=0.0, pressure_delta=0.0):
     """Time `steps` steps after `warmup` untimed ones; returns the handle, the
     results and the final (U, p, phi).  scalars: that many passive scalars
     with Prandtl number 0.71 (D = nu / 0.71), Dirichlet values y on the
@@ -152,7 +152,7 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
     m = pr.mesh
     t0 = time.perf_counter()
     h = oa.IPCS(dm, pat, pr.dt, pr.nu, pr.f, bcd, rtol_u=pr.rtol_u, rtol_p=pr.rtol_p, precision=precision,
-                inner_rtol=inner_rtol, pressure_start=pstart, inner_iters=inner_iters, velocity_update=velocity_update,
+                inner_rtol=inner_rtol, pressure_delta=pressure_delta, pressure_start=pstart, inner_iters=inner_iters, velocity_update=velocity_update,
                 diffusivity=[pr.nu / 0.71] * scalars, convection=convection)
 
     def T(a):
@@ -339,6 +339,8 @@ def main():
                     help="timed steps of the headline configuration with each option beyond the channel runs' "
                          "(inner iterations, consistent update, a passive scalar); 0 skips them")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--pressure-delta", type=float, default=0.0,
+                    help="FP32 pressure CG: residual replacement factor (0: the library's default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path here is single-GPU (no collectives); "
@@ -390,7 +392,8 @@ def main():
                 log("warm start: %s, trained on %s" % (args.weights or warmstart.DEFAULT_WEIGHTS,
                                                        wmeta.get("sizes")))
             w = warm
-        h, res, _ = run_variant(oa, torch, pr, dm, pat, bcd, prec, args.steps, args.warmup, v, w, pstart, amg)
+        h, res, _ = run_variant(oa, torch, pr, dm, pat, bcd, prec, args.steps, args.warmup, v, w, pstart, amg,
+                                pressure_delta=args.pressure_delta)
         results[v] = res
         handles[v] = h
     # headline: the fastest variant whose pressure solve starts from phi_prev

@@ -350,8 +350,12 @@ int oasis_amg_vcycle(void *stream, oasis_amg *h, const double *r, double *z);
  * b (device double [n]), x (device double [n], in: x0, out: solution).
  * opt: rtol, maxit, check_every and OASIS_KRYLOV_TIME (a solve stopped at
  * maxit then repeats its last cycle maxit times between two HIP events,
- * kernel_ms / kernel_count) are used; the CG is FP64 whatever
- * opt->precision says.  Uses the uploaded workspace: calls on one handle
+ * kernel_ms / kernel_count) are used.  With opt->precision OASIS_F32 on an
+ * FP32 handle (and no timing) the CG itself is mixed: FP32 direction,
+ * product and recursive residual, FP64 iterate and dot products, and an
+ * FP64 residual b - A x that replaces the recursive one each time the
+ * latter has fallen by opt->inner_rtol (0 = 1e-3) and decides convergence;
+ * otherwise the CG is FP64.  Uses the uploaded workspace: calls on one handle
  * must not overlap.  Synchronises `stream`. */
 int oasis_amg_pcg(void *stream, oasis_amg *h, const double *b, double *x, const oasis_krylov_opts *opt,
                   oasis_krylov_stats *stats);
@@ -378,7 +382,8 @@ typedef struct {
                                  not fix it): OASIS_PSTART_PREV (phi_prev, default) or
                                  OASIS_PSTART_ZERO (phi_0 = 0: solving for p from p*) */
     double pressure_delta;    /* F32 mode: the pressure CG replaces its FP32 residual by the FP64
-                                 one each time the former fell by this factor (0 = 0.03) */
+                                 one each time the former fell by this factor (0 = 0.03); with a
+                                 multigrid handle attached the pressure CG is FP64 */
     oasis_tuning tuning;      /* Krylov storage and kernel shapes of the step's solves */
     int32_t inner_iters;      /* Alg. 1's inner velocity-pressure iterations (0 = 1, at most 16):
                                  the coefficient matrix and the right-hand side's explicit part

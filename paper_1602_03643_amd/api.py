@@ -326,8 +326,12 @@ class AMG:
         L.check(_lib().oasis_amg_vcycle(_stream(stream), self.handle, _p(r), _p(z)), "oasis_amg_vcycle")
         return z
 
-    def pcg(self, b, x, rtol=1e-8, maxit=1000, check_every=0, time_kernel=False, stream=None, raise_on=True):
-        o = _opts(rtol, maxit, L.F64, 0.0, 0, check_every, time_kernel)
+    def pcg(self, b, x, rtol=1e-8, maxit=1000, check_every=0, time_kernel=False, stream=None, raise_on=True,
+            precision=L.F64, inner_rtol=0.0):
+        """precision F32 (FP32 handles): the mixed-precision CG, whose FP64
+        residual replaces the recursive one every inner_rtol reduction
+        (0: the library's default)."""
+        o = _opts(rtol, maxit, precision, inner_rtol, 0, check_every, time_kernel)
         st = L.KrylovStats()
         rc = _lib().oasis_amg_pcg(_stream(stream), self.handle, _p(b), _p(x), C.byref(o), C.byref(st))
         if raise_on:

@@ -263,6 +263,43 @@ __global__ __launch_bounds__(kBlock) void k_apcg_update(int n, const RP<double> 
     }
 }
 
+// The FP32 form of k_apcg_update: alpha in FP64 from the partials, the
+// iterate x += alpha p in FP64, the recursive residual r -= alpha q and the
+// cycle's y0 = w0 .* r in FP32.
+__global__ __launch_bounds__(kBlock) void k_apcg_update32(int n, const RP<float> *__restrict__ nxt,
+                                                          const float *__restrict__ q, double *__restrict__ x,
+                                                          float *__restrict__ r, const float *__restrict__ wd0,
+                                                          float *__restrict__ y0, const double *partIn, int nIn,
+                                                          CGState *st, int it) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (stopped(&st->flag)) return;
+    double v[2];
+    read_partials<2>(partIn, nIn, v, lds);
+    const double pq = v[0];
+    if (!(pq > 0.0) || !finite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->flag = finite(pq) ? 2 : 3;
+            st->it_done = it;
+        }
+        return;
+    }
+    const double a = st->rr[it & 1] / pq;
+    const float af = static_cast<float>(a);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        x[i] += a * static_cast<double>(nxt[i].p);
+        const float ri = r[i] - af * q[i];
+        r[i] = ri;
+        if (y0) y0[i] = wd0[i] * ri;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_to_f32(int n, const double *__restrict__ a, float *__restrict__ b) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = static_cast<float>(a[i]);
+}
+
 template <class C>
 int csr_grid(int n) { return grid_for(n, rows_per_block<C>(), 1 << 20); }
 
@@ -291,15 +328,15 @@ int ell_grid(int n, int cap) { return grid_for(n, kBlock / 2, cap); }
 
 }  // namespace
 
-template <typename T>
-int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_ready, double *z, int zs,
+template <typename T, typename TB, typename TO>
+int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const TB *r, bool y0_ready, TO *z, int zs,
                const double *wgt, double *part, int *gpost, const int *flag, int grid_cap) {
     const int L = c.nlev;
     const bool ell0 = c.cols.any() && c.e;
     const bool dict = c.cols.pid != nullptr;
     if (L == 1) {
         const int g = std::min(grid_for(c.nc, kBlock / kWave, 1 << 20), part ? grid_cap : 1 << 20);
-        hipLaunchKernelGGL((k_amg_dense<T, double, double>), dim3(g), dim3(kBlock), 0, s, c.nc, c.cinv, r, z, zs,
+        hipLaunchKernelGGL((k_amg_dense<T, TB, TO>), dim3(g), dim3(kBlock), 0, s, c.nc, c.cinv, r, z, zs,
                            wgt, part, flag);
         OASIS_TRY_LAUNCH();
         if (gpost) *gpost = g;
@@ -307,7 +344,7 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_rea
     }
     if (!y0_ready) {
         const AmgDevLevel<T> &v = c.lv[0];
-        hipLaunchKernelGGL((k_amg_scale<T, double>), dim3(grid_for(v.n, kBlock, 8192)), dim3(kBlock), 0, s, v.n,
+        hipLaunchKernelGGL((k_amg_scale<T, TB>), dim3(grid_for(v.n, kBlock, 8192)), dim3(kBlock), 0, s, v.n,
                            v.wd, r, v.y, flag);
         OASIS_TRY_LAUNCH();
     }
@@ -317,17 +354,17 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_rea
         if (l == 0 && ell0) {
             const int g = ell_grid(v.n, 1 << 20);
             if (dict)
-                hipLaunchKernelGGL((k_amg_pre_ell<T, double, true>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols, c.e,
+                hipLaunchKernelGGL((k_amg_pre_ell<T, TB, true>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols, c.e,
                                    v.y, r, v.t, flag);
             else
-                hipLaunchKernelGGL((k_amg_pre_ell<T, double, false>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols,
+                hipLaunchKernelGGL((k_amg_pre_ell<T, TB, false>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols,
                                    c.e, v.y, r, v.t, flag);
             OASIS_TRY_LAUNCH();
         } else {
             OASIS_TRY(with_lanes(v.alanes, [&](auto cfg) -> int {
                 using C = decltype(cfg);
                 if (l == 0)
-                    hipLaunchKernelGGL((k_amg_pre_csr<T, double, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s,
+                    hipLaunchKernelGGL((k_amg_pre_csr<T, TB, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s,
                                        v.n, v.rp, v.ci, v.val, v.y, r, v.t, flag);
                 else
                     hipLaunchKernelGGL((k_amg_pre_csr<T, T, C>), dim3(csr_grid<C>(v.n)), dim3(kBlock), 0, s, v.n,
@@ -369,10 +406,10 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_rea
         if (l == 0 && ell0) {
             const int g = ell_grid(v.n, part ? grid_cap : 1 << 20);
             if (dict)
-                hipLaunchKernelGGL((k_amg_post_ell<T, double, double, true>), dim3(g), dim3(kBlock), 0, s, v.n,
+                hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, true>), dim3(g), dim3(kBlock), 0, s, v.n,
                                    c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
             else
-                hipLaunchKernelGGL((k_amg_post_ell<T, double, double, false>), dim3(g), dim3(kBlock), 0, s, v.n,
+                hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, false>), dim3(g), dim3(kBlock), 0, s, v.n,
                                    c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
             OASIS_TRY_LAUNCH();
             if (gpost) *gpost = g;
@@ -381,7 +418,7 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_rea
                 using C = decltype(cfg);
                 if (l == 0) {
                     const int g = std::min(csr_grid<C>(v.n), part ? grid_cap : 1 << 20);
-                    hipLaunchKernelGGL((k_amg_post_csr<T, double, double, C>), dim3(g), dim3(kBlock), 0, s, v.n,
+                    hipLaunchKernelGGL((k_amg_post_csr<T, TB, TO, C>), dim3(g), dim3(kBlock), 0, s, v.n,
                                        v.rp, v.ci, v.val, v.wd, r, v.t, z, zs, wgt, part, flag);
                     if (gpost) *gpost = g;
                 } else {
@@ -528,6 +565,107 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
     return rc;
 }
 
+int amg_pcg_mixed(hipStream_t s, int n, const int *rp, const int *ci, const double *val, const double *e64,
+                  const AmgCycle<float> &c, const double *wgt, const double *b, double *x, double rtol,
+                  double delta, int maxit, int check_every, double *r64, float *r32, CGWork<float> &w,
+                  SolveOut &out) {
+    out = SolveOut();
+    const int cap = w.tun.grid_cap;
+    const EllCols cols64 = (c.cols.any() && e64) ? c.cols : EllCols{};
+    const bool ell32 = c.cols.any() && c.e;
+    const AmgDevLevel<float> &l0 = c.lv[0];
+    double *pv = w.partB;           // partials of the cycle's last kernel: (r.z, sum wgt r^2)
+    double *pq = w.partA;           // partials of the product kernel: (p.q, 0)
+    int gpost = 0, g1 = 0;
+    auto zslot = [&](int at) { return reinterpret_cast<float *>(w.pair[at & 1]); };   // z in the pair's r
+    const bool smooth0 = c.nlev > 1;
+    // FP64 residual b - A x into r64 and the state (mode 0 also sets the
+    // tolerance), its FP32 copy, and the next replacement armed at delta
+    auto replace = [&](int mode) -> int {
+        OASIS_TRY(cg_residual_state(s, cap, n, rp, ci, val, cols64, wgt, b, x, r64, 1, pv, w.st, rtol * rtol, mode,
+                                    delta));
+        hipLaunchKernelGGL(k_amg_to_f32, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, r64, r32);
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    };
+    auto precondition = [&](int at, bool y0_ready) -> int {
+        return amg_vcycle<float, float, float>(s, c, r32, y0_ready, zslot(at), 2, wgt, pv, &gpost, &w.st->flag,
+                                               cap);
+    };
+    int restart_at = 0;
+    auto iterate = [&](int itj) -> int {
+        OASIS_TRY(cg_product_launch(s, cap, n, l0.rp, l0.ci, l0.val, ell32 ? c.cols : EllCols{},
+                                    ell32 ? c.e : nullptr, w.pair[itj & 1], w.pair[(itj + 1) & 1], w.q, pv, gpost,
+                                    2, w.st, itj, itj == restart_at ? 1 : 0, pq, &g1));
+        hipLaunchKernelGGL(k_apcg_update32, dim3(grid_for(n, kBlock, kMaxPartials)), dim3(kBlock), 0, s, n,
+                           w.pair[(itj + 1) & 1], w.q, x, r32, smooth0 ? l0.wd : nullptr, smooth0 ? l0.y : nullptr,
+                           pq, g1, w.st, itj);
+        OASIS_TRY_LAUNCH();
+        return precondition(itj + 1, smooth0);
+    };
+    // as in amg_pcg_solve, the start residual is read back with the first poll
+    OASIS_TRY(replace(0));
+    OASIS_TRY(precondition(0, false));
+    CGState h;
+    double wbb = 0.0, tol2 = 0.0;
+    bool first = true;
+    auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
+    AmgPlan plan(check_every);
+    int it = 0, rc = OASIS_OK;
+    while (true) {
+        const int m = std::min(plan.next, maxit - it);
+        for (int j = 0; j < m; ++j) OASIS_TRY(iterate(it + j));
+        it += m;
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
+        if (first) {
+            first = false;
+            wbb = h.wbb;
+            tol2 = h.tol2;
+            if (h.flag == 0) plan.restart(h.wrr, 0);
+        }
+        if (h.flag == 0 && it < maxit) {
+            plan.observe(h.wrr_it, h.it_last, std::max(h.upd2, tol2));
+            continue;
+        }
+        if (h.flag == 2 || h.flag == 3) {
+            out.iters = h.it_done;
+            out.status = rc = h.flag == 2 ? OASIS_EBREAKDOWN : OASIS_ENAN;
+            out.rel_res = NAN;
+            break;
+        }
+        // converged candidate, replacement due (flag 4) or maxit: the FP64
+        // residual replaces the recursive one and decides
+        const int at = h.flag == 0 ? it : h.it_done;
+        OASIS_TRY(replace(1));
+        OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
+        out.outer += 1;
+        out.rel_res = rel(h.wrr);
+        if (!std::isfinite(h.wrr)) {
+            out.iters = at;
+            out.status = rc = OASIS_ENAN;
+            break;
+        }
+        if (h.wrr <= tol2) {
+            out.iters = at;
+            out.status = rc = OASIS_OK;
+            break;
+        }
+        if (at >= maxit) {
+            out.iters = at;
+            out.status = rc = OASIS_ENOTCONV;
+            break;
+        }
+        // continue from the replaced residual; the direction is kept
+        out.replacements += 1;
+        OASIS_TRY(precondition(at, false));
+        it = at;
+        plan.restart(h.wrr, at);
+    }
+    return rc;
+}
+
+template int amg_vcycle<float, float, float>(hipStream_t, const AmgCycle<float> &, const float *, bool, float *,
+                                             int, const double *, double *, int *, const int *, int);
 template int amg_vcycle<double>(hipStream_t, const AmgCycle<double> &, const double *, bool, double *, int,
                                 const double *, double *, int *, const int *, int);
 template int amg_vcycle<float>(hipStream_t, const AmgCycle<float> &, const double *, bool, double *, int,

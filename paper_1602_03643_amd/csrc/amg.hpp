@@ -76,14 +76,14 @@ struct AmgCycle {
     const T *cinv = nullptr;
 };
 
-// One V(1,1) cycle z = M^{-1} r on level 0: r is FP64 (the CG residual), z
-// is written as FP64 at z[i * zs].  y0_ready: level 0's y = w .* r is
+// One V(1,1) cycle z = M^{-1} r on level 0: r (type TB, the CG residual)
+// is read and z written (type TO) at z[i * zs].  y0_ready: level 0's y = w .* r is
 // already in c.lv[0].y (else the cycle forms it first).  With part (nullable), the last kernel
 // writes per-block partials (r.z, sum wgt r^2) and returns its grid in
 // *gpost.  flag (nullable): a device int; while it is nonzero every kernel
 // returns at once.  grid_cap bounds the partial-writing kernel's grid.
-template <typename T>
-int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const double *r, bool y0_ready, double *z, int zs,
+template <typename T, typename TB = double, typename TO = double>
+int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const TB *r, bool y0_ready, TO *z, int zs,
                const double *wgt, double *part, int *gpost, const int *flag, int grid_cap);
 
 // CG on level 0's matrix (FP64 ELL values e64 with c's columns) preconditioned
@@ -95,10 +95,27 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
                   const AmgCycle<T> &c, const double *wgt, const double *b, double *x, double rtol, int maxit,
                   int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out);
 
+// Mixed-precision CG around an FP32 cycle: the direction, the product with
+// level 0's FP32 ELL copy e32 (CSR level 0 of the cycle without it) and the
+// recursive residual r32 are FP32, the iterate x and the dot products FP64.
+// The FP64 residual b - A x (e64 / val, into r64) replaces the recursive
+// one each time the latter has fallen by delta since the last replacement,
+// and whenever it claims convergence; the direction is kept.  The stopping
+// test is on that FP64 residual.  w: FP32 CG workspace.
+int amg_pcg_mixed(hipStream_t s, int n, const int *rp, const int *ci, const double *val, const double *e64,
+                  const AmgCycle<float> &c, const double *wgt, const double *b, double *x, double rtol,
+                  double delta, int maxit, int check_every, double *r64, float *r32, CGWork<float> &w,
+                  SolveOut &out);
+
 // The pressure solve of an IPCS step through an uploaded handle: CG on the
-// handle's matrix with its cycle, weights wgt for the stopping test.
+// handle's matrix with its cycle, weights wgt for the stopping test; with
+// mixed and an FP32 handle, amg_pcg_mixed with replacement factor delta
+// (0: kAmgMixedDelta).
 int amg_handle_solve(hipStream_t s, oasis_amg *h, const double *wgt, const double *b, double *x, double rtol,
-                     int maxit, SolveOut &out);
+                     int maxit, SolveOut &out, bool mixed = false, double delta = 0.0);
+
+// Replacement factor of amg_pcg_mixed when none is given.
+constexpr double kAmgMixedDelta = 1e-3;
 
 // Whether h was built (and uploaded) on this matrix and null vector as a
 // singular pressure matrix.

@@ -21,6 +21,8 @@ struct AmgImage {
     AmgCycle<double> c64;
     AmgCycle<float> c32;
     CGWork<double> cg;
+    CGWork<float> cg32;                         // the mixed-precision CG (FP32 handles)
+    float *r32 = nullptr;                       // its FP32 recursive residual
     double *r = nullptr;                        // CG residual
     double *ones = nullptr;                     // unit norm weights of the stand-alone solve
     int *tmp = nullptr;
@@ -128,6 +130,10 @@ void carve_amg(Carver &c, const oasis_amg &h, AmgImage &d) {
         if (h.f32) d.e32 = c.take<float>(static_cast<size_t>(n) * kEll);
     }
     carve_cg<double>(c, n, d.cg);
+    if (h.f32) {
+        carve_cg<float>(c, n, d.cg32);
+        d.r32 = c.take<float>(n);
+    }
     d.r = c.take<double>(n);
     d.ones = c.take<double>(n);
     d.tmp = c.take<int>(8);
@@ -200,9 +206,12 @@ int upload_levels(hipStream_t s, oasis_amg &h, AmgCycle<T> &cy) {
 namespace oasis {
 
 int amg_handle_solve(hipStream_t s, oasis_amg *h, const double *wgt, const double *b, double *x, double rtol,
-                     int maxit, SolveOut &out) {
+                     int maxit, SolveOut &out, bool mixed, double delta) {
     if (!h || !h->uploaded) return OASIS_EINVAL;
     AmgImage &d = h->d;
+    if (h->f32 && mixed)
+        return amg_pcg_mixed(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, wgt, b, x, rtol,
+                             delta > 0.0 ? delta : kAmgMixedDelta, maxit, 0, d.r, d.r32, d.cg32, out);
     if (h->f32)
         return amg_pcg_solve<float>(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, wgt, b, x, rtol, maxit, 0, false,
                                     d.r, d.cg, out);
@@ -294,9 +303,9 @@ extern "C" int oasis_amg_upload(void *stream, oasis_amg *h, void *ws, size_t ws_
     carve_amg(c, *h, h->d);
     if (!c.ok) return OASIS_EWORKSPACE;
     AmgImage &d = h->d;
-    d.cg.tun = h->tun;
+    d.cg.tun = d.cg32.tun = h->tun;
     if (!h->stage.h) stage_alloc(h->stage);
-    d.cg.stage = h->stage;
+    d.cg.stage = d.cg32.stage = h->stage;
     hipLaunchKernelGGL(k_amg_fill, dim3(grid_for(h->n, kBlock, 8192)), dim3(kBlock), 0, s, h->n, d.ones, 1.0);
     OASIS_TRY_LAUNCH();
     if (h->ell_fits) {
@@ -365,7 +374,11 @@ extern "C" int oasis_amg_pcg(void *stream, oasis_amg *h, const double *b, double
     const bool timed = (opt->flags & OASIS_KRYLOV_TIME) != 0;
     AmgImage &d = h->d;
     int rc;
-    if (h->f32)
+    if (h->f32 && opt->precision == OASIS_F32 && !timed)
+        rc = amg_pcg_mixed(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, d.ones, b, x, opt->rtol,
+                           opt->inner_rtol > 0.0 ? opt->inner_rtol : kAmgMixedDelta, maxit, opt->check_every, d.r,
+                           d.r32, d.cg32, so);
+    else if (h->f32)
         rc = amg_pcg_solve<float>(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, d.ones, b, x, opt->rtol, maxit,
                                   opt->check_every, timed, d.r, d.cg, so);
     else
@@ -374,7 +387,7 @@ extern "C" int oasis_amg_pcg(void *stream, oasis_amg *h, const double *b, double
     if (rc == OASIS_EHIP) return rc;
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     stats->iters = so.iters;
-    stats->outer_iters = 0;
+    stats->outer_iters = so.outer;
     stats->status = so.status;
     stats->restarts = so.replacements;
     stats->rel_res = so.rel_res;

@@ -1824,6 +1824,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         SolveOut spi;
         int rc_p;
         if (h->amg)
+            // FP64 CG around the handle's cycle: the mixed CG (amg_pcg_mixed)
+            // needs a cycle per residual replacement, which at the step's
+            // tolerances costs more than its FP32 products save
             rc_p = amg_handle_solve(s, h->amg, h->wK, h->bs, h->xs, ko.rtol, ko.maxit, spi);
         else if (h->mixed)
             rc_p = cg_mixed_solve(s, n, h->rp, h->ci, h->Ks, h->Ks32, h->wK, h->wK32, h->vnull32, h->vscale, h->bs,

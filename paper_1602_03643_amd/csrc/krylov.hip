@@ -1146,32 +1146,49 @@ int cg_mixed_solve(hipStream_t s, int n, const int *rp, const int *ci, const dou
     });
 }
 
-int cg_product_launch(hipStream_t s, int cap, int n, const int *rp, const int *ci, const double *val,
-                      const EllCols &cols, const double *eval, const RP<double> *cur, RP<double> *nxt, double *q,
-                      const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
-                      double *partOut, int *grid) {
+template <typename T>
+static int product_launch(hipStream_t s, int cap, int n, const int *rp, const int *ci, const T *val,
+                          const EllCols &cols, const T *eval, const RP<T> *cur, RP<T> *nxt, T *q,
+                          const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
+                          double *partOut, int *grid) {
     if (cols.any() && eval) {
-        *grid = launch_p1_ell<double, kBlock>(s, cap, n, cols, eval, cur, nxt, q, partIn, nIn, stride, st, it,
-                                              beta_zero, static_cast<const double *>(nullptr), partOut);
+        *grid = launch_p1_ell<T, kBlock>(s, cap, n, cols, eval, cur, nxt, q, partIn, nIn, stride, st, it,
+                                         beta_zero, static_cast<const T *>(nullptr), partOut);
     } else {
         using C = Cfg4x4x1;
         *grid = grid_for(n, rows_per_block<C>(), kMaxPartials);
-        hipLaunchKernelGGL((k_cg_p1<double, C, kBlock>), dim3(*grid), dim3(kBlock), 0, s, n, rp, ci, val, cur, nxt,
-                           q, partIn, nIn, stride, st, it, beta_zero, static_cast<const double *>(nullptr), partOut);
+        hipLaunchKernelGGL((k_cg_p1<T, C, kBlock>), dim3(*grid), dim3(kBlock), 0, s, n, rp, ci, val, cur, nxt,
+                           q, partIn, nIn, stride, st, it, beta_zero, static_cast<const T *>(nullptr), partOut);
     }
     OASIS_TRY_LAUNCH();
     return OASIS_OK;
 }
 
+int cg_product_launch(hipStream_t s, int cap, int n, const int *rp, const int *ci, const double *val,
+                      const EllCols &cols, const double *eval, const RP<double> *cur, RP<double> *nxt, double *q,
+                      const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
+                      double *partOut, int *grid) {
+    return product_launch<double>(s, cap, n, rp, ci, val, cols, eval, cur, nxt, q, partIn, nIn, stride, st, it,
+                                  beta_zero, partOut, grid);
+}
+
+int cg_product_launch(hipStream_t s, int cap, int n, const int *rp, const int *ci, const float *val,
+                      const EllCols &cols, const float *eval, const RP<float> *cur, RP<float> *nxt, float *q,
+                      const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
+                      double *partOut, int *grid) {
+    return product_launch<float>(s, cap, n, rp, ci, val, cols, eval, cur, nxt, q, partIn, nIn, stride, st, it,
+                                 beta_zero, partOut, grid);
+}
+
 int cg_residual_state(hipStream_t s, int cap, int n, const int *rp, const int *ci, const double *val,
                       const EllCols &cols, const double *wgt, const double *b, const double *x, double *r, int rs,
-                      double *part, CGState *st, double rtol2, int mode) {
+                      double *part, CGState *st, double rtol2, int mode, double upd_factor) {
     using C = Cfg4x4x1;
     const int g = grid_for(n, rows_per_block<C>(), cap);
     hipLaunchKernelGGL((k_cg_init<double, C>), dim3(g), dim3(kBlock), 0, s, n, rp, ci, val, cols, wgt, b, x, r, rs,
                        part);
     OASIS_TRY_LAUNCH();
-    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, part, g, st, rtol2, mode, 0.0);
+    hipLaunchKernelGGL(k_cg_finalize, dim3(1), dim3(kBlock), 0, s, part, g, st, rtol2, mode, upd_factor);
     OASIS_TRY_LAUNCH();
     return OASIS_OK;
 }

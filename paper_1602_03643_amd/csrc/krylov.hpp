@@ -200,13 +200,17 @@ int cg_product_launch(hipStream_t s, int cap, int n, const int *rp, const int *c
                       const EllCols &cols, const double *eval, const RP<double> *cur, RP<double> *nxt, double *q,
                       const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
                       double *partOut, int *grid);
+int cg_product_launch(hipStream_t s, int cap, int n, const int *rp, const int *ci, const float *val,
+                      const EllCols &cols, const float *eval, const RP<float> *cur, RP<float> *nxt, float *q,
+                      const double *partIn, int nIn, int stride, CGState *st, int it, int beta_zero,
+                      double *partOut, int *grid);
 
 // r[i * rs] = b - A x with FP64 values (columns from cols when given), then
 // the CG state's norms: mode 0 starts a solve (tol2 = rtol2 sum wgt b^2),
 // mode 1 refreshes wrr only; the flag is cleared.
 int cg_residual_state(hipStream_t s, int cap, int n, const int *rp, const int *ci, const double *val,
                       const EllCols &cols, const double *wgt, const double *b, const double *x, double *r, int rs,
-                      double *part, CGState *st, double rtol2, int mode);
+                      double *part, CGState *st, double rtol2, int mode, double upd_factor = 0.0);
 
 // Weighted residual of x for the scaled system: r = b - Ms x, returns
 // (sum wgt r^2, sum wgt b^2) on the host.  Uses w's buffers.

@@ -191,6 +191,36 @@ def test_amg_pcg_f32_cycle_meets_fp64_tolerance(oa):
     assert its[1] <= its[0] + 3
 
 
+@pytest.mark.parametrize("delta", [0.0, 0.1])
+def test_amg_pcg_mixed_cg_meets_fp64_tolerance(oa, delta):
+    """The FP32 CG around the FP32 cycle (FP64 iterate, FP64 residual
+    replacing the recursive one every delta reduction and at the end) stops
+    on the FP64 true residual, which the host recomputes here from K, at
+    about the iteration count of the FP64 CG with the same cycle."""
+    mesh = synth.channel(33, 33, 25)
+    say("amg pcg mixed cg", mesh.name, "delta", delta)
+    h32, K0, s, keep32 = _device_amg(oa, mesh, oa.F32)
+    rng = np.random.default_rng(6)
+    b = rng.normal(size=mesh.n_dof)
+    b -= (b @ s) / (s @ s) * s
+    for rtol in (1e-8, 1e-11):
+        x = torch.zeros(mesh.n_dof, dtype=torch.float64, device=dev())
+        ref = h32.pcg(T(b), x, rtol=rtol, maxit=300)
+        x64 = x.cpu().numpy()
+        x = torch.zeros(mesh.n_dof, dtype=torch.float64, device=dev())
+        out = h32.pcg(T(b), x, rtol=rtol, maxit=300, precision=oa.F32, inner_rtol=delta)
+        xg = x.cpu().numpy()
+        assert out["rc"] == 0 and ref["rc"] == 0
+        true = np.linalg.norm(b - K0 @ xg) / np.linalg.norm(b)
+        say("rtol %g: FP64 CG %d it., mixed CG %d it. (%d replacements), true residual %.3g"
+            % (rtol, ref["iters"], out["iters"], out["restarts"], true))
+        assert true <= 1.0001 * rtol
+        assert out["iters"] <= ref["iters"] + 3
+        assert out["outer_iters"] >= 1
+        proj = lambda v: v - (v @ s) / (s @ s) * s  # noqa: E731
+        assert rel(proj(xg), proj(x64)) <= 1e3 * rtol
+
+
 def _run_steps(oa, prob, steps, rtol, precision, amg_precision=None):
     m = prob.mesh
     dm, pat, _ = device_mesh(m)
