@@ -1370,6 +1370,13 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, const RW<T> *r
             ev[k] = 2;
         any |= ev[k];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < NR; ++k)
+            if ((active >> k) & 1) {
+                st[k].wrr_rec = v[3 * k + 1];
+                st[k].it_rec = it;
+            }
+    }
     if (any) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             for (int k = 0; k < NR; ++k)
@@ -1386,11 +1393,7 @@ __global__ __launch_bounds__(kBlock) void k_bi_1(int n, Mat<T> m, const RW<T> *r
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int k = 0; k < NR; ++k)
-            if ((active >> k) & 1) {
-                st[k].rho[it & 1] = v[3 * k];
-                st[k].wrr_rec = v[3 * k + 1];
-                st[k].it_rec = it;
-            }
+            if ((active >> k) & 1) st[k].rho[it & 1] = v[3 * k];
     }
     double acc[NR];
 #pragma unroll
@@ -1593,7 +1596,10 @@ __global__ __launch_bounds__(kBlock) void k_bi_3(int n, const T *__restrict__ wg
     if (any) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             for (int k = 0; k < NR; ++k)
-                if (ev[k]) st[k].event = ev[k];
+                if (ev[k]) {
+                    st[k].event = ev[k];
+                    st[k].wrr_rec = v[3 * k + 2];   // weighted |s|^2
+                }
             bi_pause(glob, 3, it);
         }
         return;
@@ -1748,7 +1754,7 @@ void carve_bi(Carver &c, int n, int nrhs, BiWork<T> &w) {
 template <typename T, int NR, class C>
 static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *val, const T *wgt,
                   const T *const *b, T *const *x, double rtol, int maxit, int check_every,
-                  bool time_kernel, BiWork<T> &w, SolveOut *out, bool x_zero) {
+                  bool time_kernel, BiWork<T> &w, SolveOut *out, bool inner) {
     const int g1 = grid_for(n, rows_per_block<C>(), w.tun.grid_cap);
     const int g2 = grid_for(n, kBlock, w.tun.grid_cap);
     const int gv = grid_for(n, kBlock, 4096);
@@ -1805,7 +1811,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     };
     const int all = (1 << NR) - 1;
     OASIS_TRY(push_state());
-    if (x_zero) {
+    if (inner) {
         // the grid of the product kernels, whose partial count finalize reads
         hipLaunchKernelGGL((k_bi_start0<T, NR>), dim3(g1), dim3(kBlock), 0, s, n, wgt, cb, vx, w.ru, vrh, w.part3);
         OASIS_TRY_LAUNCH();
@@ -1960,6 +1966,20 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             int cands = 0;
             for (int k = 0; k < NR; ++k)
                 if (hs[k].active && hs[k].event == 1) cands |= 1 << k;
+            if (cands && inner) {
+                // the recursive residual is trusted (the caller's FP64 residual decides)
+                for (int k = 0; k < NR; ++k) {
+                    if (!((cands >> k) & 1)) continue;
+                    hs[k].active = 0;
+                    out[k].status = OASIS_OK;
+                    out[k].iters = pit;
+                    out[k].rel_res = rel(k, hs[k].wrr_rec);
+                }
+                cands = 0;
+            }
+            // a check leaves in part3 the partials of every residual as it
+            // now is (k_bi_resid sums all right-hand sides)
+            const bool checked = cands != 0;
             if (cands) {
                 OASIS_TRY(resid(cands, 0, cx));
                 OASIS_TRY(finalize(1));
@@ -1992,8 +2012,15 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             hg = BiGlobal{};
             if (n_active() == 0) break;
             OASIS_TRY(push_state());
-            OASIS_TRY(resid(0, mask_rhat, cx));
-            part3_count = g1;
+            // k_bi_1 of pit reads partials of the residuals as they now are:
+            // those of k_bi_3 of pit - 1, of the check, or (r_hat reset on a
+            // restart) of a partials pass
+            if (mask_rhat) {
+                OASIS_TRY(resid(0, mask_rhat, cx));
+                part3_count = g1;
+            } else if (checked) {
+                part3_count = g1;
+            }
             it = pit;
             phase = 1;
             next = plan(it);
@@ -2001,6 +2028,26 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             int cands = 0;
             for (int k = 0; k < NR; ++k)
                 if (hs[k].active && hs[k].event == 5) cands |= 1 << k;
+            if (inner) {
+                // x += alpha p in place, on the norm of s alone
+                hipLaunchKernelGGL((k_bi_xs<T, NR>), dim3(gv), dim3(kBlock), 0, s, n, cx, cp, vx, w.st, pit, cands);
+                OASIS_TRY_LAUNCH();
+                for (int k = 0; k < NR; ++k) {
+                    if (!((cands >> k) & 1)) continue;
+                    hs[k].active = 0;
+                    out[k].status = OASIS_OK;
+                    out[k].iters = pit + 1;
+                    out[k].rel_res = rel(k, hs[k].wrr_rec);
+                }
+                for (int k = 0; k < NR; ++k) hs[k].event = 0;
+                hg = BiGlobal{};
+                if (n_active() == 0) break;
+                OASIS_TRY(push_state());
+                it = pit;
+                phase = 3;
+                next = plan(it);
+                continue;
+            }
             hipLaunchKernelGGL((k_bi_xs<T, NR>), dim3(gv), dim3(kBlock), 0, s, n, cx, cp, vxs,
                                w.st, pit, cands);
             OASIS_TRY_LAUNCH();
@@ -2045,17 +2092,17 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
 template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
-                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out, bool x_zero) {
+                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out, bool inner) {
     return with_cfg([&](auto c) {
         using C = decltype(c);
         if (nrhs == 1)
             return bi_run<T, 1, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out,
-                                   x_zero);
+                                   inner);
         if (nrhs == 2)
             return bi_run<T, 2, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out,
-                                   x_zero);
+                                   inner);
         return bi_run<T, 3, C>(s, n, rp, ci, val, wgt, b, x, rtol, maxit, check_every, time_kernel, w, out,
-                               x_zero);
+                               inner);
     });
 }
 

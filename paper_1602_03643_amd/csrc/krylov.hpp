@@ -133,11 +133,15 @@ int cg_solve(hipStream_t s, int n, const int *rp, const int *ci, const T *val, c
              CGWork<T> &w, SolveOut &out);
 
 // BiCGStab for nrhs systems with the column-scaled matrix As (right Jacobi).
-// x_zero: start from x = 0, which the solve writes itself (r = b, no product).
+// inner: the solve is the inner one of a refinement loop.  It starts from
+// x = 0, which it writes itself (r = b, no product), and stops on its
+// recursive residual (or, at an s-stage exit, on the norm of s) without
+// confirming it by an explicit residual: the caller's FP64 residual
+// decides.
 template <typename T>
 int bicgstab_solve(hipStream_t s, int n, int nrhs, const int *rp, const int *ci, const T *val,
                    const T *wgt, const T *const *b, T *const *x, double rtol, int maxit,
-                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out, bool x_zero = false);
+                   int check_every, bool time_kernel, BiWork<T> &w, SolveOut *out, bool inner = false);
 
 // Mixed-precision CG with reliable updates on the scaled system: FP32
 // matrix/vectors inside the iteration, FP64 solution accumulator, and an
