@@ -399,17 +399,27 @@ class IPCS:
         """U1, U2, Un: [dim, n] float64; p, phi: [n] (updated in place).
         Scalars: C1, Cn [n_scalars, n], C_bc [n_scalars, n_bc]."""
         st = L.State()
-        for a in range(self.n_scalars):
-            st.C1[a] = C1[a].data_ptr()
-            st.Cn[a] = Cn[a].data_ptr()
-            if C_bc is not None:
-                st.C_bc[a] = C_bc[a].data_ptr()
+
+        def rows(t, count):
+            # the addresses of t[0], t[1], ... without building row views
+            if t.dim() == 1:
+                return [t.data_ptr()]
+            base, step = t.data_ptr(), t.stride(0) * t.element_size()
+            return [base + k * step for k in range(count)]
+
+        if self.n_scalars:
+            c1, cn = rows(C1, self.n_scalars), rows(Cn, self.n_scalars)
+            cb = rows(C_bc, self.n_scalars) if C_bc is not None else None
+            for a in range(self.n_scalars):
+                st.C1[a], st.Cn[a] = c1[a], cn[a]
+                if cb is not None:
+                    st.C_bc[a] = cb[a]
+        u1, u2, un = rows(U1, self.dim), rows(U2, self.dim), rows(Un, self.dim)
+        ui = rows(UI, self.dim) if UI is not None else None
         for k in range(self.dim):
-            st.U1[k] = U1[k].data_ptr()
-            st.U2[k] = U2[k].data_ptr()
-            st.Un[k] = Un[k].data_ptr()
-            if UI is not None:
-                st.UI[k] = UI[k].data_ptr()
+            st.U1[k], st.U2[k], st.Un[k] = u1[k], u2[k], un[k]
+            if ui is not None:
+                st.UI[k] = ui[k]
         st.p = p.data_ptr()
         st.phi = phi.data_ptr()
         st.b_phi = None if b_phi is None else b_phi.data_ptr()

@@ -46,6 +46,18 @@ int read_state(hipStream_t s, const HostStage &st, const void *dev, void *out, s
     OASIS_TRY_HIP(hipStreamSynchronize(s));
     return OASIS_OK;
 }
+
+int write_state(hipStream_t s, const HostStage &st, void *dev, const void *src, size_t bytes) {
+    if (st.h && bytes <= kStageBytes && bytes % 4 == 0) {
+        std::memcpy(st.h, src, bytes);
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(kBlock), 0, s, static_cast<const unsigned *>(st.d),
+                           static_cast<unsigned *>(dev), static_cast<int>(bytes / 4));
+        OASIS_TRY_LAUNCH();
+        return OASIS_OK;
+    }
+    OASIS_TRY_HIP(hipMemcpyAsync(dev, src, bytes, hipMemcpyHostToDevice, s));
+    return OASIS_OK;
+}
 }  // namespace oasis
 
 extern "C" const char *oasis_strerror(int code) {

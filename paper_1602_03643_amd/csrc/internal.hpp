@@ -195,5 +195,11 @@ void stage_free(HostStage &st);
 // bytes (a multiple of 4) of device memory at dev into host memory at out;
 // synchronises the stream
 int read_state(hipStream_t s, const HostStage &st, const void *dev, void *out, size_t bytes);
+// bytes (a multiple of 4) of host memory at src into device memory at dev,
+// in stream order, without synchronising: through the block when there is
+// one (the host fills it and a one-block kernel copies it over; the block
+// is next written by a read_state, after this copy in stream order), else
+// as an ordinary copy
+int write_state(hipStream_t s, const HostStage &st, void *dev, const void *src, size_t bytes);
 
 }  // namespace oasis

@@ -1783,10 +1783,7 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
     }
     // one copy each way: the states and the pause record share a block
     BiBlock *dblk = reinterpret_cast<BiBlock *>(w.st);
-    auto push_state = [&]() -> int {
-        OASIS_TRY_HIP(hipMemcpyAsync(dblk, &hb, sizeof(hb), hipMemcpyHostToDevice, s));
-        return OASIS_OK;
-    };
+    auto push_state = [&]() -> int { return write_state(s, w.stage, dblk, &hb, sizeof(hb)); };
     auto pull_state = [&]() -> int { return read_state(s, w.stage, dblk, &hb, sizeof(hb)); };
     auto zero_dirs = [&](int k) -> int {
         hipLaunchKernelGGL((k_zero_u<T>), dim3(gv), dim3(kBlock), 0, s, n, w.ru, NR, k);
@@ -2080,7 +2077,8 @@ static int bi_run(hipStream_t s, int n, const int *rp, const int *ci, const T *v
             next = plan(it);
         }
     }
-    OASIS_TRY_HIP(hipStreamSynchronize(s));
+    // no synchronisation here: callers go on in stream order (the
+    // stand-alone entry point synchronises itself)
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     int worst = OASIS_OK;
