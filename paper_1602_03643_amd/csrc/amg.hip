@@ -442,8 +442,13 @@ struct AmgPlan {
     int fixed;
     double rate = 0.0, w0 = 0.0;
     int it0 = 0, next = 2;
-    explicit AmgPlan(int every) : fixed(every) {
-        if (fixed > 0) next = fixed;
+    // first: the first launch's size when the caller knows roughly how many
+    // iterations a solve takes (0: 2)
+    AmgPlan(int every, int first) : fixed(every) {
+        if (fixed > 0)
+            next = fixed;
+        else if (first > 0)
+            next = first;
     }
     void restart(double wrr, int it) {
         w0 = wrr;
@@ -465,10 +470,36 @@ struct AmgPlan {
     }
 };
 
+// The convergence test that the next product kernel would make, run at the
+// end of a launched chunk so that the poll sees it at once: from the
+// partials (r.z, sum wgt r^2) of the cycle's last kernel, flag 1 (or 3 on
+// a non-finite value) at iteration `it`, and the residual recorded for the
+// host's plan.  A flag already up is left alone.
+__global__ __launch_bounds__(kBlock) void k_apcg_test(const double *part, int np, CGState *st, int it) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (stopped(&st->flag)) return;
+    double v[2];
+    read_partials<2>(part, np, v, lds);
+    if (threadIdx.x == 0) {
+        const double wrr = v[1];
+        if (!finite(wrr) || !finite(v[0])) {
+            st->flag = 3;
+            st->it_done = it;
+        } else if (wrr <= st->tol2) {
+            st->flag = 1;
+            st->it_done = it;
+            st->wrr = wrr;
+        } else {
+            st->wrr_it = wrr;
+            st->it_last = it;
+        }
+    }
+}
+
 template <typename T>
 int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val, const double *e64,
                   const AmgCycle<T> &c, const double *wgt, const double *b, double *x, double rtol, int maxit,
-                  int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out) {
+                  int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out, int first_chunk) {
     out = SolveOut();
     const int cap = w.tun.grid_cap;
     const EllCols cols = (c.cols.any() && e64) ? c.cols : EllCols{};
@@ -496,7 +527,7 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
     double wbb = 0.0, tol2 = 0.0;
     bool first = true;
     auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
-    AmgPlan plan(check_every);
+    AmgPlan plan(check_every, first_chunk);
     int it = 0, restart_at = 0, rc = OASIS_OK;
     auto iterate = [&](int itj) -> int {
         OASIS_TRY(cg_product_launch(s, cap, n, rp, ci, val, cols, e64, w.pair[itj & 1], w.pair[(itj + 1) & 1],
@@ -511,6 +542,10 @@ int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const doub
         const int m = std::min(plan.next, maxit - it);
         for (int j = 0; j < m; ++j) OASIS_TRY(iterate(it + j));
         it += m;
+        if (m > 0) {
+            hipLaunchKernelGGL(k_apcg_test, dim3(1), dim3(kBlock), 0, s, pv, gpost, w.st, it);
+            OASIS_TRY_LAUNCH();
+        }
         OASIS_TRY(read_state(s, w.stage, w.st, &h, sizeof(h)));
         if (first) {
             first = false;
@@ -610,7 +645,7 @@ int amg_pcg_mixed(hipStream_t s, int n, const int *rp, const int *ci, const doub
     double wbb = 0.0, tol2 = 0.0;
     bool first = true;
     auto rel = [&](double wrr) { return wbb > 0.0 ? std::sqrt(wrr / wbb) : std::sqrt(wrr); };
-    AmgPlan plan(check_every);
+    AmgPlan plan(check_every, 0);
     int it = 0, rc = OASIS_OK;
     while (true) {
         const int m = std::min(plan.next, maxit - it);
@@ -672,9 +707,9 @@ template int amg_vcycle<float>(hipStream_t, const AmgCycle<float> &, const doubl
                                const double *, double *, int *, const int *, int);
 template int amg_pcg_solve<double>(hipStream_t, int, const int *, const int *, const double *, const double *,
                                    const AmgCycle<double> &, const double *, const double *, double *, double, int,
-                                   int, bool, double *, CGWork<double> &, SolveOut &);
+                                   int, bool, double *, CGWork<double> &, SolveOut &, int);
 template int amg_pcg_solve<float>(hipStream_t, int, const int *, const int *, const double *, const double *,
                                   const AmgCycle<float> &, const double *, const double *, double *, double, int, int,
-                                  bool, double *, CGWork<double> &, SolveOut &);
+                                  bool, double *, CGWork<double> &, SolveOut &, int);
 
 }  // namespace oasis

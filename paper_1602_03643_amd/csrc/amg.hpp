@@ -89,11 +89,13 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const TB *r, bool y0_ready, 
 // CG on level 0's matrix (FP64 ELL values e64 with c's columns) preconditioned
 // by the cycle c; stopping test sum wgt r^2 <= rtol^2 sum wgt b^2 on the
 // true residual.  r: FP64 scratch [n]; w: CG workspace (pairs, q, partials,
-// state).
+// state).  first_chunk: iterations launched before the first poll (0: 2),
+// for callers that expect about as many as a previous solve took.
 template <typename T>
 int amg_pcg_solve(hipStream_t s, int n, const int *rp, const int *ci, const double *val, const double *e64,
                   const AmgCycle<T> &c, const double *wgt, const double *b, double *x, double rtol, int maxit,
-                  int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out);
+                  int check_every, bool time_kernel, double *r, CGWork<double> &w, SolveOut &out,
+                  int first_chunk = 0);
 
 // Mixed-precision CG around an FP32 cycle: the direction, the product with
 // level 0's FP32 ELL copy e32 (CSR level 0 of the cycle without it) and the

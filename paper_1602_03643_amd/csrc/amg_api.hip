@@ -34,6 +34,7 @@ struct oasis_amg {
     oasis_amg &operator=(const oasis_amg &) = delete;
     ~oasis_amg() { stage_free(stage); }
     HostStage stage;   // pinned read-back block of the solve loop
+    int last_iters = 0;   // iterations of the last step solve (the first launch's hint)
     oasis_amg_params par{};
     Tuning tun;
     bool f32 = false, singular = false;
@@ -212,11 +213,18 @@ int amg_handle_solve(hipStream_t s, oasis_amg *h, const double *wgt, const doubl
     if (h->f32 && mixed)
         return amg_pcg_mixed(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, wgt, b, x, rtol,
                              delta > 0.0 ? delta : kAmgMixedDelta, maxit, 0, d.r, d.r32, d.cg32, out);
+    // successive pressure solves of a time loop take similar counts: launch
+    // about 60% of the last one's iterations before the first poll
+    const int first = h->last_iters > 3 ? h->last_iters * 3 / 5 : 0;
+    int rc;
     if (h->f32)
-        return amg_pcg_solve<float>(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, wgt, b, x, rtol, maxit, 0, false,
-                                    d.r, d.cg, out);
-    return amg_pcg_solve<double>(s, h->n, h->rp, h->ci, h->val, d.e64, d.c64, wgt, b, x, rtol, maxit, 0, false, d.r,
-                                 d.cg, out);
+        rc = amg_pcg_solve<float>(s, h->n, h->rp, h->ci, h->val, d.e64, d.c32, wgt, b, x, rtol, maxit, 0, false,
+                                  d.r, d.cg, out, first);
+    else
+        rc = amg_pcg_solve<double>(s, h->n, h->rp, h->ci, h->val, d.e64, d.c64, wgt, b, x, rtol, maxit, 0, false,
+                                   d.r, d.cg, out, first);
+    if (rc == OASIS_OK) h->last_iters = out.iters;
+    return rc;
 }
 
 bool amg_handle_matches(const oasis_amg *h, int n, const int *rp, const double *val, const double *B) {
