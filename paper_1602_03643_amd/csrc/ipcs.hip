@@ -987,7 +987,7 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
             xx[q] = ir.e32[k];
         }
         // the correction starts from zero, which the solve writes itself,
-        // and the FP64 residual above judges it, not the inner solve
+        // and the FP64 residual above decides whether it is enough
         SolveOut in[3];
         const int rc = bicgstab_solve<float>(s, n, na, rp, ci, val32, w32, bb, xx, inner,
                                              o.maxit, o.check_every, o.time, bw, in, true);
