@@ -352,7 +352,7 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const TB *r, bool y0_ready, 
     for (int l = 0; l + 1 < L; ++l) {
         const AmgDevLevel<T> &v = c.lv[l];
         if (l == 0 && ell0) {
-            const int g = ell_grid(v.n, 1 << 20);
+            const int g = ell_grid(v.n, grid_cap);   // several rows per lane group: the row loop prefetches
             if (dict)
                 hipLaunchKernelGGL((k_amg_pre_ell<T, TB, true>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols, c.e,
                                    v.y, r, v.t, flag);
