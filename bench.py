@@ -16,7 +16,8 @@ phi_prev unless the name ends in _zero, where it starts from 0):
                used only when the guard prefers it to phi_prev)
   *_amg        the pressure solve is FP64 CG preconditioned by one
                smoothed-aggregation V(1,1) cycle per iteration (FP64 cycle
-               for fp64_amg, FP32 for mixed_amg / learned_amg)
+               for fp64_amg, FP32 for mixed_amg / learned_amg, whose
+               level-0 smoothing reads the matrix values stored as FP16)
 All reach the same FP64 true-residual tolerance.  The headline `value` is
 the fastest variant whose pressure solve starts from phi_prev (the plain
 start that is the fallback of the learned guess and its reference); `speedups` compare
@@ -57,6 +58,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "IPCS steps/s + SpMV HBM GB/s, 1.6M-node P1 mesh; learned+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+# FP32 multigrid cycles read level 0's matrix values stored as FP16 (the CG
+# around the cycle multiplies in FP64 and stops on its FP64 residual);
+# --amg-fp32-level0 turns it off
+AMG_HALF_LEVEL0 = True
 # sources of the CG kernels; a PMC summary whose recorded hash differs from
 # these files was taken on another kernel and is not used
 CG_KERNEL_SOURCES = ["paper_1602_03643_amd/csrc/krylov.hip", "paper_1602_03643_amd/csrc/krylov.hpp",
@@ -142,7 +147,7 @@ def device_problem(oa, torch, synth, pr, dev, rcm=False):
 
 def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm=None, pstart=0, amg=None,
                 perm=None, dof_coords=None, inner_iters=1, velocity_update=0, scalars=0, convection=0, amg_theta=0.0,
-                inner_rtol=0.0, pressure_delta=0.0):
+                inner_rtol=0.0, pressure_delta=0.0, amg_half=None):
     """Time `steps` steps after `warmup` untimed ones; returns the handle, the
     results and the final (U, p, phi).  scalars: that many passive scalars
     with Prandtl number 0.71 (D = nu / 0.71), Dirichlet values y on the
@@ -172,7 +177,8 @@ def run_variant(oa, torch, pr, dm, pat, bcd, precision, steps, warmup, tag, warm
     t_amg, levels = 0.0, 0
     if amg is not None:
         t0 = time.perf_counter()
-        hamg = h.pressure_amg(precision=amg, theta=amg_theta)
+        hamg = h.pressure_amg(precision=amg, theta=amg_theta,
+                              half_level0=AMG_HALF_LEVEL0 if amg_half is None else amg_half)
         torch.cuda.synchronize()
         t_amg = time.perf_counter() - t0
         levels = hamg.n_levels()
@@ -339,9 +345,13 @@ def main():
                     help="timed steps of the headline configuration with each option beyond the channel runs' "
                          "(inner iterations, consistent update, a passive scalar); 0 skips them")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--amg-fp32-level0", action="store_true",
+                    help="FP32 cycles read level 0's values as FP32 (default: stored as FP16)")
     ap.add_argument("--pressure-delta", type=float, default=0.0,
                     help="FP32 pressure CG: residual replacement factor (0: the library's default)")
     args = ap.parse_args()
+    global AMG_HALF_LEVEL0
+    AMG_HALF_LEVEL0 = not args.amg_fp32_level0
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path here is single-GPU (no collectives); "
               "run with --gpus 1", file=sys.stderr)

@@ -298,10 +298,19 @@ typedef struct {
     int32_t max_levels;   /* 0 = 12; at most 16 */
     int32_t precision;    /* values and vectors of the cycle: OASIS_F64 or OASIS_F32 (the CG
                              around it, its dot products and stopping test stay FP64) */
-    int32_t flags;        /* OASIS_KRYLOV_NULLSPACE_CONST: A is singular with null vector B */
+    int32_t flags;        /* OASIS_KRYLOV_NULLSPACE_CONST: A is singular with null vector B;
+                             OASIS_AMG_HALF_LEVEL0: see below */
     oasis_tuning tuning;  /* storage of level 0 (an ELL copy when its rows fit, unless CSR)
                              and the grid cap of the CG kernels */
 } oasis_amg_params;
+
+/* An FP32 cycle keeps level 0's ELL values as FP16 as well and its two
+ * smoothing kernels read those (widened to FP32): the cycle then applies a
+ * preconditioner built on A with its entries rounded to FP16 (relative
+ * 2^-11), half the level-0 value bytes per cycle.  The CG around it still
+ * multiplies by A in FP64 and stops on its FP64 residual.  Ignored for FP64
+ * cycles or when level 0 has no ELL copy. */
+#define OASIS_AMG_HALF_LEVEL0 4
 
 /* Build the hierarchy of the symmetric positive (semi-)definite F64 CSR
  * matrix A (device; row_ptr, col_idx and val are kept by reference for the

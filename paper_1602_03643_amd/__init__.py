@@ -11,7 +11,7 @@ from ._lib import (OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENAN, EWORKSPACE, EUN
                    PSTART_ZERO, ASSEMBLE_ROWS, ASSEMBLE_COLORS, INSPECT_A, INSPECT_DIAG_A, INSPECT_RHS,
                    STORAGE_AUTO, STORAGE_ELL, STORAGE_CSR, CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE,
                    UPDATE_LUMPED, UPDATE_CONSISTENT, UPDATE_GRADIENT, CONV_ABCN, CONV_ABE, MAX_SCALARS,
-                   MPNN_LOSS_MSE, MPNN_LOSS_KNORM, OasisError)
+                   MPNN_LOSS_MSE, MPNN_LOSS_KNORM, AMG_HALF_LEVEL0, OasisError)
 
 _lib.load()
 
@@ -25,4 +25,4 @@ __all__ = ["AMG", "IPCS", "MPNN", "DeviceCSR", "DeviceMesh", "assemble_p1", "bic
            "PSTART_ZERO", "ASSEMBLE_ROWS", "ASSEMBLE_COLORS", "INSPECT_A", "INSPECT_DIAG_A", "INSPECT_RHS",
            "STORAGE_AUTO", "STORAGE_ELL", "STORAGE_CSR", "CG_FORM_AUTO", "CG_FORM_TWO", "CG_FORM_SINGLE",
            "UPDATE_LUMPED", "UPDATE_CONSISTENT", "UPDATE_GRADIENT", "CONV_ABCN", "CONV_ABE", "MAX_SCALARS",
-           "MPNN_LOSS_MSE", "MPNN_LOSS_KNORM"]
+           "MPNN_LOSS_MSE", "MPNN_LOSS_KNORM", "AMG_HALF_LEVEL0"]

@@ -29,6 +29,7 @@ CG_FORM_AUTO, CG_FORM_TWO, CG_FORM_SINGLE = 0, 1, 2
 MPNN_IN, MPNN_HID, MPNN_LAYERS = 6, 32, 3
 MPNN_NPARAM = 32 * 6 + 32 + 3 * 32 * 32 * 2 + 3 * 32 + 32 + 1
 MPNN_LOSS_MSE, MPNN_LOSS_KNORM = 0, 1
+AMG_HALF_LEVEL0 = 4
 
 i32 = C.c_int32
 i64 = C.c_int64

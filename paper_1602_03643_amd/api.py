@@ -284,12 +284,15 @@ class AMG:
     by the library) and its device image in a torch-allocated workspace."""
 
     def __init__(self, A: DeviceCSR, B=None, precision=L.F64, singular=False, theta=0.0, coarse_size=0,
-                 max_levels=0, storage=L.STORAGE_AUTO, grid_cap=0, stream=None):
+                 max_levels=0, storage=L.STORAGE_AUTO, grid_cap=0, stream=None, half_level0=False):
+        """half_level0: an FP32 cycle reads level 0's values stored as FP16
+        (OASIS_AMG_HALF_LEVEL0)."""
         lib = _lib()
         self.A, self.B = A, B
         self.n = A.n
-        self.params = L.AmgParams(float(theta), int(coarse_size), int(max_levels), int(precision),
-                                  L.KRYLOV_NULLSPACE_CONST if singular else 0, _tuning(storage, grid_cap))
+        flags = (L.KRYLOV_NULLSPACE_CONST if singular else 0) | (L.AMG_HALF_LEVEL0 if half_level0 else 0)
+        self.params = L.AmgParams(float(theta), int(coarse_size), int(max_levels), int(precision), flags,
+                                  _tuning(storage, grid_cap))
         self._csr = A.c()
         h = C.c_void_p()
         L.check(lib.oasis_amg_setup(_stream(stream), C.byref(self._csr), _p(B), C.byref(self.params), C.byref(h)),
@@ -437,12 +440,13 @@ class IPCS:
                  ms_scalars=stats.ms_scalars, rc=rc)
         return d
 
-    def pressure_amg(self, precision=L.F64, theta=0.0, coarse_size=0, max_levels=0, stream=None):
+    def pressure_amg(self, precision=L.F64, theta=0.0, coarse_size=0, max_levels=0, stream=None,
+                     half_level0=False):
         """Build a multigrid hierarchy on the handle's scaled pressure matrix,
         upload it and attach it to the pressure solve (oasis_ipcs_set_amg)."""
         Ks, s = self.matrix(L.FORM_STIFF, copy=False)     # the hierarchy keeps these by reference
         amg = AMG(self.pattern.with_values(Ks), s, precision=precision, singular=True, theta=theta,
-                  coarse_size=coarse_size, max_levels=max_levels, stream=stream)
+                  coarse_size=coarse_size, max_levels=max_levels, stream=stream, half_level0=half_level0)
         self.set_amg(amg)
         return amg
 

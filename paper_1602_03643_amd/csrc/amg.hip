@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "amg.hpp"
 
@@ -68,8 +69,8 @@ __global__ __launch_bounds__(kBlock) void k_amg_scale(int n, const T *__restrict
 // pre-smoothing residual on the ELL copy: t = b - A y (straight-line row
 // loop: the next row's offsets, values and b are fetched while this row's
 // gathers are in flight)
-template <typename T, typename TB, bool DICT>
-__global__ __launch_bounds__(kBlock) void k_amg_pre_ell(int n, EllCols cols, const T *__restrict__ e,
+template <typename T, typename TB, bool DICT, typename TE = T>
+__global__ __launch_bounds__(kBlock) void k_amg_pre_ell(int n, EllCols cols, const TE *__restrict__ e,
                                                         const T *__restrict__ y, const TB *__restrict__ b,
                                                         T *__restrict__ t, const int *flag) {
     if (stopped(flag)) return;
@@ -161,8 +162,8 @@ struct PostOwn {
     TB b;
 };
 
-template <typename T, typename TB, typename TO, bool DICT>
-__global__ __launch_bounds__(kBlock) void k_amg_post_ell(int n, EllCols cols, const T *__restrict__ e,
+template <typename T, typename TB, typename TO, bool DICT, typename TE = T>
+__global__ __launch_bounds__(kBlock) void k_amg_post_ell(int n, EllCols cols, const TE *__restrict__ e,
                                                          const T *__restrict__ wd, const TB *__restrict__ b,
                                                          const T *__restrict__ t, TO *__restrict__ out, int os,
                                                          const double *__restrict__ wgt, double *part,
@@ -353,12 +354,26 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const TB *r, bool y0_ready, 
         const AmgDevLevel<T> &v = c.lv[l];
         if (l == 0 && ell0) {
             const int g = ell_grid(v.n, grid_cap);   // several rows per lane group: the row loop prefetches
-            if (dict)
-                hipLaunchKernelGGL((k_amg_pre_ell<T, TB, true>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols, c.e,
-                                   v.y, r, v.t, flag);
-            else
-                hipLaunchKernelGGL((k_amg_pre_ell<T, TB, false>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols,
-                                   c.e, v.y, r, v.t, flag);
+            bool done = false;
+            if constexpr (std::is_same<T, float>::value) {
+                if (c.e16) {   // FP16-stored level-0 values
+                    if (dict)
+                        hipLaunchKernelGGL((k_amg_pre_ell<T, TB, true, _Float16>), dim3(g), dim3(kBlock), 0, s, v.n,
+                                           c.cols, c.e16, v.y, r, v.t, flag);
+                    else
+                        hipLaunchKernelGGL((k_amg_pre_ell<T, TB, false, _Float16>), dim3(g), dim3(kBlock), 0, s,
+                                           v.n, c.cols, c.e16, v.y, r, v.t, flag);
+                    done = true;
+                }
+            }
+            if (!done) {
+                if (dict)
+                    hipLaunchKernelGGL((k_amg_pre_ell<T, TB, true>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols, c.e,
+                                       v.y, r, v.t, flag);
+                else
+                    hipLaunchKernelGGL((k_amg_pre_ell<T, TB, false>), dim3(g), dim3(kBlock), 0, s, v.n, c.cols,
+                                       c.e, v.y, r, v.t, flag);
+            }
             OASIS_TRY_LAUNCH();
         } else {
             OASIS_TRY(with_lanes(v.alanes, [&](auto cfg) -> int {
@@ -405,12 +420,26 @@ int amg_vcycle(hipStream_t s, const AmgCycle<T> &c, const TB *r, bool y0_ready, 
         }));
         if (l == 0 && ell0) {
             const int g = ell_grid(v.n, part ? grid_cap : 1 << 20);
-            if (dict)
-                hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, true>), dim3(g), dim3(kBlock), 0, s, v.n,
-                                   c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
-            else
-                hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, false>), dim3(g), dim3(kBlock), 0, s, v.n,
-                                   c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
+            bool done = false;
+            if constexpr (std::is_same<T, float>::value) {
+                if (c.e16) {
+                    if (dict)
+                        hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, true, _Float16>), dim3(g), dim3(kBlock), 0, s,
+                                           v.n, c.cols, c.e16, v.wd, r, v.t, z, zs, wgt, part, flag);
+                    else
+                        hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, false, _Float16>), dim3(g), dim3(kBlock), 0,
+                                           s, v.n, c.cols, c.e16, v.wd, r, v.t, z, zs, wgt, part, flag);
+                    done = true;
+                }
+            }
+            if (!done) {
+                if (dict)
+                    hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, true>), dim3(g), dim3(kBlock), 0, s, v.n,
+                                       c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
+                else
+                    hipLaunchKernelGGL((k_amg_post_ell<T, TB, TO, false>), dim3(g), dim3(kBlock), 0, s, v.n,
+                                       c.cols, c.e, v.wd, r, v.t, z, zs, wgt, part, flag);
+            }
             OASIS_TRY_LAUNCH();
             if (gpost) *gpost = g;
         } else {

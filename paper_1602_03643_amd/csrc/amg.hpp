@@ -72,6 +72,7 @@ struct AmgCycle {
     AmgDevLevel<T> lv[kAmgMaxLevels];
     EllCols cols;
     const T *e = nullptr;
+    const _Float16 *e16 = nullptr;   // level 0's values stored as FP16 (FP32 cycles; null: e)
     int nc = 0;
     const T *cinv = nullptr;
 };

@@ -16,6 +16,7 @@ struct AmgImage {
     short *ptab = nullptr;
     double *e64 = nullptr;
     float *e32 = nullptr;
+    _Float16 *e16 = nullptr;                    // FP16 copy of e32 (OASIS_AMG_HALF_LEVEL0)
     EllCols cols;
     int ell_storage = 0;
     AmgCycle<double> c64;
@@ -37,7 +38,7 @@ struct oasis_amg {
     int last_iters = 0;   // iterations of the last step solve (the first launch's hint)
     oasis_amg_params par{};
     Tuning tun;
-    bool f32 = false, singular = false;
+    bool f32 = false, singular = false, half0 = false;
     int n = 0, nnz = 0;
     const int *rp = nullptr, *ci = nullptr;     // the input matrix (device, by reference)
     const double *val = nullptr;
@@ -129,6 +130,7 @@ void carve_amg(Carver &c, const oasis_amg &h, AmgImage &d) {
         d.ptab = c.take<short>(static_cast<size_t>(kMaxEllPatterns) * kEll);
         d.e64 = c.take<double>(static_cast<size_t>(n) * kEll);
         if (h.f32) d.e32 = c.take<float>(static_cast<size_t>(n) * kEll);
+        if (h.f32 && h.half0) d.e16 = c.take<_Float16>(static_cast<size_t>(n) * kEll);
     }
     carve_cg<double>(c, n, d.cg);
     if (h.f32) {
@@ -142,6 +144,12 @@ void carve_amg(Carver &c, const oasis_amg &h, AmgImage &d) {
         carve_levels<float>(c, h, d.c32);
     else
         carve_levels<double>(c, h, d.c64);
+}
+
+__global__ __launch_bounds__(kBlock) void k_amg_to_f16(long long m, const float *__restrict__ a,
+                                                       _Float16 *__restrict__ b) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x)
+        b[i] = static_cast<_Float16>(a[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_amg_fill(int n, double *x, double v) {
@@ -197,6 +205,7 @@ int upload_levels(hipStream_t s, oasis_amg &h, AmgCycle<T> &cy) {
         cy.cols = h.d.cols;
         cy.e = std::is_same<T, float>::value ? reinterpret_cast<const T *>(h.d.e32)
                                              : reinterpret_cast<const T *>(h.d.e64);
+        if (std::is_same<T, float>::value) cy.e16 = h.d.e16;
     }
     return OASIS_OK;
 }
@@ -252,6 +261,7 @@ extern "C" int oasis_amg_setup(void *stream, const oasis_csr *A, const double *B
     h->tun = tun;
     h->f32 = par->precision == OASIS_F32;
     h->singular = (par->flags & OASIS_KRYLOV_NULLSPACE_CONST) != 0;
+    h->half0 = (par->flags & OASIS_AMG_HALF_LEVEL0) != 0;
     h->n = A->n;
     h->nnz = A->nnz;
     h->rp = A->row_ptr;
@@ -320,6 +330,11 @@ extern "C" int oasis_amg_upload(void *stream, oasis_amg *h, void *ws, size_t ws_
         bool fits = false;
         OASIS_TRY(csr_to_ell(s, h->n, h->rp, h->ci, h->val, d.ecol, d.e64, d.e32, d.tmp, &fits));
         if (!fits) return OASIS_EINVAL;     // the device copy disagrees with the host check
+        if (d.e16) {
+            const long long m = static_cast<long long>(h->n) * kEll;
+            hipLaunchKernelGGL(k_amg_to_f16, dim3(grid_for(m, kBlock, 8192)), dim3(kBlock), 0, s, m, d.e32, d.e16);
+            OASIS_TRY_LAUNCH();
+        }
         int npat = 0;
         OASIS_TRY(ell_dictionary(s, h->n, d.ecol, d.pid, d.ptab, &npat, h->tun.dict()));
         d.cols = ell_cols(d.ecol, d.pid, d.ptab, npat);

@@ -155,6 +155,15 @@ __device__ __forceinline__ void load4(const float *__restrict__ p, float (&v)[4]
     v[2] = t.z;
     v[3] = t.w;
 }
+// four FP16 values widened to FP32 (one 8-byte load)
+struct alignas(8) Half4 {
+    _Float16 h[4];
+};
+__device__ __forceinline__ void load4(const _Float16 *__restrict__ p, float (&v)[4]) {
+    const Half4 t = *reinterpret_cast<const Half4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = static_cast<float>(t.h[k]);
+}
 __device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[4]) {
     const double2 a = reinterpret_cast<const double2 *>(p)[0];
     const double2 b = reinterpret_cast<const double2 *>(p)[1];
@@ -170,9 +179,10 @@ __device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[
 // butterfly.  Rows are walked grid-stride, so any grid covers them.
 // Offsets (decoded to columns) and values of one lane's E entries of row
 // `row` of an ELL copy.
-template <typename TA, int E>
+// TS: the stored value type (TA, or FP16 widened to an FP32 TA)
+template <typename TA, int E, typename TS = TA>
 __device__ __forceinline__ void ell_fetch_at(const short *off, long long row, int lane, int n,
-                                             const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
+                                             const TS *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
     const long long base = row * kEll + lane * E;
     off += lane * E;
 #pragma unroll
@@ -209,11 +219,11 @@ __device__ __forceinline__ int ell_key(const EllCols &cols, long long row) {
         return 0;
 }
 
-template <bool DICT, typename TA, int E>
+template <bool DICT, typename TA, int E, typename TS = TA>
 __device__ __forceinline__ void ell_fetch_key(long long row, int key, int lane, int n, const EllCols &cols,
-                                              const TA *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
+                                              const TS *__restrict__ eval, int (&c)[E], TA (&w)[E]) {
     const short *off = DICT ? cols.ptab + key * kEll : cols.ecol + row * kEll;
-    ell_fetch_at<TA, E>(off, row, lane, n, eval, c, w);
+    ell_fetch_at<TA, E, TS>(off, row, lane, n, eval, c, w);
 }
 
 // The row loop is software-pipelined: the next row's offsets and values are
@@ -252,8 +262,10 @@ __device__ __forceinline__ void ell_rows(int n, const EllCols &cols, const TA *_
 // The gather is split in two: load(c) -> G reads the operand(s) of column c
 // and add(g, v, acc) adds one entry's contribution (padding has value 0);
 // finish(row, lane, acc, o) runs on all L lanes with o = own(row).
-template <typename TA, int NR, int L, bool DICT, class G, class O, class Load, class Add, class Own, class Finish>
-__device__ __forceinline__ void ell_rows_pipe(int n, const EllCols &cols, const TA *__restrict__ eval, Load load,
+// The stored values may be FP16 (TS) for an FP32 TA; they are widened on load.
+template <typename TA, int NR, int L, bool DICT, class G, class O, class TS, class Load, class Add, class Own,
+          class Finish>
+__device__ __forceinline__ void ell_rows_pipe(int n, const EllCols &cols, const TS *__restrict__ eval, Load load,
                                               Add add, Own own, Finish finish) {
     constexpr int E = kEll / L;
     static_assert(E % 4 == 0, "lanes per row must leave a multiple of 4 entries per lane");
@@ -269,7 +281,7 @@ __device__ __forceinline__ void ell_rows_pipe(int n, const EllCols &cols, const 
         O o;
     };
     auto fetch = [&](Stage &S, long long r, int key) {
-        ell_fetch_key<DICT, TA, E>(r, key, lane, n, cols, eval, S.c, S.w);
+        ell_fetch_key<DICT, TA, E, TS>(r, key, lane, n, cols, eval, S.c, S.w);
         S.o = own(r);
     };
     auto step = [&](const Stage &S, Stage &N, int kin, int &kout) {

@@ -47,12 +47,13 @@ def _meshes():
             synth.permute_mesh(synth.channel(17, 17, 13), 2000)[0], synth.unit_square(48)]
 
 
-def _device_amg(oa, mesh, precision, storage=0, coarse_size=0):
+def _device_amg(oa, mesh, precision, storage=0, coarse_size=0, half_level0=False):
     dm, pat, _ = device_mesh(mesh, color=False)
     Ks, s = _scaled_pressure(mesh)
     val = T(p1.on_pattern(Ks, csr_host(pat)))
     A = pat.with_values(val)
-    h = oa.AMG(A, T(s), precision=precision, singular=True, storage=storage, coarse_size=coarse_size)
+    h = oa.AMG(A, T(s), precision=precision, singular=True, storage=storage, coarse_size=coarse_size,
+               half_level0=half_level0)
     # the scaled matrix in the pattern's order (the library's level 0)
     K0 = csr_host(pat, val)
     return h, K0, s, (A, val)
@@ -131,6 +132,50 @@ def test_vcycle_matches_oracle(oa, mesh, precision, storage):
         ref = amg.vcycle(H, r)
         tol = 1e-12 if precision == "f64" else 2e-5
         assert rel(z, ref) <= tol, (k, rel(z, ref))
+
+
+@pytest.mark.parametrize("mesh", _meshes()[:2], ids=lambda m: m.name)
+def test_vcycle_with_fp16_level0_values_matches_rounded_oracle(oa, mesh):
+    """OASIS_AMG_HALF_LEVEL0: the FP32 cycle's two level-0 smoothing kernels
+    read A's values rounded to FP16 (through FP32, as the library stores
+    them).  The oracle's cycle on the library's hierarchy with level 0's
+    matrix rounded the same way matches it to the FP32 tolerance (the
+    scaled matrix's unit diagonal, which the Jacobi weights use, is exact in
+    FP16), and the cycle differs from the FP32-valued one by about the FP16
+    rounding."""
+    say("amg vcycle fp16 level 0", mesh.name)
+    h16, K0, s, keep16 = _device_amg(oa, mesh, oa.F32, half_level0=True)
+    h32, _, _, keep32 = _device_amg(oa, mesh, oa.F32)
+    H = _oracle_hierarchy([h16.level(l) for l in range(h16.n_levels())])
+    A0 = H.levels[0].A.copy()
+    A0.data = A0.data.astype(np.float32).astype(np.float16).astype(np.float64)
+    assert np.array_equal(A0.diagonal(), H.levels[0].A.diagonal().astype(np.float32).astype(np.float64))
+    H.levels[0].A = A0
+    rng = np.random.default_rng(10)
+    for k in range(3):
+        r = rng.normal(size=mesh.n_dof)
+        z16 = h16.vcycle(T(r)).cpu().numpy()
+        z32 = h32.vcycle(T(r)).cpu().numpy()
+        assert rel(z16, amg.vcycle(H, r)) <= 2e-5, (k, rel(z16, amg.vcycle(H, r)))
+        assert 1e-6 < rel(z16, z32) < 1e-2, rel(z16, z32)
+
+
+def test_amg_pcg_with_fp16_level0_values_meets_fp64_tolerance(oa):
+    mesh = synth.channel(33, 33, 25)
+    h16, K0, s, keep16 = _device_amg(oa, mesh, oa.F32, half_level0=True)
+    h32, _, _, keep32 = _device_amg(oa, mesh, oa.F32)
+    rng = np.random.default_rng(11)
+    b = rng.normal(size=mesh.n_dof)
+    b -= (b @ s) / (s @ s) * s
+    its = []
+    for h in (h32, h16):
+        x = torch.zeros(mesh.n_dof, dtype=torch.float64, device=dev())
+        out = h.pcg(T(b), x, rtol=1e-10, maxit=300)
+        assert out["rc"] == 0
+        assert np.linalg.norm(b - K0 @ x.cpu().numpy()) <= 1.0001e-10 * np.linalg.norm(b)
+        its.append(out["iters"])
+    say("amg pcg iterations, fp32 level 0 %d, fp16 level 0 %d" % tuple(its))
+    assert its[1] <= its[0] + 2
 
 
 def test_single_level_is_the_dense_pseudo_inverse(oa):
@@ -221,12 +266,13 @@ def test_amg_pcg_mixed_cg_meets_fp64_tolerance(oa, delta):
         assert rel(proj(xg), proj(x64)) <= 1e3 * rtol
 
 
-def _run_steps(oa, prob, steps, rtol, precision, amg_precision=None):
+def _run_steps(oa, prob, steps, rtol, precision, amg_precision=None, half_level0=False):
     m = prob.mesh
     dm, pat, _ = device_mesh(m)
     h = oa.IPCS(dm, pat, prob.dt, prob.nu, prob.f, T(m.bc_dofs, torch.int32), rtol_u=rtol, rtol_p=rtol,
                 precision=precision)
-    hamg = h.pressure_amg(precision=amg_precision) if amg_precision is not None else None
+    hamg = (h.pressure_amg(precision=amg_precision, half_level0=half_level0) if amg_precision is not None
+            else None)
     U = [T(prob.U2), T(prob.U1)]
     p, phi = T(prob.p), T(prob.phi_prev)
     t = prob.t0
@@ -262,10 +308,11 @@ def test_ipcs_step_with_amg_matches_oracle(oa, prob):
     assert all(s["iters_p"] < 60 for s in stats)
 
 
-def test_ipcs_mixed_with_f32_amg_per_field(oa):
+@pytest.mark.parametrize("half_level0", [False, True])
+def test_ipcs_mixed_with_f32_amg_per_field(oa, half_level0):
     prob = synth.channel_flow((33, 33, 25), seed=2)
-    say("ipcs mixed + f32 amg", prob.name)
-    U, p, phi, stats, keep = _run_steps(oa, prob, 5, 1e-8, oa.F32, amg_precision=oa.F32)
+    say("ipcs mixed + f32 amg", prob.name, "fp16 level 0" if half_level0 else "")
+    U, p, phi, stats, keep = _run_steps(oa, prob, 5, 1e-8, oa.F32, amg_precision=oa.F32, half_level0=half_level0)
     assert all(s["status"] == 0 for s in stats)
     S = ipcs.setup(prob.mesh, prob.nu, prob.dt, prob.f)
     st = ipcs.initial_state(prob)
