@@ -240,8 +240,14 @@ static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, 
 // Right-hand side, Dirichlet rows and the diagonal of A, one row per
 // lane group.  x0 of the velocity solve (U^{n-1}) is copied on the way.
 // cv (nullable per component): an explicit convection vector subtracted
-// from the right-hand side (eq:convection_ABE).
-template <int D, int L>
+// from the right-hand side (eq:convection_ABE).  The pressure term is
+// dP^k p, from the stored gradient matrices, or with GP the value that the
+// row-gather assembly left in b_k for the row (the same sums over the
+// row's cells, formed there from the cells it already walks).  With CS the
+// diagonal is already in dA (written by the assembly), and the kernel also
+// applies the right Jacobi scaling a_ij / d_j that k_colscale does
+// otherwise, writing the scaled row and its FP32 CSR or ELL copies.
+template <int D, int L, bool GP = false, bool CS = false>
 __global__ __launch_bounds__(kBlock) void k_tent_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ M,
     double *__restrict__ A, P3 dP, P3 U1, P3 cv, const double *__restrict__ p,
@@ -249,7 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
     int nbc, double f0, double f1, double f2, double two_over_dt, double *__restrict__ b0,
     double *__restrict__ b1, double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1,
     double *__restrict__ x2, double *__restrict__ dA, double *__restrict__ wA,
-    float *__restrict__ wA32) {
+    float *__restrict__ wA32, float *__restrict__ a32, double *__restrict__ e64, float *__restrict__ e32) {
+    static_assert(L >= D + 3, "one lane per output array");
     const int lane = threadIdx.x & (L - 1);
     const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
     const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
@@ -259,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
     for (long long row = gid; row < n; row += ngroups) {
         const int i = static_cast<int>(row);
         const int s = rp[i], e = rp[i + 1];
+        const int q = bc_index[i];
         double acc[D], accp[D], diag = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] = accp[k] = 0.0;
@@ -268,47 +276,86 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
             const double rhs_coef = two_over_dt * M[j] - a;
 #pragma unroll
             for (int k = 0; k < D; ++k) acc[k] += rhs_coef * U1.p[k][c];
-            if (p) {                                  // no pressure gradient for a scalar
+            if (!GP && p) {                           // no pressure gradient for a scalar
                 const double pc = p[c];
 #pragma unroll
                 for (int k = 0; k < D; ++k) accp[k] += dP.p[k][j] * pc;
             }
-            if (c == i) diag = a;
+            if (!CS && c == i) diag = a;
+            if constexpr (CS) {
+                // the Dirichlet row is the identity row; then a_ij / d_j
+                const double t = (q >= 0 ? (c == i ? 1.0 : 0.0) : a) / dA[c];
+                A[j] = t;
+                if (a32) a32[j] = static_cast<float>(t);
+                if (e64) e64[row * kEll + (j - s)] = t;
+                if (e32) e32[row * kEll + (j - s)] = static_cast<float>(t);
+            }
+        }
+        if constexpr (CS) {
+            // the ELL copies' padding slots (rows of at most kEll entries)
+            for (int k = e - s + lane; k < kEll; k += L) {
+                if (e64) e64[row * kEll + k] = 0.0;
+                if (e32) e32[row * kEll + k] = 0.f;
+            }
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             acc[k] = group_sum<L>(acc[k]);
-            accp[k] = group_sum<L>(accp[k]);
+            if (!GP) accp[k] = group_sum<L>(accp[k]);
         }
-        diag = group_sum<L>(diag);
-        const int q = bc_index[i];
-        const double dd = q >= 0 ? 1.0 : diag;
-        if (q >= 0)
-            for (int j = s + lane; j < e; j += L) A[j] = (ci[j] == i) ? 1.0 : 0.0;
-        if (lane == 0) {
+        double dd;
+        if constexpr (CS) {
+            dd = dA[i];
+        } else {
+            diag = group_sum<L>(diag);
+            dd = q >= 0 ? 1.0 : diag;
+            if (q >= 0)
+                for (int j = s + lane; j < e; j += L) A[j] = (ci[j] == i) ? 1.0 : 0.0;
+        }
+        // the row's outputs spread over the group's lanes (every lane holds
+        // the sums): lane k < D writes component k, the next three lanes the
+        // diagonal and the two weights
+        if (lane < D) {
+            double ak = acc[0], apk = accp[0], fk = f[0];
+            double *bk = bo[0], *xk = xo[0];
+            const double *uk = U1.p[0], *ck = cv.p[0];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                bo[k][i] = q >= 0 ? g[k * nbc + q]
-                                  : f[k] * ML[i] + acc[k] - accp[k] - (cv.p[k] ? cv.p[k][i] : 0.0);
-                xo[k][i] = dd * U1.p[k][i];      // y0 = D x0 for the column-scaled system
-            }
-            dA[i] = dd;
+            for (int k = 1; k < D; ++k)
+                if (lane == k) {
+                    ak = acc[k];
+                    apk = accp[k];
+                    fk = f[k];
+                    bk = bo[k];
+                    xk = xo[k];
+                    uk = U1.p[k];
+                    ck = cv.p[k];
+                }
+            const double gp = GP ? bk[i] : apk;
+            bk[i] = q >= 0 ? g[lane * nbc + q] : fk * ML[i] + ak - gp - (ck ? ck[i] : 0.0);
+            xk[i] = dd * uk[i];      // y0 = D x0 for the column-scaled system
+        } else if (lane == D) {
+            if (!CS) dA[i] = dd;
+        } else if (lane == D + 1) {
             wA[i] = 1.0;
-            if (wA32) wA32[i] = 1.f;
+        } else if (lane == D + 2 && wA32) {
+            wA32[i] = 1.f;
         }
     }
 }
 
 // u_bar = 1.5 U^{n-1} - 0.5 U^{n-2} (Alg. 2), interleaved per dof
-// ([n][4] in 3D, [n][2] in 2D) for the assembly's per-vertex gathers.
+// ([n][4] in 3D, [n][2] in 2D) for the assembly's per-vertex gathers.  In
+// 3D the fourth slot of a record carries p (zero without one), so that the
+// row-gather assembly reads the pressure in the same load.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_ubar(int n, P3 U1, P3 U2, double *__restrict__ ubar) {
+__global__ __launch_bounds__(kBlock) void k_ubar(int n, P3 U1, P3 U2, const double *__restrict__ p,
+                                                 double *__restrict__ ubar) {
     constexpr int UW = D == 3 ? 4 : 2;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int c = 0; c < D; ++c) ubar[i * UW + c] = 1.5 * U1.p[c][i] - 0.5 * U2.p[c][i];
-        if (D == 3) ubar[i * UW + 3] = 0.0;
+        if (D == 3) ubar[i * UW + 3] = p ? p[i] : 0.0;
     }
 }
 
@@ -341,12 +388,18 @@ __global__ __launch_bounds__(kBlock) void k_uu(int n, P3 U1, P3 U2, double *__re
 // (an odd tail's clamped copy is added with weight 0, so the compiler
 // cannot sink its loads behind the first cell's arithmetic), and the rows
 // are split XCD-aware so that neighbouring rows' cells share one L2.
-template <int D, int MAXC, int NC = (MAXC <= 16 ? 3 : 2)>
+// With GP (3D) the walk also forms the tentative step's pressure term
+// (dP^k p)_i = sum over the row's cells of vol/(D+1) * sum_j p_j d_k phi_j
+// (eq:dp_matrix applied to p, the 4th slot of the u_bar records) into gp_k,
+// instead of k_tent_rows streaming the three gradient matrices.
+template <int D, int MAXC, bool GP = false, int NC = (MAXC <= 16 ? 3 : 2)>
 __global__ __launch_bounds__(kBlock) void k_asm_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ B,
     const int *__restrict__ iptr, const int *__restrict__ inc, const int *__restrict__ cells,
     const int *__restrict__ v2d, const double *__restrict__ X, const double *__restrict__ ubar,
-    double *__restrict__ A) {
+    double *__restrict__ A, double *__restrict__ gp0, double *__restrict__ gp1, double *__restrict__ gp2,
+    const int *__restrict__ bc_index, double *__restrict__ dA) {
+    static_assert(!GP || D == 3, "the pressure rides in the 3D records' spare slot");
     constexpr int NV = D + 1;
     constexpr int UW = D == 3 ? 4 : 2;                  // u_bar row width
     constexpr double mfac = 0.5 / ((D + 1) * (D + 2));   // C/2 and the mass-moment factor
@@ -362,9 +415,12 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
             a[q] = q < len ? B[s + q] : 0.0;
         }
         struct Cell {
-            double x[NV][D], ub[NV][D];
+            double x[NV][D], ub[NV][D], pp[GP ? NV : 1];
             int dd[NV], la;
         };
+        double gp[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) gp[c] = 0.0;
         auto load = [&](int t, Cell &C) {
             const int code = inc[t];
             const int cell = code / NV;
@@ -378,6 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                     C.x[k][c] = X[(long long)v * D + c];
                     C.ub[k][c] = ubar[(long long)C.dd[k] * UW + c];
                 }
+                if constexpr (GP) C.pp[k] = ubar[(long long)C.dd[k] * UW + 3];
             }
         };
         auto add = [&](const Cell &C, double keep) {
@@ -395,6 +452,16 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
                 w[c] = S + ua;
             }
             const double fac = keep * e.vol * mfac;
+            if constexpr (GP) {
+                const double fg = keep * e.vol * (1.0 / NV);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int jl = 0; jl < NV; ++jl) t += e.g[jl][c] * C.pp[jl];
+                    gp[c] += fg * t;
+                }
+            }
 #pragma unroll
             for (int jl = 0; jl < NV; ++jl) {
                 double gw = 0.0;
@@ -422,6 +489,18 @@ __global__ __launch_bounds__(kBlock) void k_asm_rows(
 #pragma unroll
         for (int q = 0; q < MAXC; ++q)
             if (q < len) A[s + q] = a[q];
+        if (dA) {
+            // the diagonal the column scaling divides by (1 on a Dirichlet row)
+            double dg = 0.0;
+#pragma unroll
+            for (int q = 0; q < MAXC; ++q) dg = col[q] == i ? a[q] : dg;
+            dA[i] = bc_index[i] >= 0 ? 1.0 : dg;
+        }
+        if constexpr (GP) {
+            gp0[i] = gp[0];
+            gp1[i] = gp[1];
+            gp2[i] = gp[2];
+        }
     }
 }
 
@@ -663,11 +742,21 @@ __global__ __launch_bounds__(kBlock) void k_update_rows(int n, const int *__rest
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] = group_sum<L>(acc[k]);
-        if (lane == 0) {
+        // lane k < D writes component k (every lane holds the sums)
+        if (lane < D) {
+            double ak = acc[0];
+            double *uk = uo[0];
+            const double *vk = UI.p[0];
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+                if (lane == k) {
+                    ak = acc[k];
+                    uk = uo[k];
+                    vk = UI.p[k];
+                }
             const int q = bc_index[row];
             const double inv = ML ? dt / ML[row] : dt;   // no M_L: the gradient matrix
-#pragma unroll
-            for (int k = 0; k < D; ++k) uo[k][row] = q >= 0 ? g[k * nbc + q] : UI.p[k][row] - inv * acc[k];
+            uk[row] = q >= 0 ? g[lane * nbc + q] : vk[row] - inv * ak;
         }
     }
 }
@@ -1514,9 +1603,12 @@ extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const doubl
     }
 }
 
+// gp: the pressure term is already in h->bt (k_asm_rows<.., true>); cs:
+// the diagonal is already in h->dA, and the column scaling is done here
+// (no k_colscale pass afterwards)
 template <int D, int L>
 static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g,
-                                     double *const *x) {
+                                     double *const *x, bool gp = false, bool cs = false) {
     const int n = h->n;
     P3 dP{}, U1{}, cv{};
     for (int k = 0; k < D; ++k) {
@@ -1525,29 +1617,47 @@ static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_s
         cv.p[k] = h->abe ? h->cv[k] : nullptr;
     }
     const int grid = grid_for(n, kBlock / L, 1 << 20);
-    hipLaunchKernelGGL((k_tent_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A,
-                       dP, U1, cv, st->p, h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1],
-                       h->par.f[2], 2.0 / h->par.dt, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0],
-                       x[1], D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32);
+    const bool e = h->ell && h->tun.ell();
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A, dP, U1, cv, st->p,
+                           h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1], h->par.f[2],
+                           2.0 / h->par.dt, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0], x[1],
+                           D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32, h->mixed && !e ? h->A32 : nullptr,
+                           e ? h->eA : nullptr, e ? h->eA32 : nullptr);
+    };
+    if constexpr (D == 3) {
+        if (gp && cs) return go(k_tent_rows<D, L, true, true>);
+    }
+    if (cs) return go(k_tent_rows<D, L, false, true>);
+    go(k_tent_rows<D, L, false, false>);
 }
 
-// A = Bsrc + C(u_bar)/2 by the row-gather kernel (u_bar already in h->ubar)
-template <int D, int MAXC>
-static void launch_asm_kernel(hipStream_t s, oasis_ipcs *h, const double *Bsrc) {
-    hipLaunchKernelGGL((k_asm_rows<D, MAXC>), dim3(grid_for(h->n, kBlock, 1 << 20)), dim3(kBlock), 0, s, h->n,
-                       h->rp, h->ci, Bsrc, h->iptr, h->inc, h->rmesh.cells, h->rmesh.vert2dof, h->rmesh.coords, h->ubar,
-                       h->A);
+// A = Bsrc + C(u_bar)/2 by the row-gather kernel (u_bar already in h->ubar);
+// with GP also the pressure term dP^k p into h->bt (3D, p in the records)
+// and with cs the diagonal into h->dA
+template <int D, int MAXC, bool GP>
+static void launch_asm_kernel(hipStream_t s, oasis_ipcs *h, const double *Bsrc, bool cs) {
+    hipLaunchKernelGGL((k_asm_rows<D, MAXC, GP>), dim3(grid_for(h->n, kBlock, 1 << 20)), dim3(kBlock), 0, s,
+                       h->n, h->rp, h->ci, Bsrc, h->iptr, h->inc, h->rmesh.cells, h->rmesh.vert2dof,
+                       h->rmesh.coords, h->ubar, h->A, GP ? h->bt[0] : nullptr, GP ? h->bt[1] : nullptr,
+                       GP ? h->bt[2] : nullptr, h->bc_index, cs ? h->dA : nullptr);
 }
 
-static void launch_asm(hipStream_t s, oasis_ipcs *h, const double *Bsrc) {
-    if (h->dim == 3 && h->maxc == 16)
-        launch_asm_kernel<3, 16>(s, h, Bsrc);
+// gp: only for 3D rows of at most 16 entries (with 32 slots the extra
+// registers would halve the kernel's occupancy)
+static bool asm_gradient(const oasis_ipcs *h) { return h->dim == 3 && h->maxc == 16; }
+
+static void launch_asm(hipStream_t s, oasis_ipcs *h, const double *Bsrc, bool gp = false, bool cs = false) {
+    if (h->dim == 3 && h->maxc == 16 && gp)
+        launch_asm_kernel<3, 16, true>(s, h, Bsrc, cs);
+    else if (h->dim == 3 && h->maxc == 16)
+        launch_asm_kernel<3, 16, false>(s, h, Bsrc, cs);
     else if (h->dim == 3)
-        launch_asm_kernel<3, 32>(s, h, Bsrc);
+        launch_asm_kernel<3, 32, false>(s, h, Bsrc, cs);
     else if (h->maxc == 16)
-        launch_asm_kernel<2, 16>(s, h, Bsrc);
+        launch_asm_kernel<2, 16, false>(s, h, Bsrc, cs);
     else
-        launch_asm_kernel<2, 32>(s, h, Bsrc);
+        launch_asm_kernel<2, 32, false>(s, h, Bsrc, cs);
 }
 
 template <int D>
@@ -1558,10 +1668,14 @@ static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st,
         U1.p[k] = st->U1[k];
         U2.p[k] = st->U2[k];
     }
-    hipLaunchKernelGGL((k_ubar<D>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
-    launch_asm(s, h, h->B);
-    // right-hand sides, Dirichlet rows, diagonal and y0 (8 lanes per row)
-    launch_step_kernels_tent<D, 8>(s, h, st, g, x);
+    // in 3D the records carry p, and the assembly also forms dP^k p
+    const bool gp = asm_gradient(h);
+    hipLaunchKernelGGL((k_ubar<D>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2,
+                       gp ? static_cast<const double *>(st->p) : nullptr, h->ubar);
+    launch_asm(s, h, h->B, gp, true);
+    // right-hand sides, Dirichlet rows, y0 and the column scaling (8 lanes
+    // per row)
+    launch_step_kernels_tent<D, 8>(s, h, st, g, x, gp, true);
 }
 
 template <int D, int L>
@@ -1587,7 +1701,8 @@ static void launch_update(hipStream_t s, oasis_ipcs *h, double *const *x, const 
     }
     const int grid = grid_for(h->n, kBlock / L, 1 << 20);
     hipLaunchKernelGGL((k_update_rows<D, L>), dim3(grid), dim3(kBlock), 0, s, h->n, h->rp, h->ci, dP, UI, phi,
-                       h->gradient ? static_cast<const double *>(nullptr) : h->ML, h->bc_index, g, h->par.n_bc, h->par.dt, un[0], un[1], D > 2 ? un[2] : nullptr);
+                       h->gradient ? static_cast<const double *>(nullptr) : h->ML, h->bc_index, g, h->par.n_bc,
+                       h->par.dt, un[0], un[1], D > 2 ? un[2] : nullptr);
 }
 
 // One passive scalar: A_c = M/dt + D K/2 + C(u_bar)/2 by the step's
@@ -1619,7 +1734,8 @@ static int scalar_solve(hipStream_t s, oasis_ipcs *h, oasis_state *st, int a, in
                        none, static_cast<const double *>(nullptr), h->ML, h->bc_index, st->C_bc[a], h->par.n_bc,
                        h->par.scalar_source[a], 0.0, 0.0, 2.0 / h->par.dt, h->bt[0], static_cast<double *>(nullptr),
                        static_cast<double *>(nullptr), st->Cn[a], static_cast<double *>(nullptr),
-                       static_cast<double *>(nullptr), h->dA, h->wA, h->wA32);
+                       static_cast<double *>(nullptr), h->dA, h->wA, h->wA32, static_cast<float *>(nullptr),
+                       static_cast<double *>(nullptr), static_cast<float *>(nullptr));
     OASIS_TRY_LAUNCH();
     const bool e = h->ell && h->tun.ell();
     hipLaunchKernelGGL(k_colscale, dim3(grid_for(n, kBlock / kEll, 1 << 20)), dim3(kBlock), 0, s, n, h->rp, h->ci,
@@ -1703,7 +1819,8 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         }
         OASIS_TRY_LAUNCH();
     } else if (h->assembly == OASIS_ASSEMBLE_ROWS) {
-        // 1+2. rows gather A = B + C(u_bar)/2, right-hand sides, Dirichlet rows, scaling
+        // 1+2. rows gather A = B + C(u_bar)/2 and its diagonal, right-hand
+        // sides, Dirichlet rows, column scaling
         if (D == 3)
             launch_asm_rows<3>(s, h, st, bc_values, x);
         else
@@ -1722,8 +1839,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         OASIS_TRY_LAUNCH();
     }
     // right Jacobi: the solves run on A D^{-1} in y = D x (ELL values for
-    // the Krylov products when the pattern fits, else the FP32 CSR copy)
-    {
+    // the Krylov products when the pattern fits, else the FP32 CSR copy);
+    // the row-gather path has scaled A already
+    if (h->abe || h->assembly != OASIS_ASSEMBLE_ROWS) {
         const bool e = h->ell && h->tun.ell();
         hipLaunchKernelGGL(k_colscale, dim3(grid_for(n, kBlock / kEll, 1 << 20)), dim3(kBlock), 0, s, n, h->rp,
                            h->ci, h->dA, h->A, h->mixed && !e ? h->A32 : nullptr, e ? h->eA : nullptr,
@@ -1892,9 +2010,11 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     // in place of B, no pressure gradient
     if (h->nsc > 0 && h->abe && h->assembly == OASIS_ASSEMBLE_ROWS) {
         if (D == 3)
-            hipLaunchKernelGGL((k_ubar<3>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
+            hipLaunchKernelGGL((k_ubar<3>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2,
+                               static_cast<const double *>(nullptr), h->ubar);
         else
-            hipLaunchKernelGGL((k_ubar<2>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2, h->ubar);
+            hipLaunchKernelGGL((k_ubar<2>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2,
+                               static_cast<const double *>(nullptr), h->ubar);
         OASIS_TRY_LAUNCH();
     }
     for (int a = 0; a < h->nsc; ++a) {
@@ -2026,8 +2146,8 @@ static int pcg_run(void *stream, const oasis_csr *A, const double *b, double *x,
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, 16, k.flag, 0);
     hipLaunchKernelGGL((k_diag<double>), dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.b);
     hipLaunchKernelGGL(k_diag_vectors, dim3(gvec(n)), dim3(kBlock), 0, s, n, k.b, 0, k.s, k.w, k.w32, k.flag);
-    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s, kScaleSym,
-                       k.val, k.val32);
+    hipLaunchKernelGGL(k_scale_matrix, dim3(gvec(n)), dim3(kBlock), 0, s, n, A->row_ptr, A->col_idx, val, k.s,
+                       kScaleSym, k.val, k.val32);
     hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, b, k.s, 2, k.b);
     hipLaunchKernelGGL(k_vscale, dim3(gvec(n)), dim3(kBlock), 0, s, n, x, k.s, 1, k.x);
     OASIS_TRY_LAUNCH();
