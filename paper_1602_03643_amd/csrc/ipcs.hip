@@ -246,7 +246,15 @@ static int unit_vector_f32(hipStream_t s, int n, const double *x, double *part, 
 // row's cells, formed there from the cells it already walks).  With CS the
 // diagonal is already in dA (written by the assembly), and the kernel also
 // applies the right Jacobi scaling a_ij / d_j that k_colscale does
-// otherwise, writing the scaled row and its FP32 CSR or ELL copies.
+// otherwise, writing the scaled row and its FP32 CSR or ELL copies.  With
+// r0o set (CS only) it also writes the refinement loop's first residual:
+// r0 = b - A U^{n-1} (= b - Â y0) in FP32, from the same row and gathers,
+// with the partials (sum r0^2, sum b^2) per component that k_ir_resid would
+// produce (unit weights: right Jacobi).
+struct P3F {
+    float *p[3];
+};
+
 template <int D, int L, bool GP = false, bool CS = false>
 __global__ __launch_bounds__(kBlock) void k_tent_rows(
     int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ M,
@@ -255,8 +263,11 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
     int nbc, double f0, double f1, double f2, double two_over_dt, double *__restrict__ b0,
     double *__restrict__ b1, double *__restrict__ b2, double *__restrict__ x0, double *__restrict__ x1,
     double *__restrict__ x2, double *__restrict__ dA, double *__restrict__ wA,
-    float *__restrict__ wA32, float *__restrict__ a32, double *__restrict__ e64, float *__restrict__ e32) {
+    float *__restrict__ wA32, float *__restrict__ a32, double *__restrict__ e64, float *__restrict__ e32,
+    P3F r0o, double *__restrict__ rpart) {
     static_assert(L >= D + 3, "one lane per output array");
+    __shared__ double lds[2 * D * kBlock / kWave];
+    double rr = 0.0, rb = 0.0;   // this lane's component's r0^2 and b^2 (lane < D)
     const int lane = threadIdx.x & (L - 1);
     const long long gid = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) / L;
     const long long ngroups = (static_cast<long long>(gridDim.x) * blockDim.x) / L;
@@ -267,15 +278,19 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
         const int i = static_cast<int>(row);
         const int s = rp[i], e = rp[i + 1];
         const int q = bc_index[i];
-        double acc[D], accp[D], diag = 0.0;
+        double acc[D], accp[D], acca[D], diag = 0.0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] = accp[k] = 0.0;
+        for (int k = 0; k < D; ++k) acc[k] = accp[k] = acca[k] = 0.0;
         for (int j = s + lane; j < e; j += L) {
             const int c = ci[j];
             const double a = A[j];
             const double rhs_coef = two_over_dt * M[j] - a;
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc[k] += rhs_coef * U1.p[k][c];
+            for (int k = 0; k < D; ++k) {
+                const double u = U1.p[k][c];
+                acc[k] += rhs_coef * u;
+                if (CS) acca[k] += a * u;
+            }
             if (!GP && p) {                           // no pressure gradient for a scalar
                 const double pc = p[c];
 #pragma unroll
@@ -302,6 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
         for (int k = 0; k < D; ++k) {
             acc[k] = group_sum<L>(acc[k]);
             if (!GP) accp[k] = group_sum<L>(accp[k]);
+            if (CS) acca[k] = group_sum<L>(acca[k]);
         }
         double dd;
         if constexpr (CS) {
@@ -316,23 +332,35 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
         // the sums): lane k < D writes component k, the next three lanes the
         // diagonal and the two weights
         if (lane < D) {
-            double ak = acc[0], apk = accp[0], fk = f[0];
+            double ak = acc[0], apk = accp[0], aak = acca[0], fk = f[0];
             double *bk = bo[0], *xk = xo[0];
             const double *uk = U1.p[0], *ck = cv.p[0];
+            float *rk = r0o.p[0];
 #pragma unroll
             for (int k = 1; k < D; ++k)
                 if (lane == k) {
                     ak = acc[k];
                     apk = accp[k];
+                    aak = acca[k];
                     fk = f[k];
                     bk = bo[k];
                     xk = xo[k];
                     uk = U1.p[k];
                     ck = cv.p[k];
+                    rk = r0o.p[k];
                 }
             const double gp = GP ? bk[i] : apk;
-            bk[i] = q >= 0 ? g[lane * nbc + q] : fk * ML[i] + ak - gp - (ck ? ck[i] : 0.0);
-            xk[i] = dd * uk[i];      // y0 = D x0 for the column-scaled system
+            const double bv = q >= 0 ? g[lane * nbc + q] : fk * ML[i] + ak - gp - (ck ? ck[i] : 0.0);
+            const double u = uk[i];
+            bk[i] = bv;
+            xk[i] = dd * u;      // y0 = D x0 for the column-scaled system
+            if (CS && rk) {
+                // a Dirichlet row of Â is the unit row and y0_i = U^{n-1}_i there
+                const double r = bv - (q >= 0 ? u : aak);
+                rk[i] = static_cast<float>(r);
+                rr += r * r;
+                rb += bv * bv;
+            }
         } else if (lane == D) {
             if (!CS) dA[i] = dd;
         } else if (lane == D + 1) {
@@ -340,6 +368,15 @@ __global__ __launch_bounds__(kBlock) void k_tent_rows(
         } else if (lane == D + 2 && wA32) {
             wA32[i] = 1.f;
         }
+    }
+    if (CS && rpart) {
+        double v[2 * D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            v[2 * k] = lane == k ? rr : 0.0;
+            v[2 * k + 1] = lane == k ? rb : 0.0;
+        }
+        write_partials<2 * D>(v, rpart, lds);
     }
 }
 
@@ -968,6 +1005,18 @@ static int ir_outer_resid(hipStream_t s, int n, int nr, const int *rp, const int
     return read_state(s, ir.stage, ir.sums, host_sums, 2 * nr * sizeof(double));
 }
 
+// the sums of partials a producer left in ir.part (2 nr values per block)
+static int ir_sum_resid(hipStream_t s, int nr, int nparts, IRBufs &ir, double *host_sums) {
+    if (nr == 1)
+        hipLaunchKernelGGL((k_sum_to<2>), dim3(1), dim3(kBlock), 0, s, ir.part, nparts, ir.sums);
+    else if (nr == 2)
+        hipLaunchKernelGGL((k_sum_to<4>), dim3(1), dim3(kBlock), 0, s, ir.part, nparts, ir.sums);
+    else
+        hipLaunchKernelGGL((k_sum_to<6>), dim3(1), dim3(kBlock), 0, s, ir.part, nparts, ir.sums);
+    OASIS_TRY_LAUNCH();
+    return read_state(s, ir.stage, ir.sums, host_sums, 2 * nr * sizeof(double));
+}
+
 struct KOpts {
     double rtol;
     int maxit;
@@ -1026,10 +1075,12 @@ static int ir_cg(hipStream_t s, int n, const int *rp, const int *ci, const doubl
 }
 
 // BiCGStab for nr right-hand sides with FP32 inner solves (column-scaled system).
+// r0_parts > 0: ir.r32 and ir.part already hold the first outer residual
+// (FP32 copy and r0_parts blocks of partials, as k_ir_resid leaves them)
 static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *ci,
                        const double *val, const float *val32, const double *w, const float *w32,
                        double *const *b, double *const *x, const KOpts &o, BiWork<float> &bw,
-                       IRBufs &ir, SolveOut *out) {
+                       IRBufs &ir, SolveOut *out, int r0_parts = 0) {
     const int gv = grid_for(n, kBlock, 8192);
     P3 pb{}, px{};
     for (int k = 0; k < nr; ++k) {
@@ -1041,7 +1092,10 @@ static int ir_bicgstab(hipStream_t s, int n, int nr, const int *rp, const int *c
     bool done[3] = {false, false, false};
     double hs[6];
     for (int outer = 0;; ++outer) {
-        OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, bw.cols, bw.tun, w, pb, px, ir, hs));
+        if (outer == 0 && r0_parts > 0)
+            OASIS_TRY(ir_sum_resid(s, nr, r0_parts, ir, hs));
+        else
+            OASIS_TRY(ir_outer_resid(s, n, nr, rp, ci, val, bw.cols, bw.tun, w, pb, px, ir, hs));
         int active[3], na = 0;
         for (int k = 0; k < nr; ++k) {
             if (done[k]) continue;
@@ -1605,10 +1659,12 @@ extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const doubl
 
 // gp: the pressure term is already in h->bt (k_asm_rows<.., true>); cs:
 // the diagonal is already in h->dA, and the column scaling is done here
-// (no k_colscale pass afterwards)
+// (no k_colscale pass afterwards); r0 (with cs, mixed mode): also the
+// refinement loop's first residual into h->ir, returning the number of
+// partials written (0 otherwise)
 template <int D, int L>
-static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g,
-                                     double *const *x, bool gp = false, bool cs = false) {
+static int launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g,
+                                    double *const *x, bool gp = false, bool cs = false, bool r0 = false) {
     const int n = h->n;
     P3 dP{}, U1{}, cv{};
     for (int k = 0; k < D; ++k) {
@@ -1616,20 +1672,32 @@ static void launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_s
         U1.p[k] = st->U1[k];
         cv.p[k] = h->abe ? h->cv[k] : nullptr;
     }
-    const int grid = grid_for(n, kBlock / L, 1 << 20);
+    r0 = r0 && cs && h->mixed;
+    // the partials of the first residual: at most kMaxPartials blocks; 1536
+    // (six 4-wave blocks per CU) fill the chip in one round at this kernel's
+    // six waves per SIMD, so no partly filled second round
+    const int grid = grid_for(n, kBlock / L, r0 ? 1536 : 1 << 20);
     const bool e = h->ell && h->tun.ell();
+    P3F r0o{};
+    for (int k = 0; k < D && r0; ++k) r0o.p[k] = h->ir.r32[k];
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, n, h->rp, h->ci, h->M, h->A, dP, U1, cv, st->p,
                            h->ML, h->bc_index, g, h->par.n_bc, h->par.f[0], h->par.f[1], h->par.f[2],
                            2.0 / h->par.dt, h->bt[0], h->bt[1], D > 2 ? h->bt[2] : nullptr, x[0], x[1],
                            D > 2 ? x[2] : nullptr, h->dA, h->wA, h->wA32, h->mixed && !e ? h->A32 : nullptr,
-                           e ? h->eA : nullptr, e ? h->eA32 : nullptr);
+                           e ? h->eA : nullptr, e ? h->eA32 : nullptr, r0o, r0 ? h->ir.part : nullptr);
     };
     if constexpr (D == 3) {
-        if (gp && cs) return go(k_tent_rows<D, L, true, true>);
+        if (gp && cs) {
+            go(k_tent_rows<D, L, true, true>);
+            return r0 ? grid : 0;
+        }
     }
-    if (cs) return go(k_tent_rows<D, L, false, true>);
-    go(k_tent_rows<D, L, false, false>);
+    if (cs)
+        go(k_tent_rows<D, L, false, true>);
+    else
+        go(k_tent_rows<D, L, false, false>);
+    return r0 ? grid : 0;
 }
 
 // A = Bsrc + C(u_bar)/2 by the row-gather kernel (u_bar already in h->ubar);
@@ -1661,7 +1729,7 @@ static void launch_asm(hipStream_t s, oasis_ipcs *h, const double *Bsrc, bool gp
 }
 
 template <int D>
-static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g, double *const *x) {
+static int launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g, double *const *x) {
     const int n = h->n;
     P3 U1{}, U2{};
     for (int k = 0; k < D; ++k) {
@@ -1673,9 +1741,9 @@ static void launch_asm_rows(hipStream_t s, oasis_ipcs *h, const oasis_state *st,
     hipLaunchKernelGGL((k_ubar<D>), dim3(gvec(n)), dim3(kBlock), 0, s, n, U1, U2,
                        gp ? static_cast<const double *>(st->p) : nullptr, h->ubar);
     launch_asm(s, h, h->B, gp, true);
-    // right-hand sides, Dirichlet rows, y0 and the column scaling (8 lanes
-    // per row)
-    launch_step_kernels_tent<D, 8>(s, h, st, g, x, gp, true);
+    // right-hand sides, Dirichlet rows, y0, the column scaling and (mixed
+    // mode) the first refinement residual, 8 lanes per row
+    return launch_step_kernels_tent<D, 8>(s, h, st, g, x, gp, true, true);
 }
 
 template <int D, int L>
@@ -1735,7 +1803,8 @@ static int scalar_solve(hipStream_t s, oasis_ipcs *h, oasis_state *st, int a, in
                        h->par.scalar_source[a], 0.0, 0.0, 2.0 / h->par.dt, h->bt[0], static_cast<double *>(nullptr),
                        static_cast<double *>(nullptr), st->Cn[a], static_cast<double *>(nullptr),
                        static_cast<double *>(nullptr), h->dA, h->wA, h->wA32, static_cast<float *>(nullptr),
-                       static_cast<double *>(nullptr), static_cast<float *>(nullptr));
+                       static_cast<double *>(nullptr), static_cast<float *>(nullptr), P3F{},
+                       static_cast<double *>(nullptr));
     OASIS_TRY_LAUNCH();
     const bool e = h->ell && h->tun.ell();
     hipLaunchKernelGGL(k_colscale, dim3(grid_for(n, kBlock / kEll, 1 << 20)), dim3(kBlock), 0, s, n, h->rp, h->ci,
@@ -1800,6 +1869,7 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
     }
     double *x[3];
     for (int k = 0; k < D; ++k) x[k] = st->UI[k] ? st->UI[k] : h->ui[k];
+    int r0_parts = 0;   // > 0: the tentative kernel left the first refinement residual in h->ir
     if (h->abe) {
         // 1+2 (eq:convection_ABE): A = M/dt + nu K/2, the explicit convection
         // vectors, right-hand sides, Dirichlet rows, diagonal; y0 = D U^{n-1}
@@ -1822,9 +1892,9 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         // 1+2. rows gather A = B + C(u_bar)/2 and its diagonal, right-hand
         // sides, Dirichlet rows, column scaling
         if (D == 3)
-            launch_asm_rows<3>(s, h, st, bc_values, x);
+            r0_parts = launch_asm_rows<3>(s, h, st, bc_values, x);
         else
-            launch_asm_rows<2>(s, h, st, bc_values, x);
+            r0_parts = launch_asm_rows<2>(s, h, st, bc_values, x);
         OASIS_TRY_LAUNCH();
     } else {
         // 1. A = B + C(u_bar)/2, colour by colour
@@ -1884,7 +1954,7 @@ extern "C" int oasis_ipcs_step(void *stream, oasis_ipcs *h, oasis_state *st, con
         int rc_u;
         if (h->mixed)
             rc_u = ir_bicgstab(s, n, D, h->rp, h->ci, h->A, h->A32, h->wA, h->wA32, h->bt, x, ko, h->bi32, h->ir,
-                               sui);
+                               sui, it == 0 ? r0_parts : 0);
         else
             rc_u = bicgstab_solve<double>(s, n, D, h->rp, h->ci, h->A, h->wA, h->bt, x, ko.rtol, ko.maxit, 0, false,
                                           h->bi, sui);
