@@ -177,7 +177,7 @@ typedef struct {
                              OASIS_STORAGE_ELL: the ELL copy with per-entry offsets always;
                              OASIS_STORAGE_CSR: CSR products (no ELL copy is used) */
     int32_t grid_cap;     /* most blocks of a kernel that writes per-block partial sums
-                             (0 = 1024; otherwise 64..2048) */
+                             (0 = 512; otherwise 64..2048) */
     int32_t cg_form;      /* OASIS_CG_FORM_AUTO: one single-reduction pass per CG iteration with
                              FP32 values, two kernels with FP64 values; OASIS_CG_FORM_TWO;
                              OASIS_CG_FORM_SINGLE (both need the ELL copy) */
@@ -301,7 +301,7 @@ typedef struct {
     int32_t flags;        /* OASIS_KRYLOV_NULLSPACE_CONST: A is singular with null vector B;
                              OASIS_AMG_HALF_LEVEL0: see below */
     oasis_tuning tuning;  /* storage of level 0 (an ELL copy when its rows fit, unless CSR)
-                             and the grid cap of the CG kernels */
+                             and the grid cap of the CG and cycle kernels (0 = 1024 here) */
 } oasis_amg_params;
 
 /* An FP32 cycle keeps level 0's ELL values as FP16 as well and its two

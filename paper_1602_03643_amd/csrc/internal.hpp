@@ -41,7 +41,7 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 // Per-call storage and kernel-shape choices (oasis_tuning, validated).
 struct Tuning {
     int storage = OASIS_STORAGE_AUTO;
-    int grid_cap = kMaxPartials / 2;
+    int grid_cap = kMaxPartials / 4;   // 512: two blocks per CU, one round
     int cg_form = OASIS_CG_FORM_AUTO;
     bool ell() const { return storage != OASIS_STORAGE_CSR; }
     bool dict() const { return storage == OASIS_STORAGE_AUTO; }

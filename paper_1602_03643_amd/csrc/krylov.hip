@@ -33,11 +33,13 @@
 
 namespace oasis {
 
-// Producer grid cap (Tuning::grid_cap, default 1024): every consumer block
+// Producer grid cap (Tuning::grid_cap, default 512): every consumer block
 // reads all partials of its producer (up to 9 per block in BiCGStab), so
-// fewer, fuller producer blocks pay off: 1024 measured the velocity phase
-// at 6.9 ms per step against 8.3 ms with 2048 and 8.0 ms with 512 blocks
-// (1.6M rows).
+// fewer, fuller producer blocks pay off, and a grid that is a whole number
+// of blocks per CU (256 CUs) avoids a partly filled last round.  On the
+// 1.6M-row channel the mixed velocity phase took 4.95 ms per step at 512 and
+// 768 blocks, 5.23 at 1024, 5.45 at 640, 5.87 at 384, 6.63 at 2048; the
+// FP32 Jacobi-CG pressure phase 66.6 ms at 512, 68.2 at 1024, 70.3 at 768.
 
 // A flag written by an earlier kernel (or by block 0 of this one when it
 // decides to stop, a decision every block reaches identically), read once
