@@ -202,7 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_feat2(int n, const double *__rest
         lo[k] = scal[3 + k];
         span[k] = scal[6 + k] - scal[3 + k];
     }
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
         float4 *x4 = reinterpret_cast<float4 *>(X + i * 8);
         const float4 a = x4[0], b = x4[1];
         float xn[8];
@@ -364,7 +365,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(int n, int l, const int *__
                                                      const double *__restrict__ s, const float *__restrict__ W,
                                                      const float *__restrict__ P,
                                                      const unsigned short *__restrict__ Hin,
-                                                     unsigned short *__restrict__ Aout, unsigned short *__restrict__ Zout,
+                                                     unsigned short *__restrict__ Aout,
+                                                     unsigned short *__restrict__ Zout,
                                                      unsigned short *__restrict__ Hout, float *__restrict__ delta,
                                                      double *__restrict__ guess, const double *__restrict__ phi_prev,
                                                      const double *scal) {
@@ -493,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_bwd_dec(int n, const unsigned sho
     double loss = 0.0;
     const double sig = scal[0];
     const double tkt = ke ? scal[kScalTKT] : 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
         float gd;
         if (ke) {
             gd = tkt > 0.0 ? static_cast<float>(2.0 * ke[i] / tkt) : 0.f;
@@ -543,7 +546,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_bwd_gz(int n, int l, const double
     __shared__ unsigned short Th[kTile][kHid + 8];
     __shared__ unsigned short Ta[kTile][kHid + 8];
     __shared__ float gcp[kBlock / kHid][kHid];
-    for (int q = threadIdx.x; q < kHid * kHid; q += blockDim.x) Bn[q / kHid][q % kHid] = f2bf(P[kOffWn + l * kHid * kHid + q]);
+    for (int q = threadIdx.x; q < kHid * kHid; q += blockDim.x)
+        Bn[q / kHid][q % kHid] = f2bf(P[kOffWn + l * kHid * kHid + q]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kq = (lane >> 4) * 4;
     // this wave's 16x16 block (o-tile, k-tile) of the weight gradients
@@ -637,7 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_bwd_h(int n, int l, const int *__
     __shared__ unsigned short Bs[kHid][kHid];     // Bs[o][k] = Ws_l[o][k]
     __shared__ unsigned short Tg[kTile][kHid + 8];
     __shared__ float Tagg[kTile][kHid + 1];
-    for (int q = threadIdx.x; q < kHid * kHid; q += blockDim.x) Bs[q / kHid][q % kHid] = f2bf(P[kOffWs + l * kHid * kHid + q]);
+    for (int q = threadIdx.x; q < kHid * kHid; q += blockDim.x)
+        Bs[q / kHid][q % kHid] = f2bf(P[kOffWs + l * kHid * kHid + q]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kq = (lane >> 4) * 4;
     for (long long base = (long long)blockIdx.x * kTile; base < n; base += (long long)gridDim.x * kTile) {
@@ -744,7 +749,8 @@ __global__ __launch_bounds__(kBlock) void k_mp_kl_pair(int n, const float *__res
                                                        const double *__restrict__ s, const double *scal,
                                                        double *__restrict__ et) {
     const double sig = scal[0];
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
         const double t = (phi[i] - phi_prev[i]) / sig;
         const double e = static_cast<double>(delta[i]) - t;
         et[2 * i] = s[i] * e;
