@@ -1219,6 +1219,7 @@ struct oasis_ipcs {
     int *rcells = nullptr, *rv2d = nullptr;
     double *rcoords = nullptr;
     int assembly = OASIS_ASSEMBLE_ROWS, maxc = 16;
+    int r0_grid = 0;          // one-round grid of the tentative kernel that writes r0 (0: not yet known)
     double *ubar = nullptr;   // per step u_bar, interleaved ([n][D == 3 ? 4 : 2])
     double *bt[3] = {nullptr, nullptr, nullptr}, *ui[3] = {nullptr, nullptr, nullptr};
     double *bphi = nullptr, *bs = nullptr, *xs = nullptr, *xg = nullptr, *red = nullptr;
@@ -1662,6 +1663,19 @@ extern "C" int oasis_ipcs_matrix(const oasis_ipcs *h, int32_t which, const doubl
 // (no k_colscale pass afterwards); r0 (with cs, mixed mode): also the
 // refinement loop's first residual into h->ir, returning the number of
 // partials written (0 otherwise)
+// Blocks of kBlock threads that fill every CU once at `kern`'s occupancy,
+// at most kMaxPartials: a partial-writing grid without a partly filled
+// last round
+template <class K>
+static int one_round_grid(K kern) {
+    int dev = 0, cu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBlock, 0) != hipSuccess || per < 1 || cu < 1)
+        return kMaxPartials / 4;
+    return std::min(kMaxPartials, per * cu);
+}
+
 template <int D, int L>
 static int launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_state *st, const double *g,
                                     double *const *x, bool gp = false, bool cs = false, bool r0 = false) {
@@ -1673,10 +1687,17 @@ static int launch_step_kernels_tent(hipStream_t s, oasis_ipcs *h, const oasis_st
         cv.p[k] = h->abe ? h->cv[k] : nullptr;
     }
     r0 = r0 && cs && h->mixed;
-    // the partials of the first residual: at most kMaxPartials blocks; 1536
-    // (six 4-wave blocks per CU) fill the chip in one round at this kernel's
-    // six waves per SIMD, so no partly filled second round
-    const int grid = grid_for(n, kBlock / L, r0 ? 1536 : 1 << 20);
+    // the partials of the first residual: at most kMaxPartials blocks, and
+    // then one round of resident blocks (on gfx950 six per CU: 1536; 2048
+    // left a partly filled second round, 400 against 337 us)
+    if (r0 && h->r0_grid == 0) {
+        if constexpr (D == 3)
+            h->r0_grid = gp ? one_round_grid(k_tent_rows<D, L, true, true>)
+                            : one_round_grid(k_tent_rows<D, L, false, true>);
+        else
+            h->r0_grid = one_round_grid(k_tent_rows<D, L, false, true>);
+    }
+    const int grid = grid_for(n, kBlock / L, r0 ? h->r0_grid : 1 << 20);
     const bool e = h->ell && h->tun.ell();
     P3F r0o{};
     for (int k = 0; k < D && r0; ++k) r0o.p[k] = h->ir.r32[k];
