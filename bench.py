@@ -253,7 +253,7 @@ def time_cg_kernel(oa, torch, h, pat, precision, iters=200):
     matrix runs `iters` iterations, then its last launch of that kernel is
     repeated `iters` times back to back between two HIP events on the launch
     stream.  The grid is the one each kernel has in the timed steps: the FP64
-    product at the multigrid handle's cap (1024 blocks), the FP32 iteration
+    product at the multigrid handle's cap (768 blocks), the FP32 iteration
     at the Krylov default (512)."""
     Ks, _ = h.matrix(oa.FORM_STIFF)
     A = pat.with_values(Ks)
@@ -263,7 +263,7 @@ def time_cg_kernel(oa, torch, h, pat, precision, iters=200):
     b -= b.mean()
     x = torch.zeros_like(b)
     out = oa.pcg(A, b, x, rtol=1e-30, maxit=iters, precision=precision, time_kernel=True,
-                 raise_on=False, nullspace_const=True, grid_cap=1024 if precision == oa.F64 else 0)
+                 raise_on=False, nullspace_const=True, grid_cap=768 if precision == oa.F64 else 0)
     return out["kernel_ms"] / max(1, out["kernel_count"]), out["kernel_count"]
 
 

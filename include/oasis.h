@@ -301,7 +301,7 @@ typedef struct {
     int32_t flags;        /* OASIS_KRYLOV_NULLSPACE_CONST: A is singular with null vector B;
                              OASIS_AMG_HALF_LEVEL0: see below */
     oasis_tuning tuning;  /* storage of level 0 (an ELL copy when its rows fit, unless CSR)
-                             and the grid cap of the CG and cycle kernels (0 = 1024 here) */
+                             and the grid cap of the CG and cycle kernels (0 = 768 here) */
 } oasis_amg_params;
 
 /* An FP32 cycle keeps level 0's ELL values as FP16 as well and its two

@@ -254,11 +254,12 @@ extern "C" int oasis_amg_setup(void *stream, const oasis_csr *A, const double *B
         return OASIS_EINVAL;
     Tuning tun;
     OASIS_TRY(Tuning::from(&par->tuning, &tun));
-    // the multigrid CG and its cycle keep 1024 blocks unless told otherwise:
-    // on the 129x129x97 channel 512 took the FP32-cycle pressure phase from
-    // 6.32 to 6.45 ms per step (FP64 cycle unchanged), while the Krylov
-    // solvers elsewhere run best at the 512 default
-    if (par->tuning.grid_cap == 0) tun.grid_cap = kMaxPartials / 2;
+    // the multigrid CG and its cycle take 768 blocks (three per CU) unless
+    // told otherwise: on the 129x129x97 channel the headline step ran
+    // 12.47-12.49 ms at 768 against 12.59-12.60 at 1024 and 12.61 at 1280,
+    // and 512 took the FP32-cycle pressure phase from 6.32 to 6.45 ms, while
+    // the Krylov solvers elsewhere run best at the 512 default
+    if (par->tuning.grid_cap == 0) tun.grid_cap = 768;
     hipStream_t s = as_stream(stream);
     oasis_amg *h = new (std::nothrow) oasis_amg();
     if (!h) return OASIS_EINVAL;
